@@ -1,0 +1,29 @@
+"""FP64 CPU oracle for the LArTPC signal-simulation hot path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls, links or
+executes this package: only tests, the smoke check and the benchmark's CPU-baseline
+leg do.  It shares no code with the HIP implementation.
+
+Modules and what each follows (arXiv:2104.08265, Yu et al., "Evaluation of Portable
+Acceleration Solutions for LArTPC Simulation Using Wire-Cell Toolkit"):
+
+* ``raster``   - Sec. 2.1.1: the charge distribution S is built by rasterising each
+                 deposition into a small patch and adding the patches into a large
+                 grid ("rasterization" + "scatter adding").  Patch = truncated 2D
+                 Gaussian integrated over (impact bin x tick) cells.
+* ``convolve`` - Eq. 1 (signal term) and Eq. 2: M = R (*) S, a 2D convolution of the
+                 arriving-charge distribution with the impulse response, evaluated by
+                 its plain definition (direct sum) and by FFT in the frequency domain.
+* ``fluct``    - Sec. 4.3.1 / Table 2: binomial fluctuation of the rasterised charge,
+                 driven by a counter-based Philox4x32-10 stream (the RNG is factored out
+                 of the main loop, Sec. 5) and an exact two-regime binomial sampler
+                 that uses IEEE +,-,*,/ only.
+* ``grad``     - adjoint of the convolution and per-deposition gradients of the
+                 raster (differentiable mode; a reading beyond the paper, stated in
+                 each function).
+
+Pins (see tests/test_oracle_*.py): closed-form erf sums, charge conservation inside
+the window, brute-force direct convolution, delta / shift responses, linearity,
+padding invariance, adjoint identity, finite differences, the binomial law against
+scipy.stats.binom, and Philox against rocRAND's independent implementation.
+"""

@@ -1,0 +1,175 @@
+"""Pins for the oracle's fluctuation: Philox4x32-10, the deterministic series, the binomial sampler."""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import fluct as F
+from oracle import raster as RS
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def rocrand_philox(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available to build the rocRAND reference")
+    exe = str(tmp_path_factory.mktemp("philox") / "rr_philox")
+    src = os.path.join(HERE, "philox_ref", "rocrand_philox_host.cpp")
+    subprocess.run([hipcc, "-O1", "-o", exe, src], check=True, capture_output=True)
+    return exe
+
+
+def test_philox_matches_rocrand(rocrand_philox):
+    """Philox4x32-10 against rocRAND's independent engine (run on the host)."""
+    rng = np.random.default_rng(123)
+    n = 2000
+    key = rng.integers(0, 2 ** 63, n, dtype=np.uint64)
+    lo = rng.integers(0, 2 ** 62, n, dtype=np.uint64)  # the driver passes offset = 4*lo in 64 bits
+    hi = rng.integers(0, 2 ** 63, n, dtype=np.uint64)
+    key[:4] = [0, 1, 2 ** 32 - 1, 2 ** 40 + 3]
+    lo[:4] = [0, 0, 2 ** 32 - 1, 7]
+    hi[:4] = [0, 5, 2 ** 32, 2 ** 62]
+    inp = "\n".join(f"{a} {b} {c}" for a, b, c in zip(key, lo, hi)) + "\n"
+    out = subprocess.run([rocrand_philox], input=inp, capture_output=True, text=True, check=True).stdout
+    ref = np.array([[int(x) for x in line.split()] for line in out.strip().splitlines()], dtype=np.uint64)
+    words = []
+    for j in range(n):
+        k = int(key[j])
+        w = F.philox4x32_10([int(lo[j]) & 0xFFFFFFFF], [int(lo[j]) >> 32], [int(hi[j]) & 0xFFFFFFFF],
+                            [int(hi[j]) >> 32], k & 0xFFFFFFFF, k >> 32)
+        words.append([int(x[0]) for x in w])
+    assert np.array_equal(np.array(words, dtype=np.uint64), ref)
+
+
+def test_uniform_is_exact_and_in_range():
+    w0 = np.array([0, 0xFFFFFFFF, 0x12345678], np.uint32)
+    w1 = np.array([0, 0xFFFFFFFF, 0x9ABCDEF0], np.uint32)
+    u = F.uniform53(w0, w1)
+    assert u[0] == 0.0
+    assert u[1] == 1.0 - 2.0 ** -53
+    assert u[2] == ((0x12345678 >> 6) * 2 ** 27 + (0x9ABCDEF0 >> 5)) / 2.0 ** 53
+
+
+def test_det_erf_accuracy_and_symmetry():
+    x = np.linspace(-3.0, 3.0, 2001)
+    ref = np.array([math.erf(v) for v in x])
+    got = F.det_erf(x)
+    # the alternating series loses a few bits to cancellation near |x| = 3 (n_sigma = 4.2)
+    assert np.max(np.abs(got - ref)) < 2e-13
+    inner = np.abs(x) <= 2.2  # n_sigma = 3 reaches x = 3/sqrt(2)
+    assert np.max(np.abs(got - ref)[inner]) < 2e-14
+    assert np.array_equal(F.det_erf(-x), -F.det_erf(x))
+
+
+def test_det_log_exp_lfact_accuracy():
+    x = np.exp(np.linspace(-30, 30, 3001))
+    assert np.max(np.abs(F.det_log(x) - np.log(x))) < 4e-15 * 30
+    y = np.linspace(-40.0, 5.0, 3001)
+    assert np.max(np.abs(F.det_exp(y) / np.exp(y) - 1.0)) < 1e-14
+    n = np.arange(0, 3000)
+    ref = np.array([math.lgamma(v + 1.0) for v in n])
+    assert np.max(np.abs(F.det_lfact(n) - ref) / np.maximum(1.0, ref)) < 1e-14
+
+
+def _grid_u(n):
+    return (np.arange(n, dtype=np.float64) + 0.5) / n
+
+
+@pytest.mark.parametrize("N,p", [(1, 0.3), (5, 0.5), (20, 0.3), (100, 0.05), (1000, 0.0099), (50000, 1e-4),
+                                 (37, 0.8), (9, 0.999)])
+def test_inversion_regime_is_the_inverse_cdf(N, p):
+    """mu' < 10: k(u) = min{k : u < F(k)} exactly, away from the CDF steps."""
+    u = _grid_u(200_000)
+    k = F.binomial(N, np.full(u.size, p), u)
+    pp = min(p, 1 - p)
+    assert N * pp < 10
+    if p <= 0.5:
+        cdf = stats.binom.cdf(np.arange(N + 1), N, p)
+        ref = np.searchsorted(cdf, u, side="right")
+        far = np.min(np.abs(u[:, None] - cdf[None, : min(N + 1, 200)]), axis=1) > 1e-12
+        assert np.array_equal(k[far], ref[far])
+    # the law: fraction of the u-grid mapped to each k equals the pmf
+    cnt = np.bincount(k, minlength=N + 1)[: N + 1] / u.size
+    assert np.max(np.abs(cnt - stats.binom.pmf(np.arange(N + 1), N, p))) <= 1.0 / u.size + 1e-12
+
+
+@pytest.mark.parametrize("N,p", [(100, 0.1), (1000, 0.05), (2000, 0.25), (10000, 0.5), (100000, 0.05),
+                                 (200, 0.9), (25, 0.45)])
+def test_chopdown_regime_partitions_unit_interval_by_pmf(N, p):
+    """mu' >= 10: every k receives a set of u of measure pmf(k) (checked on a 4e5-point grid)."""
+    u = _grid_u(400_000)
+    k = F.binomial(N, np.full(u.size, p), u)
+    assert N * min(p, 1 - p) >= 10
+    cnt = np.bincount(k, minlength=N + 1)[: N + 1] / u.size
+    pmf = stats.binom.pmf(np.arange(N + 1), N, p)
+    assert np.max(np.abs(cnt - pmf)) <= 2.0 / u.size + 1e-12
+    # first two moments of the grid image
+    kk = k.astype(np.float64)
+    assert abs(kk.mean() - N * p) < 1e-3 * max(1.0, math.sqrt(N * p * (1 - p)))
+
+
+def test_binomial_edge_cases():
+    u = np.array([0.0, 0.3, 1.0 - 2.0 ** -53])
+    assert np.array_equal(F.binomial(0, np.full(3, 0.4), u), [0, 0, 0])
+    assert np.array_equal(F.binomial(7, np.zeros(3), u), [0, 0, 0])
+    assert np.array_equal(F.binomial(7, np.ones(3), u), [7, 7, 7])
+    assert F.binomial(7, np.array([0.5]), np.array([0.0]))[0] == 0
+    assert F.binomial(7, np.array([0.5]), np.array([1.0 - 2.0 ** -53]))[0] == 7
+    assert F.electrons(2.49999) == 2 and F.electrons(2.5) == 3 and F.electrons(0.0) == 0
+
+
+def test_fluctuated_patch_statistics():
+    """Over many seeds, per-cell mean -> N A B and variance -> N A B (1 - A B)."""
+    q, t, p, st, sp = 2000.0, 20.3, 3.27, 1.2, 0.35
+    nrow, ntick = 100, 60
+    n_seeds = 1500
+    acc = None
+    acc2 = None
+    for s in range(n_seeds):
+        rows, ticks, n = F.fluct_patch(q, t, p, st, sp, 0, 0, 0, 10, nrow, ntick, seed=s)
+        n = n.astype(np.float64)
+        acc = n if acc is None else acc + n
+        acc2 = n * n if acc2 is None else acc2 + n * n
+    mean = acc / n_seeds
+    var = acc2 / n_seeds - mean ** 2
+    _, _, w = RS.patch(1.0, t, p, st, sp, 10, nrow, ntick)
+    N = F.electrons(q)
+    pr = w
+    mu = N * pr
+    sd = np.sqrt(N * pr * (1 - pr))
+    live = mu > 0.5
+    z = (mean[live] - mu[live]) / (sd[live] / math.sqrt(n_seeds))
+    assert np.max(np.abs(z)) < 5.0
+    rel = np.abs(var[live] / (N * pr * (1 - pr))[live] - 1.0)
+    assert np.median(rel) < 0.1
+    # total is conserved in expectation: N * erf^2
+    assert abs(acc.sum() / n_seeds - N * RS.interior_patch_sum(1.0)) < 5 * math.sqrt(N) / math.sqrt(n_seeds) * 2
+
+
+def test_counter_keying():
+    """Streams differ by depo, event, plane and seed; a cell's variate does not depend on the patch."""
+    cell = np.arange(100)
+    base = F.cell_uniform(9, 1, 2, 3, cell)
+    assert not np.array_equal(base, F.cell_uniform(9, 1, 2, 4, cell))
+    assert not np.array_equal(base, F.cell_uniform(9, 1, 3, 3, cell))
+    assert not np.array_equal(base, F.cell_uniform(9, 2, 2, 3, cell))
+    assert not np.array_equal(base, F.cell_uniform(10, 1, 2, 3, cell))
+    assert np.array_equal(base[40:60], F.cell_uniform(9, 1, 2, 3, cell[40:60]))
+
+
+def test_fluct_at_matches_full_raster():
+    from paper_2104_08265_amd import synth
+    wl = synth.tiny(n_wires=8, n_ticks=40, n_depos=10, seed=21, dtype=synth.F32)
+    g = F.raster_fluct(wl.depos, wl.planes, seed=77)[0][0]
+    assert np.all(g == np.rint(g)) and g.sum() > 0
+    rng = np.random.default_rng(1)
+    rows = rng.integers(0, g.shape[0], 300)
+    ticks = rng.integers(0, g.shape[1], 300)
+    v = F.raster_fluct_at(wl.depos, 0, wl.planes[0], rows, ticks, seed=77)
+    assert np.array_equal(v, g[rows, ticks].astype(np.int64))

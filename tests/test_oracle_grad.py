@@ -1,0 +1,111 @@
+"""Pins for the oracle's adjoint and per-deposition gradients (differentiable mode)."""
+import math
+
+import numpy as np
+
+from oracle import convolve as C
+from oracle import grad as GR
+from oracle import raster as RS
+from paper_2104_08265_amd import synth
+
+ERF3SQ = 0.9946076967722628
+
+
+def _loss_and_grad(depos, planes, R, target):
+    S = RS.raster(depos, planes)[0][0]
+    M = C.convolve_fft(S, R, planes[0].n_impacts)
+    diff = M - target
+    L = float(np.sum(diff * diff))
+    H = C.adjoint_fft(2.0 * diff, R, planes[0].n_impacts)
+    return L, GR.gradients([[H]], depos, planes)
+
+
+def test_charge_gradient_is_patch_projection():
+    """g_Q * Q = <H, S_j> exactly (the raster is linear in Q)."""
+    rng = np.random.default_rng(0)
+    wl = synth.tiny(n_wires=8, n_ticks=50, n_depos=6, seed=31)
+    H = rng.standard_normal((wl.planes[0].n_rows, 50))
+    g = GR.gradients([[H]], wl.depos, wl.planes)
+    for j in range(len(wl.depos)):
+        d = wl.depos
+        rows, ticks, w = RS.patch(d.q[j], d.t[j], d.p[j], d.sigma_t[j], d.sigma_p[j], 10, H.shape[0], 50)
+        proj = float(np.sum(H[np.ix_(rows, ticks)] * w)) if rows.size and ticks.size else 0.0
+        assert abs(g[j, 0] * d.q[j] - proj) < 1e-12 * max(1.0, abs(proj))
+
+
+def test_constant_adjoint_interior_depo():
+    """Constant H and an interior window: position/width gradients vanish, g_Q = H erf^2."""
+    H = np.full((400, 300), 0.7)
+    g = GR.row_gradients(H, 1234.0, 150.3, 20.47, 2.2, 0.9, 10)
+    assert abs(g[0] - 0.7 * ERF3SQ) < 1e-14
+    assert max(abs(v) for v in g[1:]) < 1e-10
+
+
+def test_derivatives_match_finite_differences_axis():
+    """Per-axis weight derivatives against central differences (away from kinks)."""
+    for mu, s in [(10.37, 1.3), (5.21, 0.43), (70.02, 6.1)]:
+        ks, w, dmu, ds = GR.axis_weights_and_derivs(mu, s, 3.0, 1000)
+        h = 1e-6
+        assert GR.edge_distance(mu, s, 3.0) > 10 * h * 4
+        kp, wp, _, _ = GR.axis_weights_and_derivs(mu + h, s, 3.0, 1000)
+        km, wm, _, _ = GR.axis_weights_and_derivs(mu - h, s, 3.0, 1000)
+        assert np.array_equal(kp, ks) and np.array_equal(km, ks)
+        assert np.allclose((wp - wm) / (2 * h), dmu, rtol=0, atol=1e-8)
+        kp, wp, _, _ = GR.axis_weights_and_derivs(mu, s + h, 3.0, 1000)
+        km, wm, _, _ = GR.axis_weights_and_derivs(mu, s - h, 3.0, 1000)
+        assert np.allclose((wp - wm) / (2 * h), ds, rtol=0, atol=1e-8)
+
+
+def test_full_chain_finite_differences():
+    """dL/dtheta for L = sum (M(theta) - M*)^2 against FP64 central differences."""
+    wl = synth.tiny(n_wires=6, n_ticks=40, half_wires=2, resp_ticks=12, n_depos=5, seed=41)
+    R = wl.responses[0]
+    pl = wl.planes
+    d = wl.depos.astype(np.float64)
+    rng = np.random.default_rng(5)
+    tgt = RS.raster(d, pl)[0][0]
+    target = C.convolve_fft(tgt, R, 10) * 0.9 + 0.01 * rng.standard_normal((6, 40))
+    L0, g = _loss_and_grad(d, pl, R, target)
+    names = ["q", "t", "p", "sigma_t", "sigma_p"]
+    checked = 0
+    for j in range(len(d)):
+        for c, name in enumerate(names):
+            base = float(getattr(d, name)[j])
+            h = 1e-6 * max(1.0, abs(base)) if name in ("t", "p") else 1e-6 * base
+            if name in ("t", "sigma_t"):
+                if GR.edge_distance(d.t[j], d.sigma_t[j], 3.0) < 4 * h * 3:
+                    continue
+            if name in ("p", "sigma_p"):
+                if GR.edge_distance(10 * d.p[j], 10 * d.sigma_p[j], 3.0) < 4 * h * 30:
+                    continue
+            vals = []
+            for sgn in (+1, -1):
+                dd = d.astype(np.float64)
+                getattr(dd, name)[j] = base + sgn * h
+                vals.append(_loss_and_grad(dd, pl, R, target)[0])
+            fd = (vals[0] - vals[1]) / (2 * h)
+            scale = np.sqrt(np.mean(g[:, c] ** 2)) + 1e-30
+            assert abs(fd - g[j, c]) < 1e-5 * scale, (j, name, fd, g[j, c])
+            checked += 1
+    assert checked >= 20
+
+
+def test_directional_derivative():
+    wl = synth.tiny(n_wires=6, n_ticks=40, half_wires=2, resp_ticks=12, n_depos=4, seed=43)
+    R = wl.responses[0]
+    pl = wl.planes
+    d = wl.depos.astype(np.float64)
+    target = np.zeros((6, 40))
+    L0, g = _loss_and_grad(d, pl, R, target)
+    rng = np.random.default_rng(9)
+    v = rng.standard_normal(g.shape)
+    scale = np.array([[float(np.mean(d.q)), 1.0, 1.0, 1.0, 1.0]]) * 1e-6
+    vals = []
+    for sgn in (+1, -1):
+        dd = d.astype(np.float64)
+        for c, name in enumerate(["q", "t", "p", "sigma_t", "sigma_p"]):
+            getattr(dd, name)[:] = getattr(d, name) + sgn * v[:, c] * scale[0, c]
+        vals.append(_loss_and_grad(dd, pl, R, target)[0])
+    fd = (vals[0] - vals[1]) / 2.0
+    an = float(np.sum(g * v * scale))
+    assert abs(fd - an) < 1e-5 * abs(an)
