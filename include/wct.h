@@ -1,0 +1,172 @@
+/*
+ * wct.h - C ABI of libwct.so: LArTPC signal simulation on AMD MI355X (gfx950).
+ *
+ * Implements the signal part of the paper's Eq. 1,
+ *     M(t, x) = (R (*) S)(t, x),
+ * evaluated as in its Eq. 2 (transform S, multiply by the pre-computed response
+ * spectrum, transform back), where S is built by rasterising every energy
+ * deposition into a small patch and scatter-adding the patches into a large grid
+ * (Sec. 2.1.1 "rasterization" and "scatter adding"), optionally with binomial
+ * fluctuation of the electron counts (Sec. 4.3.1, Table 2).
+ *   Reference: H. Yu et al., "Evaluation of Portable Acceleration Solutions for LArTPC
+ *   Simulation Using Wire-Cell Toolkit", arXiv:2104.08265.
+ *
+ * Discretisation.  A plane has N_w wires, N_t ticks and I impact rows per wire pitch;
+ * the charge grid S of a plane is [N_b = I*N_w][N_t] (impact row major, ticks
+ * contiguous).  Time t is in ticks (tick k covers [k, k+1)); the pitch coordinate p
+ * is in wire pitches from the plane's low edge (wire w at p = w + 1/2, impact row b
+ * covers [b/I, (b+1)/I)).  The response R[k][i][tau] (k = -K..K stored at k+K,
+ * i in [0, I), tau in [0, T_R)) is the signal on wire w from unit charge in impact row
+ * I*(w+k)+i, tau ticks after arrival.  Then
+ *     M[w][t] = sum_{k,i,tau} R[k][i][tau] * S[I*(w+k)+i][t-tau],
+ * S taken as 0 outside the grid (linear, causal convolution cropped to the grid).
+ *
+ * Memory.  Every pointer argument of the run calls is a DEVICE pointer unless it is
+ * marked HOST.  The caller owns depositions, grids, waveforms, gradients and the
+ * workspace; the plan owns only its response spectra and twiddle tables.  Outputs are
+ * overwritten, never accumulated.  Grids and waveforms of one event pack the planes
+ * back to back (offsets from wct_plane_info); events follow one another.
+ *
+ * Streams and errors.  Run calls enqueue work on `stream` (a hipStream_t, NULL = the
+ * null stream) and return without synchronising.  Every call returns WCT_OK or a
+ * negative WCT_E_* code; wct_last_error() then describes it.  Invalid arguments are
+ * detected on the host before anything is enqueued.  Faults inside kernels surface at
+ * the caller's next synchronisation, as HIP specifies.  Only wct_plan_create
+ * allocates device memory or synchronises.  One plan must not be used by two threads
+ * at once; separate plans are independent.
+ */
+#ifndef WCT_H
+#define WCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WCT_ABI_VERSION 1
+/* Version of the fluctuation draw stream (counter layout + sampler).  Bumped whenever a
+ * change would alter any fluctuated count for the same inputs and seed. */
+#define WCT_FLUCT_SPEC_VERSION 1
+
+typedef struct wct_plan wct_plan;
+
+enum wct_dtype { WCT_F32 = 0, WCT_F64 = 1 };
+
+enum wct_status {
+  WCT_OK = 0,
+  WCT_E_INVALID = -1,     /* bad argument (NULL, size, range, dtype, option)          */
+  WCT_E_WORKSPACE = -2,   /* workspace smaller than wct_workspace_bytes() asks for     */
+  WCT_E_DEVICE = -3,      /* a HIP runtime call failed (text in wct_last_error)        */
+  WCT_E_UNSUPPORTED = -4, /* geometry the kernels do not handle (e.g. FFT length)      */
+  WCT_E_NOMEM = -5        /* device allocation at plan creation failed                  */
+};
+
+enum wct_op { WCT_OP_RASTER = 0, WCT_OP_CONVOLVE = 1, WCT_OP_SIMULATE = 2, WCT_OP_BACKWARD = 3 };
+
+/* One readout plane. */
+typedef struct {
+  int32_t n_wires;      /* N_w >= 1 */
+  int32_t n_ticks;      /* N_t >= 1 */
+  int32_t n_impacts;    /* I >= 1, impact rows per wire pitch */
+  int32_t half_wires;   /* K >= 0: the response spans wires -K..K */
+  int32_t resp_ticks;   /* T_R >= 1 */
+  const void* response; /* HOST [2K+1][I][T_R] row-major in the plan dtype; copied */
+} wct_plane_desc;
+
+typedef struct {
+  int32_t dtype;                /* WCT_F32 or WCT_F64: grids, waveforms, depo floats */
+  int32_t n_planes;             /* >= 1 */
+  const wct_plane_desc* planes; /* HOST [n_planes] */
+  int32_t max_events;           /* largest n_events any run call will pass (>= 1) */
+  int32_t device;               /* HIP device ordinal the plan and its calls use */
+} wct_plan_desc;
+
+/* Depo-plane rows: one row per (deposition, plane) projection, structure of arrays.
+ * Float arrays are in the plan dtype. */
+typedef struct {
+  int64_t n;              /* number of rows, >= 0 */
+  const void* q;          /* [n] charge, electrons, >= 0 */
+  const void* t;          /* [n] arrival time, ticks */
+  const void* p;          /* [n] pitch coordinate, wire pitches */
+  const void* sigma_t;    /* [n] longitudinal width, ticks, > 0 */
+  const void* sigma_p;    /* [n] transverse width, wire pitches, > 0 */
+  const int32_t* plane;   /* [n] plane index in [0, n_planes) */
+  const int32_t* event;   /* [n] event index in [0, n_events) */
+  const int32_t* depo_id; /* [n] deposition id (fluctuation counter word 1) */
+} wct_depos;
+
+typedef struct {
+  double nsigma;     /* truncation half-width of the Gaussian patch in sigmas, (0, 8] */
+  int32_t fluctuate; /* 0: mean charge; 1: binomial electron counts (needs nsigma <= 4.2) */
+  int32_t n_events;  /* events in this call, 1..max_events */
+  uint64_t seed;     /* fluctuation key (Philox4x32-10 key words: low, high 32 bits) */
+} wct_opts;
+
+/* Geometry of a plane as planned: out[0..9] = N_w, N_t, I, K, T_R, L_w, L_t, F,
+ * grid offset (elements within an event), waveform offset (elements within an event).
+ * L_w >= N_w + K and L_t >= N_t + T_R - 1 are the 2,3,5-smooth transform lengths,
+ * F = L_t/2 + 1 the number of tick frequencies kept. */
+int wct_plane_info(const wct_plan* plan, int32_t plane, int64_t out[10]);
+
+/* Build a plan: validates the geometry, copies the responses and pre-computes, on the
+ * device, the response spectrum of every plane (Eq. 2: "pre-calculated detector
+ * response function in the frequency domain").  The only call that allocates device
+ * memory or synchronises.  On failure *out is NULL. */
+int wct_plan_create(const wct_plan_desc* desc, wct_plan** out);
+void wct_plan_destroy(wct_plan* plan); /* NULL is a no-op; synchronises the device */
+
+/* Elements of one event's packed grid (sum over planes of I*N_w*N_t) and waveform
+ * (sum over planes of N_w*N_t).  -1 on a NULL plan. */
+int64_t wct_grid_elems(const wct_plan* plan);
+int64_t wct_wave_elems(const wct_plan* plan);
+
+/* Workspace bytes a run call needs for `n_events` events and `n_rows` depo rows
+ * (n_rows is ignored by WCT_OP_CONVOLVE).  0 on invalid arguments. */
+size_t wct_workspace_bytes(const wct_plan* plan, int32_t op, int32_t n_events, int64_t n_rows);
+
+/* Rasterisation + scatter adding (Sec. 2.1.1): grid[event][planes packed][N_b][N_t]
+ * receives, for every row, Q * A_b * B_k on the cells of its truncated window, where
+ * A_b, B_k are the Gaussian's integrals over the parts of impact row b and tick k that
+ * lie inside mu +- nsigma*sigma (u = I*p, sigma_u = I*sigma_p on the impact axis).
+ * Cells outside the grid are dropped.  With fluctuate = 1 each cell instead receives an
+ * independent Binomial(floor(Q+1/2), A_b*B_k) count drawn from Philox4x32-10 with
+ * counter (b*N_t + k, depo_id, event, plane << 24) and key `seed`, by the sampler of
+ * WCT_FLUCT_SPEC_VERSION (bit-reproducible, independent of scheduling).  Rows with
+ * sigma <= 0, Q < 0 or non-finite values contribute nothing.  The whole grid of every
+ * event in [0, n_events) is overwritten. */
+int wct_raster(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* grid, void* ws,
+               size_t ws_bytes, void* stream);
+
+/* Convolution by FFT (Eq. 2): wave[event][planes packed][N_w][N_t] = R (*) grid for
+ * n_events events.  Row transforms along ticks (real-to-complex, length L_t), column
+ * transforms along impact rows per phase (length L_w), the product with the
+ * pre-computed spectrum summed over the I phases, and the inverse transforms. */
+int wct_convolve(wct_plan* plan, const void* grid, int32_t n_events, void* wave, void* ws, size_t ws_bytes,
+                 void* stream);
+
+/* wct_raster followed by wct_convolve, the grid living in the workspace. */
+int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* wave, void* ws,
+                 size_t ws_bytes, void* stream);
+
+/* Gradients of a scalar loss with respect to each row's (Q, t, p, sigma_t, sigma_p),
+ * given grad_wave = dL/dwave (same layout as wave).  Uses the convolution's adjoint
+ * (correlation with the conjugate spectrum) and the Gaussian-pdf derivatives of the
+ * clipped bin integrals; the charge grid is recomputed, never stored.  Requires
+ * fluctuate = 0.  Each g_* is [n] in the plan dtype, overwritten. */
+int wct_simulate_backward(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, const void* grad_wave,
+                          void* g_q, void* g_t, void* g_p, void* g_sigma_t, void* g_sigma_p, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char* wct_last_error(void);
+
+int wct_abi_version(void);          /* WCT_ABI_VERSION */
+int wct_fluct_spec_version(void);   /* WCT_FLUCT_SPEC_VERSION */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WCT_H */

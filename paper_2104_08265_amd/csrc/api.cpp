@@ -1,0 +1,623 @@
+// C ABI of libwct.so (declared in include/wct.h): plans, workspace carving, argument
+// validation and the launch sequences of the raster, convolution and gradient paths.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "wct.h"
+
+using namespace wct;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(WCT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                       \
+  do {                                            \
+    hipError_t e__ = (expr);                      \
+    if (e__ != hipSuccess) return hip_fail(e__, what); \
+  } while (0)
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+bool smooth235(int64_t n) {
+  if (n < 1) return false;
+  for (int f : {2, 3, 5})
+    while (n % f == 0) n /= f;
+  return n == 1;
+}
+int64_t next_smooth(int64_t n) {
+  if (n < 1) n = 1;
+  while (!smooth235(n)) ++n;
+  return n;
+}
+
+// exp(-2 pi i m / n) with the angle reduced exactly and evaluated in long double.
+cx<double> wexp(int64_t m, int64_t n) {
+  m %= n;
+  if (m < 0) m += n;
+  const long double a = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)n;
+  return mk((double)cosl(a), (double)sinl(a));
+}
+
+bool build_fft(int n, FftPlan& fp, std::vector<cx<double>>& tw) {
+  std::memset(&fp, 0, sizeof(fp));
+  fp.n = n;
+  int a = 0, b = 0, c = 0, r = n;
+  while (r % 2 == 0) r /= 2, ++a;
+  while (r % 3 == 0) r /= 3, ++b;
+  while (r % 5 == 0) r /= 5, ++c;
+  if (r != 1) return false;
+  std::vector<int> rad;
+  while (a >= 3) rad.push_back(8), a -= 3;
+  if (a == 2) rad.push_back(4);
+  if (a == 1) rad.push_back(2);
+  for (int k = 0; k < c; ++k) rad.push_back(5);
+  for (int k = 0; k < b; ++k) rad.push_back(3);
+  if ((int)rad.size() > kMaxPass) return false;
+  tw.clear();
+  int Ns = 1;
+  fp.npass = (int)rad.size();
+  for (int p = 0; p < fp.npass; ++p) {
+    const int R = rad[p];
+    fp.radix[p] = R;
+    fp.tw_off[p] = (int)tw.size();
+    for (int k = 0; k < Ns; ++k)
+      for (int q = 1; q < R; ++q) tw.push_back(wexp((int64_t)q * k, (int64_t)Ns * R));
+    Ns *= R;
+  }
+  if (tw.empty()) tw.push_back(mk(1.0, 0.0));
+  return true;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Bump allocator over a caller-provided workspace (base == nullptr only sizes).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  void* take(size_t bytes) {
+    off = align_up(off, 256);
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+}  // namespace
+
+struct wct_plan {
+  int dtype = WCT_F32;
+  int device = 0;
+  int n_planes = 0;
+  int max_events = 1;
+  int n_cu = 256;
+  size_t esize = 4;  // bytes of one real value
+  std::vector<PlaneGeom> geom;
+  std::vector<FftPlan> fp_t, fp_w;
+  std::vector<void*> tw_t, post_t, tw_w, rtil;
+  DetTables* d_tables = nullptr;
+  std::vector<void*> allocs;
+  int64_t grid_elems = 0, wave_elems = 0, shat_elems = 0, mhat_elems = 0;
+  int ntiles_ev = 0;
+
+  void* dalloc(size_t bytes, hipError_t* e) {
+    void* p = nullptr;
+    *e = hipMalloc(&p, bytes ? bytes : 1);
+    if (*e == hipSuccess) allocs.push_back(p);
+    return p;
+  }
+  ~wct_plan() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+RasterGeom raster_geom(const wct_plan* P, int n_events) {
+  RasterGeom g;
+  std::memset(&g, 0, sizeof(g));
+  g.n_planes = P->n_planes;
+  g.n_events = n_events;
+  g.ntiles_ev = P->ntiles_ev;
+  g.grid_ev_stride = P->grid_elems;
+  for (int p = 0; p < P->n_planes; ++p) g.pl[p] = P->geom[p];
+  return g;
+}
+
+// Workspace layouts ---------------------------------------------------------------
+RasterWs carve_raster(const wct_plan* P, Carver& cv, int n_events, int64_t n_rows) {
+  RasterWs w;
+  w.ntiles = (int64_t)n_events * P->ntiles_ev;
+  const int64_t nrow = n_rows > 0 ? n_rows : 1;
+  w.max_items = w.ntiles + (4 * nrow + kRowsPerItem - 1) / kRowsPerItem + 1;
+  const int64_t nsb = (w.ntiles + kScanPerBlock - 1) / kScanPerBlock;
+  w.ctrl = static_cast<int32_t*>(cv.take(sizeof(int32_t) * (kCtrlWords + 2 * w.ntiles)));
+  w.counts = w.ctrl ? w.ctrl + kCtrlWords : nullptr;
+  w.cursor = w.counts ? w.counts + w.ntiles : nullptr;
+  w.offs = static_cast<int32_t*>(cv.take(sizeof(int32_t) * (w.ntiles + 1)));
+  w.item_off = static_cast<int32_t*>(cv.take(sizeof(int32_t) * (w.ntiles + 1)));
+  w.items = static_cast<int32_t*>(cv.take(sizeof(int32_t) * w.max_items));
+  w.list = static_cast<int32_t*>(cv.take(sizeof(int32_t) * 4 * nrow));
+  w.big = static_cast<int32_t*>(cv.take(sizeof(int32_t) * nrow));
+  w.blocks = static_cast<int32_t*>(cv.take(sizeof(int32_t) * 2 * (nsb > 0 ? nsb : 1)));
+  return w;
+}
+
+struct ConvWs {
+  void* shat;
+  void* mhat;
+};
+ConvWs carve_conv(const wct_plan* P, Carver& cv, int n_events) {
+  ConvWs c;
+  c.shat = cv.take(2 * P->esize * (size_t)n_events * P->shat_elems);
+  c.mhat = cv.take(2 * P->esize * (size_t)n_events * P->mhat_elems);
+  return c;
+}
+
+size_t ws_bytes(const wct_plan* P, int op, int n_events, int64_t n_rows) {
+  if (op == WCT_OP_RASTER) {
+    Carver cv(nullptr);
+    carve_raster(P, cv, n_events, n_rows);
+    return align_up(cv.off, 256);
+  }
+  if (op == WCT_OP_CONVOLVE) {
+    Carver cv(nullptr);
+    carve_conv(P, cv, n_events);
+    return align_up(cv.off, 256);
+  }
+  if (op == WCT_OP_SIMULATE) {
+    Carver a(nullptr);
+    a.take(P->esize * (size_t)n_events * P->grid_elems);
+    const size_t head = align_up(a.off, 256);
+    Carver r(nullptr), c(nullptr);
+    carve_raster(P, r, n_events, n_rows);
+    carve_conv(P, c, n_events);
+    return head + align_up(r.off > c.off ? r.off : c.off, 256);
+  }
+  if (op == WCT_OP_BACKWARD) {
+    Carver a(nullptr);
+    a.take(P->esize * (size_t)n_events * P->grid_elems);        // H = dL/dS
+    a.take(2 * P->esize * (size_t)n_events * P->mhat_elems);    // dL/dM-hat
+    a.take(2 * P->esize * (size_t)n_events * P->shat_elems);    // dL/dS-hat
+    return align_up(a.off, 256);
+  }
+  return 0;
+}
+
+// Validation -----------------------------------------------------------------------
+int check_opts(const wct_plan* P, const wct_opts* o, bool need_nsigma) {
+  if (!o) return fail(WCT_E_INVALID, "opts is NULL");
+  if (o->n_events < 1 || o->n_events > P->max_events)
+    return fail(WCT_E_INVALID, "n_events %d outside [1, %d]", o->n_events, P->max_events);
+  if (need_nsigma && !(o->nsigma > 0.0 && o->nsigma <= 8.0))
+    return fail(WCT_E_INVALID, "nsigma %g outside (0, 8]", o->nsigma);
+  if (o->fluctuate != 0 && o->fluctuate != 1) return fail(WCT_E_INVALID, "fluctuate must be 0 or 1");
+  if (o->fluctuate && o->nsigma > 4.2)
+    return fail(WCT_E_INVALID, "fluctuation needs nsigma <= 4.2 (the erf series range), got %g", o->nsigma);
+  return WCT_OK;
+}
+
+int check_depos(const wct_depos* d) {
+  if (!d) return fail(WCT_E_INVALID, "depos is NULL");
+  if (d->n < 0 || d->n > 0x7fffffffLL) return fail(WCT_E_INVALID, "depos.n %lld out of range", (long long)d->n);
+  if (d->n > 0 && (!d->q || !d->t || !d->p || !d->sigma_t || !d->sigma_p))
+    return fail(WCT_E_INVALID, "depos float arrays must not be NULL");
+  return WCT_OK;
+}
+
+template <typename T>
+DepoView<T> view(const wct_depos* d) {
+  DepoView<T> v;
+  v.n = d->n;
+  v.q = static_cast<const T*>(d->q);
+  v.t = static_cast<const T*>(d->t);
+  v.p = static_cast<const T*>(d->p);
+  v.st = static_cast<const T*>(d->sigma_t);
+  v.sp = static_cast<const T*>(d->sigma_p);
+  v.plane = d->plane;
+  v.event = d->event;
+  v.depo_id = d->depo_id;
+  return v;
+}
+
+// Launch sequences -------------------------------------------------------------------
+template <typename T>
+int run_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, T* grid, Carver& cv, hipStream_t st) {
+  const RasterGeom g = raster_geom(P, o->n_events);
+  const RasterWs ws = carve_raster(P, cv, o->n_events, d->n);
+  HIP_TRY(launch_raster<T>(view<T>(d), g, o->nsigma, o->fluctuate, o->seed, grid, ws, P->d_tables, P->n_cu, st),
+          "raster launch");
+  return WCT_OK;
+}
+
+template <typename T>
+int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, hipStream_t st) {
+  const ConvWs c = carve_conv(P, cv, n_events);
+  cx<T>* shat = static_cast<cx<T>*>(c.shat);
+  cx<T>* mhat = static_cast<cx<T>*>(c.mhat);
+  for (int p = 0; p < P->n_planes; ++p) {
+    const PlaneGeom& G = P->geom[p];
+    const cx<T>* tw_t = static_cast<const cx<T>*>(P->tw_t[p]);
+    const cx<T>* post = static_cast<const cx<T>*>(P->post_t[p]);
+    const cx<T>* tw_w = static_cast<const cx<T>*>(P->tw_w[p]);
+    HIP_TRY(launch_rows_r2c<T>(grid + G.grid_off, P->grid_elems, shat + G.shat_off, P->shat_elems, G.nt, G.I, G.nw,
+                               G.nchunk, n_events, P->fp_t[p], tw_t, post, st),
+            "row transform launch");
+    HIP_TRY(launch_colpass<T>(shat + G.shat_off, P->shat_elems, static_cast<const cx<T>*>(P->rtil[p]),
+                              mhat + G.mhat_off, P->mhat_elems, G.nw, G.I, G.nchunk, n_events, P->fp_w[p], tw_w, st),
+            "column pass launch");
+    HIP_TRY(launch_rows_c2r<T>(mhat + G.mhat_off, P->mhat_elems, wave + G.wave_off, P->wave_elems, G.nt, false, 1,
+                               G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, st),
+            "inverse row transform launch");
+  }
+  return WCT_OK;
+}
+
+template <typename T>
+int run_backward(wct_plan* P, const wct_depos* d, const wct_opts* o, const T* gw, T* gq, T* gt, T* gp, T* gst,
+                 T* gsp, Carver& cv, hipStream_t st) {
+  const int ne = o->n_events;
+  T* H = static_cast<T*>(cv.take(P->esize * (size_t)ne * P->grid_elems));
+  cx<T>* ghat = static_cast<cx<T>*>(cv.take(2 * P->esize * (size_t)ne * P->mhat_elems));
+  cx<T>* hhat = static_cast<cx<T>*>(cv.take(2 * P->esize * (size_t)ne * P->shat_elems));
+  for (int p = 0; p < P->n_planes; ++p) {
+    const PlaneGeom& G = P->geom[p];
+    const cx<T>* tw_t = static_cast<const cx<T>*>(P->tw_t[p]);
+    const cx<T>* post = static_cast<const cx<T>*>(P->post_t[p]);
+    const cx<T>* tw_w = static_cast<const cx<T>*>(P->tw_w[p]);
+    HIP_TRY(launch_rows_r2c<T>(gw + G.wave_off, P->wave_elems, ghat + G.mhat_off, P->mhat_elems, G.nt, 1, G.nw,
+                               G.nchunk, ne, P->fp_t[p], tw_t, post, st),
+            "adjoint row transform launch");
+    HIP_TRY(launch_colpass_adj<T>(ghat + G.mhat_off, P->mhat_elems, static_cast<const cx<T>*>(P->rtil[p]),
+                                  hhat + G.shat_off, P->shat_elems, G.nw, G.I, G.nchunk, ne, P->fp_w[p], tw_w, st),
+            "adjoint column pass launch");
+    HIP_TRY(launch_rows_c2r<T>(hhat + G.shat_off, P->shat_elems, H + G.grid_off, P->grid_elems, G.nt, true, G.I, G.nw,
+                               G.nchunk, ne, P->fp_t[p], tw_t, post, st),
+            "adjoint inverse row transform launch");
+  }
+  HIP_TRY(launch_grad_gather<T>(view<T>(d), raster_geom(P, ne), o->nsigma, H, gq, gt, gp, gst, gsp, st),
+          "gradient gather launch");
+  return WCT_OK;
+}
+
+// Plan creation ------------------------------------------------------------------------
+template <typename T>
+int upload_table(wct_plan* P, const std::vector<cx<double>>& h, void** out) {
+  std::vector<cx<T>> v(h.size());
+  for (size_t i = 0; i < h.size(); ++i) v[i] = mk((T)h[i].x, (T)h[i].y);
+  hipError_t e;
+  void* d = P->dalloc(sizeof(cx<T>) * v.size(), &e);
+  if (e != hipSuccess) return fail(WCT_E_NOMEM, "hipMalloc of a twiddle table failed: %s", hipGetErrorString(e));
+  HIP_TRY(hipMemcpy(d, v.data(), sizeof(cx<T>) * v.size(), hipMemcpyHostToDevice), "twiddle upload");
+  *out = d;
+  return WCT_OK;
+}
+
+template <typename T>
+int plan_tables(wct_plan* P, const wct_plan_desc* desc) {
+  const size_t lds_max = 160 * 1024;
+  for (int p = 0; p < P->n_planes; ++p) {
+    PlaneGeom& G = P->geom[p];
+    if ((size_t)G.M * sizeof(cx<T>) > lds_max || !conv_fits<T>(G.M))
+      return fail(WCT_E_UNSUPPORTED, "plane %d: tick transform length %d exceeds the LDS-resident limit", p, G.lt);
+    if ((size_t)G.lw * kChunk * sizeof(cx<T>) > lds_max || !conv_fits<T>(G.lw * kChunk))
+      return fail(WCT_E_UNSUPPORTED, "plane %d: wire transform length %d exceeds the LDS-resident limit", p, G.lw);
+    std::vector<cx<double>> tw;
+    FftPlan fp;
+    if (!build_fft(G.M, fp, tw)) return fail(WCT_E_UNSUPPORTED, "plane %d: length %d not 2,3,5-smooth", p, G.M);
+    P->fp_t.push_back(fp);
+    void* d = nullptr;
+    int rc = upload_table<T>(P, tw, &d);
+    if (rc) return rc;
+    P->tw_t.push_back(d);
+    std::vector<cx<double>> post(G.M + 1);
+    for (int k = 0; k <= G.M; ++k) post[k] = wexp(k, G.lt);
+    rc = upload_table<T>(P, post, &d);
+    if (rc) return rc;
+    P->post_t.push_back(d);
+    if (!build_fft(G.lw, fp, tw)) return fail(WCT_E_UNSUPPORTED, "plane %d: length %d not 2,3,5-smooth", p, G.lw);
+    P->fp_w.push_back(fp);
+    rc = upload_table<T>(P, tw, &d);
+    if (rc) return rc;
+    P->tw_w.push_back(d);
+
+    // response spectrum, FP64 on the device, stored in the plan dtype
+    const wct_plane_desc& pd = desc->planes[p];
+    const int nk = 2 * G.K + 1;
+    const size_t nr = (size_t)nk * G.I * G.TR;
+    std::vector<double> R(nr);
+    for (size_t i = 0; i < nr; ++i) R[i] = (double)static_cast<const T*>(pd.response)[i];
+    std::vector<cx<double>> tlt(G.lt), tlw(G.lw);
+    for (int m = 0; m < G.lt; ++m) tlt[m] = wexp(m, G.lt);
+    for (int m = 0; m < G.lw; ++m) tlw[m] = wexp(m, G.lw);
+    double* dR = nullptr;
+    cx<double>*dtlt = nullptr, *dtlw = nullptr, *drt = nullptr;
+    hipError_t e = hipMalloc(&dR, sizeof(double) * nr);
+    if (e == hipSuccess) e = hipMalloc(&dtlt, sizeof(cx<double>) * G.lt);
+    if (e == hipSuccess) e = hipMalloc(&dtlw, sizeof(cx<double>) * G.lw);
+    if (e == hipSuccess) e = hipMalloc(&drt, sizeof(cx<double>) * (size_t)nk * G.I * G.F);
+    void* rtil = nullptr;
+    if (e == hipSuccess) rtil = P->dalloc(sizeof(cx<T>) * (size_t)G.nchunk * G.I * G.lw * kChunk, &e);
+    if (e == hipSuccess) e = hipMemcpy(dR, R.data(), sizeof(double) * nr, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dtlt, tlt.data(), sizeof(cx<double>) * G.lt, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dtlw, tlw.data(), sizeof(cx<double>) * G.lw, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_resp_tick(dR, nk, G.I, G.TR, G.lt, G.F, dtlt, drt, nullptr);
+    if (e == hipSuccess)
+      e = launch_resp_wire<T>(drt, G.K, G.I, G.F, G.lw, G.lt, G.nchunk, dtlw, static_cast<cx<T>*>(rtil), nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    (void)hipFree(dR);
+    (void)hipFree(dtlt);
+    (void)hipFree(dtlw);
+    (void)hipFree(drt);
+    if (e != hipSuccess) return hip_fail(e, "response spectrum");
+    P->rtil.push_back(rtil);
+  }
+  return WCT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wct_abi_version(void) { return WCT_ABI_VERSION; }
+int wct_fluct_spec_version(void) { return WCT_FLUCT_SPEC_VERSION; }
+const char* wct_last_error(void) { return g_err.c_str(); }
+
+int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
+  g_err.clear();
+  if (!out) return fail(WCT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!desc) return fail(WCT_E_INVALID, "desc is NULL");
+  if (desc->dtype != WCT_F32 && desc->dtype != WCT_F64) return fail(WCT_E_INVALID, "dtype %d", desc->dtype);
+  if (desc->n_planes < 1 || desc->n_planes > kMaxPlanes)
+    return fail(WCT_E_INVALID, "n_planes %d outside [1, %d]", desc->n_planes, kMaxPlanes);
+  if (!desc->planes) return fail(WCT_E_INVALID, "planes is NULL");
+  if (desc->max_events < 1) return fail(WCT_E_INVALID, "max_events %d < 1", desc->max_events);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(WCT_E_DEVICE, "no HIP device available");
+  if (desc->device < 0 || desc->device >= ndev) return fail(WCT_E_INVALID, "device %d of %d", desc->device, ndev);
+
+  wct_plan* P = new wct_plan();
+  P->dtype = desc->dtype;
+  P->device = desc->device;
+  P->n_planes = desc->n_planes;
+  P->max_events = desc->max_events;
+  P->esize = desc->dtype == WCT_F32 ? 4 : 8;
+  const int TH = desc->dtype == WCT_F32 ? TileShape<float>::TH : TileShape<double>::TH;
+  const int TW = desc->dtype == WCT_F32 ? TileShape<float>::TW : TileShape<double>::TW;
+  int64_t goff = 0, woff = 0, soff = 0, moff = 0, toff = 0;
+  for (int p = 0; p < P->n_planes; ++p) {
+    const wct_plane_desc& pd = desc->planes[p];
+    if (pd.n_wires < 1 || pd.n_ticks < 1 || pd.n_impacts < 1 || pd.half_wires < 0 || pd.resp_ticks < 1 ||
+        !pd.response) {
+      delete P;
+      return fail(WCT_E_INVALID, "plane %d: bad geometry or NULL response", p);
+    }
+    PlaneGeom G;
+    std::memset(&G, 0, sizeof(G));
+    G.nw = pd.n_wires;
+    G.nt = pd.n_ticks;
+    G.I = pd.n_impacts;
+    G.K = pd.half_wires;
+    G.TR = pd.resp_ticks;
+    G.nb = G.I * G.nw;
+    const int64_t nbt = (int64_t)G.nb * G.nt;
+    if ((int64_t)G.nb > 0x7fffffff / 2 || nbt >= (1LL << 32)) {
+      delete P;
+      return fail(WCT_E_UNSUPPORTED, "plane %d: grid of %lld cells exceeds 2^32", p, (long long)nbt);
+    }
+    G.lw = (int)next_smooth((int64_t)G.nw + G.K);
+    G.lt = 2 * (int)next_smooth(((int64_t)G.nt + G.TR - 1 + 1) / 2);
+    G.M = G.lt / 2;
+    G.F = G.M + 1;
+    G.nchunk = (G.F + kChunk - 1) / kChunk;
+    G.grid_off = goff;
+    G.wave_off = woff;
+    G.shat_off = soff;
+    G.mhat_off = moff;
+    G.tile_off = toff;
+    G.ntr = (G.nb + TH - 1) / TH;
+    G.ntc = (G.nt + TW - 1) / TW;
+    goff += nbt;
+    woff += (int64_t)G.nw * G.nt;
+    soff += (int64_t)G.nchunk * kChunk * G.nb;
+    moff += (int64_t)G.nw * G.nchunk * kChunk;
+    toff += (int64_t)G.ntr * G.ntc;
+    P->geom.push_back(G);
+  }
+  P->grid_elems = goff;
+  P->wave_elems = woff;
+  P->shat_elems = soff;
+  P->mhat_elems = moff;
+  if (toff * (int64_t)P->max_events > 0x3fffffffLL) {
+    delete P;
+    return fail(WCT_E_UNSUPPORTED, "too many raster tiles (%lld per event)", (long long)toff);
+  }
+  P->ntiles_ev = (int)toff;
+
+  DeviceGuard dg(P->device);
+  if (!dg.ok) {
+    delete P;
+    return fail(WCT_E_DEVICE, "hipSetDevice(%d) failed", desc->device);
+  }
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device) == hipSuccess && ncu > 0)
+    P->n_cu = ncu;
+  conv_init_kernels();
+  int rc = P->dtype == WCT_F32 ? plan_tables<float>(P, desc) : plan_tables<double>(P, desc);
+  if (rc) {
+    delete P;
+    return rc;
+  }
+  DetTables tb;
+  std::memset(&tb, 0, sizeof(tb));
+  for (int j = 1; j < 256; ++j) tb.inv[j] = 1.0 / (double)j;
+  double f = 1.0;
+  for (int j = 0; j <= 18; ++j) {
+    if (j > 0) f *= (double)j;
+    tb.fact[j] = f;
+    if (j <= 16) tb.inv_fact[j] = 1.0 / f;
+  }
+  hipError_t e;
+  P->d_tables = static_cast<DetTables*>(P->dalloc(sizeof(DetTables), &e));
+  if (e != hipSuccess) {
+    delete P;
+    return fail(WCT_E_NOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
+  }
+  e = hipMemcpy(P->d_tables, &tb, sizeof(tb), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    delete P;
+    return hip_fail(e, "table upload");
+  }
+  *out = P;
+  return WCT_OK;
+}
+
+void wct_plan_destroy(wct_plan* plan) {
+  if (!plan) return;
+  DeviceGuard dg(plan->device);
+  (void)hipDeviceSynchronize();
+  delete plan;
+}
+
+int64_t wct_grid_elems(const wct_plan* plan) { return plan ? plan->grid_elems : -1; }
+int64_t wct_wave_elems(const wct_plan* plan) { return plan ? plan->wave_elems : -1; }
+
+int wct_plane_info(const wct_plan* plan, int32_t plane, int64_t out[10]) {
+  g_err.clear();
+  if (!plan || !out) return fail(WCT_E_INVALID, "NULL argument");
+  if (plane < 0 || plane >= plan->n_planes) return fail(WCT_E_INVALID, "plane %d of %d", plane, plan->n_planes);
+  const PlaneGeom& G = plan->geom[plane];
+  const int64_t v[10] = {G.nw, G.nt, G.I, G.K, G.TR, G.lw, G.lt, G.F, G.grid_off, G.wave_off};
+  for (int i = 0; i < 10; ++i) out[i] = v[i];
+  return WCT_OK;
+}
+
+size_t wct_workspace_bytes(const wct_plan* plan, int32_t op, int32_t n_events, int64_t n_rows) {
+  if (!plan || n_events < 1 || n_events > plan->max_events || n_rows < 0) return 0;
+  return ws_bytes(plan, op, n_events, n_rows);
+}
+
+int wct_raster(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* grid, void* ws, size_t ws_size,
+               void* stream) {
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  int rc = check_opts(plan, opts, true);
+  if (rc) return rc;
+  if ((rc = check_depos(depos))) return rc;
+  if (!grid) return fail(WCT_E_INVALID, "grid is NULL");
+  const size_t need = ws_bytes(plan, WCT_OP_RASTER, opts->n_events, depos->n);
+  if (!ws || ws_size < need) return fail(WCT_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_size, need);
+  DeviceGuard dg(plan->device);
+  if (!dg.ok) return fail(WCT_E_DEVICE, "hipSetDevice(%d) failed", plan->device);
+  Carver cv(ws);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return plan->dtype == WCT_F32 ? run_raster<float>(plan, depos, opts, static_cast<float*>(grid), cv, st)
+                                : run_raster<double>(plan, depos, opts, static_cast<double*>(grid), cv, st);
+}
+
+int wct_convolve(wct_plan* plan, const void* grid, int32_t n_events, void* wave, void* ws, size_t ws_size,
+                 void* stream) {
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  if (n_events < 1 || n_events > plan->max_events)
+    return fail(WCT_E_INVALID, "n_events %d outside [1, %d]", n_events, plan->max_events);
+  if (!grid || !wave) return fail(WCT_E_INVALID, "grid or wave is NULL");
+  const size_t need = ws_bytes(plan, WCT_OP_CONVOLVE, n_events, 0);
+  if (!ws || ws_size < need) return fail(WCT_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_size, need);
+  DeviceGuard dg(plan->device);
+  if (!dg.ok) return fail(WCT_E_DEVICE, "hipSetDevice(%d) failed", plan->device);
+  Carver cv(ws);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return plan->dtype == WCT_F32
+             ? run_convolve<float>(plan, static_cast<const float*>(grid), n_events, static_cast<float*>(wave), cv, st)
+             : run_convolve<double>(plan, static_cast<const double*>(grid), n_events, static_cast<double*>(wave), cv,
+                                    st);
+}
+
+int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* wave, void* ws, size_t ws_size,
+                 void* stream) {
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  int rc = check_opts(plan, opts, true);
+  if (rc) return rc;
+  if ((rc = check_depos(depos))) return rc;
+  if (!wave) return fail(WCT_E_INVALID, "wave is NULL");
+  const size_t need = ws_bytes(plan, WCT_OP_SIMULATE, opts->n_events, depos->n);
+  if (!ws || ws_size < need) return fail(WCT_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_size, need);
+  DeviceGuard dg(plan->device);
+  if (!dg.ok) return fail(WCT_E_DEVICE, "hipSetDevice(%d) failed", plan->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Carver head(ws);
+  void* grid = head.take(plan->esize * (size_t)opts->n_events * plan->grid_elems);
+  const size_t rest = align_up(head.off, 256);
+  Carver cr(static_cast<char*>(ws) + rest), cc(static_cast<char*>(ws) + rest);
+  if (plan->dtype == WCT_F32) {
+    if ((rc = run_raster<float>(plan, depos, opts, static_cast<float*>(grid), cr, st))) return rc;
+    return run_convolve<float>(plan, static_cast<const float*>(grid), opts->n_events, static_cast<float*>(wave), cc,
+                               st);
+  }
+  if ((rc = run_raster<double>(plan, depos, opts, static_cast<double*>(grid), cr, st))) return rc;
+  return run_convolve<double>(plan, static_cast<const double*>(grid), opts->n_events, static_cast<double*>(wave), cc,
+                              st);
+}
+
+int wct_simulate_backward(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, const void* grad_wave,
+                          void* g_q, void* g_t, void* g_p, void* g_sigma_t, void* g_sigma_p, void* ws, size_t ws_size,
+                          void* stream) {
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  int rc = check_opts(plan, opts, true);
+  if (rc) return rc;
+  if (opts->fluctuate) return fail(WCT_E_INVALID, "the backward pass requires fluctuate = 0");
+  if ((rc = check_depos(depos))) return rc;
+  if (!grad_wave) return fail(WCT_E_INVALID, "grad_wave is NULL");
+  if (depos->n > 0 && (!g_q || !g_t || !g_p || !g_sigma_t || !g_sigma_p))
+    return fail(WCT_E_INVALID, "gradient outputs must not be NULL");
+  const size_t need = ws_bytes(plan, WCT_OP_BACKWARD, opts->n_events, depos->n);
+  if (!ws || ws_size < need) return fail(WCT_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_size, need);
+  DeviceGuard dg(plan->device);
+  if (!dg.ok) return fail(WCT_E_DEVICE, "hipSetDevice(%d) failed", plan->device);
+  Carver cv(ws);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (plan->dtype == WCT_F32)
+    return run_backward<float>(plan, depos, opts, static_cast<const float*>(grad_wave), static_cast<float*>(g_q),
+                               static_cast<float*>(g_t), static_cast<float*>(g_p), static_cast<float*>(g_sigma_t),
+                               static_cast<float*>(g_sigma_p), cv, st);
+  return run_backward<double>(plan, depos, opts, static_cast<const double*>(grad_wave), static_cast<double*>(g_q),
+                              static_cast<double*>(g_t), static_cast<double*>(g_p), static_cast<double*>(g_sigma_t),
+                              static_cast<double*>(g_sigma_p), cv, st);
+}
+
+}  // extern "C"

@@ -1,0 +1,320 @@
+// FFT convolution of charge grids with the wire response (Eq. 2 of arXiv:2104.08265):
+// transform S, multiply by the pre-computed response spectrum, transform back.
+//
+// Pass A  (k_rows_r2c):  every impact row of S, zero-padded from N_t to L_t = 2M ticks,
+//                         is transformed real-to-complex through one length-M complex
+//                         transform (even/odd samples packed as re/im) and a post-twiddle;
+//                         the F = M+1 tick frequencies go to S-hat in the column-chunk
+//                         layout [chunk][phase i][wire c][C].
+// Pass B  (k_colpass):    per chunk of C tick frequencies: for every phase i, the N_w
+//                         values of rows I*c+i are transformed along wires (length L_w,
+//                         zero padded), multiplied by the phase's spectrum R~_i and summed
+//                         over i in registers (the impact-to-wire reduction); the sum is
+//                         transformed back along wires and the N_w wires are kept.
+// Pass C  (k_rows_c2r):  every wire's F frequencies are transformed complex-to-real back
+//                         to L_t ticks and cropped to N_t.
+// The 1/(L_w L_t) normalisation is folded into R~ at plan time.
+//
+// The backward (adjoint) variants reuse the passes: rows of dL/dM through pass A, a
+// column pass that transforms once and applies conj(R~_i) per phase, and pass C over
+// the I*N_w impact rows of the column-chunk layout.
+#include "fft.hpp"
+#include "kernels.hpp"
+
+namespace wct {
+
+// Blocks are dispatched to the 8 XCDs round-robin; map them so that consecutive
+// logical indices share an XCD (and its L2).
+__device__ __forceinline__ int xcd_remap(int b, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7;
+  const int xcd = b & 7, pos = b >> 3;
+  return xcd < r ? xcd * (q + 1) + pos : r * (q + 1) + (xcd - r) * q + pos;
+}
+
+// ---------------------------------------------------------------------------
+// Pass A: real rows -> half spectra, column-chunk layout
+// ---------------------------------------------------------------------------
+template <typename T, int C, int E>
+__global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_rows_r2c(const T* __restrict__ src, int64_t src_ev_stride,
+                                                   cx<T>* __restrict__ dst, int64_t dst_ev_stride, int nt,
+                                                   int nphase, int nper, int nchunk, FftPlan plan,
+                                                   const cx<T>* __restrict__ tw,
+                                                   const cx<T>* __restrict__ post) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* z = reinterpret_cast<cx<T>*>(smem_raw);
+  T* zr = reinterpret_cast<T*>(smem_raw);
+  const int M = plan.n;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int i = L / nper, c = L - (L / nper) * nper;
+  const int64_t row = (int64_t)c * nphase + i;
+  const T* s = src + blockIdx.y * src_ev_stride + row * nt;
+  for (int n = threadIdx.x; n < 2 * M; n += blockDim.x) zr[n] = n < nt ? s[n] : T(0);
+  __syncthreads();
+  fft_lds<T, false, 1, E>(z, plan, tw);
+  cx<T>* out = dst + blockIdx.y * dst_ev_stride;
+  const int fpad = nchunk * C;
+  for (int k = threadIdx.x; k < fpad; k += blockDim.x) {
+    cx<T> X = mk(T(0), T(0));
+    if (k <= M) {
+      const cx<T> A = z[k == M ? 0 : k];
+      const cx<T> B = conj(z[k == 0 ? 0 : M - k]);
+      const cx<T> Ev = scale(A + B, T(0.5));
+      const cx<T> D = scale(A - B, T(0.5));
+      const cx<T> O = mk(D.y, -D.x);  // (A - B) / (2i)
+      X = Ev + cmul(post[k], O);
+    }
+    const int ch = k / C, cc = k - (k / C) * C;
+    out[(((int64_t)ch * nphase + i) * nper + c) * C + cc] = X;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass B (forward): transforms along wires per phase, spectrum product, phase sum
+// ---------------------------------------------------------------------------
+template <typename T, int C, int E>
+__global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_colpass(const cx<T>* __restrict__ shat, int64_t shat_ev_stride,
+                                                  const cx<T>* __restrict__ rtil, cx<T>* __restrict__ mhat,
+                                                  int64_t mhat_ev_stride, int nw, int nphase, int nchunk,
+                                                  FftPlan plan, const cx<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int lw = plan.n;
+  const int ne = lw * C;
+  const int nin = nw * C;
+  const int ch = blockIdx.x;
+  cx<T> acc[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) acc[q] = mk(T(0), T(0));
+  const cx<T>* src = shat + blockIdx.y * shat_ev_stride + (int64_t)ch * nphase * nin;
+  const cx<T>* rt = rtil + (int64_t)ch * nphase * ne;
+  for (int i = 0; i < nphase; ++i) {
+    const cx<T>* s = src + (int64_t)i * nin;
+    for (int idx = threadIdx.x; idx < ne; idx += blockDim.x) buf[idx] = idx < nin ? s[idx] : mk(T(0), T(0));
+    __syncthreads();
+    fft_lds<T, false, C, E>(buf, plan, tw);
+    const cx<T>* r = rt + (int64_t)i * ne;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int idx = threadIdx.x + q * blockDim.x;
+      if (idx < ne) acc[q] = acc[q] + cmul(buf[idx], r[idx]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    if (idx < ne) buf[idx] = acc[q];
+  }
+  __syncthreads();
+  fft_lds<T, true, C, E>(buf, plan, tw);
+  cx<T>* dst = mhat + blockIdx.y * mhat_ev_stride;
+  const int fpad = nchunk * C;
+  for (int idx = threadIdx.x; idx < nin; idx += blockDim.x) {
+    const int w = idx / C, cc = idx - (idx / C) * C;
+    dst[(int64_t)w * fpad + ch * C + cc] = buf[idx];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass B (adjoint): one transform of dL/dM-hat along wires, conj(R~_i) per phase,
+// inverse transform per phase into the column-chunk layout
+// ---------------------------------------------------------------------------
+template <typename T, int C, int E>
+__global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_colpass_adj(const cx<T>* __restrict__ ghat, int64_t ghat_ev_stride,
+                                                      const cx<T>* __restrict__ rtil, cx<T>* __restrict__ hhat,
+                                                      int64_t hhat_ev_stride, int nw, int nphase, int nchunk,
+                                                      FftPlan plan, const cx<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int lw = plan.n;
+  const int ne = lw * C;
+  const int nin = nw * C;
+  const int ch = blockIdx.x;
+  const cx<T>* s = ghat + blockIdx.y * ghat_ev_stride + (int64_t)ch * nin;
+  for (int idx = threadIdx.x; idx < ne; idx += blockDim.x) buf[idx] = idx < nin ? s[idx] : mk(T(0), T(0));
+  __syncthreads();
+  fft_lds<T, false, C, E>(buf, plan, tw);
+  cx<T> g[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    g[q] = idx < ne ? buf[idx] : mk(T(0), T(0));
+  }
+  __syncthreads();
+  const cx<T>* rt = rtil + (int64_t)ch * nphase * ne;
+  cx<T>* dst = hhat + blockIdx.y * hhat_ev_stride + (int64_t)ch * nphase * nin;
+  for (int i = 0; i < nphase; ++i) {
+    const cx<T>* r = rt + (int64_t)i * ne;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int idx = threadIdx.x + q * blockDim.x;
+      if (idx < ne) buf[idx] = cmulc(g[q], r[idx]);
+    }
+    __syncthreads();
+    fft_lds<T, true, C, E>(buf, plan, tw);
+    cx<T>* d = dst + (int64_t)i * nin;
+    for (int idx = threadIdx.x; idx < nin; idx += blockDim.x) d[idx] = buf[idx];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass C: half spectra -> real rows.  Input either wire-major rows [w][fpad]
+// (TILED = false) or the column-chunk layout [chunk][phase][c][C] (TILED = true).
+// ---------------------------------------------------------------------------
+template <typename T, int C, bool TILED, int E>
+__global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_rows_c2r(const cx<T>* __restrict__ src, int64_t src_ev_stride,
+                                                   T* __restrict__ dst, int64_t dst_ev_stride, int nt,
+                                                   int nphase, int nper, int nchunk, FftPlan plan,
+                                                   const cx<T>* __restrict__ tw,
+                                                   const cx<T>* __restrict__ post) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* z = reinterpret_cast<cx<T>*>(smem_raw);
+  T* zr = reinterpret_cast<T*>(smem_raw);
+  const int M = plan.n;
+  const int L = TILED ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int i = L / nper, c = L - (L / nper) * nper;
+  const int64_t row = TILED ? (int64_t)c * nphase + i : (int64_t)L;
+  const cx<T>* in = src + blockIdx.y * src_ev_stride;
+  const int fpad = nchunk * C;
+  auto X = [&](int k) -> cx<T> {
+    if (TILED) return in[(((int64_t)(k / C) * nphase + i) * nper + c) * C + (k % C)];
+    return in[(int64_t)L * fpad + k];
+  };
+  for (int k = threadIdx.x; k < M; k += blockDim.x) {
+    const cx<T> A = X(k);
+    const cx<T> B = conj(X(M - k));
+    const cx<T> Ev = A + B;
+    const cx<T> O = cmulc(A - B, post[k]);  // (A - B) * W_L^-k
+    z[k] = mk(Ev.x - O.y, Ev.y + O.x);      // Ev + i*O
+  }
+  __syncthreads();
+  fft_lds<T, true, 1, E>(z, plan, tw);
+  T* out = dst + blockIdx.y * dst_ev_stride + row * nt;
+  for (int n = threadIdx.x; n < nt; n += blockDim.x) out[n] = zr[n];
+}
+
+// ---------------------------------------------------------------------------
+// host launchers: pick the smallest register budget E whose block fits
+// ---------------------------------------------------------------------------
+template <typename T>
+static int pick_e(int elems) {
+  const int cands[4] = {8, 16, 24, 32};
+  const int ncand = sizeof(T) == 4 ? 4 : 2;
+  for (int k = 0; k < ncand; ++k) {
+    const int e = cands[k];
+    const int bound = e <= 8 ? LaunchBound<T, 8>::value : LaunchBound<T, 16>::value;
+    if ((elems + e - 1) / e <= bound) return e;
+  }
+  return 0;
+}
+static int threads_for(int elems, int e) {
+  int t = (elems + e - 1) / e;
+  t = ((t + 63) / 64) * 64;
+  return t < 64 ? 64 : t;
+}
+
+template <typename T>
+bool conv_fits(int elems) { return pick_e<T>(elems) > 0; }
+template bool conv_fits<float>(int);
+template bool conv_fits<double>(int);
+
+#define WCT_DISPATCH_E(T, elems, CALL)          \
+  switch (pick_e<T>(elems)) {                  \
+    case 8: { constexpr int E_ = 8; CALL; break; }   \
+    case 16: { constexpr int E_ = 16; CALL; break; } \
+    case 24: if constexpr (sizeof(T) == 4) { constexpr int E_ = 24; CALL; } break; \
+    case 32: if constexpr (sizeof(T) == 4) { constexpr int E_ = 32; CALL; } break; \
+    default: return hipErrorInvalidValue;      \
+  }
+
+template <typename T>
+hipError_t launch_rows_r2c(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt, int nphase,
+                           int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
+                           const cx<T>* post, hipStream_t st) {
+  const size_t lds = sizeof(cx<T>) * plan.n;
+  const dim3 grid(nphase * nper, n_events);
+  WCT_DISPATCH_E(T, plan.n,
+                 hipLaunchKernelGGL((k_rows_r2c<T, kChunk, E_>), grid, dim3(threads_for(plan.n, E_)), lds, st, src,
+                                    src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, plan, tw, post))
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_colpass(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtil, cx<T>* mhat,
+                          int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, const FftPlan& plan,
+                          const cx<T>* tw, hipStream_t st) {
+  const int elems = plan.n * kChunk;
+  const size_t lds = sizeof(cx<T>) * elems;
+  const dim3 grid(nchunk, n_events);
+  WCT_DISPATCH_E(T, elems,
+                 hipLaunchKernelGGL((k_colpass<T, kChunk, E_>), grid, dim3(threads_for(elems, E_)), lds, st, shat,
+                                    shat_ev_stride, rtil, mhat, mhat_ev_stride, nw, nphase, nchunk, plan, tw))
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_colpass_adj(const cx<T>* ghat, int64_t ghat_ev_stride, const cx<T>* rtil, cx<T>* hhat,
+                              int64_t hhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
+                              const FftPlan& plan, const cx<T>* tw, hipStream_t st) {
+  const int elems = plan.n * kChunk;
+  const size_t lds = sizeof(cx<T>) * elems;
+  const dim3 grid(nchunk, n_events);
+  WCT_DISPATCH_E(T, elems,
+                 hipLaunchKernelGGL((k_colpass_adj<T, kChunk, E_>), grid, dim3(threads_for(elems, E_)), lds, st,
+                                    ghat, ghat_ev_stride, rtil, hhat, hhat_ev_stride, nw, nphase, nchunk, plan, tw))
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rows_c2r(const cx<T>* src, int64_t src_ev_stride, T* dst, int64_t dst_ev_stride, int nt,
+                           bool tiled, int nphase, int nper, int nchunk, int n_events, const FftPlan& plan,
+                           const cx<T>* tw, const cx<T>* post, hipStream_t st) {
+  const size_t lds = sizeof(cx<T>) * plan.n;
+  const dim3 grid(nphase * nper, n_events);
+  if (tiled) {
+    WCT_DISPATCH_E(T, plan.n,
+                   hipLaunchKernelGGL((k_rows_c2r<T, kChunk, true, E_>), grid, dim3(threads_for(plan.n, E_)), lds, st,
+                                      src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, plan, tw, post))
+  } else {
+    WCT_DISPATCH_E(T, plan.n,
+                   hipLaunchKernelGGL((k_rows_c2r<T, kChunk, false, E_>), grid, dim3(threads_for(plan.n, E_)), lds,
+                                      st, src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, plan, tw,
+                                      post))
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int E>
+static void raise_lds_limit_e() {
+  const int lim = 160 * 1024;
+  hipFuncSetAttribute((const void*)k_rows_r2c<T, kChunk, E>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_colpass<T, kChunk, E>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_colpass_adj<T, kChunk, E>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_rows_c2r<T, kChunk, true, E>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_rows_c2r<T, kChunk, false, E>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+}
+
+void conv_init_kernels() {
+  raise_lds_limit_e<float, 8>();
+  raise_lds_limit_e<float, 16>();
+  raise_lds_limit_e<float, 24>();
+  raise_lds_limit_e<float, 32>();
+  raise_lds_limit_e<double, 8>();
+  raise_lds_limit_e<double, 16>();
+}
+
+#define WCT_INST(T)                                                                                            \
+  template hipError_t launch_rows_r2c<T>(const T*, int64_t, cx<T>*, int64_t, int, int, int, int, int,          \
+                                         const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);            \
+  template hipError_t launch_colpass<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int, int,   \
+                                        int, const FftPlan&, const cx<T>*, hipStream_t);                       \
+  template hipError_t launch_colpass_adj<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int,    \
+                                            int, int, const FftPlan&, const cx<T>*, hipStream_t);              \
+  template hipError_t launch_rows_c2r<T>(const cx<T>*, int64_t, T*, int64_t, int, bool, int, int, int, int,    \
+                                         const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);
+WCT_INST(float)
+WCT_INST(double)
+#undef WCT_INST
+
+}  // namespace wct

@@ -1,0 +1,183 @@
+// Stockham auto-sort FFT staged in LDS, radices 2, 3, 4, 5 and 8, for gfx950.
+//
+// A workgroup transforms C interleaved sequences of length n held in LDS as
+// buf[m*C + c] (m in [0, n), c in [0, C)).  Each Stockham pass of radix R with stride Ns
+// (the product of the radices already applied) reads, for butterfly j,
+//     v[r] = buf[(j + r*n/R)*C + c],  r = 0..R-1,
+// multiplies v[r] by W_{Ns*R}^{r*(j mod Ns)}, applies the length-R DFT and writes
+//     buf[((j - j mod Ns)*R + j mod Ns + r*Ns)*C + c] = v[r].
+// After the last pass the output is in natural order.  Every thread keeps its
+// butterflies in registers between the read and the write half of a pass, so one LDS
+// buffer suffices (two barriers per pass).  E bounds the values one thread holds.
+// Forward transforms use W = exp(-2 pi i/R); the inverse (INV = true) uses the
+// conjugate and is unnormalised.
+#pragma once
+
+#include "common.hpp"
+
+namespace wct {
+
+template <typename T>
+struct FftConst;
+template <>
+struct FftConst<float> {
+  static constexpr float s3 = 0.86602540378443864676f;   // sin(2 pi / 3)
+  static constexpr float c51 = 0.30901699437494742410f;  // cos(2 pi / 5)
+  static constexpr float c52 = -0.80901699437494742410f; // cos(4 pi / 5)
+  static constexpr float s51 = 0.95105651629515357212f;  // sin(2 pi / 5)
+  static constexpr float s52 = 0.58778525229247312917f;  // sin(4 pi / 5)
+  static constexpr float r2 = 0.70710678118654752440f;   // 1 / sqrt(2)
+};
+template <>
+struct FftConst<double> {
+  static constexpr double s3 = 0.86602540378443864676;
+  static constexpr double c51 = 0.30901699437494742410;
+  static constexpr double c52 = -0.80901699437494742410;
+  static constexpr double s51 = 0.95105651629515357212;
+  static constexpr double s52 = 0.58778525229247312917;
+  static constexpr double r2 = 0.70710678118654752440;
+};
+
+// -i*a for the forward sign, +i*a for the inverse.
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> rot(cx<T> a) {
+  return INV ? mk(-a.y, a.x) : mk(a.y, -a.x);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(cx<T>* v) {
+  cx<T> a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft3(cx<T>* v) {
+  cx<T> t = v[1] + v[2];
+  cx<T> m = v[0] - scale(t, T(0.5));
+  cx<T> d = scale(rot<T, INV>(v[1] - v[2]), FftConst<T>::s3);
+  v[0] = v[0] + t;
+  v[1] = m + d;
+  v[2] = m - d;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cx<T>* v) {
+  cx<T> t0 = v[0] + v[2], t1 = v[0] - v[2];
+  cx<T> t2 = v[1] + v[3], t3 = rot<T, INV>(v[1] - v[3]);
+  v[0] = t0 + t2;
+  v[2] = t0 - t2;
+  v[1] = t1 + t3;
+  v[3] = t1 - t3;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft5(cx<T>* v) {
+  using K = FftConst<T>;
+  cx<T> t1 = v[1] + v[4], t2 = v[2] + v[3];
+  cx<T> t3 = v[1] - v[4], t4 = v[2] - v[3];
+  cx<T> p1 = v[0] + scale(t1, K::c51) + scale(t2, K::c52);
+  cx<T> p2 = v[0] + scale(t1, K::c52) + scale(t2, K::c51);
+  cx<T> q1 = rot<T, INV>(scale(t3, K::s51) + scale(t4, K::s52));
+  cx<T> q2 = rot<T, INV>(scale(t3, K::s52) - scale(t4, K::s51));
+  v[0] = v[0] + t1 + t2;
+  v[1] = p1 + q1;
+  v[4] = p1 - q1;
+  v[2] = p2 + q2;
+  v[3] = p2 - q2;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(cx<T>* v) {
+  using K = FftConst<T>;
+  cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+  cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<T, INV>(e);
+  dft4<T, INV>(o);
+  // twiddles W8^k (forward) or W8^-k (inverse) on o[1..3]
+  cx<T> o1, o3;
+  if (!INV) {
+    o1 = mk((o[1].x + o[1].y) * K::r2, (o[1].y - o[1].x) * K::r2);
+    o3 = mk((o[3].y - o[3].x) * K::r2, -(o[3].x + o[3].y) * K::r2);
+  } else {
+    o1 = mk((o[1].x - o[1].y) * K::r2, (o[1].x + o[1].y) * K::r2);
+    o3 = mk(-(o[3].x + o[3].y) * K::r2, (o[3].x - o[3].y) * K::r2);
+  }
+  cx<T> o2 = rot<T, INV>(o[2]);
+  v[0] = e[0] + o[0];
+  v[4] = e[0] - o[0];
+  v[1] = e[1] + o1;
+  v[5] = e[1] - o1;
+  v[2] = e[2] + o2;
+  v[6] = e[2] - o2;
+  v[3] = e[3] + o3;
+  v[7] = e[3] - o3;
+}
+
+template <int R, typename T, bool INV>
+__device__ __forceinline__ void dftR(cx<T>* v) {
+  if constexpr (R == 2) dft2<T, INV>(v);
+  else if constexpr (R == 3) dft3<T, INV>(v);
+  else if constexpr (R == 4) dft4<T, INV>(v);
+  else if constexpr (R == 5) dft5<T, INV>(v);
+  else dft8<T, INV>(v);
+}
+
+// One Stockham pass over C interleaved sequences of length n in LDS.
+template <int R, typename T, bool INV, int C, int E>
+__device__ __forceinline__ void stockham_pass(cx<T>* buf, int n, int Ns, const cx<T>* __restrict__ tw) {
+  constexpr int MAXB = (E + R - 1) / R;
+  const int nr = n / R;
+  const int nbf = nr * C;
+  cx<T> v[MAXB][R];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    if (idx < nbf) {
+      const int c = idx % C, j = idx / C;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = buf[(j + r * nr) * C + c];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    if (idx < nbf) {
+      const int c = idx % C, j = idx / C;
+      const int k = j % Ns;
+      if (Ns > 1) {
+        const cx<T>* w = tw + k * (R - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = INV ? cmulc(v[q][r], w[r - 1]) : cmul(v[q][r], w[r - 1]);
+      }
+      dftR<R, T, INV>(v[q]);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[(base + r * Ns) * C + c] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full transform; every thread of the block must call it, and the block must have at
+// least n*C/E threads (E = elements a thread holds).  `tw` is the length's
+// twiddle table (per pass p, W_{Ns*R}^{r*k} at tw_off[p] + k*(R-1) + r-1).
+template <typename T, bool INV, int C, int E>
+__device__ void fft_lds(cx<T>* buf, const FftPlan& plan, const cx<T>* __restrict__ tw) {
+  int Ns = 1;
+  for (int p = 0; p < plan.npass; ++p) {
+    const int R = plan.radix[p];
+    const cx<T>* twp = tw + plan.tw_off[p];
+    switch (R) {
+      case 2: stockham_pass<2, T, INV, C, E>(buf, plan.n, Ns, twp); break;
+      case 3: stockham_pass<3, T, INV, C, E>(buf, plan.n, Ns, twp); break;
+      case 4: stockham_pass<4, T, INV, C, E>(buf, plan.n, Ns, twp); break;
+      case 5: stockham_pass<5, T, INV, C, E>(buf, plan.n, Ns, twp); break;
+      default: stockham_pass<8, T, INV, C, E>(buf, plan.n, Ns, twp); break;
+    }
+    Ns *= R;
+  }
+}
+
+}  // namespace wct

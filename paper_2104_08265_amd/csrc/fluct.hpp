@@ -1,0 +1,169 @@
+// Binomial fluctuation of rasterised charge (arXiv:2104.08265 Sec. 4.3.1, Table 2: the
+// fluctuation is binomial; generating the random numbers dominated the CPU time, so
+// the generator is counter-based and inline here, with no pool and no host traffic).
+//
+// Draw stream, version WCT_FLUCT_SPEC_VERSION = 1:
+//  * generator: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = (seed low,
+//    seed high), counter = (b*N_t + k, depo_id, event, plane << 24) for cell (b, k);
+//  * variate: u = ((w0 >> 6) * 2^27 + (w1 >> 5)) * 2^-53, exact, in [0, 1);
+//  * count: Binomial(N = floor(Q + 1/2), p = A_b * B_k) by inversion from 0 when
+//    N*p' < 10 (p' = min(p, 1-p)), otherwise by a chop-down search alternating below
+//    and above the mode; p > 1/2 is sampled as N minus a draw with 1-p.
+// Every operation is an IEEE-754 double +, -, *, / (this file must be compiled with
+// floating-point contraction off), frexp, ldexp, rint, floor, in a fixed order, so the
+// counts do not depend on the device, the schedule or the compiler's choices.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace wct {
+
+// Small tables, filled on the host with correctly rounded divisions.
+struct DetTables {
+  double inv[256];      // inv[j] = 1/j (inv[0] = 0)
+  double inv_fact[17];  // 1/j!
+  double fact[19];      // j! (exact)
+};
+
+constexpr double kTwoOverSqrtPi = 1.1283791670955126;
+constexpr double kSqrt2 = 1.4142135623730951;
+constexpr double kSqrtHalf = 0.7071067811865476;
+constexpr double kLn2 = 0.6931471805599453;
+constexpr double kLog2e = 1.4426950408889634;
+constexpr double kHalfLn2Pi = 0.91893853320467274;
+constexpr int kErfTerms = 60;
+constexpr double kMuSwitch = 10.0;
+constexpr int64_t kInversionCap = 128;
+
+struct Philox4 {
+  uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                 uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return Philox4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ double uniform53(uint32_t w0, uint32_t w1) {
+  return ((double)(w0 >> 6) * 134217728.0 + (double)(w1 >> 5)) * 0x1p-53;
+}
+
+__device__ __forceinline__ double det_erf(double x, const double* __restrict__ inv) {
+  const double mx2 = -(x * x);
+  double term = x, acc = x;
+  for (int j = 1; j < kErfTerms; ++j) {
+    term = (term * mx2) * inv[j];
+    acc = acc + term * inv[2 * j + 1];
+  }
+  return kTwoOverSqrtPi * acc;
+}
+
+__device__ __forceinline__ double det_log(double x, const double* __restrict__ inv) {
+  int e;
+  double m = frexp(x, &e);
+  if (m < kSqrtHalf) {
+    m = m * 2.0;
+    e = e - 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double s2 = s * s;
+  double poly = inv[23];
+  for (int j = 10; j >= 0; --j) poly = poly * s2 + inv[2 * j + 1];
+  return (s * poly) * 2.0 + (double)e * kLn2;
+}
+
+__device__ __forceinline__ double det_exp(double x, const DetTables& tb) {
+  const double n = rint(x * kLog2e);
+  const double r = x - n * kLn2;
+  double poly = tb.inv_fact[16];
+  for (int j = 15; j >= 0; --j) poly = poly * r + tb.inv_fact[j];
+  return ldexp(poly, (int)n);
+}
+
+__device__ __forceinline__ double det_lfact(int64_t n, const DetTables& tb) {
+  if (n <= 18) return det_log(tb.fact[n], tb.inv);
+  const double x = (double)n;
+  const double r = 1.0 / x;
+  const double r2 = r * r;
+  const double series = r * ((1.0 / 12.0) - r2 * ((1.0 / 360.0) - r2 * ((1.0 / 1260.0) - r2 * (1.0 / 1680.0))));
+  return (x + 0.5) * det_log(x, tb.inv) - x + kHalfLn2Pi + series;
+}
+
+__device__ __forceinline__ int64_t binom_inversion(int64_t N, double pp, double q, double u, const DetTables& tb) {
+  double f = 1.0;
+  for (int b = 63 - __clzll((unsigned long long)N); b >= 0; --b) {
+    f = f * f;
+    if ((N >> b) & 1) f = f * q;
+  }
+  const double r = pp / q;
+  double F = f;
+  int64_t k = 0;
+  const int64_t cap = N < kInversionCap ? N : kInversionCap;
+  while (u >= F && k < cap) {
+    f = (f * (r * (double)(N - k))) * tb.inv[k + 1];
+    k += 1;
+    F = F + f;
+  }
+  return k;
+}
+
+__device__ __forceinline__ int64_t binom_chopdown(int64_t N, double pp, double q, double u, const DetTables& tb) {
+  const double Nf = (double)N;
+  int64_t m = (int64_t)floor((Nf + 1.0) * pp);
+  if (m > N) m = N;
+  const double x = det_lfact(N, tb) - det_lfact(m, tb) - det_lfact(N - m, tb) + (double)m * det_log(pp, tb.inv) +
+                   (double)(N - m) * det_log(q, tb.inv);
+  const double pm = det_exp(x, tb);
+  double v = u - pm;
+  if (v < 0.0) return m;
+  int64_t lo = m, hi = m;
+  double plo = pm, phi = pm;
+  for (;;) {
+    bool moved = false;
+    if (lo > 0 && plo > 0.0) {
+      plo = plo * ((double)lo * q) / ((double)(N - lo + 1) * pp);
+      lo -= 1;
+      v = v - plo;
+      moved = true;
+      if (v < 0.0) return lo;
+    }
+    if (hi < N && phi > 0.0) {
+      phi = phi * ((double)(N - hi) * pp) / (((double)hi + 1.0) * q);
+      hi += 1;
+      v = v - phi;
+      moved = true;
+      if (v < 0.0) return hi;
+    }
+    if (!moved) return m;
+  }
+}
+
+__device__ __forceinline__ int64_t binomial(int64_t N, double p, double u, const DetTables& tb) {
+  if (N <= 0) return 0;
+  if (p >= 1.0) return N;
+  if (!(p > 0.0)) return 0;
+  const bool flip = p > 0.5;
+  const double pp = flip ? 1.0 - p : p;
+  const double q = 1.0 - pp;
+  const double mu = (double)N * pp;
+  const int64_t k = mu < kMuSwitch ? binom_inversion(N, pp, q, u, tb) : binom_chopdown(N, pp, q, u, tb);
+  return flip ? N - k : k;
+}
+
+}  // namespace wct

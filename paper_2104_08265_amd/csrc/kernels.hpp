@@ -1,0 +1,104 @@
+// Host-side launchers of the HIP kernels (one translation unit per kernel family).
+#pragma once
+
+#include "common.hpp"
+#include "fluct.hpp"
+
+namespace wct {
+
+constexpr int kMaxPlanes = 8;
+
+// Depo-plane rows as the kernels read them.
+template <typename T>
+struct DepoView {
+  int64_t n;
+  const T *q, *t, *p, *st, *sp;
+  const int32_t *plane, *event, *depo_id;
+};
+
+// Geometry of all planes of a plan, passed to the raster and gradient kernels by value.
+struct RasterGeom {
+  int n_planes;
+  int n_events;
+  int ntiles_ev;           // raster tiles per event
+  int64_t grid_ev_stride;  // grid elements per event
+  PlaneGeom pl[kMaxPlanes];
+};
+
+// Control words at the head of the raster workspace.
+enum RasterCtrl {
+  kCtrlHead = 0,    // work-queue head of the tile kernel
+  kCtrlNItems = 1,  // number of tile work items
+  kCtrlNBig = 2,    // rows whose window covers more than 4 tiles
+  kCtrlTotal = 3,   // total (row, tile) pairs
+  kCtrlWords = 64
+};
+constexpr int kRowsPerItem = 256;  // rows one tile work item processes at most
+constexpr int kScanPerBlock = 4096;
+
+// Raster tile shapes (rows x ticks), 32 KB of LDS each.
+template <typename T>
+struct TileShape;
+template <>
+struct TileShape<float> {
+  static constexpr int TH = 64, TW = 128;
+};
+template <>
+struct TileShape<double> {
+  static constexpr int TH = 32, TW = 128;
+};
+
+struct RasterWs {
+  int32_t* ctrl;      // kCtrlWords
+  int32_t* counts;    // [ntiles]
+  int32_t* cursor;    // [ntiles]
+  int32_t* offs;      // [ntiles + 1]
+  int32_t* item_off;  // [ntiles + 1]
+  int32_t* items;     // [max_items]
+  int32_t* list;      // [4 n]
+  int32_t* big;       // [n]
+  int32_t* blocks;    // [2 * nscan_blocks]
+  int64_t ntiles;
+  int64_t max_items;
+};
+
+// raster.hip
+template <typename T>
+hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigma, int fluctuate, uint64_t seed,
+                         T* grid, const RasterWs& ws, const DetTables* tables, int n_cu, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+
+// conv.hip
+template <typename T>
+hipError_t launch_rows_r2c(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt, int nphase,
+                           int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
+                           const cx<T>* post, hipStream_t st);
+template <typename T>
+hipError_t launch_colpass(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtil, cx<T>* mhat,
+                          int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, const FftPlan& plan,
+                          const cx<T>* tw, hipStream_t st);
+template <typename T>
+hipError_t launch_colpass_adj(const cx<T>* ghat, int64_t ghat_ev_stride, const cx<T>* rtil, cx<T>* hhat,
+                              int64_t hhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
+                              const FftPlan& plan, const cx<T>* tw, hipStream_t st);
+template <typename T>
+hipError_t launch_rows_c2r(const cx<T>* src, int64_t src_ev_stride, T* dst, int64_t dst_ev_stride, int nt,
+                           bool tiled, int nphase, int nper, int nchunk, int n_events, const FftPlan& plan,
+                           const cx<T>* tw, const cx<T>* post, hipStream_t st);
+template <typename T>
+bool conv_fits(int elems);  // a transform of `elems` complex values fits one block
+void conv_init_kernels();
+
+// plan.hip
+hipError_t launch_resp_tick(const double* R, int nk, int I, int TR, int lt, int F, const cx<double>* tw_lt,
+                            cx<double>* out, hipStream_t st);
+template <typename T>
+hipError_t launch_resp_wire(const cx<double>* rt, int K, int I, int F, int lw, int lt, int nchunk,
+                            const cx<double>* tw_lw, cx<T>* rtil, hipStream_t st);
+
+// grad.hip
+template <typename T>
+hipError_t launch_grad_gather(const DepoView<T>& d, const RasterGeom& g, double nsigma, const T* H, T* gq, T* gt,
+                              T* gp, T* gst, T* gsp, hipStream_t st);
+
+}  // namespace wct

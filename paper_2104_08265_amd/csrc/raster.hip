@@ -1,0 +1,480 @@
+// Rasterisation and scatter adding of depositions (arXiv:2104.08265 Sec. 2.1.1):
+// every depo-plane row becomes a patch of clipped Gaussian bin integrals Q*A_b*B_k
+// (or binomial electron counts, Sec. 4.3.1) that is added into its plane's grid.
+//
+// Scatter adding goes through LDS-privatised tiles of TH x TW cells:
+//  1. k_count    - each row counts the tiles its window overlaps (<= 4; wider rows go
+//                  to a separate list handled with global atomics, k_big);
+//  2. scan       - exclusive prefix sums give each tile its slice of a row list and
+//                  a number of work items (ceil(rows / kRowsPerItem), at least 1);
+//  3. k_fill     - rows are written into their tiles' slices;
+//  4. k_tile     - a persistent kernel pops work items from an atomic queue; a work
+//                  item accumulates its rows' in-tile sub-patches with LDS atomics and
+//                  then writes the tile: plain stores when the tile has one item (the
+//                  tile is owned, so empty tiles write zeros and the grid needs no
+//                  clearing), global atomic adds when a crowded tile was split across
+//                  items (those tiles are cleared first by k_zero_split).
+// Window bounds are formed in FP64 exactly as the oracle forms them, so both sides
+// agree on which cells a row touches; fluctuated counts use the deterministic
+// Philox + binomial chain of fluct.hpp (this file is compiled with contraction off).
+#include "kernels.hpp"
+
+namespace wct {
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct RowWin {
+  double q, u, su, t, st;
+  double ulo, uhi, tlo, thi;
+  int b0, b1, k0, k1;  // cell ranges clipped to the grid, [b0, b1) x [k0, k1)
+  int plane, event;
+  bool ok;
+};
+
+__device__ __forceinline__ int clamp_idx(double v) {
+  v = fmin(fmax(v, -1.0e9), 1.0e9);
+  return (int)v;
+}
+
+template <typename T>
+__device__ __forceinline__ RowWin row_window(const DepoView<T>& d, int64_t j, const RasterGeom& g, double nsigma) {
+  RowWin w;
+  w.plane = d.plane ? d.plane[j] : 0;
+  w.event = d.event ? d.event[j] : 0;
+  w.ok = w.plane >= 0 && w.plane < g.n_planes && w.event >= 0 && w.event < g.n_events;
+  if (!w.ok) return w;
+  const PlaneGeom& pl = g.pl[w.plane];
+  w.q = (double)d.q[j];
+  const double p = (double)d.p[j];
+  const double sp = (double)d.sp[j];
+  w.t = (double)d.t[j];
+  w.st = (double)d.st[j];
+  w.ok = (w.q >= 0.0) && (w.st > 0.0) && (sp > 0.0) && isfinite(w.q) && isfinite(w.t) && isfinite(p) &&
+         isfinite(w.st) && isfinite(sp);
+  if (!w.ok) return w;
+  w.u = (double)pl.I * p;
+  w.su = (double)pl.I * sp;
+  const double hu = nsigma * w.su;
+  w.ulo = w.u - hu;
+  w.uhi = w.u + hu;
+  const double ht = nsigma * w.st;
+  w.tlo = w.t - ht;
+  w.thi = w.t + ht;
+  w.b0 = max(clamp_idx(floor(w.ulo)), 0);
+  w.b1 = min(clamp_idx(ceil(w.uhi)), pl.nb);
+  w.k0 = max(clamp_idx(floor(w.tlo)), 0);
+  w.k1 = min(clamp_idx(ceil(w.thi)), pl.nt);
+  w.ok = w.b0 < w.b1 && w.k0 < w.k1;
+  return w;
+}
+
+// Clipped Gaussian integral over cell k: 0.5 (erf(x_hi) - erf(x_lo)), x = (edge - mu) / (sigma sqrt2).
+__device__ __forceinline__ double cell_weight(int k, double mu, double sigma, double lo, double hi) {
+  const double elo = fmax((double)k, lo);
+  const double ehi = fmin((double)k + 1.0, hi);
+  const double s2 = sigma * kSqrt2;
+  return 0.5 * (erf((ehi - mu) / s2) - erf((elo - mu) / s2));
+}
+__device__ __forceinline__ double cell_prob(int k, double mu, double sigma, double lo, double hi,
+                                            const double* __restrict__ inv) {
+  const double elo = fmax((double)k, lo);
+  const double ehi = fmin((double)k + 1.0, hi);
+  const double s2 = sigma * kSqrt2;
+  return 0.5 * (det_erf((ehi - mu) / s2, inv) - det_erf((elo - mu) / s2, inv));
+}
+
+__device__ __forceinline__ int find_plane(const RasterGeom& g, int tin) {
+  int p = 0;
+  for (int k = 1; k < g.n_planes; ++k)
+    if (tin >= g.pl[k].tile_off) p = k;
+  return p;
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// 1. tiles per row ---------------------------------------------------------
+template <typename T, int TH, int TW>
+__global__ void k_count(DepoView<T> d, RasterGeom g, double nsigma, int32_t* __restrict__ counts,
+                        int32_t* __restrict__ big, int32_t* __restrict__ ctrl) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= d.n) return;
+  const RowWin w = row_window(d, j, g, nsigma);
+  if (!w.ok) return;
+  const PlaneGeom& pl = g.pl[w.plane];
+  const int tr0 = w.b0 / TH, tr1 = (w.b1 - 1) / TH, tc0 = w.k0 / TW, tc1 = (w.k1 - 1) / TW;
+  if ((tr1 - tr0 + 1) * (tc1 - tc0 + 1) > 4) {
+    big[atomicAdd(&ctrl[kCtrlNBig], 1)] = (int32_t)j;
+    return;
+  }
+  const int64_t base = (int64_t)w.event * g.ntiles_ev + pl.tile_off;
+  for (int tr = tr0; tr <= tr1; ++tr)
+    for (int tc = tc0; tc <= tc1; ++tc) atomicAdd(&counts[base + (int64_t)tr * pl.ntc + tc], 1);
+}
+
+// 2. scan of (rows, items) per tile -------------------------------------------
+__device__ __forceinline__ int items_of(int c) { return c > kRowsPerItem ? (c + kRowsPerItem - 1) / kRowsPerItem : 1; }
+
+// Inclusive block scan of int2 over 1024 threads (16 waves of 64).
+__device__ int2 block_scan_incl(int2 v, int2* s_wave) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int ax = __shfl_up(v.x, o, 64), ay = __shfl_up(v.y, o, 64);
+    if (lane >= o) {
+      v.x += ax;
+      v.y += ay;
+    }
+  }
+  if (lane == 63) s_wave[wv] = v;
+  __syncthreads();
+  if (wv == 0) {
+    const int nw = blockDim.x >> 6;
+    int2 t = lane < nw ? s_wave[lane] : make_int2(0, 0);
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int ax = __shfl_up(t.x, o, 64), ay = __shfl_up(t.y, o, 64);
+      if (lane >= o) {
+        t.x += ax;
+        t.y += ay;
+      }
+    }
+    if (lane < nw) s_wave[lane] = t;
+  }
+  __syncthreads();
+  if (wv > 0) {
+    v.x += s_wave[wv - 1].x;
+    v.y += s_wave[wv - 1].y;
+  }
+  return v;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_local(const int32_t* __restrict__ counts, int64_t n,
+                                                     int2* __restrict__ blocks) {
+  __shared__ int2 s_wave[16];
+  const int64_t base = (int64_t)blockIdx.x * kScanPerBlock + threadIdx.x * 4;
+  int2 s = make_int2(0, 0);
+  for (int e = 0; e < 4; ++e)
+    if (base + e < n) {
+      const int c = counts[base + e];
+      s.x += c;
+      s.y += items_of(c);
+    }
+  const int2 incl = block_scan_incl(s, s_wave);
+  if (threadIdx.x == blockDim.x - 1) blocks[blockIdx.x] = incl;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_blocks(int2* __restrict__ blocks, int nblocks,
+                                                      int32_t* __restrict__ ctrl) {
+  __shared__ int2 s_wave[16];
+  __shared__ int2 s_carry;
+  if (threadIdx.x == 0) s_carry = make_int2(0, 0);
+  __syncthreads();
+  for (int b0 = 0; b0 < nblocks; b0 += blockDim.x) {
+    const int b = b0 + threadIdx.x;
+    const int2 v = b < nblocks ? blocks[b] : make_int2(0, 0);
+    const int2 incl = block_scan_incl(v, s_wave);
+    const int2 carry = s_carry;
+    if (b < nblocks) blocks[b] = make_int2(carry.x + incl.x - v.x, carry.y + incl.y - v.y);  // exclusive
+    __syncthreads();
+    if (threadIdx.x == blockDim.x - 1) s_carry = make_int2(carry.x + incl.x, carry.y + incl.y);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    ctrl[kCtrlTotal] = s_carry.x;
+    ctrl[kCtrlNItems] = s_carry.y;
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_scan_apply(const int32_t* __restrict__ counts, int64_t n,
+                                                     const int2* __restrict__ blocks, int32_t* __restrict__ offs,
+                                                     int32_t* __restrict__ item_off) {
+  __shared__ int2 s_wave[16];
+  const int64_t base = (int64_t)blockIdx.x * kScanPerBlock + threadIdx.x * 4;
+  int c[4];
+  int2 s = make_int2(0, 0);
+  for (int e = 0; e < 4; ++e) {
+    c[e] = base + e < n ? counts[base + e] : 0;
+    s.x += c[e];
+    s.y += base + e < n ? items_of(c[e]) : 0;
+  }
+  const int2 incl = block_scan_incl(s, s_wave);
+  const int2 bo = blocks[blockIdx.x];
+  int2 run = make_int2(bo.x + incl.x - s.x, bo.y + incl.y - s.y);
+  for (int e = 0; e < 4; ++e) {
+    const int64_t t = base + e;
+    if (t < n) {
+      offs[t] = run.x;
+      item_off[t] = run.y;
+      run.x += c[e];
+      run.y += items_of(c[e]);
+      if (t == n - 1) {
+        offs[n] = run.x;
+        item_off[n] = run.y;
+      }
+    }
+  }
+}
+
+// 3. rows into tile slices; 4a. item -> tile map; 4b. clear split tiles -------
+template <typename T, int TH, int TW>
+__global__ void k_fill(DepoView<T> d, RasterGeom g, double nsigma, const int32_t* __restrict__ offs,
+                       int32_t* __restrict__ cursor, int32_t* __restrict__ list) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= d.n) return;
+  const RowWin w = row_window(d, j, g, nsigma);
+  if (!w.ok) return;
+  const PlaneGeom& pl = g.pl[w.plane];
+  const int tr0 = w.b0 / TH, tr1 = (w.b1 - 1) / TH, tc0 = w.k0 / TW, tc1 = (w.k1 - 1) / TW;
+  if ((tr1 - tr0 + 1) * (tc1 - tc0 + 1) > 4) return;
+  const int64_t base = (int64_t)w.event * g.ntiles_ev + pl.tile_off;
+  for (int tr = tr0; tr <= tr1; ++tr)
+    for (int tc = tc0; tc <= tc1; ++tc) {
+      const int64_t t = base + (int64_t)tr * pl.ntc + tc;
+      list[offs[t] + atomicAdd(&cursor[t], 1)] = (int32_t)j;
+    }
+}
+
+__global__ void k_items(const int32_t* __restrict__ item_off, int64_t ntiles, int32_t* __restrict__ items) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  for (int k = item_off[t]; k < item_off[t + 1]; ++k) items[k] = (int32_t)t;
+}
+
+template <typename T, int TH, int TW>
+__global__ void k_zero_split(RasterGeom g, const int32_t* __restrict__ counts, int64_t ntiles, T* __restrict__ grid) {
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    if (counts[t] <= kRowsPerItem) continue;
+    const int ev = (int)(t / g.ntiles_ev);
+    const int tin = (int)(t - (int64_t)ev * g.ntiles_ev);
+    const PlaneGeom& pl = g.pl[find_plane(g, tin)];
+    const int tl = tin - pl.tile_off;
+    const int tr = tl / pl.ntc, tc = tl - (tl / pl.ntc) * pl.ntc;
+    const int tb0 = tr * TH, tk0 = tc * TW;
+    T* gp = grid + (int64_t)ev * g.grid_ev_stride + pl.grid_off;
+    for (int x = threadIdx.x; x < TH * TW; x += blockDim.x) {
+      const int r = x / TW, c = x - (x / TW) * TW;
+      if (tb0 + r < pl.nb && tk0 + c < pl.nt) gp[(int64_t)(tb0 + r) * pl.nt + tk0 + c] = T(0);
+    }
+  }
+}
+
+// 4. persistent tile kernel -------------------------------------------------
+template <typename T, bool FLUCT, int TH, int TW>
+__global__ void __launch_bounds__(256) k_tile(DepoView<T> d, RasterGeom g, double nsigma, uint64_t seed,
+                                              T* __restrict__ grid, const int32_t* __restrict__ list,
+                                              const int32_t* __restrict__ offs, const int32_t* __restrict__ items,
+                                              const int32_t* __restrict__ item_off, int32_t* __restrict__ ctrl,
+                                              const DetTables* __restrict__ tables) {
+  constexpr int NWAVE = 4;
+  __shared__ T tile[TH * TW];
+  __shared__ double s_a[NWAVE][TH];
+  __shared__ double s_b[NWAVE][TW];
+  __shared__ DetTables s_tb;
+  __shared__ int s_item;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (FLUCT) {
+    const double* src = reinterpret_cast<const double*>(tables);
+    double* dst = reinterpret_cast<double*>(&s_tb);
+    for (int x = threadIdx.x; x < (int)(sizeof(DetTables) / sizeof(double)); x += blockDim.x) dst[x] = src[x];
+  }
+  const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&ctrl[kCtrlHead], 1);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= ctrl[kCtrlNItems]) break;
+    const int t = items[item];
+    const int chunk = item - item_off[t];
+    const bool owned = (item_off[t + 1] - item_off[t]) == 1;
+    const int ev = t / g.ntiles_ev;
+    const int tin = t - ev * g.ntiles_ev;
+    const int pi = find_plane(g, tin);
+    const PlaneGeom& pl = g.pl[pi];
+    const int tl = tin - pl.tile_off;
+    const int tr = tl / pl.ntc, tc = tl - (tl / pl.ntc) * pl.ntc;
+    const int tb0 = tr * TH, tk0 = tc * TW;
+    const int th = min(TH, pl.nb - tb0), tw = min(TW, pl.nt - tk0);
+    for (int x = threadIdx.x; x < TH * TW; x += blockDim.x) tile[x] = T(0);
+    __syncthreads();
+    const int r0 = offs[t] + chunk * kRowsPerItem;
+    const int r1 = min(offs[t] + (chunk + 1) * kRowsPerItem, offs[t + 1]);
+    for (int r = r0 + wv; r < r1; r += NWAVE) {
+      const int64_t j = list[r];
+      const RowWin w = row_window(d, j, g, nsigma);
+      const int bb0 = max(w.b0, tb0), bb1 = min(w.b1, tb0 + th);
+      const int kk0 = max(w.k0, tk0), kk1 = min(w.k1, tk0 + tw);
+      if (!w.ok || bb0 >= bb1 || kk0 >= kk1) continue;
+      const int nbr = bb1 - bb0, nkr = kk1 - kk0;
+      for (int x = lane; x < nbr; x += 64)
+        s_a[wv][x] = FLUCT ? cell_prob(bb0 + x, w.u, w.su, w.ulo, w.uhi, s_tb.inv)
+                           : cell_weight(bb0 + x, w.u, w.su, w.ulo, w.uhi);
+      for (int x = lane; x < nkr; x += 64)
+        s_b[wv][x] = FLUCT ? cell_prob(kk0 + x, w.t, w.st, w.tlo, w.thi, s_tb.inv)
+                           : cell_weight(kk0 + x, w.t, w.st, w.tlo, w.thi);
+      wave_sync();
+      const int64_t N = FLUCT ? (int64_t)floor(w.q + 0.5) : 0;
+      const uint32_t did = d.depo_id ? (uint32_t)d.depo_id[j] : (uint32_t)j;
+      for (int x = lane; x < nbr * nkr; x += 64) {
+        const int bi = x / nkr, ki = x - (x / nkr) * nkr;
+        T val;
+        if (FLUCT) {
+          const double pr = s_a[wv][bi] * s_b[wv][ki];
+          const uint32_t cell = (uint32_t)((int64_t)(bb0 + bi) * pl.nt + (kk0 + ki));
+          const Philox4 ph = philox4x32_10(cell, did, (uint32_t)ev, (uint32_t)pi << 24, key0, key1);
+          const int64_t n = binomial(N, pr, uniform53(ph.w0, ph.w1), s_tb);
+          if (n == 0) continue;
+          val = (T)n;
+        } else {
+          val = (T)(w.q * (s_a[wv][bi] * s_b[wv][ki]));
+        }
+        atomicAdd(&tile[(bb0 + bi - tb0) * TW + (kk0 + ki - tk0)], val);
+      }
+      wave_sync();
+    }
+    __syncthreads();
+    T* gp = grid + (int64_t)ev * g.grid_ev_stride + pl.grid_off;
+    for (int x = threadIdx.x; x < th * TW; x += blockDim.x) {
+      const int rr = x / TW, c = x - (x / TW) * TW;
+      if (c < tw) {
+        T* dst = gp + (int64_t)(tb0 + rr) * pl.nt + tk0 + c;
+        if (owned)
+          *dst = tile[x];
+        else if (tile[x] != T(0))
+          atomicAdd(dst, tile[x]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// 5. rows wider than 4 tiles: chunked, straight to global atomics ---------------
+template <typename T, bool FLUCT>
+__global__ void __launch_bounds__(256) k_big(DepoView<T> d, RasterGeom g, double nsigma, uint64_t seed,
+                                             T* __restrict__ grid, const int32_t* __restrict__ big,
+                                             const int32_t* __restrict__ ctrl, const DetTables* __restrict__ tables) {
+  constexpr int CB = 64, CK = 256;
+  __shared__ double s_a[CB];
+  __shared__ double s_b[CK];
+  __shared__ DetTables s_tb;
+  if (FLUCT) {
+    const double* src = reinterpret_cast<const double*>(tables);
+    double* dst = reinterpret_cast<double*>(&s_tb);
+    for (int x = threadIdx.x; x < (int)(sizeof(DetTables) / sizeof(double)); x += blockDim.x) dst[x] = src[x];
+    __syncthreads();
+  }
+  const int nbig = ctrl[kCtrlNBig];
+  const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
+  for (int r = blockIdx.x; r < nbig; r += gridDim.x) {
+    const int64_t j = big[r];
+    const RowWin w = row_window(d, j, g, nsigma);
+    if (!w.ok) continue;
+    const PlaneGeom& pl = g.pl[w.plane];
+    T* gp = grid + (int64_t)w.event * g.grid_ev_stride + pl.grid_off;
+    const int64_t N = FLUCT ? (int64_t)floor(w.q + 0.5) : 0;
+    const uint32_t did = d.depo_id ? (uint32_t)d.depo_id[j] : (uint32_t)j;
+    for (int cb = w.b0; cb < w.b1; cb += CB)
+      for (int ck = w.k0; ck < w.k1; ck += CK) {
+        const int nbr = min(CB, w.b1 - cb), nkr = min(CK, w.k1 - ck);
+        __syncthreads();
+        for (int x = threadIdx.x; x < nbr; x += blockDim.x)
+          s_a[x] = FLUCT ? cell_prob(cb + x, w.u, w.su, w.ulo, w.uhi, s_tb.inv)
+                         : cell_weight(cb + x, w.u, w.su, w.ulo, w.uhi);
+        for (int x = threadIdx.x; x < nkr; x += blockDim.x)
+          s_b[x] = FLUCT ? cell_prob(ck + x, w.t, w.st, w.tlo, w.thi, s_tb.inv)
+                         : cell_weight(ck + x, w.t, w.st, w.tlo, w.thi);
+        __syncthreads();
+        for (int x = threadIdx.x; x < nbr * nkr; x += blockDim.x) {
+          const int bi = x / nkr, ki = x - (x / nkr) * nkr;
+          T val;
+          if (FLUCT) {
+            const double pr = s_a[bi] * s_b[ki];
+            const uint32_t cell = (uint32_t)((int64_t)(cb + bi) * pl.nt + (ck + ki));
+            const Philox4 ph = philox4x32_10(cell, did, (uint32_t)w.event, (uint32_t)w.plane << 24, key0, key1);
+            const int64_t n = binomial(N, pr, uniform53(ph.w0, ph.w1), s_tb);
+            if (n == 0) continue;
+            val = (T)n;
+          } else {
+            val = (T)(w.q * (s_a[bi] * s_b[ki]));
+          }
+          atomicAdd(gp + (int64_t)(cb + bi) * pl.nt + ck + ki, val);
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+#define WCT_CHECK_LAUNCH()                  \
+  do {                                      \
+    hipError_t e_ = hipGetLastError();      \
+    if (e_ != hipSuccess) return e_;        \
+  } while (0)
+
+template <typename T>
+hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigma, int fluctuate, uint64_t seed,
+                         T* grid, const RasterWs& ws, const DetTables* tables, int n_cu, hipStream_t st) {
+  constexpr int TH = TileShape<T>::TH, TW = TileShape<T>::TW;
+  const int64_t nt = ws.ntiles;
+  // control words, counts and cursors are contiguous
+  hipError_t e = launch_fill_i32(ws.ctrl, kCtrlWords + 2 * nt, 0, st);
+  if (e != hipSuccess) return e;
+  const unsigned rblocks = (unsigned)((d.n + 255) / 256);
+  if (d.n > 0) {
+    hipLaunchKernelGGL((k_count<T, TH, TW>), dim3(rblocks), dim3(256), 0, st, d, g, nsigma, ws.counts, ws.big,
+                       ws.ctrl);
+    WCT_CHECK_LAUNCH();
+  }
+  const int nsb = (int)((nt + kScanPerBlock - 1) / kScanPerBlock);
+  int2* blocks = reinterpret_cast<int2*>(ws.blocks);
+  hipLaunchKernelGGL(k_scan_local, dim3(nsb), dim3(1024), 0, st, ws.counts, nt, blocks);
+  WCT_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, blocks, nsb, ws.ctrl);
+  WCT_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_scan_apply, dim3(nsb), dim3(1024), 0, st, ws.counts, nt, blocks, ws.offs, ws.item_off);
+  WCT_CHECK_LAUNCH();
+  if (d.n > 0) {
+    hipLaunchKernelGGL((k_fill<T, TH, TW>), dim3(rblocks), dim3(256), 0, st, d, g, nsigma, ws.offs, ws.cursor,
+                       ws.list);
+    WCT_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(k_items, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, ws.item_off, nt, ws.items);
+  WCT_CHECK_LAUNCH();
+  hipLaunchKernelGGL((k_zero_split<T, TH, TW>), dim3(1024), dim3(256), 0, st, g, ws.counts, nt, grid);
+  WCT_CHECK_LAUNCH();
+  const unsigned pblocks = (unsigned)(n_cu * 4);
+  if (fluctuate) {
+    hipLaunchKernelGGL((k_tile<T, true, TH, TW>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.list,
+                       ws.offs, ws.items, ws.item_off, ws.ctrl, tables);
+    WCT_CHECK_LAUNCH();
+    hipLaunchKernelGGL((k_big<T, true>), dim3(256), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.big, ws.ctrl,
+                       tables);
+  } else {
+    hipLaunchKernelGGL((k_tile<T, false, TH, TW>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid,
+                       ws.list, ws.offs, ws.items, ws.item_off, ws.ctrl, tables);
+    WCT_CHECK_LAUNCH();
+    hipLaunchKernelGGL((k_big<T, false>), dim3(256), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.big, ws.ctrl,
+                       tables);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_raster<float>(const DepoView<float>&, const RasterGeom&, double, int, uint64_t, float*,
+                                         const RasterWs&, const DetTables*, int, hipStream_t);
+template hipError_t launch_raster<double>(const DepoView<double>&, const RasterGeom&, double, int, uint64_t, double*,
+                                          const RasterWs&, const DetTables*, int, hipStream_t);
+
+}  // namespace wct

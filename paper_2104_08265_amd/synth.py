@@ -198,16 +198,19 @@ def detector_uboone_like(n_ticks=9600, wires=(2400, 2400, 3456)) -> Detector:
     width = pitch * wires[2]
     # choose H so the +-60 degree planes exactly span the box
     height = (pitch * wires[0] - width * 0.5) / math.sin(math.radians(60.0))
-    return Detector(x_max=256.0, height=height, width=width, angles_deg=(60.0, -60.0, 0.0),
-                    pitch_cm=pitch, planes=planes, t0_max=max(0.0, n_ticks - 256.0 / 0.08 - 100.0))
+    x_max = 256.0 * min(1.0, n_ticks / 9600.0)  # drift length shrinks with a shorter readout window
+    return Detector(x_max=x_max, height=height, width=width, angles_deg=(60.0, -60.0, 0.0),
+                    pitch_cm=pitch, planes=planes, t0_max=max(0.0, n_ticks - x_max / 0.08 - 100.0))
 
 
 def detector_dune_like(n_ticks=6000, wires=(800, 800, 960)) -> Detector:
     planes = [Plane(wires[0], n_ticks, kind="induction"), Plane(wires[1], n_ticks, kind="induction"),
               Plane(wires[2], n_ticks, kind="collection")]
     pitch = 0.47
-    return Detector(x_max=360.0, height=300.0, width=pitch * wires[2], angles_deg=(35.7, -35.7, 0.0),
-                    pitch_cm=pitch, planes=planes, t0_max=max(0.0, n_ticks - 360.0 / 0.08 - 100.0))
+    x_max = 360.0 * min(1.0, n_ticks / 6000.0)
+    return Detector(x_max=x_max, height=300.0 * min(1.0, wires[2] / 960.0), width=pitch * wires[2],
+                    angles_deg=(35.7, -35.7, 0.0), pitch_cm=pitch, planes=planes,
+                    t0_max=max(0.0, n_ticks - x_max / 0.08 - 100.0))
 
 
 def _rows_from_points(det: Detector, xyz, t0, q, event, depo_ids, plane_offset=0) -> Depos:
@@ -227,6 +230,8 @@ def _isotropic(rng, n):
 def track_points(rng, det: Detector, n_tracks: int, n_points: int, lmin=10.0, lmax=200.0):
     """n_points spread evenly (in length) over n_tracks straight tracks inside the box."""
     ext = np.array([det.x_max, det.height, det.width])
+    lmax = min(lmax, 0.95 * float(ext.min()))  # small test boxes: tracks still fit
+    lmin = min(lmin, 0.5 * lmax)
     L = rng.uniform(lmin, lmax, n_tracks)
     d = _isotropic(rng, n_tracks)
     start = np.empty((n_tracks, 3))

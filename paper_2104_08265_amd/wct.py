@@ -1,0 +1,266 @@
+"""ctypes binding of libwct.so: the C ABI of include/wct.h with the same call names.
+
+Argument marshalling only: every step of the simulation runs in the library's HIP
+kernels.  Device memory and streams come from PyTorch (tensors' data pointers and the
+current HIP stream).  Importing this module loads the library and raises ImportError if
+it has not been built (python -m paper_2104_08265_amd.build).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_size_t, c_uint64, c_void_p
+
+# torch is imported first so that its bundled HIP runtime is the one in the process:
+# libwct.so's dependency on libamdhip64.so.7 then resolves (by soname) to that same
+# runtime, and torch's device pointers and streams are valid in the library's calls.
+import torch  # noqa: F401  (load order matters)
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwct.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2104_08265_amd.build`")
+lib = ctypes.CDLL(LIB_PATH)
+
+WCT_F32, WCT_F64 = 0, 1
+WCT_OK, WCT_E_INVALID, WCT_E_WORKSPACE, WCT_E_DEVICE, WCT_E_UNSUPPORTED, WCT_E_NOMEM = 0, -1, -2, -3, -4, -5
+OP_RASTER, OP_CONVOLVE, OP_SIMULATE, OP_BACKWARD = 0, 1, 2, 3
+STATUS = {0: "WCT_OK", -1: "WCT_E_INVALID", -2: "WCT_E_WORKSPACE", -3: "WCT_E_DEVICE", -4: "WCT_E_UNSUPPORTED",
+          -5: "WCT_E_NOMEM"}
+
+
+class wct_plane_desc(ctypes.Structure):
+    _fields_ = [("n_wires", c_int32), ("n_ticks", c_int32), ("n_impacts", c_int32), ("half_wires", c_int32),
+                ("resp_ticks", c_int32), ("response", c_void_p)]
+
+
+class wct_plan_desc(ctypes.Structure):
+    _fields_ = [("dtype", c_int32), ("n_planes", c_int32), ("planes", POINTER(wct_plane_desc)),
+                ("max_events", c_int32), ("device", c_int32)]
+
+
+class wct_depos(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("q", c_void_p), ("t", c_void_p), ("p", c_void_p), ("sigma_t", c_void_p),
+                ("sigma_p", c_void_p), ("plane", c_void_p), ("event", c_void_p), ("depo_id", c_void_p)]
+
+
+class wct_opts(ctypes.Structure):
+    _fields_ = [("nsigma", c_double), ("fluctuate", c_int32), ("n_events", c_int32), ("seed", c_uint64)]
+
+
+PlanP = c_void_p
+
+
+def _sig(name, restype, argtypes):
+    f = getattr(lib, name)
+    f.restype = restype
+    f.argtypes = argtypes
+    return f
+
+
+wct_plan_create = _sig("wct_plan_create", c_int32, [POINTER(wct_plan_desc), POINTER(c_void_p)])
+wct_plan_destroy = _sig("wct_plan_destroy", None, [PlanP])
+wct_grid_elems = _sig("wct_grid_elems", c_int64, [PlanP])
+wct_wave_elems = _sig("wct_wave_elems", c_int64, [PlanP])
+wct_plane_info = _sig("wct_plane_info", c_int32, [PlanP, c_int32, POINTER(c_int64)])
+wct_workspace_bytes = _sig("wct_workspace_bytes", c_size_t, [PlanP, c_int32, c_int32, c_int64])
+wct_raster = _sig("wct_raster", c_int32, [PlanP, POINTER(wct_depos), POINTER(wct_opts), c_void_p, c_void_p, c_size_t,
+                                         c_void_p])
+wct_convolve = _sig("wct_convolve", c_int32, [PlanP, c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p])
+wct_simulate = _sig("wct_simulate", c_int32, [PlanP, POINTER(wct_depos), POINTER(wct_opts), c_void_p, c_void_p,
+                                             c_size_t, c_void_p])
+wct_simulate_backward = _sig("wct_simulate_backward", c_int32,
+                             [PlanP, POINTER(wct_depos), POINTER(wct_opts), c_void_p, c_void_p, c_void_p, c_void_p,
+                              c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
+wct_last_error = _sig("wct_last_error", c_char_p, [])
+wct_abi_version = _sig("wct_abi_version", c_int32, [])
+wct_fluct_spec_version = _sig("wct_fluct_spec_version", c_int32, [])
+
+
+class WctError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {STATUS.get(code, code)}: {last_error()}")
+
+
+def last_error() -> str:
+    return (wct_last_error() or b"").decode()
+
+
+def check(code, what="wct call"):
+    if code != WCT_OK:
+        raise WctError(code, what)
+    return code
+
+
+# ---------------------------------------------------------------------------
+# torch-facing helpers (torch supplies device memory and the stream)
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dt(dtype):
+    torch = _torch()
+    return torch.float32 if dtype == WCT_F32 else torch.float64
+
+
+def _ptr(t):
+    return c_void_p(t.data_ptr()) if t is not None else c_void_p(0)
+
+
+class DeviceDepos:
+    """Depo-plane rows resident on the device (structure of arrays)."""
+
+    def __init__(self, q, t, p, sigma_t, sigma_p, plane=None, event=None, depo_id=None):
+        self.q, self.t, self.p, self.sigma_t, self.sigma_p = q, t, p, sigma_t, sigma_p
+        self.plane, self.event, self.depo_id = plane, event, depo_id
+        self.n = int(q.shape[0])
+        for a in (t, p, sigma_t, sigma_p):
+            if a.shape[0] != self.n or a.dtype != q.dtype or a.device != q.device or not a.is_contiguous():
+                raise ValueError("depo float arrays must share length, dtype and device and be contiguous")
+        for a in (plane, event, depo_id):
+            if a is not None and (a.shape[0] != self.n or str(a.dtype) != "torch.int32" or not a.is_contiguous()):
+                raise ValueError("plane/event/depo_id must be contiguous int32 of the same length")
+
+    @staticmethod
+    def from_numpy(d, device, dtype):
+        """From an object with numpy fields q, t, p, sigma_t, sigma_p, plane, event, depo_id."""
+        torch = _torch()
+        f = lambda a: torch.as_tensor(a).to(device=device, dtype=dtype).contiguous()
+        i = lambda a: torch.as_tensor(a.astype("int32")).to(device=device).contiguous()
+        return DeviceDepos(f(d.q), f(d.t), f(d.p), f(d.sigma_t), f(d.sigma_p), i(d.plane), i(d.event), i(d.depo_id))
+
+    def c(self):
+        return wct_depos(self.n, _ptr(self.q), _ptr(self.t), _ptr(self.p), _ptr(self.sigma_t), _ptr(self.sigma_p),
+                         _ptr(self.plane), _ptr(self.event), _ptr(self.depo_id))
+
+
+def opts(nsigma=3.0, fluctuate=False, n_events=1, seed=0):
+    return wct_opts(float(nsigma), int(bool(fluctuate)), int(n_events), int(seed) & 0xFFFFFFFFFFFFFFFF)
+
+
+class Plan:
+    """A wct_plan plus torch-allocated workspaces.
+
+    planes: sequence of objects with n_wires, n_ticks, n_impacts, half_wires, resp_ticks;
+    responses: one host array [2K+1][I][T_R] per plane (converted to the plan dtype).
+    """
+
+    def __init__(self, planes, responses, dtype="f32", max_events=1, device=0):
+        import numpy as np
+        self.dtype = WCT_F32 if dtype in ("f32", WCT_F32) else WCT_F64
+        npdt = np.float32 if self.dtype == WCT_F32 else np.float64
+        self._resp = [np.ascontiguousarray(np.asarray(r, dtype=npdt)) for r in responses]
+        descs = (wct_plane_desc * len(planes))()
+        for k, (pl, r) in enumerate(zip(planes, self._resp)):
+            K = (r.shape[0] - 1) // 2
+            if r.shape != (2 * K + 1, pl.n_impacts, r.shape[2]):
+                raise ValueError("response shape must be [2K+1][I][T_R]")
+            descs[k] = wct_plane_desc(pl.n_wires, pl.n_ticks, pl.n_impacts, K, r.shape[2],
+                                      r.ctypes.data_as(c_void_p))
+        self.device = int(device)
+        self.max_events = int(max_events)
+        desc = wct_plan_desc(self.dtype, len(planes), descs, self.max_events, self.device)
+        h = c_void_p()
+        check(wct_plan_create(ctypes.byref(desc), ctypes.byref(h)), "wct_plan_create")
+        self.h = h
+        self.n_planes = len(planes)
+        self.grid_elems = int(wct_grid_elems(h))
+        self.wave_elems = int(wct_wave_elems(h))
+        self.info = [self.plane_info(k) for k in range(self.n_planes)]
+        self._ws = None
+
+    def plane_info(self, plane):
+        out = (c_int64 * 10)()
+        check(wct_plane_info(self.h, plane, out), "wct_plane_info")
+        keys = ["n_wires", "n_ticks", "n_impacts", "half_wires", "resp_ticks", "lw", "lt", "F", "grid_off",
+                "wave_off"]
+        return dict(zip(keys, [int(v) for v in out]))
+
+    @property
+    def torch_dtype(self):
+        return _dt(self.dtype)
+
+    def workspace(self, op, n_events, n_rows=0):
+        torch = _torch()
+        need = int(wct_workspace_bytes(self.h, op, n_events, n_rows))
+        if need == 0:
+            raise WctError(WCT_E_INVALID, "wct_workspace_bytes")
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws, need
+
+    def _stream(self):
+        torch = _torch()
+        return c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def new_grid(self, n_events=1):
+        torch = _torch()
+        return torch.empty(n_events * self.grid_elems, dtype=self.torch_dtype, device=f"cuda:{self.device}")
+
+    def new_wave(self, n_events=1):
+        torch = _torch()
+        return torch.empty(n_events * self.wave_elems, dtype=self.torch_dtype, device=f"cuda:{self.device}")
+
+    def raster(self, depos: DeviceDepos, o: wct_opts, grid=None):
+        grid = self.new_grid(o.n_events) if grid is None else grid
+        ws, nb = self.workspace(OP_RASTER, o.n_events, depos.n)
+        d = depos.c()
+        check(wct_raster(self.h, ctypes.byref(d), ctypes.byref(o), _ptr(grid), _ptr(ws), nb, self._stream()),
+              "wct_raster")
+        return grid
+
+    def convolve(self, grid, n_events=1, wave=None):
+        wave = self.new_wave(n_events) if wave is None else wave
+        ws, nb = self.workspace(OP_CONVOLVE, n_events, 0)
+        check(wct_convolve(self.h, _ptr(grid), n_events, _ptr(wave), _ptr(ws), nb, self._stream()), "wct_convolve")
+        return wave
+
+    def simulate(self, depos: DeviceDepos, o: wct_opts, wave=None):
+        wave = self.new_wave(o.n_events) if wave is None else wave
+        ws, nb = self.workspace(OP_SIMULATE, o.n_events, depos.n)
+        d = depos.c()
+        check(wct_simulate(self.h, ctypes.byref(d), ctypes.byref(o), _ptr(wave), _ptr(ws), nb, self._stream()),
+              "wct_simulate")
+        return wave
+
+    def simulate_backward(self, depos: DeviceDepos, o: wct_opts, grad_wave):
+        torch = _torch()
+        outs = [torch.empty(depos.n, dtype=self.torch_dtype, device=f"cuda:{self.device}") for _ in range(5)]
+        ws, nb = self.workspace(OP_BACKWARD, o.n_events, depos.n)
+        d = depos.c()
+        check(wct_simulate_backward(self.h, ctypes.byref(d), ctypes.byref(o), _ptr(grad_wave), *[_ptr(x) for x in outs],
+                                    _ptr(ws), nb, self._stream()), "wct_simulate_backward")
+        return outs
+
+    def grid_view(self, grid, event=0):
+        """Per-plane [N_b][N_t] views of one event of a packed grid."""
+        out = []
+        base = event * self.grid_elems
+        for inf in self.info:
+            n = inf["n_impacts"] * inf["n_wires"] * inf["n_ticks"]
+            out.append(grid[base + inf["grid_off"]: base + inf["grid_off"] + n].view(
+                inf["n_impacts"] * inf["n_wires"], inf["n_ticks"]))
+        return out
+
+    def wave_view(self, wave, event=0):
+        out = []
+        base = event * self.wave_elems
+        for inf in self.info:
+            n = inf["n_wires"] * inf["n_ticks"]
+            out.append(wave[base + inf["wave_off"]: base + inf["wave_off"] + n].view(inf["n_wires"], inf["n_ticks"]))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            wct_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,208 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 plans agree to a relative L2 of 1e-12; FP32 plans to 1e-5 (the
+relative-L2 bar stated for FP32); fluctuated grids hold integer electron counts and
+must agree bit for bit.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import device_depos, make_plan, rel_l2, say, to_np
+from oracle import convolve as OC
+from oracle import fluct as OF
+from oracle import raster as OR
+from paper_2104_08265_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def slice_workload(fluctuate=False, n_depos=2000):
+    """The three-plane track workload at a tenth of the wire count and ticks."""
+    return synth.config2(n_depos=n_depos, n_tracks=5, n_ticks=960, wires=(240, 240, 346), fluctuate=fluctuate)
+
+
+def oracle_wave(wl, grids):
+    return [OC.convolve_fft(g, R, pl.n_impacts) for g, R, pl in
+            zip(grids, [r.astype(np.float64) for r in synth.round_responses(wl)], wl.planes)]
+
+
+def test_config1_raster_fp64(wct):
+    wl = synth.config1()
+    say("config1 raster fp64", len(wl.depos))
+    plan = make_plan(wct, wl)
+    grid = plan.raster(device_depos(wct, wl), wct.opts(3.0, False, 1, wl.seed))
+    got = to_np(plan.grid_view(grid)[0])
+    ref = OR.raster(wl.depos, wl.planes)[0][0]
+    assert rel_l2(got, ref) < TOL64
+
+
+def test_config1_convolve_and_simulate_fp64(wct):
+    import torch
+    wl = synth.config1()
+    say("config1 convolve fp64")
+    plan = make_plan(wct, wl)
+    S = OR.raster(wl.depos, wl.planes)[0][0]
+    grid = torch.as_tensor(S.ravel()).to("cuda:0")
+    wave = plan.convolve(grid, 1)
+    ref = oracle_wave(wl, [S])[0]
+    assert rel_l2(to_np(plan.wave_view(wave)[0]), ref) < TOL64
+    say("config1 simulate fp64")
+    wave2 = plan.simulate(device_depos(wct, wl), wct.opts(3.0, False, 1, wl.seed))
+    assert rel_l2(to_np(plan.wave_view(wave2)[0]), ref) < TOL64
+
+
+def test_slice_fp32_mean(wct):
+    wl = slice_workload()
+    say("slice fp32 mean raster/convolve/simulate", len(wl.depos))
+    plan = make_plan(wct, wl)
+    dd = device_depos(wct, wl)
+    o = wct.opts(3.0, False, 1, wl.seed)
+    grid = plan.raster(dd, o)
+    ref_grids = OR.raster(wl.depos, wl.planes)[0]
+    for k, g in enumerate(plan.grid_view(grid)):
+        assert rel_l2(to_np(g), ref_grids[k]) < TOL32, k
+    ref_waves = oracle_wave(wl, ref_grids)
+    wave = plan.convolve(grid, 1)
+    for k, w in enumerate(plan.wave_view(wave)):
+        assert rel_l2(to_np(w), ref_waves[k]) < TOL32, k
+    wave2 = plan.simulate(dd, o)
+    for k, w in enumerate(plan.wave_view(wave2)):
+        assert rel_l2(to_np(w), ref_waves[k]) < TOL32, k
+
+
+def test_slice_fp32_fluct_bitexact(wct):
+    wl = slice_workload(fluctuate=True)
+    say("slice fp32 fluctuation", len(wl.depos))
+    plan = make_plan(wct, wl)
+    grid = plan.raster(device_depos(wct, wl), wct.opts(3.0, True, 1, wl.seed))
+    ref = OF.raster_fluct(wl.depos, wl.planes, seed=wl.seed)[0]
+    for k, g in enumerate(plan.grid_view(grid)):
+        got = to_np(g)
+        assert ref[k].max() < 2 ** 24
+        assert np.array_equal(got, ref[k]), (k, int(np.sum(got != ref[k])))
+
+
+def edge_workload(dtype):
+    """Rows at and beyond every grid edge, zero charge, tiny and very wide windows."""
+    pl = synth.Plane(12, 300, 10, 2, 12)
+    rng = np.random.default_rng(3)
+    rows = [
+        (1500.0, 0.2, 0.1, 1.0, 0.3),      # low corner
+        (1500.0, 299.7, 11.9, 1.0, 0.3),   # high corner
+        (900.0, -5.0, 6.0, 1.0, 0.3),      # window partly below tick 0
+        (900.0, 302.0, 6.0, 1.5, 0.3),     # partly above the last tick
+        (900.0, 30.0, -0.4, 1.0, 0.5),     # partly below wire 0
+        (900.0, 30.0, 12.4, 1.0, 0.5),     # partly above the last wire
+        (900.0, -50.0, 6.0, 1.0, 0.3),     # fully outside: no charge
+        (0.0, 20.0, 5.0, 1.0, 0.3),        # zero charge
+        (0.4, 20.0, 5.0, 1.0, 0.3),        # rounds to zero electrons
+        (5000.0, 32.0, 6.0, 9.0, 1.9),     # wide window
+        (20000.0, 150.0, 6.0, 50.0, 5.0),  # wider than 4 raster tiles: the separate wide-row path
+        (5000.0, 10.0, 3.0, 0.01, 0.002),  # window inside one cell
+        (3.0e5, 40.5, 7.5, 2.0, 0.4),      # heavy: chop-down sampler regime
+    ]
+    for _ in range(20):
+        rows.append((float(rng.lognormal(7, 1)), float(rng.uniform(-3, 303)), float(rng.uniform(-1, 13)),
+                     float(rng.uniform(0.3, 4)), float(rng.uniform(0.05, 2))))
+    a = np.array(rows)
+    n = len(a)
+    d = synth.Depos(a[:, 0], a[:, 1], a[:, 2], a[:, 3], a[:, 4], np.zeros(n, np.int32), np.zeros(n, np.int32),
+                    np.arange(n, dtype=np.int32))
+    resp = [synth.make_response(pl, np.random.default_rng(4))]
+    wl = synth.Workload("edges", [pl], resp, synth._finish(d, dtype), dtype=dtype, seed=99)
+    return wl
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_edge_rows(wct, dtype):
+    wl = edge_workload(dtype)
+    say("edge rows", dtype)
+    plan = make_plan(wct, wl)
+    dd = device_depos(wct, wl)
+    grid = plan.raster(dd, wct.opts(3.0, False, 1, wl.seed))
+    ref = OR.raster(wl.depos, wl.planes)[0][0]
+    assert rel_l2(to_np(plan.grid_view(grid)[0]), ref) < (TOL64 if dtype == "f64" else TOL32)
+    grid = plan.raster(dd, wct.opts(3.0, True, 1, wl.seed))
+    reff = OF.raster_fluct(wl.depos, wl.planes, seed=wl.seed)[0][0]
+    assert np.array_equal(to_np(plan.grid_view(grid)[0]), reff)
+
+
+def test_empty_and_nsigma(wct):
+    wl = edge_workload("f32")
+    plan = make_plan(wct, wl)
+    say("empty depo list")
+    empty = wl.depos.select(np.zeros(len(wl.depos), bool))
+    grid = plan.raster(device_depos(wct, wl, empty), wct.opts(3.0, True, 1, 1))
+    assert np.all(to_np(grid) == 0.0)
+    wave = plan.simulate(device_depos(wct, wl, empty), wct.opts(3.0, False, 1, 1))
+    assert np.all(to_np(wave) == 0.0)
+    say("nsigma 2 and 4")
+    for ns in (2.0, 4.0):
+        grid = plan.raster(device_depos(wct, wl), wct.opts(ns, False, 1, 1))
+        ref = OR.raster(wl.depos, wl.planes, nsigma=ns)[0][0]
+        assert rel_l2(to_np(plan.grid_view(grid)[0]), ref) < TOL32
+        grid = plan.raster(device_depos(wct, wl), wct.opts(ns, True, 1, 5))
+        reff = OF.raster_fluct(wl.depos, wl.planes, seed=5, nsigma=ns)[0][0]
+        assert np.array_equal(to_np(plan.grid_view(grid)[0]), reff)
+
+
+def test_crowded_tile_split(wct):
+    """More than 256 rows in one raster tile: the tile is split across work items that add atomically."""
+    pl = synth.Plane(40, 300, 10, 2, 12)
+    rng = np.random.default_rng(8)
+    n = 1500
+    d = synth.Depos(rng.lognormal(7, 0.5, n), rng.uniform(40, 80, n), rng.uniform(10, 13, n),
+                    rng.uniform(0.5, 1.5, n), rng.uniform(0.05, 0.2, n), np.zeros(n, np.int32),
+                    np.zeros(n, np.int32), np.arange(n, dtype=np.int32))
+    wl = synth.Workload("crowd", [pl], [synth.make_response(pl, rng)], synth._finish(d, "f32"), dtype="f32", seed=3)
+    say("crowded tile", n)
+    plan = make_plan(wct, wl)
+    dd = device_depos(wct, wl)
+    grid = plan.raster(dd, wct.opts(3.0, True, 1, 3))
+    reff = OF.raster_fluct(wl.depos, wl.planes, seed=3)[0][0]
+    assert np.array_equal(to_np(plan.grid_view(grid)[0]), reff)
+    grid = plan.raster(dd, wct.opts(3.0, False, 1, 3))
+    ref = OR.raster(wl.depos, wl.planes)[0][0]
+    assert rel_l2(to_np(plan.grid_view(grid)[0]), ref) < TOL32
+
+
+def test_delta_response(wct):
+    """R = delta(k=0, tau=0) for every phase: the waveform is the sum of each wire's impact rows."""
+    import torch
+    pl = synth.Plane(30, 100, 10, 3, 20)
+    R = np.zeros((7, 10, 20))
+    R[3, :, 0] = 1.0
+    wl = synth.Workload("delta", [pl], [R], None, dtype="f64")
+    plan = make_plan(wct, wl)
+    rng = np.random.default_rng(2)
+    S = rng.standard_normal((300, 100))
+    say("delta response")
+    wave = plan.convolve(torch.as_tensor(S.ravel()).to("cuda:0"), 1)
+    got = to_np(plan.wave_view(wave)[0])
+    assert np.allclose(got, S.reshape(30, 10, 100).sum(axis=1), rtol=0, atol=1e-12)
+
+
+def test_multi_event(wct):
+    """Three events in one call equal three one-event calls (fluctuated: bitwise)."""
+    wl = slice_workload(fluctuate=True, n_depos=600)
+    parts = []
+    for e in range(3):
+        d = wl.depos.select(np.arange(len(wl.depos)) % 3 == e)
+        d.event = np.full(len(d), e, np.int32)
+        parts.append(d)
+    allrows = synth.Depos.concat(parts)
+    say("multi event", len(allrows))
+    plan = make_plan(wct, wl, max_events=3)
+    grid = plan.raster(device_depos(wct, wl, allrows), wct.opts(3.0, True, 3, 11))
+    ref = OF.raster_fluct(allrows, wl.planes, seed=11, n_events=3)
+    for e in range(3):
+        for k, g in enumerate(plan.grid_view(grid, e)):
+            assert np.array_equal(to_np(g), ref[e][k]), (e, k)
+    wave = plan.convolve(grid, 3)
+    for e in range(3):
+        ref_w = oracle_wave(wl, ref[e])
+        for k, w in enumerate(plan.wave_view(wave, e)):
+            assert rel_l2(to_np(w), ref_w[k]) < TOL32, (e, k)
