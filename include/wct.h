@@ -159,6 +159,17 @@ int wct_simulate_backward(wct_plan* plan, const wct_depos* depos, const wct_opts
                           void* g_q, void* g_t, void* g_p, void* g_sigma_t, void* g_sigma_p, void* ws,
                           size_t ws_bytes, void* stream);
 
+/* Kernel timing.  While enabled, each kernel (or launch group) a run call enqueues is
+ * bracketed by HIP events on the call's stream.  wct_profile_count synchronises on the
+ * recorded events and returns the number of distinct kernel names seen since the last
+ * reset; wct_profile_get(idx) reports a name (HOST buffer of name_len bytes), its summed
+ * device milliseconds and its number of launches.  Enabling creates events per launch:
+ * a measurement mode, not for production calls. */
+int wct_profile_enable(wct_plan* plan, int32_t enable);
+int wct_profile_reset(wct_plan* plan);
+int wct_profile_count(wct_plan* plan);
+int wct_profile_get(wct_plan* plan, int32_t idx, char* name, size_t name_len, double* total_ms, int64_t* launches);
+
 /* Thread-local text of the last error on this thread ("" if none). */
 const char* wct_last_error(void);
 

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -114,9 +115,51 @@ struct Carver {
   }
 };
 
+// Kernel timing: events recorded around launch groups while enabled, folded into
+// per-name totals when read.
+struct Profiler final : ProfHook {
+  struct Rec {
+    std::string name;
+    hipEvent_t a = nullptr, b = nullptr;
+  };
+  bool on = false;
+  std::vector<Rec> pending;
+  std::map<std::string, std::pair<double, int64_t>> acc;
+  void begin(const char* name, hipStream_t st) override {
+    Rec r;
+    r.name = name;
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+    (void)hipEventRecord(r.a, st);
+    pending.push_back(r);
+  }
+  void end(hipStream_t st) override {
+    if (!pending.empty()) (void)hipEventRecord(pending.back().b, st);
+  }
+  hipError_t collect() {
+    hipError_t err = hipSuccess;
+    for (Rec& r : pending) {
+      float ms = 0.f;
+      hipError_t e = hipEventSynchronize(r.b);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+      if (e == hipSuccess) {
+        auto& v = acc[r.name];
+        v.first += ms;
+        v.second += 1;
+      } else {
+        err = e;
+      }
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    pending.clear();
+    return err;
+  }
+};
+
 }  // namespace
 
 struct wct_plan {
+  Profiler prof;
   int dtype = WCT_F32;
   int device = 0;
   int n_planes = 0;
@@ -143,6 +186,18 @@ struct wct_plan {
 };
 
 namespace {
+
+ProfHook* hook(wct_plan* P) { return P->prof.on ? &P->prof : nullptr; }
+
+// Brackets one launch with profiler events when timing is enabled.
+#define PROF_LAUNCH(P, name, st, expr, what)         \
+  do {                                              \
+    ProfHook* h__ = hook(P);                        \
+    if (h__) h__->begin(name, st);                  \
+    hipError_t e__ = (expr);                        \
+    if (h__) h__->end(st);                          \
+    if (e__ != hipSuccess) return hip_fail(e__, what); \
+  } while (0)
 
 RasterGeom raster_geom(const wct_plan* P, int n_events) {
   RasterGeom g;
@@ -256,7 +311,8 @@ template <typename T>
 int run_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, T* grid, Carver& cv, hipStream_t st) {
   const RasterGeom g = raster_geom(P, o->n_events);
   const RasterWs ws = carve_raster(P, cv, o->n_events, d->n);
-  HIP_TRY(launch_raster<T>(view<T>(d), g, o->nsigma, o->fluctuate, o->seed, grid, ws, P->d_tables, P->n_cu, st),
+  HIP_TRY(launch_raster<T>(view<T>(d), g, o->nsigma, o->fluctuate, o->seed, grid, ws, P->d_tables, P->n_cu, st,
+                           hook(P)),
           "raster launch");
   return WCT_OK;
 }
@@ -271,15 +327,19 @@ int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, 
     const cx<T>* tw_t = static_cast<const cx<T>*>(P->tw_t[p]);
     const cx<T>* post = static_cast<const cx<T>*>(P->post_t[p]);
     const cx<T>* tw_w = static_cast<const cx<T>*>(P->tw_w[p]);
-    HIP_TRY(launch_rows_r2c<T>(grid + G.grid_off, P->grid_elems, shat + G.shat_off, P->shat_elems, G.nt, G.I, G.nw,
-                               G.nchunk, n_events, P->fp_t[p], tw_t, post, st),
-            "row transform launch");
-    HIP_TRY(launch_colpass<T>(shat + G.shat_off, P->shat_elems, static_cast<const cx<T>*>(P->rtil[p]),
-                              mhat + G.mhat_off, P->mhat_elems, G.nw, G.I, G.nchunk, n_events, P->fp_w[p], tw_w, st),
-            "column pass launch");
-    HIP_TRY(launch_rows_c2r<T>(mhat + G.mhat_off, P->mhat_elems, wave + G.wave_off, P->wave_elems, G.nt, false, 1,
-                               G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, st),
-            "inverse row transform launch");
+    PROF_LAUNCH(P, "rows_r2c", st,
+                launch_rows_r2c<T>(grid + G.grid_off, P->grid_elems, shat + G.shat_off, P->shat_elems, G.nt, G.I,
+                                   G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, st),
+                "row transform launch");
+    PROF_LAUNCH(P, "colpass", st,
+                launch_colpass<T>(shat + G.shat_off, P->shat_elems, static_cast<const cx<T>*>(P->rtil[p]),
+                                  mhat + G.mhat_off, P->mhat_elems, G.nw, G.I, G.nchunk, n_events, P->fp_w[p], tw_w,
+                                  st),
+                "column pass launch");
+    PROF_LAUNCH(P, "rows_c2r", st,
+                launch_rows_c2r<T>(mhat + G.mhat_off, P->mhat_elems, wave + G.wave_off, P->wave_elems, G.nt, false,
+                                   1, G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, st),
+                "inverse row transform launch");
   }
   return WCT_OK;
 }
@@ -296,18 +356,23 @@ int run_backward(wct_plan* P, const wct_depos* d, const wct_opts* o, const T* gw
     const cx<T>* tw_t = static_cast<const cx<T>*>(P->tw_t[p]);
     const cx<T>* post = static_cast<const cx<T>*>(P->post_t[p]);
     const cx<T>* tw_w = static_cast<const cx<T>*>(P->tw_w[p]);
-    HIP_TRY(launch_rows_r2c<T>(gw + G.wave_off, P->wave_elems, ghat + G.mhat_off, P->mhat_elems, G.nt, 1, G.nw,
-                               G.nchunk, ne, P->fp_t[p], tw_t, post, st),
-            "adjoint row transform launch");
-    HIP_TRY(launch_colpass_adj<T>(ghat + G.mhat_off, P->mhat_elems, static_cast<const cx<T>*>(P->rtil[p]),
-                                  hhat + G.shat_off, P->shat_elems, G.nw, G.I, G.nchunk, ne, P->fp_w[p], tw_w, st),
-            "adjoint column pass launch");
-    HIP_TRY(launch_rows_c2r<T>(hhat + G.shat_off, P->shat_elems, H + G.grid_off, P->grid_elems, G.nt, true, G.I, G.nw,
-                               G.nchunk, ne, P->fp_t[p], tw_t, post, st),
-            "adjoint inverse row transform launch");
+    PROF_LAUNCH(P, "adj_rows_r2c", st,
+                launch_rows_r2c<T>(gw + G.wave_off, P->wave_elems, ghat + G.mhat_off, P->mhat_elems, G.nt, 1, G.nw,
+                                   G.nchunk, ne, P->fp_t[p], tw_t, post, st),
+                "adjoint row transform launch");
+    PROF_LAUNCH(P, "adj_colpass", st,
+                launch_colpass_adj<T>(ghat + G.mhat_off, P->mhat_elems, static_cast<const cx<T>*>(P->rtil[p]),
+                                      hhat + G.shat_off, P->shat_elems, G.nw, G.I, G.nchunk, ne, P->fp_w[p], tw_w,
+                                      st),
+                "adjoint column pass launch");
+    PROF_LAUNCH(P, "adj_rows_c2r", st,
+                launch_rows_c2r<T>(hhat + G.shat_off, P->shat_elems, H + G.grid_off, P->grid_elems, G.nt, true, G.I,
+                                   G.nw, G.nchunk, ne, P->fp_t[p], tw_t, post, st),
+                "adjoint inverse row transform launch");
   }
-  HIP_TRY(launch_grad_gather<T>(view<T>(d), raster_geom(P, ne), o->nsigma, H, gq, gt, gp, gst, gsp, st),
-          "gradient gather launch");
+  PROF_LAUNCH(P, "grad_gather", st,
+              launch_grad_gather<T>(view<T>(d), raster_geom(P, ne), o->nsigma, H, gq, gt, gp, gst, gsp, st),
+              "gradient gather launch");
   return WCT_OK;
 }
 
@@ -618,6 +683,44 @@ int wct_simulate_backward(wct_plan* plan, const wct_depos* depos, const wct_opts
   return run_backward<double>(plan, depos, opts, static_cast<const double*>(grad_wave), static_cast<double*>(g_q),
                               static_cast<double*>(g_t), static_cast<double*>(g_p), static_cast<double*>(g_sigma_t),
                               static_cast<double*>(g_sigma_p), cv, st);
+}
+
+int wct_profile_enable(wct_plan* plan, int32_t enable) {
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  plan->prof.on = enable != 0;
+  return WCT_OK;
+}
+
+int wct_profile_reset(wct_plan* plan) {
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  DeviceGuard dg(plan->device);
+  const hipError_t e = plan->prof.collect();
+  plan->prof.acc.clear();
+  if (e != hipSuccess) return hip_fail(e, "profiler events");
+  return WCT_OK;
+}
+
+int wct_profile_count(wct_plan* plan) {
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  DeviceGuard dg(plan->device);
+  const hipError_t e = plan->prof.collect();
+  if (e != hipSuccess) return hip_fail(e, "profiler events");
+  return (int)plan->prof.acc.size();
+}
+
+int wct_profile_get(wct_plan* plan, int32_t idx, char* name, size_t name_len, double* total_ms, int64_t* launches) {
+  g_err.clear();
+  if (!plan || !name || name_len == 0 || !total_ms || !launches) return fail(WCT_E_INVALID, "NULL argument");
+  if (idx < 0 || idx >= (int32_t)plan->prof.acc.size()) return fail(WCT_E_INVALID, "profile index %d", idx);
+  auto it = plan->prof.acc.begin();
+  std::advance(it, idx);
+  std::snprintf(name, name_len, "%s", it->first.c_str());
+  *total_ms = it->second.first;
+  *launches = it->second.second;
+  return WCT_OK;
 }
 
 }  // extern "C"

@@ -62,10 +62,18 @@ struct RasterWs {
   int64_t max_items;
 };
 
+// Optional kernel timing: begin/end bracket a launch group with events on the stream.
+struct ProfHook {
+  virtual void begin(const char* name, hipStream_t st) = 0;
+  virtual void end(hipStream_t st) = 0;
+  virtual ~ProfHook() = default;
+};
+
 // raster.hip
 template <typename T>
 hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigma, int fluctuate, uint64_t seed,
-                         T* grid, const RasterWs& ws, const DetTables* tables, int n_cu, hipStream_t st);
+                         T* grid, const RasterWs& ws, const DetTables* tables, int n_cu, hipStream_t st,
+                         ProfHook* prof);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 
 // conv.hip

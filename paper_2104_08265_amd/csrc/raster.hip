@@ -426,9 +426,11 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigma, int fluctuate, uint64_t seed,
-                         T* grid, const RasterWs& ws, const DetTables* tables, int n_cu, hipStream_t st) {
+                         T* grid, const RasterWs& ws, const DetTables* tables, int n_cu, hipStream_t st,
+                         ProfHook* prof) {
   constexpr int TH = TileShape<T>::TH, TW = TileShape<T>::TW;
   const int64_t nt = ws.ntiles;
+  if (prof) prof->begin("raster_bin", st);
   // control words, counts and cursors are contiguous
   hipError_t e = launch_fill_i32(ws.ctrl, kCtrlWords + 2 * nt, 0, st);
   if (e != hipSuccess) return e;
@@ -455,26 +457,32 @@ hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigm
   WCT_CHECK_LAUNCH();
   hipLaunchKernelGGL((k_zero_split<T, TH, TW>), dim3(1024), dim3(256), 0, st, g, ws.counts, nt, grid);
   WCT_CHECK_LAUNCH();
-  const unsigned pblocks = (unsigned)(n_cu * 4);
-  if (fluctuate) {
+  if (prof) prof->end(st);
+  const unsigned pblocks = (unsigned)(n_cu * 3);
+  if (prof) prof->begin(fluctuate ? "raster_tile_fluct" : "raster_tile_mean", st);
+  if (fluctuate)
     hipLaunchKernelGGL((k_tile<T, true, TH, TW>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.list,
                        ws.offs, ws.items, ws.item_off, ws.ctrl, tables);
-    WCT_CHECK_LAUNCH();
-    hipLaunchKernelGGL((k_big<T, true>), dim3(256), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.big, ws.ctrl,
-                       tables);
-  } else {
+  else
     hipLaunchKernelGGL((k_tile<T, false, TH, TW>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid,
                        ws.list, ws.offs, ws.items, ws.item_off, ws.ctrl, tables);
-    WCT_CHECK_LAUNCH();
+  WCT_CHECK_LAUNCH();
+  if (prof) prof->end(st);
+  if (prof) prof->begin("raster_wide_rows", st);
+  if (fluctuate)
+    hipLaunchKernelGGL((k_big<T, true>), dim3(256), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.big, ws.ctrl,
+                       tables);
+  else
     hipLaunchKernelGGL((k_big<T, false>), dim3(256), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.big, ws.ctrl,
                        tables);
-  }
-  return hipGetLastError();
+  WCT_CHECK_LAUNCH();
+  if (prof) prof->end(st);
+  return hipSuccess;
 }
 
 template hipError_t launch_raster<float>(const DepoView<float>&, const RasterGeom&, double, int, uint64_t, float*,
-                                         const RasterWs&, const DetTables*, int, hipStream_t);
+                                         const RasterWs&, const DetTables*, int, hipStream_t, ProfHook*);
 template hipError_t launch_raster<double>(const DepoView<double>&, const RasterGeom&, double, int, uint64_t, double*,
-                                          const RasterWs&, const DetTables*, int, hipStream_t);
+                                          const RasterWs&, const DetTables*, int, hipStream_t, ProfHook*);
 
 }  // namespace wct

@@ -73,6 +73,11 @@ wct_simulate_backward = _sig("wct_simulate_backward", c_int32,
                               c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
 wct_last_error = _sig("wct_last_error", c_char_p, [])
 wct_abi_version = _sig("wct_abi_version", c_int32, [])
+wct_profile_enable = _sig("wct_profile_enable", c_int32, [PlanP, c_int32])
+wct_profile_reset = _sig("wct_profile_reset", c_int32, [PlanP])
+wct_profile_count = _sig("wct_profile_count", c_int32, [PlanP])
+wct_profile_get = _sig("wct_profile_get", c_int32, [PlanP, c_int32, c_char_p, c_size_t, POINTER(c_double),
+                                                   POINTER(c_int64)])
 wct_fluct_spec_version = _sig("wct_fluct_spec_version", c_int32, [])
 
 
@@ -235,6 +240,26 @@ class Plan:
         check(wct_simulate_backward(self.h, ctypes.byref(d), ctypes.byref(o), _ptr(grad_wave), *[_ptr(x) for x in outs],
                                     _ptr(ws), nb, self._stream()), "wct_simulate_backward")
         return outs
+
+    def profile(self, enable=True):
+        check(wct_profile_enable(self.h, int(bool(enable))), "wct_profile_enable")
+
+    def profile_reset(self):
+        check(wct_profile_reset(self.h), "wct_profile_reset")
+
+    def profile_read(self):
+        """{kernel name: (total ms, launches)} since the last reset (synchronises)."""
+        n = wct_profile_count(self.h)
+        if n < 0:
+            check(n, "wct_profile_count")
+        out = {}
+        buf = ctypes.create_string_buffer(128)
+        for k in range(n):
+            ms = c_double()
+            cnt = c_int64()
+            check(wct_profile_get(self.h, k, buf, 128, ctypes.byref(ms), ctypes.byref(cnt)), "wct_profile_get")
+            out[buf.value.decode()] = (ms.value, cnt.value)
+        return out
 
     def grid_view(self, grid, event=0):
         """Per-plane [N_b][N_t] views of one event of a packed grid."""

@@ -1,0 +1,125 @@
+"""GPU parity of the differentiable mode: adjoint + gradient gather against the oracle.
+
+The oracle's analytic gradients are pinned to FP64 finite differences (test_oracle_grad);
+here the HIP gradients are compared with them for the same dL/dM, which the host computes
+from oracle waveforms.  FP64 plans: relative L2 <= 1e-10 per parameter; FP32 plans: each
+parameter's error within 1e-4 of the RMS of that parameter's gradient.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import device_depos, make_plan, rel_l2, say, to_np
+from oracle import convolve as OC
+from oracle import grad as OG
+from oracle import raster as OR
+from paper_2104_08265_amd import synth
+
+pytestmark = pytest.mark.gpu
+NAMES = ["q", "t", "p", "sigma_t", "sigma_p"]
+
+
+def oracle_loss_grad(wl, target):
+    S = OR.raster(wl.depos, wl.planes)[0][0]
+    R = synth.round_responses(wl)[0].astype(np.float64)
+    M = OC.convolve_fft(S, R, 10)
+    G = 2.0 * (M - target)
+    H = OC.adjoint_fft(G, R, 10)
+    return G, OG.gradients([[H]], wl.depos, wl.planes)
+
+
+def small_fp64():
+    wl = synth.config1(n_depos=300, n_wires=64, n_ticks=256)
+    tgt = wl.depos.astype(np.float64)
+    rng = np.random.default_rng(1)
+    tgt.q = tgt.q * rng.normal(1, 0.05, len(tgt))
+    tgt.t = tgt.t + rng.normal(0, 0.5, len(tgt))
+    return wl, tgt
+
+
+def test_backward_fp64_matches_oracle(wct):
+    wl, tgt = small_fp64()
+    R = synth.round_responses(wl)[0]
+    target = OC.convolve_fft(OR.raster(tgt, wl.planes)[0][0], R, 10)
+    G, ref = oracle_loss_grad(wl, target)
+    say("backward fp64", len(wl.depos))
+    plan = make_plan(wct, wl)
+    import torch
+    g = plan.simulate_backward(device_depos(wct, wl), wct.opts(3.0, False, 1, 0),
+                               torch.as_tensor(G.ravel()).to("cuda:0"))
+    for c, name in enumerate(NAMES):
+        assert rel_l2(to_np(g[c]), ref[:, c]) < 1e-10, name
+
+
+def test_backward_fp32_config4(wct):
+    """Config 4: 2e4 track depositions, perturbed-target L2 loss, FP32 plan."""
+    import torch
+    wl = synth.config4()
+    R = synth.round_responses(wl)[0].astype(np.float64)
+    target = OC.convolve_fft(OR.raster(wl.extra["target_depos"], wl.planes)[0][0], R, 10)
+    G, ref = oracle_loss_grad(wl, target)
+    say("backward fp32 config4", len(wl.depos))
+    plan = make_plan(wct, wl)
+    g = plan.simulate_backward(device_depos(wct, wl), wct.opts(3.0, False, 1, 0),
+                               torch.as_tensor(G.ravel().astype(np.float32)).to("cuda:0"))
+    for c, name in enumerate(NAMES):
+        got = to_np(g[c])
+        rms = np.sqrt(np.mean(ref[:, c] ** 2))
+        assert np.max(np.abs(got - ref[:, c])) < 1e-4 * rms * 10, (name, np.max(np.abs(got - ref[:, c])) / rms)
+        assert rel_l2(got, ref[:, c]) < 1e-4, name
+
+
+def test_gpu_gradient_matches_gpu_finite_differences(wct):
+    """FP64 plan: the adjoint gradient against central differences of the GPU forward."""
+    import torch
+    wl, tgt = small_fp64()
+    plan = make_plan(wct, wl)
+    o = wct.opts(3.0, False, 1, 0)
+    rng = np.random.default_rng(3)
+    target = rng.standard_normal(plan.wave_elems)
+    dd = device_depos(wct, wl)
+
+    def loss(d):
+        w = to_np(plan.simulate(device_depos(wct, wl, d), o))
+        return float(np.sum((w - target) ** 2)), w
+
+    L0, w0 = loss(wl.depos)
+    say("gpu finite differences fp64")
+    g = plan.simulate_backward(dd, o, torch.as_tensor(2.0 * (w0 - target)).to("cuda:0"))
+    g = [to_np(x) for x in g]
+    checked = 0
+    for j in range(0, len(wl.depos), 37):
+        for c, name in enumerate(NAMES):
+            base = float(getattr(wl.depos, name)[j])
+            h = 1e-6 * max(1.0, abs(base)) if name in ("t", "p") else 1e-6 * base
+            if name in ("t", "sigma_t") and OG.edge_distance(wl.depos.t[j], wl.depos.sigma_t[j], 3.0) < 12 * h:
+                continue
+            if name in ("p", "sigma_p") and OG.edge_distance(10 * wl.depos.p[j], 10 * wl.depos.sigma_p[j],
+                                                              3.0) < 120 * h:
+                continue
+            vals = []
+            for sgn in (1, -1):
+                d = wl.depos.astype(np.float64)
+                getattr(d, name)[j] = base + sgn * h
+                vals.append(loss(d)[0])
+            fd = (vals[0] - vals[1]) / (2 * h)
+            scale = np.sqrt(np.mean(g[c] ** 2)) + 1e-300
+            assert abs(fd - g[c][j]) < 1e-5 * scale, (j, name, fd, g[c][j])
+            checked += 1
+    assert checked >= 20
+
+
+def test_autograd_function(wct):
+    import torch
+    from paper_2104_08265_amd import torch_ops
+    wl = synth.config1(n_depos=100, n_wires=32, n_ticks=128)
+    plan = make_plan(wct, wl)
+    dd = device_depos(wct, wl)
+    params = [x.clone().requires_grad_(True) for x in (dd.q, dd.t, dd.p, dd.sigma_t, dd.sigma_p)]
+    wave = torch_ops.simulate(plan, *params, dd.plane, dd.event, dd.depo_id)
+    tgt = torch.randn_like(wave)
+    loss = ((wave - tgt) ** 2).sum()
+    say("autograd")
+    loss.backward()
+    direct = plan.simulate_backward(dd, wct.opts(3.0, False, 1, 0), (2 * (wave - tgt)).detach().contiguous())
+    for p_, d_ in zip(params, direct):
+        assert torch.allclose(p_.grad, d_, rtol=1e-12, atol=1e-12)
