@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "fftplan.hpp"
 #include "kernels.hpp"
 #include "wct.h"
 
@@ -60,44 +61,6 @@ int64_t next_smooth(int64_t n) {
   if (n < 1) n = 1;
   while (!smooth235(n)) ++n;
   return n;
-}
-
-// exp(-2 pi i m / n) with the angle reduced exactly and evaluated in long double.
-cx<double> wexp(int64_t m, int64_t n) {
-  m %= n;
-  if (m < 0) m += n;
-  const long double a = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)n;
-  return mk((double)cosl(a), (double)sinl(a));
-}
-
-bool build_fft(int n, FftPlan& fp, std::vector<cx<double>>& tw) {
-  std::memset(&fp, 0, sizeof(fp));
-  fp.n = n;
-  int a = 0, b = 0, c = 0, r = n;
-  while (r % 2 == 0) r /= 2, ++a;
-  while (r % 3 == 0) r /= 3, ++b;
-  while (r % 5 == 0) r /= 5, ++c;
-  if (r != 1) return false;
-  std::vector<int> rad;
-  while (a >= 3) rad.push_back(8), a -= 3;
-  if (a == 2) rad.push_back(4);
-  if (a == 1) rad.push_back(2);
-  for (int k = 0; k < c; ++k) rad.push_back(5);
-  for (int k = 0; k < b; ++k) rad.push_back(3);
-  if ((int)rad.size() > kMaxPass) return false;
-  tw.clear();
-  int Ns = 1;
-  fp.npass = (int)rad.size();
-  for (int p = 0; p < fp.npass; ++p) {
-    const int R = rad[p];
-    fp.radix[p] = R;
-    fp.tw_off[p] = (int)tw.size();
-    for (int k = 0; k < Ns; ++k)
-      for (int q = 1; q < R; ++q) tw.push_back(wexp((int64_t)q * k, (int64_t)Ns * R));
-    Ns *= R;
-  }
-  if (tw.empty()) tw.push_back(mk(1.0, 0.0));
-  return true;
 }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -400,7 +363,7 @@ int plan_tables(wct_plan* P, const wct_plan_desc* desc) {
       return fail(WCT_E_UNSUPPORTED, "plane %d: wire transform length %d exceeds the LDS-resident limit", p, G.lw);
     std::vector<cx<double>> tw;
     FftPlan fp;
-    if (!build_fft(G.M, fp, tw)) return fail(WCT_E_UNSUPPORTED, "plane %d: length %d not 2,3,5-smooth", p, G.M);
+    if (!build_fft(G.M, 0, fp, tw)) return fail(WCT_E_UNSUPPORTED, "plane %d: length %d not 2,3,5-smooth", p, G.M);
     P->fp_t.push_back(fp);
     void* d = nullptr;
     int rc = upload_table<T>(P, tw, &d);
@@ -411,7 +374,7 @@ int plan_tables(wct_plan* P, const wct_plan_desc* desc) {
     rc = upload_table<T>(P, post, &d);
     if (rc) return rc;
     P->post_t.push_back(d);
-    if (!build_fft(G.lw, fp, tw)) return fail(WCT_E_UNSUPPORTED, "plane %d: length %d not 2,3,5-smooth", p, G.lw);
+    if (!build_fft(G.lw, 0, fp, tw)) return fail(WCT_E_UNSUPPORTED, "plane %d: length %d not 2,3,5-smooth", p, G.lw);
     P->fp_w.push_back(fp);
     rc = upload_table<T>(P, tw, &d);
     if (rc) return rc;

@@ -56,7 +56,7 @@ struct FftPlan {
 // Stockham pass in registers without spilling.
 template <typename T, int E>
 struct LaunchBound {
-  static constexpr int value = E <= 8 ? 1024 : 512;
+  static constexpr int value = (E <= 8 && sizeof(T) == 4) ? 1024 : 512;
 };
 
 // Layout constants of the frequency-domain work arrays.

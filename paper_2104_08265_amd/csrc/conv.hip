@@ -203,7 +203,7 @@ static int pick_e(int elems) {
   const int ncand = sizeof(T) == 4 ? 4 : 2;
   for (int k = 0; k < ncand; ++k) {
     const int e = cands[k];
-    const int bound = e <= 8 ? LaunchBound<T, 8>::value : LaunchBound<T, 16>::value;
+    const int bound = e <= 8 ? LaunchBound<T, 8>::value : LaunchBound<T, 16>::value;  // mirrors the kernels
     if ((elems + e - 1) / e <= bound) return e;
   }
   return 0;
