@@ -114,6 +114,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward-ratio measurement")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run 3 plain device copies of this many MiB (a known-size reference for "
+                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); events and planes shard "
@@ -122,6 +125,15 @@ def main():
         sys.exit(2)
     import torch
     from paper_2104_08265_amd import synth, wct
+
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     wl = synth.config2()
     plan = wct.Plan(wl.planes, synth.round_responses(wl), dtype="f32")

@@ -48,7 +48,7 @@ extern "C" {
 #define WCT_ABI_VERSION 1
 /* Version of the fluctuation draw stream (counter layout + sampler).  Bumped whenever a
  * change would alter any fluctuated count for the same inputs and seed. */
-#define WCT_FLUCT_SPEC_VERSION 1
+#define WCT_FLUCT_SPEC_VERSION 2
 
 typedef struct wct_plan wct_plan;
 
@@ -131,9 +131,11 @@ size_t wct_workspace_bytes(const wct_plan* plan, int32_t op, int32_t n_events, i
  * A_b, B_k are the Gaussian's integrals over the parts of impact row b and tick k that
  * lie inside mu +- nsigma*sigma (u = I*p, sigma_u = I*sigma_p on the impact axis).
  * Cells outside the grid are dropped.  With fluctuate = 1 each cell instead receives an
- * independent Binomial(floor(Q+1/2), A_b*B_k) count drawn from Philox4x32-10 with
- * counter (b*N_t + k, depo_id, event, plane << 24) and key `seed`, by the sampler of
- * WCT_FLUCT_SPEC_VERSION (bit-reproducible, independent of scheduling).  Rows with
+ * independent Binomial(floor(Q+1/2), A_b*B_k) count drawn from Philox4x32-10 with key
+ * `seed`; cells (b, 2m) and (b, 2m+1) share the counter (b*ceil(N_t/2) + m, depo_id,
+ * event, plane << 24), the even tick taking words 0-1 and the odd tick words 2-3; the
+ * sampler is that of WCT_FLUCT_SPEC_VERSION (bit-reproducible, independent of
+ * scheduling).  Rows with
  * sigma <= 0, Q < 0 or non-finite values contribute nothing.  The whole grid of every
  * event in [0, n_events) is overwritten. */
 int wct_raster(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* grid, void* ws,

@@ -10,8 +10,10 @@ It fixes neither the generator nor the sampler.  This module takes the reading:
   p_bk = A_b * B_k, the product of the two clipped axis integrals (no renormalisation,
   so E[n_bk] equals the mean raster for integer Q);
 * the uniform variate of cell (b, k) comes from the counter-based generator
-  Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11) keyed by the run seed, with the
-  counter (b*N_t + k, depo_id, event, plane << 24);
+  Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11) keyed by the run seed; the two
+  cells (b, 2m) and (b, 2m+1) share the block with counter
+  (b*ceil(N_t/2) + m, depo_id, event, plane << 24), the even tick using output words
+  0-1 and the odd tick words 2-3 (draw-stream version 2);
 * the variate is mapped to a count by a fixed two-regime sampler (inversion from 0
   when N*p' < 10, otherwise a chop-down search centred on the mode), where
   p' = min(p, 1-p).
@@ -35,7 +37,7 @@ import math
 
 import numpy as np
 
-from .raster import window
+from .raster import rows_touching, window
 
 # ---------------------------------------------------------------------------
 # Philox4x32-10 (Salmon et al., SC'11): 10 rounds, two 32x32->64 multiplies per round,
@@ -77,14 +79,19 @@ def uniform53(w0, w1):
     return (a * 134217728.0 + b) * (2.0 ** -53)
 
 
-def cell_uniform(seed, plane, event, depo_id, cell):
-    """Uniform variate of one cell: counter (cell, depo_id, event, plane<<24), key = seed."""
-    cell = np.asarray(cell, np.uint64)
-    c1 = np.asarray(depo_id, np.uint64) + np.zeros_like(cell)
-    c2 = np.asarray(event, np.uint64) + np.zeros_like(cell)
-    c3 = (np.asarray(plane, np.uint64) << np.uint64(24)) + np.zeros_like(cell)
-    w0, w1, _, _ = philox4x32_10(cell, c1, c2, c3, int(seed) & MASK32, (int(seed) >> 32) & MASK32)
-    return uniform53(w0, w1)
+def cell_uniform(seed, plane, event, depo_id, b, k, n_ticks):
+    """Uniform variate of cell (b, k): the block of counter
+    (b*ceil(N_t/2) + floor(k/2), depo_id, event, plane << 24) under key = seed, words 0-1
+    for even k and words 2-3 for odd k."""
+    b = np.asarray(b, np.int64)
+    k = np.asarray(k, np.int64)
+    b, k = np.broadcast_arrays(b, k)
+    c0 = (b * ((int(n_ticks) + 1) // 2) + (k >> 1)).astype(np.uint64)
+    c1 = np.asarray(depo_id, np.uint64) + np.zeros_like(c0)
+    c2 = np.asarray(event, np.uint64) + np.zeros_like(c0)
+    c3 = (np.asarray(plane, np.uint64) << np.uint64(24)) + np.zeros_like(c0)
+    w0, w1, w2, w3 = philox4x32_10(c0, c1, c2, c3, int(seed) & MASK32, (int(seed) >> 32) & MASK32)
+    return np.where((k & 1) == 1, uniform53(w2, w3), uniform53(w0, w1))
 
 
 # ---------------------------------------------------------------------------
@@ -167,29 +174,35 @@ MU_SWITCH = 10.0
 INVERSION_CAP = 128
 
 
-def _pow_int(q, n: int):
-    """q^n by left-to-right square-and-multiply over the bits of n (n >= 1)."""
+def _pow_int(q, n):
+    """q^n by left-to-right square-and-multiply over the bits of n (n >= 1, scalar or per element).
+
+    Leading zero bits square 1.0, which is exact, so every element sees exactly the
+    squarings and multiplications of its own bits.
+    """
+    n = np.broadcast_to(np.asarray(n, np.int64), q.shape)
     f = np.ones_like(q)
-    for bit in bin(int(n))[2:]:
+    for bit in range(int(n.max()).bit_length() - 1, -1, -1):
         f = f * f
-        if bit == "1":
-            f = f * q
+        on = ((n >> bit) & 1) == 1
+        f = np.where(on, f * q, f)
     return f
 
 
-def _inversion(N: int, pp, q, u):
+def _inversion(N, pp, q, u):
     f = _pow_int(q, N)
     r = pp / q
     F = f.copy()
     k = np.zeros(u.shape, np.int64)
-    cap = min(N, INVERSION_CAP)
+    cap = np.minimum(N, INVERSION_CAP)
+    inv = np.array(INV_INT)
     active = u >= F
     while np.any(active):
         act = active & (k < cap)
         if not np.any(act):
             break
         kk = k[act]
-        fa = (f[act] * (r[act] * (N - kk).astype(np.float64))) * np.array(INV_INT)[kk + 1]
+        fa = (f[act] * (r[act] * (N[act] - kk).astype(np.float64))) * inv[kk + 1]
         f[act] = fa
         k[act] = kk + 1
         F[act] = F[act] + fa
@@ -197,11 +210,11 @@ def _inversion(N: int, pp, q, u):
     return k
 
 
-def _chopdown(N: int, pp, q, u):
-    Nf = float(N)
+def _chopdown(N, pp, q, u):
+    Nf = N.astype(np.float64)
     m = np.floor((Nf + 1.0) * pp).astype(np.int64)
     m = np.minimum(m, N)
-    x = det_lfact(np.full(m.shape, N)) - det_lfact(m) - det_lfact(N - m) \
+    x = det_lfact(N) - det_lfact(m) - det_lfact(N - m) \
         + m.astype(np.float64) * det_log(pp) + (N - m).astype(np.float64) * det_log(q)
     Pm = det_exp(x)
     v = u - Pm
@@ -218,7 +231,7 @@ def _chopdown(N: int, pp, q, u):
         s = act & (lo > 0) & (plo > 0.0)
         if np.any(s):
             lf = lo[s].astype(np.float64)
-            plo[s] = plo[s] * (lf * q[s]) / ((N - lo[s] + 1).astype(np.float64) * pp[s])
+            plo[s] = plo[s] * (lf * q[s]) / ((N[s] - lo[s] + 1).astype(np.float64) * pp[s])
             lo[s] -= 1
             v[s] = v[s] - plo[s]
             moved |= s
@@ -229,7 +242,7 @@ def _chopdown(N: int, pp, q, u):
         s = act & ~done & (hi < N) & (phi > 0.0)
         if np.any(s):
             hf = hi[s].astype(np.float64)
-            phi[s] = phi[s] * ((N - hi[s]).astype(np.float64) * pp[s]) / ((hf + 1.0) * q[s])
+            phi[s] = phi[s] * ((N[s] - hi[s]).astype(np.float64) * pp[s]) / ((hf + 1.0) * q[s])
             hi[s] += 1
             v[s] = v[s] - phi[s]
             moved |= s
@@ -243,31 +256,32 @@ def _chopdown(N: int, pp, q, u):
     return out
 
 
-def binomial(N: int, p, u):
-    """Counts k ~ Binomial(N, p) for arrays p, u in [0, 1), one shared N >= 0."""
+def binomial(N, p, u):
+    """Counts k ~ Binomial(N, p) for arrays p, u in [0, 1) and N >= 0 (scalar or per element)."""
     p = np.asarray(p, np.float64)
     u = np.asarray(u, np.float64)
+    N = np.broadcast_to(np.asarray(N, np.int64), p.shape).copy()
     k = np.zeros(p.shape, np.int64)
-    if N <= 0:
-        return k
-    full = p >= 1.0
-    k[full] = N
-    live = (p > 0.0) & ~full
+    pos = N > 0
+    full = pos & (p >= 1.0)
+    k[full] = N[full]
+    live = pos & (p > 0.0) & ~full
     if not np.any(live):
         return k
     pl = p[live]
+    Nl = N[live]
     flip = pl > 0.5
     pp = np.where(flip, 1.0 - pl, pl)
     q = 1.0 - pp
-    mu = float(N) * pp
+    mu = Nl.astype(np.float64) * pp
     ul = u[live]
     kl = np.zeros(pl.shape, np.int64)
     small = mu < MU_SWITCH
     if np.any(small):
-        kl[small] = _inversion(N, pp[small], q[small], ul[small])
+        kl[small] = _inversion(Nl[small], pp[small], q[small], ul[small])
     if np.any(~small):
-        kl[~small] = _chopdown(N, pp[~small], q[~small], ul[~small])
-    k[live] = np.where(flip, N - kl, kl)
+        kl[~small] = _chopdown(Nl[~small], pp[~small], q[~small], ul[~small])
+    k[live] = np.where(flip, Nl - kl, kl)
     return k
 
 
@@ -280,13 +294,16 @@ def electrons(q) -> int:
 # fluctuated raster
 # ---------------------------------------------------------------------------
 
-def det_axis_probs(mu: float, sigma: float, nsigma: float, n_bins: int):
+def det_axis_probs(mu: float, sigma: float, nsigma: float, n_bins: int, keep_lo: int = 0, keep_hi: int | None = None):
     """Clipped axis integrals with det_erf: bins in [0, n_bins) and their probabilities.
 
     Edge values: d = edge - mu, x = d / (sigma * sqrt2), weight = 0.5*(erf(x_hi) - erf(x_lo)).
+    keep_lo/keep_hi optionally restrict the bins returned (each bin's value depends only on
+    its own edges, so a restricted evaluation returns the same values).
     """
     lo, hi, k0, k1 = window(mu, sigma, nsigma)
-    ks = np.arange(max(k0, 0), min(k1, n_bins), dtype=np.int64)
+    keep_hi = n_bins if keep_hi is None else min(keep_hi, n_bins)
+    ks = np.arange(max(k0, 0, keep_lo), min(k1, keep_hi), dtype=np.int64)
     if ks.size == 0:
         return ks, np.zeros(0)
     elo = np.maximum(ks.astype(np.float64), lo)
@@ -296,17 +313,20 @@ def det_axis_probs(mu: float, sigma: float, nsigma: float, n_bins: int):
 
 
 def fluct_patch(q, t, p, sigma_t, sigma_p, plane, event, depo_id, n_impacts, n_rows, n_ticks, seed,
-                nsigma=3.0):
-    """Counts of one depo-plane row: (rows, ticks, n[b, k]) as int64."""
+                nsigma=3.0, box=None):
+    """Counts of one depo-plane row: (rows, ticks, n[b, k]) as int64.
+
+    box = (b_lo, b_hi, k_lo, k_hi) restricts the evaluation to those cells (same values).
+    """
     q, t, p, st, sp = (float(v) for v in (q, t, p, sigma_t, sigma_p))
     N = electrons(q)
-    rows, a = det_axis_probs(n_impacts * p, n_impacts * sp, nsigma, n_rows)
-    ticks, b = det_axis_probs(t, st, nsigma, n_ticks)
+    b_lo, b_hi, k_lo, k_hi = box if box is not None else (0, None, 0, None)
+    rows, a = det_axis_probs(n_impacts * p, n_impacts * sp, nsigma, n_rows, b_lo, b_hi)
+    ticks, b = det_axis_probs(t, st, nsigma, n_ticks, k_lo, k_hi)
     if rows.size == 0 or ticks.size == 0 or N == 0:
         return rows, ticks, np.zeros((rows.size, ticks.size), np.int64)
     prob = a[:, None] * b[None, :]
-    cell = rows[:, None] * n_ticks + ticks[None, :]
-    u = cell_uniform(seed, plane, event, depo_id, cell.ravel()).reshape(prob.shape)
+    u = cell_uniform(seed, plane, event, depo_id, rows[:, None], ticks[None, :], n_ticks)
     return rows, ticks, binomial(N, prob, u)
 
 
@@ -327,27 +347,52 @@ def raster_fluct(depos, planes, seed, nsigma=3.0, n_events=1):
 
 
 def raster_fluct_at(depos, plane_idx, plane, rows, ticks, seed, nsigma=3.0, event=0):
-    """Fluctuated counts at selected cells of one plane (sampled checks of full-size grids)."""
+    """Fluctuated counts at selected cells of one plane (sampled checks of full-size grids).
+
+    Evaluated for all (row, cell) pairs of the cells' bounding box at once; per element the
+    operations are those of ``fluct_patch`` (pinned against the full raster in the tests).
+    """
     rows = np.asarray(rows, np.int64)
     ticks = np.asarray(ticks, np.int64)
     out = np.zeros(rows.size, np.int64)
-    sel = np.nonzero((depos.plane == plane_idx) & (depos.event == event))[0]
+    if rows.size == 0:
+        return out
+    b_lo, b_hi, k_lo, k_hi = int(rows.min()), int(rows.max()) + 1, int(ticks.min()), int(ticks.max()) + 1
+    sel = rows_touching(depos, plane_idx, plane, b_lo, b_hi, k_lo, k_hi, nsigma, event)
+    if sel.size == 0:
+        return out
     I = plane.n_impacts
-    for j in sel:
-        q, t, p, st, sp = (float(v) for v in (depos.q[j], depos.t[j], depos.p[j], depos.sigma_t[j],
-                                                depos.sigma_p[j]))
-        _, _, b0, b1 = window(I * p, I * sp, nsigma)
-        _, _, k0, k1 = window(t, st, nsigma)
-        hit = np.nonzero((rows >= b0) & (rows < b1) & (ticks >= k0) & (ticks < k1))[0]
-        if hit.size == 0:
-            continue
-        rr, kk, cnt = fluct_patch(q, t, p, st, sp, plane_idx, event, int(depos.depo_id[j]), I, plane.n_rows,
-                                  plane.n_ticks, seed, nsigma)
-        if rr.size == 0 or kk.size == 0:
-            continue
-        for h in hit:
-            ri = np.searchsorted(rr, rows[h])
-            ki = np.searchsorted(kk, ticks[h])
-            if ri < rr.size and rr[ri] == rows[h] and ki < kk.size and kk[ki] == ticks[h]:
-                out[h] += cnt[ri, ki]
-    return out
+    nb, nk = b_hi - b_lo, k_hi - k_lo
+    # every (row, cell of the box) pair; cells outside a row's window get probability 0
+    jj = np.repeat(sel, nb * nk)
+    bb = np.tile(np.repeat(np.arange(b_lo, b_hi), nk), sel.size)
+    kk = np.tile(np.tile(np.arange(k_lo, k_hi), nb), sel.size)
+    q = depos.q[jj].astype(np.float64)
+    t = depos.t[jj].astype(np.float64)
+    p = depos.p[jj].astype(np.float64)
+    st = depos.sigma_t[jj].astype(np.float64)
+    sp = depos.sigma_p[jj].astype(np.float64)
+    u = float(I) * p
+    su = float(I) * sp
+
+    def probs(mu, sigma, cell):
+        half = nsigma * sigma
+        lo = mu - half
+        hi = mu + half
+        inside = (cell >= np.floor(lo)) & (cell < np.ceil(hi)) & (cell >= 0)
+        elo = np.maximum(cell.astype(np.float64), lo)
+        ehi = np.minimum(cell.astype(np.float64) + 1.0, hi)
+        s2 = sigma * SQRT2
+        w = 0.5 * (det_erf((ehi - mu) / s2) - det_erf((elo - mu) / s2))
+        return np.where(inside, w, 0.0), inside
+
+    a, ina = probs(u, su, bb)
+    b, inb = probs(t, st, kk)
+    ok = ina & inb & (bb < plane.n_rows) & (kk < plane.n_ticks)
+    N = np.floor(q + 0.5).astype(np.int64)
+    prob = a * b
+    uu = cell_uniform(seed, plane_idx, event, depos.depo_id[jj].astype(np.int64) & MASK32, bb, kk,
+                      plane.n_ticks)
+    cnt = np.where(ok, binomial(N, np.where(ok, prob, 0.0), uu), 0)
+    box = cnt.reshape(sel.size, nb, nk).sum(axis=0)
+    return box[rows - b_lo, ticks - k_lo]

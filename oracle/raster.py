@@ -77,6 +77,28 @@ def raster(depos, planes, nsigma=3.0, n_events=1):
     return grids
 
 
+def rows_touching(depos, plane_idx, plane, b_lo, b_hi, k_lo, k_hi, nsigma=3.0, event=0):
+    """Indices of the depo rows of one plane whose window meets rows [b_lo, b_hi) x ticks [k_lo, k_hi).
+
+    Window bounds are formed element-wise exactly as ``window`` forms them.
+    """
+    I = plane.n_impacts
+    m = (depos.plane == plane_idx) & (depos.event == event)
+    p = depos.p.astype(np.float64)
+    sp = depos.sigma_p.astype(np.float64)
+    t = depos.t.astype(np.float64)
+    st = depos.sigma_t.astype(np.float64)
+    u = float(I) * p
+    hu = nsigma * (float(I) * sp)
+    ht = nsigma * st
+    b0 = np.floor(u - hu)
+    b1 = np.ceil(u + hu)
+    k0 = np.floor(t - ht)
+    k1 = np.ceil(t + ht)
+    m &= (b0 < b_hi) & (b1 > b_lo) & (k0 < k_hi) & (k1 > k_lo)
+    return np.nonzero(m)[0]
+
+
 def raster_at(depos, plane_idx, plane, rows, ticks, nsigma=3.0, event=0):
     """Mean raster value at selected cells (rows[j], ticks[j]) of one plane.
 
@@ -85,8 +107,11 @@ def raster_at(depos, plane_idx, plane, rows, ticks, nsigma=3.0, event=0):
     """
     rows = np.asarray(rows, np.int64)
     ticks = np.asarray(ticks, np.int64)
-    sel = np.nonzero((depos.plane == plane_idx) & (depos.event == event))[0]
     out = np.zeros(rows.size)
+    if rows.size == 0:
+        return out
+    sel = rows_touching(depos, plane_idx, plane, rows.min(), rows.max() + 1, ticks.min(), ticks.max() + 1,
+                        nsigma, event)
     I = plane.n_impacts
     for j in sel:
         q, t, p, st, sp = (float(v) for v in (depos.q[j], depos.t[j], depos.p[j], depos.sigma_t[j],

@@ -2,10 +2,12 @@
 // fluctuation is binomial; generating the random numbers dominated the CPU time, so
 // the generator is counter-based and inline here, with no pool and no host traffic).
 //
-// Draw stream, version WCT_FLUCT_SPEC_VERSION = 1:
+// Draw stream, version WCT_FLUCT_SPEC_VERSION = 2:
 //  * generator: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = (seed low,
-//    seed high), counter = (b*N_t + k, depo_id, event, plane << 24) for cell (b, k);
-//  * variate: u = ((w0 >> 6) * 2^27 + (w1 >> 5)) * 2^-53, exact, in [0, 1);
+//    seed high); cells (b, 2m) and (b, 2m+1) share the block with counter
+//    (b*ceil(N_t/2) + m, depo_id, event, plane << 24);
+//  * variate: u = ((x >> 6) * 2^27 + (y >> 5)) * 2^-53, exact, in [0, 1), with
+//    (x, y) = words (0, 1) for the even tick and words (2, 3) for the odd tick;
 //  * count: Binomial(N = floor(Q + 1/2), p = A_b * B_k) by inversion from 0 when
 //    N*p' < 10 (p' = min(p, 1-p)), otherwise by a chop-down search alternating below
 //    and above the mode; p > 1/2 is sampled as N minus a draw with 1-p.
@@ -162,6 +164,12 @@ __device__ __forceinline__ int64_t binomial(int64_t N, double p, double u, const
   const double pp = flip ? 1.0 - p : p;
   const double q = 1.0 - pp;
   const double mu = (double)N * pp;
+  // Shortcut with the same result: inversion returns 0 when u < F(0), the computed q^N.
+  // The rounded q is at least 1 - (p + 2^-53), so by Bernoulli's inequality the exact
+  // power of it is at least 1 - N p - N 2^-53; the square-and-multiply adds at most 128
+  // roundings (< 2e-14) and mu = N p carries < 2e-15.  Hence u below
+  // (1 - mu) - (1e-12 + 2.5e-16 N) implies u < F(0) and the inversion would return 0.
+  if (!flip && mu < kMuSwitch && u < (1.0 - mu) - (1.0e-12 + (double)N * 2.5e-16)) return 0;
   const int64_t k = mu < kMuSwitch ? binom_inversion(N, pp, q, u, tb) : binom_chopdown(N, pp, q, u, tb);
   return flip ? N - k : k;
 }

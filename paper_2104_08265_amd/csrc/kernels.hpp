@@ -36,16 +36,19 @@ enum RasterCtrl {
 constexpr int kRowsPerItem = 256;  // rows one tile work item processes at most
 constexpr int kScanPerBlock = 4096;
 
-// Raster tile shapes (rows x ticks), 32 KB of LDS each.
+// Raster tile shapes (rows x ticks), 32 KB of LDS each.  Tall tiles: a window of up to
+// 129 impact rows (sigma_p <= 2 pitches at 3 sigma) and 65 ticks spans at most 2 x 2
+// tiles, so typical rows take the tile path.  TW is even so that the tick pairs that
+// share a Philox block never straddle two tiles.
 template <typename T>
 struct TileShape;
 template <>
 struct TileShape<float> {
-  static constexpr int TH = 64, TW = 128;
+  static constexpr int TH = 128, TW = 64;
 };
 template <>
 struct TileShape<double> {
-  static constexpr int TH = 32, TW = 128;
+  static constexpr int TH = 64, TW = 64;
 };
 
 struct RasterWs {

@@ -4,7 +4,7 @@
 //
 // Scatter adding goes through LDS-privatised tiles of TH x TW cells:
 //  1. k_count    - each row counts the tiles its window overlaps (<= 4; wider rows go
-//                  to a separate list handled with global atomics, k_big);
+//                  to a separate list handled in 64 x 64 chunks with global atomics, k_big);
 //  2. scan       - exclusive prefix sums give each tile its slice of a row list and
 //                  a number of work items (ceil(rows / kRowsPerItem), at least 1);
 //  3. k_fill     - rows are written into their tiles' slices;
@@ -72,26 +72,81 @@ __device__ __forceinline__ RowWin row_window(const DepoView<T>& d, int64_t j, co
   return w;
 }
 
-// Clipped Gaussian integral over cell k: 0.5 (erf(x_hi) - erf(x_lo)), x = (edge - mu) / (sigma sqrt2).
-__device__ __forceinline__ double cell_weight(int k, double mu, double sigma, double lo, double hi) {
-  const double elo = fmax((double)k, lo);
-  const double ehi = fmin((double)k + 1.0, hi);
-  const double s2 = sigma * kSqrt2;
-  return 0.5 * (erf((ehi - mu) / s2) - erf((elo - mu) / s2));
-}
-__device__ __forceinline__ double cell_prob(int k, double mu, double sigma, double lo, double hi,
-                                            const double* __restrict__ inv) {
-  const double elo = fmax((double)k, lo);
-  const double ehi = fmin((double)k + 1.0, hi);
-  const double s2 = sigma * kSqrt2;
-  return 0.5 * (det_erf((ehi - mu) / s2, inv) - det_erf((elo - mu) / s2, inv));
-}
-
 __device__ __forceinline__ int find_plane(const RasterGeom& g, int tin) {
   int p = 0;
   for (int k = 1; k < g.n_planes; ++k)
     if (tin >= g.pl[k].tile_off) p = k;
   return p;
+}
+
+// Axis weights of cells [k0, k1) of a window (lo, hi) around mu: the Gaussian's integral
+// over each cell's part inside the window, from erf evaluated once per cell edge
+// (edge 0 = max(k0, lo), edge n = min(k1, hi), interior edges the integers between), so a
+// cell's weight is 0.5 (E(e_hi) - E(e_lo)) computed from the same doubles the oracle uses.
+template <bool FLUCT>
+__device__ __forceinline__ void axis_fill(double* __restrict__ e, double* __restrict__ wgt, int k0, int k1, double mu,
+                                          double sigma, double lo, double hi, const double* __restrict__ inv,
+                                          int lane) {
+  const int n = k1 - k0;
+  const double s2 = sigma * kSqrt2;
+  for (int x = lane; x <= n; x += 64) {
+    const double edge = x == 0 ? fmax((double)k0, lo) : (x == n ? fmin((double)k1, hi) : (double)(k0 + x));
+    e[x] = FLUCT ? det_erf((edge - mu) / s2, inv) : erf((edge - mu) / s2);
+  }
+  wave_sync();
+  for (int x = lane; x < n; x += 64) wgt[x] = 0.5 * (e[x + 1] - e[x]);
+  wave_sync();
+}
+
+// x / d for 0 <= x < 2^22 without an integer divide (float reciprocal, then corrected).
+__device__ __forceinline__ int div_small(int x, int d, float rd) {
+  int q = (int)((float)x * rd);
+  if (q * d > x) --q;
+  else if ((q + 1) * d <= x) ++q;
+  return q;
+}
+
+// One wave rasterises the cells [b0, b1) x [k0, k1) of a row and hands each nonzero
+// contribution to `add(b, k, value)`.  Fluctuated cells are drawn in tick pairs: the
+// pair (b, 2m), (b, 2m+1) shares one Philox4x32-10 block (counter b*ceil(N_t/2) + m),
+// words 0-1 for the even tick and 2-3 for the odd one.
+template <typename T, bool FLUCT, typename Add>
+__device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int k0, int k1, int nt, uint32_t did,
+                                            uint32_t ev, uint32_t plane, uint32_t key0, uint32_t key1,
+                                            double* __restrict__ sa, double* __restrict__ sb, double* __restrict__ ea,
+                                            double* __restrict__ eb, const DetTables& tb, int lane, Add add) {
+  const int nbr = b1 - b0, nkr = k1 - k0;
+  axis_fill<FLUCT>(ea, sa, b0, b1, w.u, w.su, w.ulo, w.uhi, tb.inv, lane);
+  axis_fill<FLUCT>(eb, sb, k0, k1, w.t, w.st, w.tlo, w.thi, tb.inv, lane);
+  if (!FLUCT) {
+    const float rd = 1.0f / (float)nkr;
+    for (int x = lane; x < nbr * nkr; x += 64) {
+      const int bi = div_small(x, nkr, rd), ki = x - bi * nkr;
+      add(b0 + bi, k0 + ki, (T)(w.q * (sa[bi] * sb[ki])));
+    }
+  } else {
+    const int64_t N = (int64_t)floor(w.q + 0.5);
+    if (N > 0) {
+      const int j0 = k0 >> 1, np = ((k1 - 1) >> 1) - j0 + 1;
+      const uint32_t half_nt = (uint32_t)((nt + 1) >> 1);
+      const float rd = 1.0f / (float)np;
+      for (int x = lane; x < nbr * np; x += 64) {
+        const int bi = div_small(x, np, rd), pj = x - bi * np;
+        const int b = b0 + bi, m = j0 + pj;
+        const Philox4 ph = philox4x32_10((uint32_t)b * half_nt + (uint32_t)m, did, ev, plane << 24, key0, key1);
+        const int ke = 2 * m, ko = 2 * m + 1;
+        if (ke >= k0) {
+          const int64_t n = binomial(N, sa[bi] * sb[ke - k0], uniform53(ph.w0, ph.w1), tb);
+          if (n) add(b, ke, (T)n);
+        }
+        if (ko < k1) {
+          const int64_t n = binomial(N, sa[bi] * sb[ko - k0], uniform53(ph.w2, ph.w3), tb);
+          if (n) add(b, ko, (T)n);
+        }
+      }
+    }
+  }
+  wave_sync();
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
@@ -276,6 +331,8 @@ __global__ void __launch_bounds__(256) k_tile(DepoView<T> d, RasterGeom g, doubl
   __shared__ T tile[TH * TW];
   __shared__ double s_a[NWAVE][TH];
   __shared__ double s_b[NWAVE][TW];
+  __shared__ double s_ea[NWAVE][TH + 1];
+  __shared__ double s_eb[NWAVE][TW + 1];
   __shared__ DetTables s_tb;
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -311,32 +368,10 @@ __global__ void __launch_bounds__(256) k_tile(DepoView<T> d, RasterGeom g, doubl
       const int bb0 = max(w.b0, tb0), bb1 = min(w.b1, tb0 + th);
       const int kk0 = max(w.k0, tk0), kk1 = min(w.k1, tk0 + tw);
       if (!w.ok || bb0 >= bb1 || kk0 >= kk1) continue;
-      const int nbr = bb1 - bb0, nkr = kk1 - kk0;
-      for (int x = lane; x < nbr; x += 64)
-        s_a[wv][x] = FLUCT ? cell_prob(bb0 + x, w.u, w.su, w.ulo, w.uhi, s_tb.inv)
-                           : cell_weight(bb0 + x, w.u, w.su, w.ulo, w.uhi);
-      for (int x = lane; x < nkr; x += 64)
-        s_b[wv][x] = FLUCT ? cell_prob(kk0 + x, w.t, w.st, w.tlo, w.thi, s_tb.inv)
-                           : cell_weight(kk0 + x, w.t, w.st, w.tlo, w.thi);
-      wave_sync();
-      const int64_t N = FLUCT ? (int64_t)floor(w.q + 0.5) : 0;
       const uint32_t did = d.depo_id ? (uint32_t)d.depo_id[j] : (uint32_t)j;
-      for (int x = lane; x < nbr * nkr; x += 64) {
-        const int bi = x / nkr, ki = x - (x / nkr) * nkr;
-        T val;
-        if (FLUCT) {
-          const double pr = s_a[wv][bi] * s_b[wv][ki];
-          const uint32_t cell = (uint32_t)((int64_t)(bb0 + bi) * pl.nt + (kk0 + ki));
-          const Philox4 ph = philox4x32_10(cell, did, (uint32_t)ev, (uint32_t)pi << 24, key0, key1);
-          const int64_t n = binomial(N, pr, uniform53(ph.w0, ph.w1), s_tb);
-          if (n == 0) continue;
-          val = (T)n;
-        } else {
-          val = (T)(w.q * (s_a[wv][bi] * s_b[wv][ki]));
-        }
-        atomicAdd(&tile[(bb0 + bi - tb0) * TW + (kk0 + ki - tk0)], val);
-      }
-      wave_sync();
+      patch_cells<T, FLUCT>(w, bb0, bb1, kk0, kk1, pl.nt, did, (uint32_t)ev, (uint32_t)pi, key0, key1, s_a[wv],
+                            s_b[wv], s_ea[wv], s_eb[wv], s_tb, lane,
+                            [&](int b, int k, T v) { atomicAdd(&tile[(b - tb0) * TW + (k - tk0)], v); });
     }
     __syncthreads();
     T* gp = grid + (int64_t)ev * g.grid_ev_stride + pl.grid_off;
@@ -354,15 +389,18 @@ __global__ void __launch_bounds__(256) k_tile(DepoView<T> d, RasterGeom g, doubl
   }
 }
 
-// 5. rows wider than 4 tiles: chunked, straight to global atomics ---------------
+// 5. rows wider than 4 tiles: 64 x 64 chunks per wave, straight to global atomics ------
 template <typename T, bool FLUCT>
 __global__ void __launch_bounds__(256) k_big(DepoView<T> d, RasterGeom g, double nsigma, uint64_t seed,
                                              T* __restrict__ grid, const int32_t* __restrict__ big,
                                              const int32_t* __restrict__ ctrl, const DetTables* __restrict__ tables) {
-  constexpr int CB = 64, CK = 256;
-  __shared__ double s_a[CB];
-  __shared__ double s_b[CK];
+  constexpr int NWAVE = 4, CB = 64, CK = 64;
+  __shared__ double s_a[NWAVE][CB];
+  __shared__ double s_b[NWAVE][CK];
+  __shared__ double s_ea[NWAVE][CB + 1];
+  __shared__ double s_eb[NWAVE][CK + 1];
   __shared__ DetTables s_tb;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (FLUCT) {
     const double* src = reinterpret_cast<const double*>(tables);
     double* dst = reinterpret_cast<double*>(&s_tb);
@@ -377,35 +415,17 @@ __global__ void __launch_bounds__(256) k_big(DepoView<T> d, RasterGeom g, double
     if (!w.ok) continue;
     const PlaneGeom& pl = g.pl[w.plane];
     T* gp = grid + (int64_t)w.event * g.grid_ev_stride + pl.grid_off;
-    const int64_t N = FLUCT ? (int64_t)floor(w.q + 0.5) : 0;
     const uint32_t did = d.depo_id ? (uint32_t)d.depo_id[j] : (uint32_t)j;
-    for (int cb = w.b0; cb < w.b1; cb += CB)
-      for (int ck = w.k0; ck < w.k1; ck += CK) {
-        const int nbr = min(CB, w.b1 - cb), nkr = min(CK, w.k1 - ck);
-        __syncthreads();
-        for (int x = threadIdx.x; x < nbr; x += blockDim.x)
-          s_a[x] = FLUCT ? cell_prob(cb + x, w.u, w.su, w.ulo, w.uhi, s_tb.inv)
-                         : cell_weight(cb + x, w.u, w.su, w.ulo, w.uhi);
-        for (int x = threadIdx.x; x < nkr; x += blockDim.x)
-          s_b[x] = FLUCT ? cell_prob(ck + x, w.t, w.st, w.tlo, w.thi, s_tb.inv)
-                         : cell_weight(ck + x, w.t, w.st, w.tlo, w.thi);
-        __syncthreads();
-        for (int x = threadIdx.x; x < nbr * nkr; x += blockDim.x) {
-          const int bi = x / nkr, ki = x - (x / nkr) * nkr;
-          T val;
-          if (FLUCT) {
-            const double pr = s_a[bi] * s_b[ki];
-            const uint32_t cell = (uint32_t)((int64_t)(cb + bi) * pl.nt + (ck + ki));
-            const Philox4 ph = philox4x32_10(cell, did, (uint32_t)w.event, (uint32_t)w.plane << 24, key0, key1);
-            const int64_t n = binomial(N, pr, uniform53(ph.w0, ph.w1), s_tb);
-            if (n == 0) continue;
-            val = (T)n;
-          } else {
-            val = (T)(w.q * (s_a[bi] * s_b[ki]));
-          }
-          atomicAdd(gp + (int64_t)(cb + bi) * pl.nt + ck + ki, val);
-        }
-      }
+    const int kstart = w.k0 & ~1;  // chunks start on even ticks: a Philox pair never straddles two
+    const int ncb = (w.b1 - w.b0 + CB - 1) / CB, nck = (w.k1 - kstart + CK - 1) / CK;
+    for (int c = wv; c < ncb * nck; c += NWAVE) {
+      const int cb = c / nck, ck = c - (c / nck) * nck;
+      const int b0 = w.b0 + cb * CB, b1 = min(b0 + CB, w.b1);
+      const int k0 = max(kstart + ck * CK, w.k0), k1 = min(kstart + (ck + 1) * CK, w.k1);
+      patch_cells<T, FLUCT>(w, b0, b1, k0, k1, pl.nt, did, (uint32_t)w.event, (uint32_t)w.plane, key0, key1,
+                            s_a[wv], s_b[wv], s_ea[wv], s_eb[wv], s_tb, lane,
+                            [&](int b, int k, T v) { atomicAdd(gp + (int64_t)b * pl.nt + k, v); });
+    }
   }
 }
 

@@ -154,13 +154,23 @@ def test_fluctuated_patch_statistics():
 
 def test_counter_keying():
     """Streams differ by depo, event, plane and seed; a cell's variate does not depend on the patch."""
-    cell = np.arange(100)
-    base = F.cell_uniform(9, 1, 2, 3, cell)
-    assert not np.array_equal(base, F.cell_uniform(9, 1, 2, 4, cell))
-    assert not np.array_equal(base, F.cell_uniform(9, 1, 3, 3, cell))
-    assert not np.array_equal(base, F.cell_uniform(9, 2, 2, 3, cell))
-    assert not np.array_equal(base, F.cell_uniform(10, 1, 2, 3, cell))
-    assert np.array_equal(base[40:60], F.cell_uniform(9, 1, 2, 3, cell[40:60]))
+    k = np.arange(100)
+    base = F.cell_uniform(9, 1, 2, 3, 7, k, 101)
+    assert not np.array_equal(base, F.cell_uniform(9, 1, 2, 4, 7, k, 101))
+    assert not np.array_equal(base, F.cell_uniform(9, 1, 3, 3, 7, k, 101))
+    assert not np.array_equal(base, F.cell_uniform(9, 2, 2, 3, 7, k, 101))
+    assert not np.array_equal(base, F.cell_uniform(10, 1, 2, 3, 7, k, 101))
+    assert np.array_equal(base[40:60], F.cell_uniform(9, 1, 2, 3, 7, k[40:60], 101))
+    assert len(np.unique(base)) == base.size
+
+
+def test_tick_pairs_share_one_block():
+    """Cells (b, 2m) and (b, 2m+1) take words 0-1 and 2-3 of the block with counter b*ceil(N_t/2)+m."""
+    nt, b, m = 9, 5, 3
+    w = F.philox4x32_10([b * 5 + m], [11], [2], [1 << 24], 77, 0)
+    even = F.cell_uniform(77, 1, 2, 11, b, 2 * m, nt)
+    odd = F.cell_uniform(77, 1, 2, 11, b, 2 * m + 1, nt)
+    assert even == F.uniform53(w[0], w[1])[0] and odd == F.uniform53(w[2], w[3])[0]
 
 
 def test_fluct_at_matches_full_raster():
