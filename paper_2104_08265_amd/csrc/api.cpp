@@ -292,7 +292,7 @@ int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, 
     const cx<T>* tw_w = static_cast<const cx<T>*>(P->tw_w[p]);
     PROF_LAUNCH(P, "rows_r2c", st,
                 launch_rows_r2c<T>(grid + G.grid_off, P->grid_elems, shat + G.shat_off, P->shat_elems, G.nt, G.I,
-                                   G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, st),
+                                   G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, P->n_cu, st),
                 "row transform launch");
     PROF_LAUNCH(P, "colpass", st,
                 launch_colpass<T>(shat + G.shat_off, P->shat_elems, static_cast<const cx<T>*>(P->rtil[p]),
@@ -321,7 +321,7 @@ int run_backward(wct_plan* P, const wct_depos* d, const wct_opts* o, const T* gw
     const cx<T>* tw_w = static_cast<const cx<T>*>(P->tw_w[p]);
     PROF_LAUNCH(P, "adj_rows_r2c", st,
                 launch_rows_r2c<T>(gw + G.wave_off, P->wave_elems, ghat + G.mhat_off, P->mhat_elems, G.nt, 1, G.nw,
-                                   G.nchunk, ne, P->fp_t[p], tw_t, post, st),
+                                   G.nchunk, ne, P->fp_t[p], tw_t, post, P->n_cu, st),
                 "adjoint row transform launch");
     PROF_LAUNCH(P, "adj_colpass", st,
                 launch_colpass_adj<T>(ghat + G.mhat_off, P->mhat_elems, static_cast<const cx<T>*>(P->rtil[p]),

@@ -31,47 +31,118 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk) {
   return xcd < r ? xcd * (q + 1) + pos : r * (q + 1) + (xcd - r) * q + pos;
 }
 
+// 16-byte vector of the real type (4 floats or 2 doubles) for row loads: a clang vector,
+// so register arrays of it stay in registers.
+template <typename T>
+struct Vec16 {
+  static constexpr int n = 16 / sizeof(T);
+  typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
+};
+
+// Complex value as a clang 2-vector for register arrays (aggregates there can end up in
+// scratch memory).
+template <typename T>
+using cv2 = T __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ cv2<T> to_v(cx<T> a) {
+  cv2<T> r;
+  r.x = a.x;
+  r.y = a.y;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cx<T> from_v(cv2<T> a) { return mk(a.x, a.y); }
+
 // ---------------------------------------------------------------------------
-// Pass A: real rows -> half spectra, column-chunk layout
+// Pass A: real rows -> half spectra, column-chunk layout.  Persistent: a workgroup
+// walks rows L = first + k * gridDim.x; the next row is loaded into registers while the
+// current one is transformed, so HBM reads overlap the LDS work.
 // ---------------------------------------------------------------------------
 template <typename T, int C, int E>
 __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_rows_r2c(const T* __restrict__ src, int64_t src_ev_stride,
                                                    cx<T>* __restrict__ dst, int64_t dst_ev_stride, int nt,
-                                                   int nphase, int nper, int nchunk, FftPlan plan,
+                                                   int nphase, int nper, int nchunk, int n_events, FftPlan plan,
                                                    const cx<T>* __restrict__ tw,
                                                    const cx<T>* __restrict__ post) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::n;
+  constexpr int PF = (2 * E + VN - 1) / VN;  // 16-byte loads per thread: a row has <= 2 E reals per thread
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* z = reinterpret_cast<cx<T>*>(smem_raw);
   T* zr = reinterpret_cast<T*>(smem_raw);
+  V* zv = reinterpret_cast<V*>(smem_raw);
   const int M = plan.n;
-  const int L = xcd_remap(blockIdx.x, gridDim.x);
-  const int i = L / nper, c = L - (L / nper) * nper;
-  const int64_t row = (int64_t)c * nphase + i;
-  const T* s = src + blockIdx.y * src_ev_stride + row * nt;
-  for (int n = threadIdx.x; n < 2 * M; n += blockDim.x) zr[n] = n < nt ? s[n] : T(0);
-  __syncthreads();
-  fft_lds<T, false, 1, E>(z, plan, tw);
-  cx<T>* out = dst + blockIdx.y * dst_ev_stride;
-  const int fpad = nchunk * C;
-  for (int k = threadIdx.x; k < fpad; k += blockDim.x) {
-    cx<T> X = mk(T(0), T(0));
-    if (k <= M) {
-      const cx<T> A = z[k == M ? 0 : k];
-      const cx<T> B = conj(z[k == 0 ? 0 : M - k]);
-      const cx<T> Ev = scale(A + B, T(0.5));
-      const cx<T> D = scale(A - B, T(0.5));
-      const cx<T> O = mk(D.y, -D.x);  // (A - B) / (2i)
-      X = Ev + cmul(post[k], O);
+  const int rows = nphase * nper;
+  const int total = rows * n_events;
+  // Rows whose length or base is not a multiple of 16 bytes are read with scalar loads
+  // and without prefetch.
+  const bool vec = (nt % VN) == 0 && (reinterpret_cast<uintptr_t>(src) % 16) == 0 && (src_ev_stride % VN) == 0;
+  const int ntv = vec ? nt / VN : 0;
+  V pre[PF];
+  int L = xcd_remap(blockIdx.x, gridDim.x);
+  if (vec && L < total) {
+    const int ev = L / rows, rin = L - (L / rows) * rows;
+    const int i = rin / nper, c = rin - (rin / nper) * nper;
+    const V* s = reinterpret_cast<const V*>(src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt);
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {  // unconditional (clamped) loads keep pre[] in registers
+      const int u = threadIdx.x + q * blockDim.x;
+      pre[q] = s[u < ntv ? u : 0];
     }
-    const int ch = k / C, cc = k - (k / C) * C;
-    out[(((int64_t)ch * nphase + i) * nper + c) * C + cc] = X;
+  }
+  while (L < total) {
+    const int ev = L / rows, rin = L - (L / rows) * rows;
+    const int i = rin / nper, c = rin - (rin / nper) * nper;
+    if (vec) {
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int u = threadIdx.x + q * blockDim.x;
+        if (u < ntv) zv[u] = pre[q];
+      }
+      for (int u = ntv * VN + threadIdx.x; u < 2 * M; u += blockDim.x) zr[u] = T(0);
+    } else {
+      const T* s = src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt;
+      for (int u = threadIdx.x; u < 2 * M; u += blockDim.x) zr[u] = u < nt ? s[u] : T(0);
+    }
+    __syncthreads();
+    const int Ln = L + gridDim.x;
+    if (vec && Ln < total) {  // next row in flight during this row's transform
+      const int evn = Ln / rows, rn = Ln - (Ln / rows) * rows;
+      const int in = rn / nper, cn = rn - (rn / nper) * nper;
+      const V* s = reinterpret_cast<const V*>(src + evn * src_ev_stride + ((int64_t)cn * nphase + in) * nt);
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int u = threadIdx.x + q * blockDim.x;
+        pre[q] = s[u < ntv ? u : 0];
+      }
+    }
+    fft_lds<T, false, 1, E>(z, plan, tw);
+    cx<T>* out = dst + ev * dst_ev_stride;
+    const int fpad = nchunk * C;
+    for (int k = threadIdx.x; k < fpad; k += blockDim.x) {
+      cx<T> X = mk(T(0), T(0));
+      if (k <= M) {
+        const cx<T> A = z[k == M ? 0 : k];
+        const cx<T> B = conj(z[k == 0 ? 0 : M - k]);
+        const cx<T> Ev = scale(A + B, T(0.5));
+        const cx<T> D = scale(A - B, T(0.5));
+        const cx<T> O = mk(D.y, -D.x);  // (A - B) / (2i)
+        X = Ev + cmul(post[k], O);
+      }
+      const int ch = k / C, cc = k - (k / C) * C;
+      out[(((int64_t)ch * nphase + i) * nper + c) * C + cc] = X;
+    }
+    __syncthreads();
+    L = Ln;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Pass B (forward): transforms along wires per phase, spectrum product, phase sum
+// Pass B (forward): transforms along wires per phase, spectrum product, phase sum.
+// The next phase's S-hat block and the current phase's spectrum are loaded into
+// registers while the current phase is transformed (PF, for small register budgets E).
 // ---------------------------------------------------------------------------
-template <typename T, int C, int E>
+template <typename T, int C, int E, bool PF>
 __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_colpass(const cx<T>* __restrict__ shat, int64_t shat_ev_stride,
                                                   const cx<T>* __restrict__ rtil, cx<T>* __restrict__ mhat,
                                                   int64_t mhat_ev_stride, int nw, int nphase, int nchunk,
@@ -82,28 +153,56 @@ __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_colpass(const cx
   const int ne = lw * C;
   const int nin = nw * C;
   const int ch = blockIdx.x;
-  cx<T> acc[E];
+  constexpr bool PFS = PF;
+  cv2<T> acc[E], rreg[PF ? E : 1], sreg[PFS ? E : 1];
 #pragma unroll
-  for (int q = 0; q < E; ++q) acc[q] = mk(T(0), T(0));
+  for (int q = 0; q < E; ++q) acc[q] = to_v(mk(T(0), T(0)));
   const cx<T>* src = shat + blockIdx.y * shat_ev_stride + (int64_t)ch * nphase * nin;
   const cx<T>* rt = rtil + (int64_t)ch * nphase * ne;
-  for (int i = 0; i < nphase; ++i) {
-    const cx<T>* s = src + (int64_t)i * nin;
-    for (int idx = threadIdx.x; idx < ne; idx += blockDim.x) buf[idx] = idx < nin ? s[idx] : mk(T(0), T(0));
-    __syncthreads();
-    fft_lds<T, false, C, E>(buf, plan, tw);
-    const cx<T>* r = rt + (int64_t)i * ne;
+  if (PFS) {
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int idx = threadIdx.x + q * blockDim.x;
-      if (idx < ne) acc[q] = acc[q] + cmul(buf[idx], r[idx]);
+      sreg[PFS ? q : 0] = to_v(idx < nin ? src[idx] : mk(T(0), T(0)));
+    }
+  }
+  for (int i = 0; i < nphase; ++i) {
+    const cx<T>* s = src + (int64_t)i * nin;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int idx = threadIdx.x + q * blockDim.x;
+      if (idx < ne) buf[idx] = PFS ? from_v(sreg[PFS ? q : 0]) : (idx < nin ? s[idx] : mk(T(0), T(0)));
+    }
+    __syncthreads();
+    // this phase's spectrum and the next phase's data in flight during the transform
+    const cx<T>* r = rt + (int64_t)i * ne;
+    if (PF) {
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int idx = threadIdx.x + q * blockDim.x;
+        rreg[PF ? q : 0] = to_v(r[idx < ne ? idx : 0]);
+      }
+    }
+    if (PFS && i + 1 < nphase) {
+      const cx<T>* sn = s + nin;
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int idx = threadIdx.x + q * blockDim.x;
+        sreg[PFS ? q : 0] = to_v(idx < nin ? sn[idx] : mk(T(0), T(0)));
+      }
+    }
+    fft_lds<T, false, C, E>(buf, plan, tw);
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int idx = threadIdx.x + q * blockDim.x;
+      if (idx < ne) acc[q] = acc[q] + to_v(cmul(buf[idx], PF ? from_v(rreg[PF ? q : 0]) : r[idx]));
     }
     __syncthreads();
   }
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int idx = threadIdx.x + q * blockDim.x;
-    if (idx < ne) buf[idx] = acc[q];
+    if (idx < ne) buf[idx] = from_v(acc[q]);
   }
   __syncthreads();
   fft_lds<T, true, C, E>(buf, plan, tw);
@@ -134,11 +233,11 @@ __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_colpass_adj(cons
   for (int idx = threadIdx.x; idx < ne; idx += blockDim.x) buf[idx] = idx < nin ? s[idx] : mk(T(0), T(0));
   __syncthreads();
   fft_lds<T, false, C, E>(buf, plan, tw);
-  cx<T> g[E];
+  cv2<T> g[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int idx = threadIdx.x + q * blockDim.x;
-    g[q] = idx < ne ? buf[idx] : mk(T(0), T(0));
+    g[q] = to_v(buf[idx < ne ? idx : 0]);
   }
   __syncthreads();
   const cx<T>* rt = rtil + (int64_t)ch * nphase * ne;
@@ -148,7 +247,7 @@ __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_colpass_adj(cons
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int idx = threadIdx.x + q * blockDim.x;
-      if (idx < ne) buf[idx] = cmulc(g[q], r[idx]);
+      if (idx < ne) buf[idx] = cmulc(from_v(g[q]), r[idx]);
     }
     __syncthreads();
     fft_lds<T, true, C, E>(buf, plan, tw);
@@ -228,15 +327,28 @@ template bool conv_fits<double>(int);
     default: return hipErrorInvalidValue;      \
   }
 
+// Persistent grid: as many workgroups as fit on the device at once (LDS and waves).
+static int persistent_blocks(int n_cu, size_t lds, int threads, int work) {
+  int per_cu = (int)((160 * 1024) / (lds > 0 ? lds : 1));
+  const int waves = (threads + 63) / 64;
+  if (per_cu * waves > 32) per_cu = 32 / waves;
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu > 8) per_cu = 8;
+  const int g = n_cu * per_cu;
+  return work < g ? work : g;
+}
+
 template <typename T>
 hipError_t launch_rows_r2c(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt, int nphase,
                            int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
-                           const cx<T>* post, hipStream_t st) {
+                           const cx<T>* post, int n_cu, hipStream_t st) {
   const size_t lds = sizeof(cx<T>) * plan.n;
-  const dim3 grid(nphase * nper, n_events);
+  const int total = nphase * nper * n_events;
   WCT_DISPATCH_E(T, plan.n,
-                 hipLaunchKernelGGL((k_rows_r2c<T, kChunk, E_>), grid, dim3(threads_for(plan.n, E_)), lds, st, src,
-                                    src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, plan, tw, post))
+                 const int thr = threads_for(plan.n, E_);
+                 hipLaunchKernelGGL((k_rows_r2c<T, kChunk, E_>), dim3(persistent_blocks(n_cu, lds, thr, total)),
+                                    dim3(thr), lds, st, src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper,
+                                    nchunk, n_events, plan, tw, post))
   return hipGetLastError();
 }
 
@@ -248,8 +360,9 @@ hipError_t launch_colpass(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>
   const size_t lds = sizeof(cx<T>) * elems;
   const dim3 grid(nchunk, n_events);
   WCT_DISPATCH_E(T, elems,
-                 hipLaunchKernelGGL((k_colpass<T, kChunk, E_>), grid, dim3(threads_for(elems, E_)), lds, st, shat,
-                                    shat_ev_stride, rtil, mhat, mhat_ev_stride, nw, nphase, nchunk, plan, tw))
+                 hipLaunchKernelGGL((k_colpass<T, kChunk, E_, (sizeof(T) == 4 ? E_ == 16 : E_ == 8)>), grid, dim3(threads_for(elems, E_)), lds,
+                                    st, shat, shat_ev_stride, rtil, mhat, mhat_ev_stride, nw, nphase, nchunk, plan,
+                                    tw))
   return hipGetLastError();
 }
 
@@ -289,7 +402,8 @@ template <typename T, int E>
 static void raise_lds_limit_e() {
   const int lim = 160 * 1024;
   hipFuncSetAttribute((const void*)k_rows_r2c<T, kChunk, E>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_colpass<T, kChunk, E>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_colpass<T, kChunk, E, (sizeof(T) == 4 ? E == 16 : E == 8)>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      lim);
   hipFuncSetAttribute((const void*)k_colpass_adj<T, kChunk, E>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_rows_c2r<T, kChunk, true, E>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_rows_c2r<T, kChunk, false, E>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
@@ -306,7 +420,7 @@ void conv_init_kernels() {
 
 #define WCT_INST(T)                                                                                            \
   template hipError_t launch_rows_r2c<T>(const T*, int64_t, cx<T>*, int64_t, int, int, int, int, int,          \
-                                         const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);            \
+                                         const FftPlan&, const cx<T>*, const cx<T>*, int, hipStream_t);       \
   template hipError_t launch_colpass<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int, int,   \
                                         int, const FftPlan&, const cx<T>*, hipStream_t);                       \
   template hipError_t launch_colpass_adj<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int,    \

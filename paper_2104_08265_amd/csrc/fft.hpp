@@ -248,7 +248,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, int n, int Ns, const c
 // least n*C/E threads (E = elements a thread holds).  `tw` is the length's
 // twiddle table (per pass p, W_{Ns*R}^{r*k} at tw_off[p] + k*(R-1) + r-1).
 template <typename T, bool INV, int C, int E>
-__device__ void fft_lds(cx<T>* buf, const FftPlan& plan, const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void fft_lds(cx<T>* buf, const FftPlan& plan, const cx<T>* __restrict__ tw) {
   int Ns = 1;
   for (int p = 0; p < plan.npass; ++p) {
     const int R = plan.radix[p];

@@ -80,10 +80,11 @@ hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigm
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 
 // conv.hip
+// Rows are read with 16-byte loads (and the next row prefetched) when their length and base allow it.
 template <typename T>
 hipError_t launch_rows_r2c(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt, int nphase,
                            int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
-                           const cx<T>* post, hipStream_t st);
+                           const cx<T>* post, int n_cu, hipStream_t st);
 template <typename T>
 hipError_t launch_colpass(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtil, cx<T>* mhat,
                           int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, const FftPlan& plan,

@@ -79,24 +79,21 @@ __device__ __forceinline__ int find_plane(const RasterGeom& g, int tin) {
   return p;
 }
 
-// Axis weights of cells [k0, k1) of a window (lo, hi) around mu: the Gaussian's integral
-// over each cell's part inside the window, from erf evaluated once per cell edge
-// (edge 0 = max(k0, lo), edge n = min(k1, hi), interior edges the integers between), so a
-// cell's weight is 0.5 (E(e_hi) - E(e_lo)) computed from the same doubles the oracle uses.
+// Erf at the cell edges of [k0, k1) for a window (lo, hi) around mu: edge 0 = max(k0, lo),
+// edge n = min(k1, hi), interior edges the integers between.  A cell's weight (the
+// Gaussian's integral over its part inside the window) is then 0.5 (e[x+1] - e[x]),
+// computed from the same doubles the oracle uses, with one erf per edge.
 template <bool FLUCT>
-__device__ __forceinline__ void axis_fill(double* __restrict__ e, double* __restrict__ wgt, int k0, int k1, double mu,
-                                          double sigma, double lo, double hi, const double* __restrict__ inv,
-                                          int lane) {
+__device__ __forceinline__ void edge_fill(double* __restrict__ e, int k0, int k1, double mu, double sigma, double lo,
+                                          double hi, const double* __restrict__ inv, int lane) {
   const int n = k1 - k0;
   const double s2 = sigma * kSqrt2;
   for (int x = lane; x <= n; x += 64) {
     const double edge = x == 0 ? fmax((double)k0, lo) : (x == n ? fmin((double)k1, hi) : (double)(k0 + x));
     e[x] = FLUCT ? det_erf((edge - mu) / s2, inv) : erf((edge - mu) / s2);
   }
-  wave_sync();
-  for (int x = lane; x < n; x += 64) wgt[x] = 0.5 * (e[x + 1] - e[x]);
-  wave_sync();
 }
+__device__ __forceinline__ double edge_weight(const double* e, int x) { return 0.5 * (e[x + 1] - e[x]); }
 
 // x / d for 0 <= x < 2^22 without an integer divide (float reciprocal, then corrected).
 __device__ __forceinline__ int div_small(int x, int d, float rd) {
@@ -106,23 +103,86 @@ __device__ __forceinline__ int div_small(int x, int d, float rd) {
   return q;
 }
 
-// One wave rasterises the cells [b0, b1) x [k0, k1) of a row and hands each nonzero
-// contribution to `add(b, k, value)`.  Fluctuated cells are drawn in tick pairs: the
-// pair (b, 2m), (b, 2m+1) shares one Philox4x32-10 block (counter b*ceil(N_t/2) + m),
-// words 0-1 for the even tick and 2-3 for the odd one.
-template <typename T, bool FLUCT, typename Add>
+// Per-wave queue of cells whose count needs the full sampler.  Cells whose count follows
+// from the cheap tests (p <= 0, p >= 1, or the exact zero shortcut) never enter it, so
+// the expensive inversion / chop-down paths run with all 64 lanes on queued cells
+// instead of diverging inside every wave.
+constexpr int kQCap = 128;  // up to 63 left over + 64 pushed
+struct SampleQueue {
+  double p[kQCap];
+  double u[kQCap];
+  int n[kQCap];
+  uint32_t dst[kQCap];
+};
+
+__device__ __forceinline__ int binom_quick(int64_t N, double p, double u) {
+  if (N <= 0) return 0;
+  if (p >= 1.0) return -1;  // rare: the full path returns N
+  if (!(p > 0.0)) return 0;
+  if (p <= 0.5) {
+    const double mu = (double)N * p;
+    if (mu < kMuSwitch && u < (1.0 - mu) - (1.0e-12 + (double)N * 2.5e-16)) return 0;
+  }
+  return -1;
+}
+
+__device__ __forceinline__ int lanes_below(uint64_t mask, int lane) {
+  return __popcll(mask & ((1ull << lane) - 1ull));
+}
+
+// The full sampler for one queued cell.
+__device__ __forceinline__ int sample_queued(const SampleQueue* q, int at, const DetTables* tb) {
+  return (int)binomial((int64_t)q->n[at], q->p[at], q->u[at], *tb);
+}
+
+__device__ __forceinline__ void queue_push(SampleQueue& q, int& qn, bool need, double p, double u, int64_t N,
+                                           uint32_t dst, int lane) {
+  const uint64_t mask = __ballot(need);
+  if (need) {
+    const int at = qn + lanes_below(mask, lane);
+    q.p[at] = p;
+    q.u[at] = u;
+    q.n[at] = (int)N;
+    q.dst[at] = dst;
+  }
+  qn += __popcll(mask);
+}
+
+// Samples queued cells with all lanes, 64 at a time from the top of the queue: full
+// batches only (all = false, inside the cell loop) or everything (all = true).
+template <typename T, typename Add>
+__device__ __forceinline__ void queue_run(SampleQueue& q, int& qn, bool all, int lane, const DetTables& tb, Add add) {
+  wave_sync();
+  while (qn >= 64 || (all && qn > 0)) {
+    const int take = qn < 64 ? qn : 64;
+    if (lane < take) {
+      const int at = qn - take + lane;
+      const int n = sample_queued(&q, at, &tb);
+      if (n) add(q.dst[at], (T)n);
+    }
+    qn -= take;
+    wave_sync();
+  }
+}
+
+// One wave rasterises the cells [b0, b1) x [k0, k1) of a row; `dst(b, k)` names a cell and
+// `add(dst, value)` accumulates a nonzero contribution.  Fluctuated cells are drawn in
+// tick pairs: cells (b, 2m), (b, 2m+1) share one Philox4x32-10 block (counter
+// b*ceil(N_t/2) + m), words 0-1 for the even tick and 2-3 for the odd one.
+template <typename T, bool FLUCT, typename Dst, typename Add>
 __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int k0, int k1, int nt, uint32_t did,
                                             uint32_t ev, uint32_t plane, uint32_t key0, uint32_t key1,
-                                            double* __restrict__ sa, double* __restrict__ sb, double* __restrict__ ea,
-                                            double* __restrict__ eb, const DetTables& tb, int lane, Add add) {
+                                            double* __restrict__ ea, double* __restrict__ eb, SampleQueue& q,
+                                            int& qn, const DetTables& tb, int lane, Dst dst, Add add) {
   const int nbr = b1 - b0, nkr = k1 - k0;
-  axis_fill<FLUCT>(ea, sa, b0, b1, w.u, w.su, w.ulo, w.uhi, tb.inv, lane);
-  axis_fill<FLUCT>(eb, sb, k0, k1, w.t, w.st, w.tlo, w.thi, tb.inv, lane);
+  edge_fill<FLUCT>(ea, b0, b1, w.u, w.su, w.ulo, w.uhi, tb.inv, lane);
+  edge_fill<FLUCT>(eb, k0, k1, w.t, w.st, w.tlo, w.thi, tb.inv, lane);
+  wave_sync();
   if (!FLUCT) {
     const float rd = 1.0f / (float)nkr;
     for (int x = lane; x < nbr * nkr; x += 64) {
       const int bi = div_small(x, nkr, rd), ki = x - bi * nkr;
-      add(b0 + bi, k0 + ki, (T)(w.q * (sa[bi] * sb[ki])));
+      add(dst(b0 + bi, k0 + ki), (T)(w.q * (edge_weight(ea, bi) * edge_weight(eb, ki))));
     }
   } else {
     const int64_t N = (int64_t)floor(w.q + 0.5);
@@ -130,19 +190,35 @@ __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int
       const int j0 = k0 >> 1, np = ((k1 - 1) >> 1) - j0 + 1;
       const uint32_t half_nt = (uint32_t)((nt + 1) >> 1);
       const float rd = 1.0f / (float)np;
-      for (int x = lane; x < nbr * np; x += 64) {
-        const int bi = div_small(x, np, rd), pj = x - bi * np;
-        const int b = b0 + bi, m = j0 + pj;
-        const Philox4 ph = philox4x32_10((uint32_t)b * half_nt + (uint32_t)m, did, ev, plane << 24, key0, key1);
-        const int ke = 2 * m, ko = 2 * m + 1;
-        if (ke >= k0) {
-          const int64_t n = binomial(N, sa[bi] * sb[ke - k0], uniform53(ph.w0, ph.w1), tb);
-          if (n) add(b, ke, (T)n);
+      const int total = nbr * np;
+      for (int base = 0; base < total; base += 64) {
+        const int x = base + lane;
+        bool need_e = false, need_o = false;
+        double pe = 0.0, po = 0.0, ue = 0.0, uo = 0.0;
+        uint32_t de = 0, dodd = 0;
+        if (x < total) {
+          const int bi = div_small(x, np, rd), pj = x - bi * np;
+          const int b = b0 + bi, m = j0 + pj;
+          const Philox4 ph = philox4x32_10((uint32_t)b * half_nt + (uint32_t)m, did, ev, plane << 24, key0, key1);
+          const double a = edge_weight(ea, bi);
+          const int ke = 2 * m, ko = 2 * m + 1;
+          if (ke >= k0) {
+            pe = a * edge_weight(eb, ke - k0);
+            ue = uniform53(ph.w0, ph.w1);
+            de = dst(b, ke);
+            need_e = binom_quick(N, pe, ue) != 0;
+          }
+          if (ko < k1) {
+            po = a * edge_weight(eb, ko - k0);
+            uo = uniform53(ph.w2, ph.w3);
+            dodd = dst(b, ko);
+            need_o = binom_quick(N, po, uo) != 0;
+          }
         }
-        if (ko < k1) {
-          const int64_t n = binomial(N, sa[bi] * sb[ko - k0], uniform53(ph.w2, ph.w3), tb);
-          if (n) add(b, ko, (T)n);
-        }
+        queue_push(q, qn, need_e, pe, ue, N, de, lane);
+        if (qn >= 64) queue_run<T>(q, qn, false, lane, tb, add);
+        queue_push(q, qn, need_o, po, uo, N, dodd, lane);
+        if (qn >= 64) queue_run<T>(q, qn, false, lane, tb, add);
       }
     }
   }
@@ -322,17 +398,16 @@ __global__ void k_zero_split(RasterGeom g, const int32_t* __restrict__ counts, i
 
 // 4. persistent tile kernel -------------------------------------------------
 template <typename T, bool FLUCT, int TH, int TW>
-__global__ void __launch_bounds__(256) k_tile(DepoView<T> d, RasterGeom g, double nsigma, uint64_t seed,
+__global__ void __launch_bounds__(256, 3) k_tile(DepoView<T> d, RasterGeom g, double nsigma, uint64_t seed,
                                               T* __restrict__ grid, const int32_t* __restrict__ list,
                                               const int32_t* __restrict__ offs, const int32_t* __restrict__ items,
                                               const int32_t* __restrict__ item_off, int32_t* __restrict__ ctrl,
                                               const DetTables* __restrict__ tables) {
   constexpr int NWAVE = 4;
   __shared__ T tile[TH * TW];
-  __shared__ double s_a[NWAVE][TH];
-  __shared__ double s_b[NWAVE][TW];
   __shared__ double s_ea[NWAVE][TH + 1];
   __shared__ double s_eb[NWAVE][TW + 1];
+  __shared__ SampleQueue s_q[FLUCT ? NWAVE : 1];
   __shared__ DetTables s_tb;
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -345,7 +420,7 @@ __global__ void __launch_bounds__(256) k_tile(DepoView<T> d, RasterGeom g, doubl
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(&ctrl[kCtrlHead], 1);
     __syncthreads();
-    const int item = s_item;
+    const int item = __builtin_amdgcn_readfirstlane(s_item);  // block-uniform: keep it scalar
     if (item >= ctrl[kCtrlNItems]) break;
     const int t = items[item];
     const int chunk = item - item_off[t];
@@ -362,17 +437,22 @@ __global__ void __launch_bounds__(256) k_tile(DepoView<T> d, RasterGeom g, doubl
     __syncthreads();
     const int r0 = offs[t] + chunk * kRowsPerItem;
     const int r1 = min(offs[t] + (chunk + 1) * kRowsPerItem, offs[t + 1]);
+    int qn = 0;
+    SampleQueue& q = s_q[FLUCT ? wv : 0];
+    auto dst = [&](int b, int k) { return (uint32_t)((b - tb0) * TW + (k - tk0)); };
+    auto add = [&](uint32_t o, T v) { atomicAdd(&tile[o], v); };
     for (int r = r0 + wv; r < r1; r += NWAVE) {
-      const int64_t j = list[r];
+      // the row is wave-uniform: a scalar index makes its parameters scalar loads and registers
+      const int64_t j = __builtin_amdgcn_readfirstlane(list[__builtin_amdgcn_readfirstlane(r)]);
       const RowWin w = row_window(d, j, g, nsigma);
       const int bb0 = max(w.b0, tb0), bb1 = min(w.b1, tb0 + th);
       const int kk0 = max(w.k0, tk0), kk1 = min(w.k1, tk0 + tw);
       if (!w.ok || bb0 >= bb1 || kk0 >= kk1) continue;
       const uint32_t did = d.depo_id ? (uint32_t)d.depo_id[j] : (uint32_t)j;
-      patch_cells<T, FLUCT>(w, bb0, bb1, kk0, kk1, pl.nt, did, (uint32_t)ev, (uint32_t)pi, key0, key1, s_a[wv],
-                            s_b[wv], s_ea[wv], s_eb[wv], s_tb, lane,
-                            [&](int b, int k, T v) { atomicAdd(&tile[(b - tb0) * TW + (k - tk0)], v); });
+      patch_cells<T, FLUCT>(w, bb0, bb1, kk0, kk1, pl.nt, did, (uint32_t)ev, (uint32_t)pi, key0, key1, s_ea[wv],
+                            s_eb[wv], q, qn, s_tb, lane, dst, add);
     }
+    if (FLUCT) queue_run<T>(q, qn, true, lane, s_tb, add);
     __syncthreads();
     T* gp = grid + (int64_t)ev * g.grid_ev_stride + pl.grid_off;
     for (int x = threadIdx.x; x < th * TW; x += blockDim.x) {
@@ -391,14 +471,13 @@ __global__ void __launch_bounds__(256) k_tile(DepoView<T> d, RasterGeom g, doubl
 
 // 5. rows wider than 4 tiles: 64 x 64 chunks per wave, straight to global atomics ------
 template <typename T, bool FLUCT>
-__global__ void __launch_bounds__(256) k_big(DepoView<T> d, RasterGeom g, double nsigma, uint64_t seed,
+__global__ void __launch_bounds__(256, 3) k_big(DepoView<T> d, RasterGeom g, double nsigma, uint64_t seed,
                                              T* __restrict__ grid, const int32_t* __restrict__ big,
                                              const int32_t* __restrict__ ctrl, const DetTables* __restrict__ tables) {
   constexpr int NWAVE = 4, CB = 64, CK = 64;
-  __shared__ double s_a[NWAVE][CB];
-  __shared__ double s_b[NWAVE][CK];
   __shared__ double s_ea[NWAVE][CB + 1];
   __shared__ double s_eb[NWAVE][CK + 1];
+  __shared__ SampleQueue s_q[FLUCT ? NWAVE : 1];
   __shared__ DetTables s_tb;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (FLUCT) {
@@ -410,7 +489,7 @@ __global__ void __launch_bounds__(256) k_big(DepoView<T> d, RasterGeom g, double
   const int nbig = ctrl[kCtrlNBig];
   const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
   for (int r = blockIdx.x; r < nbig; r += gridDim.x) {
-    const int64_t j = big[r];
+    const int64_t j = __builtin_amdgcn_readfirstlane(big[r]);
     const RowWin w = row_window(d, j, g, nsigma);
     if (!w.ok) continue;
     const PlaneGeom& pl = g.pl[w.plane];
@@ -418,14 +497,19 @@ __global__ void __launch_bounds__(256) k_big(DepoView<T> d, RasterGeom g, double
     const uint32_t did = d.depo_id ? (uint32_t)d.depo_id[j] : (uint32_t)j;
     const int kstart = w.k0 & ~1;  // chunks start on even ticks: a Philox pair never straddles two
     const int ncb = (w.b1 - w.b0 + CB - 1) / CB, nck = (w.k1 - kstart + CK - 1) / CK;
+    int qn = 0;
+    SampleQueue& q = s_q[FLUCT ? wv : 0];
+    const int nt = pl.nt;
+    auto dst = [&](int b, int k) { return (uint32_t)((int64_t)b * nt + k); };
+    auto add = [&](uint32_t o, T v) { atomicAdd(gp + o, v); };
     for (int c = wv; c < ncb * nck; c += NWAVE) {
       const int cb = c / nck, ck = c - (c / nck) * nck;
       const int b0 = w.b0 + cb * CB, b1 = min(b0 + CB, w.b1);
       const int k0 = max(kstart + ck * CK, w.k0), k1 = min(kstart + (ck + 1) * CK, w.k1);
       patch_cells<T, FLUCT>(w, b0, b1, k0, k1, pl.nt, did, (uint32_t)w.event, (uint32_t)w.plane, key0, key1,
-                            s_a[wv], s_b[wv], s_ea[wv], s_eb[wv], s_tb, lane,
-                            [&](int b, int k, T v) { atomicAdd(gp + (int64_t)b * pl.nt + k, v); });
+                            s_ea[wv], s_eb[wv], q, qn, s_tb, lane, dst, add);
     }
+    if (FLUCT) queue_run<T>(q, qn, true, lane, s_tb, add);
   }
 }
 
