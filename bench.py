@@ -24,6 +24,112 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+ROOT = os.path.dirname(os.path.abspath(__file__))
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_JSON = os.path.join(PROFILES, "hbm_traffic.json")
+CSRC = os.path.join(ROOT, "paper_2104_08265_amd", "csrc")
+
+# The commands whose output --summarize reads (run from /tmp on the GPU host, R = repo root).
+PROFILE_COMMANDS = {
+    "trace": "rocprofv3 --kernel-trace --stats -f csv -d $R/gpurun_out/prof_cfg2 -o cfg2 -- "
+             "python3 $R/bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-extras",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d $R/gpurun_out/pmc_fetch -o fetch -- "
+             "python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --copy-calibration-mib 1024",
+    "write": "rocprofv3 --pmc WRITE_SIZE -f csv -d $R/gpurun_out/pmc_write -o write -- "
+             "python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --copy-calibration-mib 1024",
+}
+FAMILIES = [("k_tile<float, true", "raster_tile_fluct"), ("k_tile<float, false", "raster_tile_mean"),
+            ("k_rows_r2c<", "rows_r2c"), ("k_colpass<", "colpass"), ("k_rows_c2r<float, 4, false", "rows_c2r"),
+            ("k_big<", "raster_wide_rows")]
+
+
+def sources_digest():
+    """Hash of the kernel sources; counter data are used only while it is unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()
+
+
+def family(kernel_name):
+    for prefix, fam in FAMILIES:
+        if prefix in kernel_name:
+            return fam
+    return None
+
+
+def summarize(out_dir):
+    """Write profiles/*.md and profiles/hbm_traffic.json from rocprofv3 CSV output."""
+    import csv
+    import glob
+    import collections
+    os.makedirs(PROFILES, exist_ok=True)
+    stats = glob.glob(os.path.join(out_dir, "prof_cfg2", "*kernel_stats.csv"))[0]
+    rows = list(csv.DictReader(open(stats)))
+    lines = ["# Kernel time summary: three-plane track workload (1e5 depositions, fluctuation on, FP32)", "",
+             "Command (from /tmp, R = repository root):", "", "    " + PROFILE_COMMANDS["trace"], "",
+             "5 timed + 1 warm-up steps of wct_simulate, plus plan creation (k_resp_*).", "",
+             "| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
+    for r in rows[:16]:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
+    open(os.path.join(PROFILES, "simulate_3plane_1e5_kernel_stats.md"), "w").write("\n".join(lines) + "\n")
+
+    def counters(tag, counter):
+        path = glob.glob(os.path.join(out_dir, f"pmc_{tag}", "*counter_collection.csv"))[0]
+        acc = collections.defaultdict(lambda: [0.0, 0])
+        copies = []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            kib = float(r["Counter_Value"])
+            if r["Kernel_Name"] == "__amd_rocclr_copyBuffer":
+                copies.append(kib)
+            fam = family(r["Kernel_Name"])
+            if fam:
+                acc[fam][0] += kib
+                acc[fam][1] += 1
+        # three 1 GiB device copies: the counter's reading for a known 1 GiB (= 1048576 KiB)
+        big = sorted(copies)[-3:]
+        scale = 1048576.0 / (sum(big) / len(big))
+        return acc, scale
+
+    fetch, fs = counters("fetch", "FETCH_SIZE")
+    write, ws = counters("write", "WRITE_SIZE")
+    traffic = {"sources_sha256": sources_digest(), "fetch_scale": fs, "write_scale": ws, "kernels": {},
+               "commands": {k: PROFILE_COMMANDS[k] for k in ("fetch", "write")}}
+    lines = ["# HBM traffic per kernel family: three-plane track workload, one step", "",
+             "Commands (separate runs, from /tmp, R = repository root):", "",
+             "    " + PROFILE_COMMANDS["fetch"], "    " + PROFILE_COMMANDS["write"], "",
+             f"Calibration: three plain 1 GiB device copies read {1048576 / fs:.0f} KiB (FETCH_SIZE) and wrote "
+             f"{1048576 / ws:.0f} KiB (WRITE_SIZE) per copy, so the counters are scaled by {fs:.4f} (fetch) "
+             f"and {ws:.4f} (write).", "",
+             "| family | launches | fetch GB | write GB | total GB per launch |", "|---|---|---|---|---|"]
+    for fam in sorted(set(fetch) | set(write)):
+        f_b = fetch[fam][0] * 1024 * fs
+        w_b = write[fam][0] * 1024 * ws
+        n = max(fetch[fam][1], write[fam][1], 1)
+        traffic["kernels"][fam] = {"fetch_bytes": f_b, "write_bytes": w_b, "launches": n,
+                                   "bytes_per_launch": (f_b + w_b) / n}
+        lines.append(f"| {fam} | {n} | {f_b / 1e9:.3f} | {w_b / 1e9:.3f} | {(f_b + w_b) / n / 1e9:.3f} |")
+    open(os.path.join(PROFILES, "simulate_3plane_1e5_hbm_traffic.md"), "w").write("\n".join(lines) + "\n")
+    json.dump(traffic, open(TRAFFIC_JSON, "w"), indent=1)
+    print("\n".join(lines))
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from committed counters, or None when the kernels changed since."""
+    try:
+        t = json.load(open(TRAFFIC_JSON))
+    except (OSError, ValueError):
+        return None
+    if t.get("sources_sha256") != sources_digest() or kernel not in t.get("kernels", {}):
+        return None
+    return t["kernels"][kernel]["bytes_per_launch"]
 
 
 def algorithmic_bytes(plan, esize=4):
@@ -114,10 +220,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward-ratio measurement")
+    ap.add_argument("--summarize", metavar="DIR", help="write profiles/ summaries from rocprofv3 output in DIR")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run 3 plain device copies of this many MiB (a known-size reference for "
                          "hardware byte counters)")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); events and planes shard "
               "across GPUs without communication, so per-GPU throughput is the single-GPU figure.",
@@ -175,7 +285,7 @@ def main():
     fft_dom = max(("rows_r2c", "colpass", "rows_c2r"), key=lambda k: kernels.get(k, {}).get("ms_per_step", 0))
     kd = kernels[fft_dom]
     roofline = {"kernel": fft_dom, "bound": "hbm", "achieved": kd["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": kd["GBps"] / HBM_PEAK_GBS, "traffic": None,
+                "frac": kd["GBps"] / HBM_PEAK_GBS, "traffic": measured_traffic(fft_dom),
                 "alg_bytes_per_launch": alg[fft_dom] / n_planes,
                 "avg_launch_ms": kd["ms_per_step"] / kd["launches_per_step"],
                 "note": "algorithmic bytes / mean launch time from HIP events on the launch stream"}

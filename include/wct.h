@@ -31,9 +31,9 @@
  * null stream) and return without synchronising.  Every call returns WCT_OK or a
  * negative WCT_E_* code; wct_last_error() then describes it.  Invalid arguments are
  * detected on the host before anything is enqueued.  Faults inside kernels surface at
- * the caller's next synchronisation, as HIP specifies.  Only wct_plan_create
- * allocates device memory or synchronises.  One plan must not be used by two threads
- * at once; separate plans are independent.
+ * the caller's next synchronisation, as HIP specifies.  Only wct_plan_create and the
+ * set-up call wct_plan_set_fft allocate device memory or synchronise.  One plan must
+ * not be used by two threads at once; separate plans are independent.
  */
 #ifndef WCT_H
 #define WCT_H
@@ -111,9 +111,10 @@ typedef struct {
 int wct_plane_info(const wct_plan* plan, int32_t plane, int64_t out[10]);
 
 /* Build a plan: validates the geometry, copies the responses and pre-computes, on the
- * device, the response spectrum of every plane (Eq. 2: "pre-calculated detector
- * response function in the frequency domain").  The only call that allocates device
- * memory or synchronises.  On failure *out is NULL. */
+ * device, the response spectrum of every plane (Eq. 2 takes the response in the
+ * frequency domain, transformed once ahead of the per-event work).  Allocates device
+ * memory and synchronises (as does wct_plan_set_fft; no run call does).  On failure
+ * *out is NULL. */
 int wct_plan_create(const wct_plan_desc* desc, wct_plan** out);
 void wct_plan_destroy(wct_plan* plan); /* NULL is a no-op; synchronises the device */
 
@@ -171,6 +172,24 @@ int wct_profile_enable(wct_plan* plan, int32_t enable);
 int wct_profile_reset(wct_plan* plan);
 int wct_profile_count(wct_plan* plan);
 int wct_profile_get(wct_plan* plan, int32_t idx, char* name, size_t name_len, double* total_ms, int64_t* launches);
+
+/* Transform variants.  The Stockham transforms of Eq. 2 along ticks (kind 0: passes A
+ * and C, half-length complex transforms of length L_t/2) and along wires (kind 1:
+ * pass B, length L_w) run either a runtime plan (any 2,3,5-smooth length) or one of the
+ * plans compiled into the library, whose radices and block size are fixed at build
+ * time.  A plan starts with the first compiled variant that matches each length, or
+ * the runtime plan when none does; every choice computes the same transform (results
+ * differ by floating-point rounding only).
+ * wct_fft_variant_info(idx, out[12]) fills out = {kind, is_double, threads per block,
+ * length, number of passes, radices[0..6] (0-padded)} (HOST buffer).
+ * wct_plan_get_fft reports a plane's current choice (-1 = runtime plan);
+ * wct_plan_set_fft selects one: -1 or a variant of that kind, dtype and length, else
+ * WCT_E_INVALID.  set_fft allocates the new twiddle tables and synchronises the device;
+ * it is a set-up call (for example for an autotuner), not a run call. */
+int wct_fft_variant_count(void);
+int wct_fft_variant_info(int32_t idx, int32_t* out);
+int wct_plan_get_fft(const wct_plan* plan, int32_t plane, int32_t kind, int32_t* variant);
+int wct_plan_set_fft(wct_plan* plan, int32_t plane, int32_t kind, int32_t variant);
 
 /* Thread-local text of the last error on this thread ("" if none). */
 const char* wct_last_error(void);

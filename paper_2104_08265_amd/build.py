@@ -17,6 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libwct.so")
+DIGEST = os.path.join(PKG, "libwct.sha256")  # digest of the sources libwct.so was built from
 
 ARCH = "gfx950"
 COMMON = [
@@ -32,9 +33,22 @@ SOURCES = {
     "api.cpp": ["-x", "hip"],
     "raster.hip": ["-ffp-contract=off"],
     "conv.hip": [],
+    "conv_ct.hip": [],
     "plan.hip": [],
     "grad.hip": [],
 }
+
+
+def sources_digest() -> str:
+    """SHA-256 over the kernel and ABI sources (names and contents)."""
+    import hashlib
+    h = hashlib.sha256()
+    for d in (CSRC, INCLUDE):
+        for name in sorted(os.listdir(d)):
+            if name.endswith((".hip", ".hpp", ".cpp", ".h")):
+                with open(os.path.join(d, name), "rb") as f:
+                    h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
 
 
 def hipcc() -> str:
@@ -58,6 +72,7 @@ def _compile(src: str, flags: list[str], verbose: bool) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every source and link libwct.so; returns the library path."""
     os.makedirs(BUILD_DIR, exist_ok=True)
+    digest = sources_digest()
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda kv: _compile(kv[0], kv[1], verbose), SOURCES.items()))
     tmp = LIB + ".tmp"
@@ -68,6 +83,8 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"linking libwct.so failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    with open(DIGEST, "w") as f:
+        f.write(digest + "\n")
     return LIB
 
 

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "fftplan.hpp"
+#include "fftvariants.hpp"
 #include "kernels.hpp"
 #include "wct.h"
 
@@ -131,7 +132,7 @@ struct wct_plan {
   size_t esize = 4;  // bytes of one real value
   std::vector<PlaneGeom> geom;
   std::vector<FftPlan> fp_t, fp_w;
-  std::vector<void*> tw_t, post_t, tw_w, rtil;
+  std::vector<void*> tw_t, post_t, tw_w, tw_w_rev, rtil;
   DetTables* d_tables = nullptr;
   std::vector<void*> allocs;
   int64_t grid_elems = 0, wave_elems = 0, shat_elems = 0, mhat_elems = 0;
@@ -290,6 +291,7 @@ int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, 
     const cx<T>* tw_t = static_cast<const cx<T>*>(P->tw_t[p]);
     const cx<T>* post = static_cast<const cx<T>*>(P->post_t[p]);
     const cx<T>* tw_w = static_cast<const cx<T>*>(P->tw_w[p]);
+    const cx<T>* tw_wr = static_cast<const cx<T>*>(P->tw_w_rev[p]);
     PROF_LAUNCH(P, "rows_r2c", st,
                 launch_rows_r2c<T>(grid + G.grid_off, P->grid_elems, shat + G.shat_off, P->shat_elems, G.nt, G.I,
                                    G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, P->n_cu, st),
@@ -297,7 +299,7 @@ int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, 
     PROF_LAUNCH(P, "colpass", st,
                 launch_colpass<T>(shat + G.shat_off, P->shat_elems, static_cast<const cx<T>*>(P->rtil[p]),
                                   mhat + G.mhat_off, P->mhat_elems, G.nw, G.I, G.nchunk, n_events, P->fp_w[p], tw_w,
-                                  st),
+                                  tw_wr, st),
                 "column pass launch");
     PROF_LAUNCH(P, "rows_c2r", st,
                 launch_rows_c2r<T>(mhat + G.mhat_off, P->mhat_elems, wave + G.wave_off, P->wave_elems, G.nt, false,
@@ -319,6 +321,7 @@ int run_backward(wct_plan* P, const wct_depos* d, const wct_opts* o, const T* gw
     const cx<T>* tw_t = static_cast<const cx<T>*>(P->tw_t[p]);
     const cx<T>* post = static_cast<const cx<T>*>(P->post_t[p]);
     const cx<T>* tw_w = static_cast<const cx<T>*>(P->tw_w[p]);
+    const cx<T>* tw_wr = static_cast<const cx<T>*>(P->tw_w_rev[p]);
     PROF_LAUNCH(P, "adj_rows_r2c", st,
                 launch_rows_r2c<T>(gw + G.wave_off, P->wave_elems, ghat + G.mhat_off, P->mhat_elems, G.nt, 1, G.nw,
                                    G.nchunk, ne, P->fp_t[p], tw_t, post, P->n_cu, st),
@@ -326,7 +329,7 @@ int run_backward(wct_plan* P, const wct_depos* d, const wct_opts* o, const T* gw
     PROF_LAUNCH(P, "adj_colpass", st,
                 launch_colpass_adj<T>(ghat + G.mhat_off, P->mhat_elems, static_cast<const cx<T>*>(P->rtil[p]),
                                       hhat + G.shat_off, P->shat_elems, G.nw, G.I, G.nchunk, ne, P->fp_w[p], tw_w,
-                                      st),
+                                      tw_wr, st),
                 "adjoint column pass launch");
     PROF_LAUNCH(P, "adj_rows_c2r", st,
                 launch_rows_c2r<T>(hhat + G.shat_off, P->shat_elems, H + G.grid_off, P->grid_elems, G.nt, true, G.I,
@@ -352,6 +355,71 @@ int upload_table(wct_plan* P, const std::vector<cx<double>>& h, void** out) {
   return WCT_OK;
 }
 
+// First compiled variant of a kind, precision and length, or -1.
+int find_variant(int kind, bool dbl, int n) {
+  int cnt = 0;
+  const FftVariantDesc* v = fft_variants(&cnt);
+  for (int i = 0; i < cnt; ++i)
+    if (v[i].kind == kind && v[i].dbl == (int)dbl && v[i].n == n) return i;
+  return -1;
+}
+
+void free_table(wct_plan* P, void* d) {
+  if (!d) return;
+  for (size_t i = 0; i < P->allocs.size(); ++i)
+    if (P->allocs[i] == d) {
+      (void)hipFree(d);
+      P->allocs.erase(P->allocs.begin() + i);
+      return;
+    }
+}
+
+// (Re)builds the transform plan and twiddle tables of plane p along ticks (kind 0) or
+// wires (kind 1): compiled variant v, or the runtime plan (v < 0).  Column variants
+// also get the table of their radices reversed (the inverse transform's plan).
+template <typename T>
+int set_fft(wct_plan* P, int p, int kind, int v) {
+  const PlaneGeom& G = P->geom[p];
+  const int n = kind == 0 ? G.M : G.lw;
+  FftPlan fp;
+  std::vector<cx<double>> tw, twr;
+  if (v >= 0) {
+    int cnt = 0;
+    const FftVariantDesc* vd = fft_variants(&cnt);
+    if (v >= cnt || vd[v].kind != kind || vd[v].dbl != (int)(sizeof(T) == 8) || vd[v].n != n)
+      return fail(WCT_E_INVALID, "transform variant %d does not apply to plane %d kind %d (length %d)", v, p, kind,
+                  n);
+    if (!build_fft_variant(vd[v], v, fp, tw)) return fail(WCT_E_INVALID, "transform variant %d: bad plan", v);
+    std::vector<int> rad(vd[v].radix, vd[v].radix + vd[v].npass);
+    std::reverse(rad.begin(), rad.end());
+    FftPlan fr;
+    if (kind == 1 && !build_fft_radices(n, rad, fr, twr))
+      return fail(WCT_E_INVALID, "transform variant %d: bad reversed plan", v);
+  } else if (!build_fft(n, 0, fp, tw)) {
+    return fail(WCT_E_UNSUPPORTED, "plane %d: length %d not 2,3,5-smooth", p, n);
+  }
+  void* d = nullptr;
+  int rc = upload_table<T>(P, tw, &d);
+  if (rc) return rc;
+  void* dr = d;
+  if (!twr.empty()) {
+    rc = upload_table<T>(P, twr, &dr);
+    if (rc) return rc;
+  }
+  if (kind == 0) {
+    free_table(P, P->tw_t[p]);
+    P->fp_t[p] = fp;
+    P->tw_t[p] = d;
+  } else {
+    if (P->tw_w_rev[p] != P->tw_w[p]) free_table(P, P->tw_w_rev[p]);
+    free_table(P, P->tw_w[p]);
+    P->fp_w[p] = fp;
+    P->tw_w[p] = d;
+    P->tw_w_rev[p] = dr;
+  }
+  return WCT_OK;
+}
+
 template <typename T>
 int plan_tables(wct_plan* P, const wct_plan_desc* desc) {
   const size_t lds_max = 160 * 1024;
@@ -361,24 +429,21 @@ int plan_tables(wct_plan* P, const wct_plan_desc* desc) {
       return fail(WCT_E_UNSUPPORTED, "plane %d: tick transform length %d exceeds the LDS-resident limit", p, G.lt);
     if ((size_t)G.lw * kChunk * sizeof(cx<T>) > lds_max || !conv_fits<T>(G.lw * kChunk))
       return fail(WCT_E_UNSUPPORTED, "plane %d: wire transform length %d exceeds the LDS-resident limit", p, G.lw);
-    std::vector<cx<double>> tw;
-    FftPlan fp;
-    if (!build_fft(G.M, 0, fp, tw)) return fail(WCT_E_UNSUPPORTED, "plane %d: length %d not 2,3,5-smooth", p, G.M);
-    P->fp_t.push_back(fp);
-    void* d = nullptr;
-    int rc = upload_table<T>(P, tw, &d);
+    P->fp_t.emplace_back();
+    P->fp_w.emplace_back();
+    P->tw_t.push_back(nullptr);
+    P->tw_w.push_back(nullptr);
+    P->tw_w_rev.push_back(nullptr);
+    int rc = set_fft<T>(P, p, 0, find_variant(0, sizeof(T) == 8, G.M));
     if (rc) return rc;
-    P->tw_t.push_back(d);
+    rc = set_fft<T>(P, p, 1, find_variant(1, sizeof(T) == 8, G.lw));
+    if (rc) return rc;
     std::vector<cx<double>> post(G.M + 1);
     for (int k = 0; k <= G.M; ++k) post[k] = wexp(k, G.lt);
+    void* d = nullptr;
     rc = upload_table<T>(P, post, &d);
     if (rc) return rc;
     P->post_t.push_back(d);
-    if (!build_fft(G.lw, 0, fp, tw)) return fail(WCT_E_UNSUPPORTED, "plane %d: length %d not 2,3,5-smooth", p, G.lw);
-    P->fp_w.push_back(fp);
-    rc = upload_table<T>(P, tw, &d);
-    if (rc) return rc;
-    P->tw_w.push_back(d);
 
     // response spectrum, FP64 on the device, stored in the plan dtype
     const wct_plane_desc& pd = desc->planes[p];
@@ -646,6 +711,49 @@ int wct_simulate_backward(wct_plan* plan, const wct_depos* depos, const wct_opts
   return run_backward<double>(plan, depos, opts, static_cast<const double*>(grad_wave), static_cast<double*>(g_q),
                               static_cast<double*>(g_t), static_cast<double*>(g_p), static_cast<double*>(g_sigma_t),
                               static_cast<double*>(g_sigma_p), cv, st);
+}
+
+int wct_fft_variant_count(void) {
+  int cnt = 0;
+  (void)fft_variants(&cnt);
+  return cnt;
+}
+
+int wct_fft_variant_info(int32_t idx, int32_t* out) {
+  g_err.clear();
+  int cnt = 0;
+  const FftVariantDesc* v = fft_variants(&cnt);
+  if (!out) return fail(WCT_E_INVALID, "out is NULL");
+  if (idx < 0 || idx >= cnt) return fail(WCT_E_INVALID, "variant index %d out of range [0, %d)", idx, cnt);
+  std::memset(out, 0, sizeof(int32_t) * 12);
+  out[0] = v[idx].kind;
+  out[1] = v[idx].dbl;
+  out[2] = v[idx].threads;
+  out[3] = v[idx].n;
+  out[4] = v[idx].npass;
+  for (int k = 0; k < v[idx].npass && k < 7; ++k) out[5 + k] = v[idx].radix[k];
+  return WCT_OK;
+}
+
+int wct_plan_get_fft(const wct_plan* plan, int32_t plane, int32_t kind, int32_t* variant) {
+  g_err.clear();
+  if (!plan || !variant) return fail(WCT_E_INVALID, "plan or variant is NULL");
+  if (plane < 0 || plane >= plan->n_planes || (kind != 0 && kind != 1))
+    return fail(WCT_E_INVALID, "plane %d / kind %d out of range", plane, kind);
+  *variant = kind == 0 ? plan->fp_t[plane].variant : plan->fp_w[plane].variant;
+  return WCT_OK;
+}
+
+int wct_plan_set_fft(wct_plan* plan, int32_t plane, int32_t kind, int32_t variant) {
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  if (plane < 0 || plane >= plan->n_planes || (kind != 0 && kind != 1))
+    return fail(WCT_E_INVALID, "plane %d / kind %d out of range", plane, kind);
+  DeviceGuard dg(plan->device);
+  const hipError_t e = hipDeviceSynchronize();  // tables may be in use by queued work
+  if (e != hipSuccess) return hip_fail(e, "synchronise before replacing twiddle tables");
+  return plan->dtype == WCT_F32 ? set_fft<float>(plan, plane, kind, variant < 0 ? -1 : variant)
+                                : set_fft<double>(plan, plane, kind, variant < 0 ? -1 : variant);
 }
 
 int wct_profile_enable(wct_plan* plan, int32_t enable) {

@@ -45,6 +45,7 @@ __host__ __device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return mk(a.x * 
 constexpr int kMaxPass = 16;
 struct FftPlan {
   int n;
+  int variant;  // index of a compiled variant with this plan, or -1 (runtime plan)
   int npass;
   int radix[kMaxPass];
   int tw_off[kMaxPass];

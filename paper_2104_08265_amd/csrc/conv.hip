@@ -18,60 +18,30 @@
 // The backward (adjoint) variants reuse the passes: rows of dL/dM through pass A, a
 // column pass that transforms once and applies conj(R~_i) per phase, and pass C over
 // the I*N_w impact rows of the column-chunk layout.
-#include "fft.hpp"
-#include "kernels.hpp"
+#include "convcommon.hpp"
 
 namespace wct {
-
-// Blocks are dispatched to the 8 XCDs round-robin; map them so that consecutive
-// logical indices share an XCD (and its L2).
-__device__ __forceinline__ int xcd_remap(int b, int nblk) {
-  const int q = nblk >> 3, r = nblk & 7;
-  const int xcd = b & 7, pos = b >> 3;
-  return xcd < r ? xcd * (q + 1) + pos : r * (q + 1) + (xcd - r) * q + pos;
-}
-
-// 16-byte vector of the real type (4 floats or 2 doubles) for row loads: a clang vector,
-// so register arrays of it stay in registers.
-template <typename T>
-struct Vec16 {
-  static constexpr int n = 16 / sizeof(T);
-  typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
-};
-
-// Complex value as a clang 2-vector for register arrays (aggregates there can end up in
-// scratch memory).
-template <typename T>
-using cv2 = T __attribute__((ext_vector_type(2)));
-template <typename T>
-__device__ __forceinline__ cv2<T> to_v(cx<T> a) {
-  cv2<T> r;
-  r.x = a.x;
-  r.y = a.y;
-  return r;
-}
-template <typename T>
-__device__ __forceinline__ cx<T> from_v(cv2<T> a) { return mk(a.x, a.y); }
 
 // ---------------------------------------------------------------------------
 // Pass A: real rows -> half spectra, column-chunk layout.  Persistent: a workgroup
 // walks rows L = first + k * gridDim.x; the next row is loaded into registers while the
 // current one is transformed, so HBM reads overlap the LDS work.
 // ---------------------------------------------------------------------------
-template <typename T, int C, int E>
-__global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_rows_r2c(const T* __restrict__ src, int64_t src_ev_stride,
+template <typename T, int C, typename F>
+__global__ void __launch_bounds__(F::kBound) k_rows_r2c(const T* __restrict__ src, int64_t src_ev_stride,
                                                    cx<T>* __restrict__ dst, int64_t dst_ev_stride, int nt,
-                                                   int nphase, int nper, int nchunk, int n_events, FftPlan plan,
+                                                   int nphase, int nper, int nchunk, int n_events, F f,
                                                    const cx<T>* __restrict__ tw,
                                                    const cx<T>* __restrict__ post) {
   using V = typename Vec16<T>::type;
   constexpr int VN = Vec16<T>::n;
-  constexpr int PF = (2 * E + VN - 1) / VN;  // 16-byte loads per thread: a row has <= 2 E reals per thread
+  constexpr int PF = (2 * F::E + VN - 1) / VN;  // 16-byte loads per thread: a row has <= 2 E reals per thread
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* z = reinterpret_cast<cx<T>*>(smem_raw);
   T* zr = reinterpret_cast<T*>(smem_raw);
   V* zv = reinterpret_cast<V*>(smem_raw);
-  const int M = plan.n;
+  const int M = f.n();
+  const int nthr = f.nthr();
   const int rows = nphase * nper;
   const int total = rows * n_events;
   // Rows whose length or base is not a multiple of 16 bytes are read with scalar loads
@@ -86,7 +56,7 @@ __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_rows_r2c(const T
     const V* s = reinterpret_cast<const V*>(src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt);
 #pragma unroll
     for (int q = 0; q < PF; ++q) {  // unconditional (clamped) loads keep pre[] in registers
-      const int u = threadIdx.x + q * blockDim.x;
+      const int u = threadIdx.x + q * nthr;
       pre[q] = s[u < ntv ? u : 0];
     }
   }
@@ -96,13 +66,13 @@ __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_rows_r2c(const T
     if (vec) {
 #pragma unroll
       for (int q = 0; q < PF; ++q) {
-        const int u = threadIdx.x + q * blockDim.x;
+        const int u = threadIdx.x + q * nthr;
         if (u < ntv) zv[u] = pre[q];
       }
-      for (int u = ntv * VN + threadIdx.x; u < 2 * M; u += blockDim.x) zr[u] = T(0);
+      for (int u = ntv * VN + threadIdx.x; u < 2 * M; u += nthr) zr[u] = T(0);
     } else {
       const T* s = src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt;
-      for (int u = threadIdx.x; u < 2 * M; u += blockDim.x) zr[u] = u < nt ? s[u] : T(0);
+      for (int u = threadIdx.x; u < 2 * M; u += nthr) zr[u] = u < nt ? s[u] : T(0);
     }
     __syncthreads();
     const int Ln = L + gridDim.x;
@@ -112,14 +82,14 @@ __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_rows_r2c(const T
       const V* s = reinterpret_cast<const V*>(src + evn * src_ev_stride + ((int64_t)cn * nphase + in) * nt);
 #pragma unroll
       for (int q = 0; q < PF; ++q) {
-        const int u = threadIdx.x + q * blockDim.x;
+        const int u = threadIdx.x + q * nthr;
         pre[q] = s[u < ntv ? u : 0];
       }
     }
-    fft_lds<T, false, 1, E>(z, plan, tw);
+    f.template run<false>(z, tw);
     cx<T>* out = dst + ev * dst_ev_stride;
     const int fpad = nchunk * C;
-    for (int k = threadIdx.x; k < fpad; k += blockDim.x) {
+    for (int k = threadIdx.x; k < fpad; k += nthr) {
       cx<T> X = mk(T(0), T(0));
       if (k <= M) {
         const cx<T> A = z[k == M ? 0 : k];
@@ -142,14 +112,16 @@ __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_rows_r2c(const T
 // The next phase's S-hat block and the current phase's spectrum are loaded into
 // registers while the current phase is transformed (PF, for small register budgets E).
 // ---------------------------------------------------------------------------
-template <typename T, int C, int E, bool PF>
-__global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_colpass(const cx<T>* __restrict__ shat, int64_t shat_ev_stride,
+template <typename T, int C, typename F, bool PF>
+__global__ void __launch_bounds__(F::kBound) k_colpass(const cx<T>* __restrict__ shat, int64_t shat_ev_stride,
                                                   const cx<T>* __restrict__ rtil, cx<T>* __restrict__ mhat,
                                                   int64_t mhat_ev_stride, int nw, int nphase, int nchunk,
-                                                  FftPlan plan, const cx<T>* __restrict__ tw) {
+                                                  F f, const cx<T>* __restrict__ tw) {
+  constexpr int E = F::E;
+  const int nthr = f.nthr();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  const int lw = plan.n;
+  const int lw = f.n();
   const int ne = lw * C;
   const int nin = nw * C;
   const int ch = blockIdx.x;
@@ -162,7 +134,7 @@ __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_colpass(const cx
   if (PFS) {
 #pragma unroll
     for (int q = 0; q < E; ++q) {
-      const int idx = threadIdx.x + q * blockDim.x;
+      const int idx = threadIdx.x + q * nthr;
       sreg[PFS ? q : 0] = to_v(idx < nin ? src[idx] : mk(T(0), T(0)));
     }
   }
@@ -170,7 +142,7 @@ __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_colpass(const cx
     const cx<T>* s = src + (int64_t)i * nin;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
-      const int idx = threadIdx.x + q * blockDim.x;
+      const int idx = threadIdx.x + q * nthr;
       if (idx < ne) buf[idx] = PFS ? from_v(sreg[PFS ? q : 0]) : (idx < nin ? s[idx] : mk(T(0), T(0)));
     }
     __syncthreads();
@@ -179,7 +151,7 @@ __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_colpass(const cx
     if (PF) {
 #pragma unroll
       for (int q = 0; q < E; ++q) {
-        const int idx = threadIdx.x + q * blockDim.x;
+        const int idx = threadIdx.x + q * nthr;
         rreg[PF ? q : 0] = to_v(r[idx < ne ? idx : 0]);
       }
     }
@@ -187,28 +159,28 @@ __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_colpass(const cx
       const cx<T>* sn = s + nin;
 #pragma unroll
       for (int q = 0; q < E; ++q) {
-        const int idx = threadIdx.x + q * blockDim.x;
+        const int idx = threadIdx.x + q * nthr;
         sreg[PFS ? q : 0] = to_v(idx < nin ? sn[idx] : mk(T(0), T(0)));
       }
     }
-    fft_lds<T, false, C, E>(buf, plan, tw);
+    f.template run<false>(buf, tw);
 #pragma unroll
     for (int q = 0; q < E; ++q) {
-      const int idx = threadIdx.x + q * blockDim.x;
+      const int idx = threadIdx.x + q * nthr;
       if (idx < ne) acc[q] = acc[q] + to_v(cmul(buf[idx], PF ? from_v(rreg[PF ? q : 0]) : r[idx]));
     }
     __syncthreads();
   }
 #pragma unroll
   for (int q = 0; q < E; ++q) {
-    const int idx = threadIdx.x + q * blockDim.x;
+    const int idx = threadIdx.x + q * nthr;
     if (idx < ne) buf[idx] = from_v(acc[q]);
   }
   __syncthreads();
-  fft_lds<T, true, C, E>(buf, plan, tw);
+  f.template run<true>(buf, tw);
   cx<T>* dst = mhat + blockIdx.y * mhat_ev_stride;
   const int fpad = nchunk * C;
-  for (int idx = threadIdx.x; idx < nin; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < nin; idx += nthr) {
     const int w = idx / C, cc = idx - (idx / C) * C;
     dst[(int64_t)w * fpad + ch * C + cc] = buf[idx];
   }
@@ -218,25 +190,27 @@ __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_colpass(const cx
 // Pass B (adjoint): one transform of dL/dM-hat along wires, conj(R~_i) per phase,
 // inverse transform per phase into the column-chunk layout
 // ---------------------------------------------------------------------------
-template <typename T, int C, int E>
-__global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_colpass_adj(const cx<T>* __restrict__ ghat, int64_t ghat_ev_stride,
+template <typename T, int C, typename F>
+__global__ void __launch_bounds__(F::kBound) k_colpass_adj(const cx<T>* __restrict__ ghat, int64_t ghat_ev_stride,
                                                       const cx<T>* __restrict__ rtil, cx<T>* __restrict__ hhat,
                                                       int64_t hhat_ev_stride, int nw, int nphase, int nchunk,
-                                                      FftPlan plan, const cx<T>* __restrict__ tw) {
+                                                      F f, const cx<T>* __restrict__ tw) {
+  constexpr int E = F::E;
+  const int nthr = f.nthr();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  const int lw = plan.n;
+  const int lw = f.n();
   const int ne = lw * C;
   const int nin = nw * C;
   const int ch = blockIdx.x;
   const cx<T>* s = ghat + blockIdx.y * ghat_ev_stride + (int64_t)ch * nin;
-  for (int idx = threadIdx.x; idx < ne; idx += blockDim.x) buf[idx] = idx < nin ? s[idx] : mk(T(0), T(0));
+  for (int idx = threadIdx.x; idx < ne; idx += nthr) buf[idx] = idx < nin ? s[idx] : mk(T(0), T(0));
   __syncthreads();
-  fft_lds<T, false, C, E>(buf, plan, tw);
+  f.template run<false>(buf, tw);
   cv2<T> g[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) {
-    const int idx = threadIdx.x + q * blockDim.x;
+    const int idx = threadIdx.x + q * nthr;
     g[q] = to_v(buf[idx < ne ? idx : 0]);
   }
   __syncthreads();
@@ -246,13 +220,13 @@ __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_colpass_adj(cons
     const cx<T>* r = rt + (int64_t)i * ne;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
-      const int idx = threadIdx.x + q * blockDim.x;
+      const int idx = threadIdx.x + q * nthr;
       if (idx < ne) buf[idx] = cmulc(from_v(g[q]), r[idx]);
     }
     __syncthreads();
-    fft_lds<T, true, C, E>(buf, plan, tw);
+    f.template run<true>(buf, tw);
     cx<T>* d = dst + (int64_t)i * nin;
-    for (int idx = threadIdx.x; idx < nin; idx += blockDim.x) d[idx] = buf[idx];
+    for (int idx = threadIdx.x; idx < nin; idx += nthr) d[idx] = buf[idx];
     __syncthreads();
   }
 }
@@ -261,16 +235,17 @@ __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_colpass_adj(cons
 // Pass C: half spectra -> real rows.  Input either wire-major rows [w][fpad]
 // (TILED = false) or the column-chunk layout [chunk][phase][c][C] (TILED = true).
 // ---------------------------------------------------------------------------
-template <typename T, int C, bool TILED, int E>
-__global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_rows_c2r(const cx<T>* __restrict__ src, int64_t src_ev_stride,
+template <typename T, int C, bool TILED, typename F>
+__global__ void __launch_bounds__(F::kBound) k_rows_c2r(const cx<T>* __restrict__ src, int64_t src_ev_stride,
                                                    T* __restrict__ dst, int64_t dst_ev_stride, int nt,
-                                                   int nphase, int nper, int nchunk, FftPlan plan,
+                                                   int nphase, int nper, int nchunk, F f,
                                                    const cx<T>* __restrict__ tw,
                                                    const cx<T>* __restrict__ post) {
+  const int nthr = f.nthr();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* z = reinterpret_cast<cx<T>*>(smem_raw);
   T* zr = reinterpret_cast<T*>(smem_raw);
-  const int M = plan.n;
+  const int M = f.n();
   const int L = TILED ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
   const int i = L / nper, c = L - (L / nper) * nper;
   const int64_t row = TILED ? (int64_t)c * nphase + i : (int64_t)L;
@@ -280,7 +255,7 @@ __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_rows_c2r(const c
     if (TILED) return in[(((int64_t)(k / C) * nphase + i) * nper + c) * C + (k % C)];
     return in[(int64_t)L * fpad + k];
   };
-  for (int k = threadIdx.x; k < M; k += blockDim.x) {
+  for (int k = threadIdx.x; k < M; k += nthr) {
     const cx<T> A = X(k);
     const cx<T> B = conj(X(M - k));
     const cx<T> Ev = A + B;
@@ -288,13 +263,14 @@ __global__ void __launch_bounds__((LaunchBound<T, E>::value)) k_rows_c2r(const c
     z[k] = mk(Ev.x - O.y, Ev.y + O.x);      // Ev + i*O
   }
   __syncthreads();
-  fft_lds<T, true, 1, E>(z, plan, tw);
+  f.template run<true>(z, tw);
   T* out = dst + blockIdx.y * dst_ev_stride + row * nt;
-  for (int n = threadIdx.x; n < nt; n += blockDim.x) out[n] = zr[n];
+  for (int n = threadIdx.x; n < nt; n += nthr) out[n] = zr[n];
 }
 
 // ---------------------------------------------------------------------------
-// host launchers: pick the smallest register budget E whose block fits
+// host launchers: the plan's compiled variant, or the runtime plan with the smallest
+// register budget E whose block fits
 // ---------------------------------------------------------------------------
 template <typename T>
 static int pick_e(int elems) {
@@ -318,113 +294,153 @@ bool conv_fits(int elems) { return pick_e<T>(elems) > 0; }
 template bool conv_fits<float>(int);
 template bool conv_fits<double>(int);
 
-#define WCT_DISPATCH_E(T, elems, CALL)          \
-  switch (pick_e<T>(elems)) {                  \
-    case 8: { constexpr int E_ = 8; CALL; break; }   \
-    case 16: { constexpr int E_ = 16; CALL; break; } \
-    case 24: if constexpr (sizeof(T) == 4) { constexpr int E_ = 24; CALL; } break; \
-    case 32: if constexpr (sizeof(T) == 4) { constexpr int E_ = 32; CALL; } break; \
-    default: return hipErrorInvalidValue;      \
-  }
+// Column passes keep the next phase and the spectrum in registers when E is small.
+template <typename T, typename F>
+constexpr bool colpass_prefetch() { return sizeof(T) == 4 ? (F::E > 8 && F::E <= 16) : F::E <= 8; }
 
-// Persistent grid: as many workgroups as fit on the device at once (LDS and waves).
-static int persistent_blocks(int n_cu, size_t lds, int threads, int work) {
-  int per_cu = (int)((160 * 1024) / (lds > 0 ? lds : 1));
-  const int waves = (threads + 63) / 64;
-  if (per_cu * waves > 32) per_cu = 32 / waves;
-  if (per_cu < 1) per_cu = 1;
-  if (per_cu > 8) per_cu = 8;
-  const int g = n_cu * per_cu;
-  return work < g ? work : g;
+// Calls fn(policy, threads) with the runtime plan and the smallest register budget E
+// whose block fits (KIND 0: rows, 1: columns).
+template <typename T, int KIND, typename Fn>
+static hipError_t with_fft(const FftPlan& plan, Fn&& fn) {
+  constexpr int CI = KIND == 0 ? 1 : kChunk;
+  const int elems = plan.n * CI;
+  switch (pick_e<T>(elems)) {
+    case 8: fn(RtFft<T, CI, 8>{plan}, threads_for(elems, 8)); return hipSuccess;
+    case 16: fn(RtFft<T, CI, 16>{plan}, threads_for(elems, 16)); return hipSuccess;
+    case 24:
+      if constexpr (sizeof(T) == 4) {
+        fn(RtFft<T, CI, 24>{plan}, threads_for(elems, 24));
+        return hipSuccess;
+      }
+      break;
+    case 32:
+      if constexpr (sizeof(T) == 4) {
+        fn(RtFft<T, CI, 32>{plan}, threads_for(elems, 32));
+        return hipSuccess;
+      }
+      break;
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+
+// Every runtime policy of one kind and type (for per-kernel set-up).
+template <typename T, int KIND, typename Fn>
+static void for_all_fft(Fn&& fn) {
+  constexpr int CI = KIND == 0 ? 1 : kChunk;
+  fn(RtFft<T, CI, 8>{});
+  fn(RtFft<T, CI, 16>{});
+  if constexpr (sizeof(T) == 4) {
+    fn(RtFft<T, CI, 24>{});
+    fn(RtFft<T, CI, 32>{});
+  }
 }
 
 template <typename T>
 hipError_t launch_rows_r2c(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt, int nphase,
                            int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
                            const cx<T>* post, int n_cu, hipStream_t st) {
+  if (plan.variant >= 0)
+    return launch_rows_r2c_ct<T>(src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, n_events, plan, tw,
+                                 post, n_cu, st);
   const size_t lds = sizeof(cx<T>) * plan.n;
   const int total = nphase * nper * n_events;
-  WCT_DISPATCH_E(T, plan.n,
-                 const int thr = threads_for(plan.n, E_);
-                 hipLaunchKernelGGL((k_rows_r2c<T, kChunk, E_>), dim3(persistent_blocks(n_cu, lds, thr, total)),
-                                    dim3(thr), lds, st, src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper,
-                                    nchunk, n_events, plan, tw, post))
-  return hipGetLastError();
+  const hipError_t e = with_fft<T, 0>(plan, [&](auto f, int thr) {
+    using F = decltype(f);
+    hipLaunchKernelGGL((k_rows_r2c<T, kChunk, F>), dim3(persistent_blocks(n_cu, lds, thr, total)), dim3(thr), lds,
+                       st, src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, n_events, f, tw, post);
+  });
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_colpass(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtil, cx<T>* mhat,
                           int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, const FftPlan& plan,
-                          const cx<T>* tw, hipStream_t st) {
-  const int elems = plan.n * kChunk;
-  const size_t lds = sizeof(cx<T>) * elems;
+                          const cx<T>* tw, const cx<T>* tw_rev, hipStream_t st) {
+  if (plan.variant >= 0)
+    return launch_colpass_ct<T>(shat, shat_ev_stride, rtil, mhat, mhat_ev_stride, nw, nphase, nchunk, n_events, plan,
+                                tw, tw_rev, st);
+  const size_t lds = sizeof(cx<T>) * plan.n * kChunk;
   const dim3 grid(nchunk, n_events);
-  WCT_DISPATCH_E(T, elems,
-                 hipLaunchKernelGGL((k_colpass<T, kChunk, E_, (sizeof(T) == 4 ? E_ == 16 : E_ == 8)>), grid, dim3(threads_for(elems, E_)), lds,
-                                    st, shat, shat_ev_stride, rtil, mhat, mhat_ev_stride, nw, nphase, nchunk, plan,
-                                    tw))
-  return hipGetLastError();
+  const hipError_t e = with_fft<T, 1>(plan, [&](auto f, int thr) {
+    using F = decltype(f);
+    hipLaunchKernelGGL((k_colpass<T, kChunk, F, colpass_prefetch<T, F>()>), grid, dim3(thr), lds, st, shat,
+                       shat_ev_stride, rtil, mhat, mhat_ev_stride, nw, nphase, nchunk, f, tw);
+  });
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_colpass_adj(const cx<T>* ghat, int64_t ghat_ev_stride, const cx<T>* rtil, cx<T>* hhat,
                               int64_t hhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
-                              const FftPlan& plan, const cx<T>* tw, hipStream_t st) {
-  const int elems = plan.n * kChunk;
-  const size_t lds = sizeof(cx<T>) * elems;
+                              const FftPlan& plan, const cx<T>* tw, const cx<T>* tw_rev, hipStream_t st) {
+  if (plan.variant >= 0)
+    return launch_colpass_adj_ct<T>(ghat, ghat_ev_stride, rtil, hhat, hhat_ev_stride, nw, nphase, nchunk, n_events,
+                                    plan, tw, tw_rev, st);
+  const size_t lds = sizeof(cx<T>) * plan.n * kChunk;
   const dim3 grid(nchunk, n_events);
-  WCT_DISPATCH_E(T, elems,
-                 hipLaunchKernelGGL((k_colpass_adj<T, kChunk, E_>), grid, dim3(threads_for(elems, E_)), lds, st,
-                                    ghat, ghat_ev_stride, rtil, hhat, hhat_ev_stride, nw, nphase, nchunk, plan, tw))
-  return hipGetLastError();
+  const hipError_t e = with_fft<T, 1>(plan, [&](auto f, int thr) {
+    using F = decltype(f);
+    hipLaunchKernelGGL((k_colpass_adj<T, kChunk, F>), grid, dim3(thr), lds, st, ghat, ghat_ev_stride, rtil, hhat,
+                       hhat_ev_stride, nw, nphase, nchunk, f, tw);
+  });
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_rows_c2r(const cx<T>* src, int64_t src_ev_stride, T* dst, int64_t dst_ev_stride, int nt,
                            bool tiled, int nphase, int nper, int nchunk, int n_events, const FftPlan& plan,
                            const cx<T>* tw, const cx<T>* post, hipStream_t st) {
+  if (plan.variant >= 0)
+    return launch_rows_c2r_ct<T>(src, src_ev_stride, dst, dst_ev_stride, nt, tiled, nphase, nper, nchunk, n_events,
+                                 plan, tw, post, st);
   const size_t lds = sizeof(cx<T>) * plan.n;
   const dim3 grid(nphase * nper, n_events);
-  if (tiled) {
-    WCT_DISPATCH_E(T, plan.n,
-                   hipLaunchKernelGGL((k_rows_c2r<T, kChunk, true, E_>), grid, dim3(threads_for(plan.n, E_)), lds, st,
-                                      src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, plan, tw, post))
-  } else {
-    WCT_DISPATCH_E(T, plan.n,
-                   hipLaunchKernelGGL((k_rows_c2r<T, kChunk, false, E_>), grid, dim3(threads_for(plan.n, E_)), lds,
-                                      st, src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, plan, tw,
-                                      post))
-  }
-  return hipGetLastError();
+  const hipError_t e = with_fft<T, 0>(plan, [&](auto f, int thr) {
+    using F = decltype(f);
+    if (tiled)
+      hipLaunchKernelGGL((k_rows_c2r<T, kChunk, true, F>), grid, dim3(thr), lds, st, src, src_ev_stride, dst,
+                         dst_ev_stride, nt, nphase, nper, nchunk, f, tw, post);
+    else
+      hipLaunchKernelGGL((k_rows_c2r<T, kChunk, false, F>), grid, dim3(thr), lds, st, src, src_ev_stride, dst,
+                         dst_ev_stride, nt, nphase, nper, nchunk, f, tw, post);
+  });
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
-template <typename T, int E>
-static void raise_lds_limit_e() {
+template <typename T>
+static void raise_lds_limits() {
   const int lim = 160 * 1024;
-  hipFuncSetAttribute((const void*)k_rows_r2c<T, kChunk, E>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_colpass<T, kChunk, E, (sizeof(T) == 4 ? E == 16 : E == 8)>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      lim);
-  hipFuncSetAttribute((const void*)k_colpass_adj<T, kChunk, E>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_rows_c2r<T, kChunk, true, E>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_rows_c2r<T, kChunk, false, E>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  for_all_fft<T, 0>([&](auto f) {
+    using F = decltype(f);
+    (void)hipFuncSetAttribute((const void*)k_rows_r2c<T, kChunk, F>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_rows_c2r<T, kChunk, true, F>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_rows_c2r<T, kChunk, false, F>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  });
+  for_all_fft<T, 1>([&](auto f) {
+    using F = decltype(f);
+    (void)hipFuncSetAttribute((const void*)k_colpass<T, kChunk, F, colpass_prefetch<T, F>()>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_colpass_adj<T, kChunk, F>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lim);
+  });
 }
 
 void conv_init_kernels() {
-  raise_lds_limit_e<float, 8>();
-  raise_lds_limit_e<float, 16>();
-  raise_lds_limit_e<float, 24>();
-  raise_lds_limit_e<float, 32>();
-  raise_lds_limit_e<double, 8>();
-  raise_lds_limit_e<double, 16>();
+  raise_lds_limits<float>();
+  raise_lds_limits<double>();
+  conv_ct_init_kernels();
 }
 
 #define WCT_INST(T)                                                                                            \
   template hipError_t launch_rows_r2c<T>(const T*, int64_t, cx<T>*, int64_t, int, int, int, int, int,          \
                                          const FftPlan&, const cx<T>*, const cx<T>*, int, hipStream_t);       \
   template hipError_t launch_colpass<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int, int,   \
-                                        int, const FftPlan&, const cx<T>*, hipStream_t);                       \
+                                        int, const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);         \
   template hipError_t launch_colpass_adj<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int,    \
-                                            int, int, const FftPlan&, const cx<T>*, hipStream_t);              \
+                                            int, int, const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);\
   template hipError_t launch_rows_c2r<T>(const cx<T>*, int64_t, T*, int64_t, int, bool, int, int, int, int,    \
                                          const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);
 WCT_INST(float)

@@ -1,0 +1,403 @@
+// The transform passes of conv.hip for the compiled plans of fftvariants.hpp.
+//
+// Same arithmetic, same layouts and same results as the runtime-plan kernels; the
+// difference is where values live between HBM and the transform.  A compiled plan
+// knows which elements each thread's first-pass butterflies read, so the kernels load
+// those straight from HBM into registers (no LDS staging), and its last pass leaves its
+// outputs in registers in a fixed arrangement:
+//   pass A:  HBM -> registers -> passes -> LDS -> post-twiddle -> HBM;
+//   pass B:  per phase HBM -> registers -> passes -> registers, multiplied by R~_i and
+//            summed in registers; the inverse transform runs with the radices reversed,
+//            so its first pass reads exactly the sums each thread holds, and its last pass
+//            writes HBM from registers;
+//   pass C:  pre-twiddle HBM -> registers -> passes -> registers -> HBM.
+#include "convcommon.hpp"
+
+namespace wct {
+
+// ---------------------------------------------------------------------------
+// Pass A (compiled plan).  Persistent over rows; the next row's first-pass inputs are
+// requested as soon as the current row's first pass has consumed its registers.
+// ---------------------------------------------------------------------------
+template <typename T, int C, typename F>
+__global__ void __launch_bounds__(F::kThreads) k_rows_r2c_ct(const T* __restrict__ src, int64_t src_ev_stride,
+                                                             cx<T>* __restrict__ dst, int64_t dst_ev_stride, int nt,
+                                                             int nphase, int nper, int nchunk, int n_events,
+                                                             const cx<T>* __restrict__ tw,
+                                                             const cx<T>* __restrict__ post) {
+  constexpr int M = F::N, NT = F::kThreads, R0 = F::R0;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* z = reinterpret_cast<cx<T>*>(smem_raw);
+  const int rows = nphase * nper;
+  const int total = rows * n_events;
+  // sample pairs (x[2m], x[2m+1]) are one 2-vector load when rows allow it
+  const bool v2 = (nt % 2) == 0 && (reinterpret_cast<uintptr_t>(src) % (2 * sizeof(T))) == 0 &&
+                  (src_ev_stride % 2) == 0;
+  cx<T> in[F::IN];
+  auto row_of = [&](int L, int& ev, int& i, int& c) {
+    ev = L / rows;
+    const int rin = L - ev * rows;
+    i = rin / nper;
+    c = rin - i * nper;
+  };
+  auto load = [&](int L) {
+    int ev, i, c;
+    row_of(L, ev, i, c);
+    const T* s = src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt;
+#pragma unroll
+    for (int q = 0; q < F::MB0; ++q) {
+      if (!F::in_ok(q)) continue;
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int m = F::in_elem(q, r);
+        if (v2) {
+          if (2 * m < nt) {
+            const cv2<T> p = *reinterpret_cast<const cv2<T>*>(s + 2 * m);
+            in[q * R0 + r] = mk(p.x, p.y);
+          } else {
+            in[q * R0 + r] = mk(T(0), T(0));
+          }
+        } else {
+          in[q * R0 + r] = mk(2 * m < nt ? s[2 * m] : T(0), 2 * m + 1 < nt ? s[2 * m + 1] : T(0));
+        }
+      }
+    }
+  };
+  int L = xcd_remap(blockIdx.x, gridDim.x);
+  if (L < total) load(L);
+  while (L < total) {
+    const int Ln = L + gridDim.x;
+    int ev, i, c;
+    row_of(L, ev, i, c);
+    F::template rl<false>(z, tw, in, [&]() {
+      if (Ln < total) load(Ln);
+    });
+    cx<T>* out = dst + ev * dst_ev_stride;
+    const int fpad = nchunk * C;
+    for (int k = threadIdx.x; k < fpad; k += NT) {
+      cx<T> X = mk(T(0), T(0));
+      if (k <= M) {
+        const cx<T> A = z[k == M ? 0 : k];
+        const cx<T> B = conj(z[k == 0 ? 0 : M - k]);
+        const cx<T> Ev = scale(A + B, T(0.5));
+        const cx<T> D = scale(A - B, T(0.5));
+        const cx<T> O = mk(D.y, -D.x);  // (A - B) / (2i)
+        X = Ev + cmul(post[k], O);
+      }
+      const int ch = k / C, cc = k - (k / C) * C;
+      out[(((int64_t)ch * nphase + i) * nper + c) * C + cc] = X;
+    }
+    __syncthreads();
+    L = Ln;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass B (compiled plan): phase transforms along wires, product with R~_i and phase
+// sum in registers, inverse transform with the reversed plan.
+// ---------------------------------------------------------------------------
+template <typename T, int C, typename F>
+__global__ void __launch_bounds__(F::kThreads) k_colpass_ct(const cx<T>* __restrict__ shat, int64_t shat_ev_stride,
+                                                            const cx<T>* __restrict__ rtil, cx<T>* __restrict__ mhat,
+                                                            int64_t mhat_ev_stride, int nw, int nphase, int nchunk,
+                                                            const cx<T>* __restrict__ tw,
+                                                            const cx<T>* __restrict__ tw_rev) {
+  using FI = typename F::Reverse;
+  constexpr int NE = F::N * C, R0 = F::R0, RL = F::RL;
+  static_assert(FI::R0 == RL && FI::IN == F::OUT, "the reversed plan must start where the forward one ends");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int nin = nw * C;
+  const int ch = blockIdx.x;
+  const cx<T>* src = shat + blockIdx.y * shat_ev_stride + (int64_t)ch * nphase * nin;
+  const cx<T>* rt = rtil + (int64_t)ch * nphase * NE;
+  cx<T> in[F::IN], out[F::OUT], acc[F::OUT];
+#pragma unroll
+  for (int u = 0; u < F::OUT; ++u) acc[u] = mk(T(0), T(0));
+  auto load = [&](const cx<T>* s) {
+#pragma unroll
+    for (int q = 0; q < F::MB0; ++q) {
+      if (!F::in_ok(q)) continue;
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int e = F::in_elem(q, r);
+        in[q * R0 + r] = e < nin ? s[e] : mk(T(0), T(0));
+      }
+    }
+  };
+  for (int i = 0; i < nphase; ++i) {
+    load(src + (int64_t)i * nin);
+    F::template rr<false>(buf, tw, in, out, []() {});
+    const cx<T>* r = rt + (int64_t)i * NE;
+#pragma unroll
+    for (int q = 0; q < F::MBL; ++q) {
+      if (!F::out_ok(q)) continue;
+#pragma unroll
+      for (int rr = 0; rr < RL; ++rr) acc[q * RL + rr] = acc[q * RL + rr] + cmul(out[q * RL + rr], r[F::out_elem(q, rr)]);
+    }
+    // keep the next phase's loads behind this product (register budget)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  cx<T> res[FI::OUT];
+  FI::template rr<true>(buf, tw_rev, acc, res, []() {});
+  cx<T>* dst = mhat + blockIdx.y * mhat_ev_stride;
+  const int fpad = nchunk * C;
+#pragma unroll
+  for (int q = 0; q < FI::MBL; ++q) {
+    if (!FI::out_ok(q)) continue;
+#pragma unroll
+    for (int r = 0; r < FI::RL; ++r) {
+      const int e = FI::out_elem(q, r);
+      if (e < nin) dst[(int64_t)(e / C) * fpad + ch * C + (e % C)] = res[q * FI::RL + r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass B adjoint (compiled plan): one forward transform of dL/dM-hat, then per phase
+// conj(R~_i) and an inverse transform with the reversed plan, written from registers.
+// ---------------------------------------------------------------------------
+template <typename T, int C, typename F>
+__global__ void __launch_bounds__(F::kThreads) k_colpass_adj_ct(const cx<T>* __restrict__ ghat,
+                                                                int64_t ghat_ev_stride,
+                                                                const cx<T>* __restrict__ rtil,
+                                                                cx<T>* __restrict__ hhat, int64_t hhat_ev_stride,
+                                                                int nw, int nphase, int nchunk,
+                                                                const cx<T>* __restrict__ tw,
+                                                                const cx<T>* __restrict__ tw_rev) {
+  using FI = typename F::Reverse;
+  constexpr int NE = F::N * C, R0 = F::R0, RL = F::RL;
+  static_assert(FI::R0 == RL && FI::IN == F::OUT, "the reversed plan must start where the forward one ends");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int nin = nw * C;
+  const int ch = blockIdx.x;
+  const cx<T>* s = ghat + blockIdx.y * ghat_ev_stride + (int64_t)ch * nin;
+  cx<T> in[F::IN], g[F::OUT];
+#pragma unroll
+  for (int q = 0; q < F::MB0; ++q) {
+    if (!F::in_ok(q)) continue;
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int e = F::in_elem(q, r);
+      in[q * R0 + r] = e < nin ? s[e] : mk(T(0), T(0));
+    }
+  }
+  F::template rr<false>(buf, tw, in, g, []() {});
+  const cx<T>* rt = rtil + (int64_t)ch * nphase * NE;
+  cx<T>* dst = hhat + blockIdx.y * hhat_ev_stride + (int64_t)ch * nphase * nin;
+  for (int i = 0; i < nphase; ++i) {
+    const cx<T>* r = rt + (int64_t)i * NE;
+    cx<T> h[FI::IN], res[FI::OUT];
+#pragma unroll
+    for (int q = 0; q < F::MBL; ++q) {
+      if (!F::out_ok(q)) continue;
+#pragma unroll
+      for (int rr = 0; rr < RL; ++rr) h[q * RL + rr] = cmulc(g[q * RL + rr], r[F::out_elem(q, rr)]);
+    }
+    FI::template rr<true>(buf, tw_rev, h, res, []() {});
+    cx<T>* d = dst + (int64_t)i * nin;
+#pragma unroll
+    for (int q = 0; q < FI::MBL; ++q) {
+      if (!FI::out_ok(q)) continue;
+#pragma unroll
+      for (int r2 = 0; r2 < FI::RL; ++r2) {
+        const int e = FI::out_elem(q, r2);
+        if (e < nin) d[e] = res[q * FI::RL + r2];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass C (compiled plan): pre-twiddled half spectrum -> registers -> real row.
+// ---------------------------------------------------------------------------
+template <typename T, int C, bool TILED, typename F>
+__global__ void __launch_bounds__(F::kThreads) k_rows_c2r_ct(const cx<T>* __restrict__ src, int64_t src_ev_stride,
+                                                             T* __restrict__ dst, int64_t dst_ev_stride, int nt,
+                                                             int nphase, int nper, int nchunk,
+                                                             const cx<T>* __restrict__ tw,
+                                                             const cx<T>* __restrict__ post) {
+  constexpr int M = F::N, R0 = F::R0, RL = F::RL;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* z = reinterpret_cast<cx<T>*>(smem_raw);
+  const int L = TILED ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int i = L / nper, c = L - (L / nper) * nper;
+  const int64_t row = TILED ? (int64_t)c * nphase + i : (int64_t)L;
+  const cx<T>* inp = src + blockIdx.y * src_ev_stride;
+  const int fpad = nchunk * C;
+  auto X = [&](int k) -> cx<T> {
+    if (TILED) return inp[(((int64_t)(k / C) * nphase + i) * nper + c) * C + (k % C)];
+    return inp[(int64_t)L * fpad + k];
+  };
+  cx<T> in[F::IN], out[F::OUT];
+#pragma unroll
+  for (int q = 0; q < F::MB0; ++q) {
+    if (!F::in_ok(q)) continue;
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int k = F::in_elem(q, r);
+      const cx<T> A = X(k);
+      const cx<T> B = conj(X(M - k));
+      const cx<T> Ev = A + B;
+      const cx<T> O = cmulc(A - B, post[k]);        // (A - B) * W_L^-k
+      in[q * R0 + r] = mk(Ev.x - O.y, Ev.y + O.x);  // Ev + i*O
+    }
+  }
+  F::template rr<true>(z, tw, in, out, []() {});
+  T* o = dst + blockIdx.y * dst_ev_stride + row * nt;
+  const bool v2 = (nt % 2) == 0 && (reinterpret_cast<uintptr_t>(dst) % (2 * sizeof(T))) == 0 &&
+                  (dst_ev_stride % 2) == 0;
+#pragma unroll
+  for (int q = 0; q < F::MBL; ++q) {
+    if (!F::out_ok(q)) continue;
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int m = F::out_elem(q, r);
+      const cx<T> v = out[q * RL + r];
+      if (v2) {
+        if (2 * m < nt) {
+          cv2<T> p;
+          p.x = v.x;
+          p.y = v.y;
+          *reinterpret_cast<cv2<T>*>(o + 2 * m) = p;
+        }
+      } else {
+        if (2 * m < nt) o[2 * m] = v.x;
+        if (2 * m + 1 < nt) o[2 * m + 1] = v.y;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+// Calls fn(policy) for compiled variant `v` of kind KIND and type T.
+template <typename T, int KIND, typename Fn>
+static hipError_t with_variant(int v, Fn&& fn) {
+  constexpr int CI = KIND == 0 ? 1 : kChunk;
+  bool done = false;
+  int id = 0;
+#define WCT_VARIANT_CASE(K, TT, NT, ...)                       \
+  if constexpr (K == KIND && std::is_same<T, TT>::value) {     \
+    if (id == v) {                                             \
+      fn(CtFft<T, CI, NT, __VA_ARGS__>{});                     \
+      done = true;                                             \
+    }                                                          \
+  }                                                            \
+  ++id;
+  WCT_FFT_VARIANTS(WCT_VARIANT_CASE)
+#undef WCT_VARIANT_CASE
+  return done ? hipSuccess : hipErrorInvalidValue;
+}
+
+template <typename T, int KIND, typename Fn>
+static void for_all_variants(Fn&& fn) {
+  constexpr int CI = KIND == 0 ? 1 : kChunk;
+#define WCT_VARIANT_ALL(K, TT, NT, ...) \
+  if constexpr (K == KIND && std::is_same<T, TT>::value) fn(CtFft<T, CI, NT, __VA_ARGS__>{});
+  WCT_FFT_VARIANTS(WCT_VARIANT_ALL)
+#undef WCT_VARIANT_ALL
+}
+
+template <typename T>
+hipError_t launch_rows_r2c_ct(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt,
+                              int nphase, int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
+                              const cx<T>* post, int n_cu, hipStream_t st) {
+  const size_t lds = sizeof(cx<T>) * plan.n;
+  const int total = nphase * nper * n_events;
+  const hipError_t e = with_variant<T, 0>(plan.variant, [&](auto f) {
+    using F = decltype(f);
+    hipLaunchKernelGGL((k_rows_r2c_ct<T, kChunk, F>), dim3(persistent_blocks(n_cu, lds, F::kThreads, total)),
+                       dim3(F::kThreads), lds, st, src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk,
+                       n_events, tw, post);
+  });
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_colpass_ct(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtil, cx<T>* mhat,
+                             int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
+                             const FftPlan& plan, const cx<T>* tw, const cx<T>* tw_rev, hipStream_t st) {
+  const size_t lds = sizeof(cx<T>) * plan.n * kChunk;
+  const hipError_t e = with_variant<T, 1>(plan.variant, [&](auto f) {
+    using F = decltype(f);
+    hipLaunchKernelGGL((k_colpass_ct<T, kChunk, F>), dim3(nchunk, n_events), dim3(F::kThreads), lds, st, shat,
+                       shat_ev_stride, rtil, mhat, mhat_ev_stride, nw, nphase, nchunk, tw, tw_rev);
+  });
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_colpass_adj_ct(const cx<T>* ghat, int64_t ghat_ev_stride, const cx<T>* rtil, cx<T>* hhat,
+                                 int64_t hhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
+                                 const FftPlan& plan, const cx<T>* tw, const cx<T>* tw_rev, hipStream_t st) {
+  const size_t lds = sizeof(cx<T>) * plan.n * kChunk;
+  const hipError_t e = with_variant<T, 1>(plan.variant, [&](auto f) {
+    using F = decltype(f);
+    hipLaunchKernelGGL((k_colpass_adj_ct<T, kChunk, F>), dim3(nchunk, n_events), dim3(F::kThreads), lds, st, ghat,
+                       ghat_ev_stride, rtil, hhat, hhat_ev_stride, nw, nphase, nchunk, tw, tw_rev);
+  });
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rows_c2r_ct(const cx<T>* src, int64_t src_ev_stride, T* dst, int64_t dst_ev_stride, int nt,
+                              bool tiled, int nphase, int nper, int nchunk, int n_events, const FftPlan& plan,
+                              const cx<T>* tw, const cx<T>* post, hipStream_t st) {
+  const size_t lds = sizeof(cx<T>) * plan.n;
+  const dim3 grid(nphase * nper, n_events);
+  const hipError_t e = with_variant<T, 0>(plan.variant, [&](auto f) {
+    using F = decltype(f);
+    if (tiled)
+      hipLaunchKernelGGL((k_rows_c2r_ct<T, kChunk, true, F>), grid, dim3(F::kThreads), lds, st, src, src_ev_stride,
+                         dst, dst_ev_stride, nt, nphase, nper, nchunk, tw, post);
+    else
+      hipLaunchKernelGGL((k_rows_c2r_ct<T, kChunk, false, F>), grid, dim3(F::kThreads), lds, st, src,
+                         src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, tw, post);
+  });
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
+template <typename T>
+static void raise_lds_limits_ct() {
+  const int lim = 160 * 1024;
+  for_all_variants<T, 0>([&](auto f) {
+    using F = decltype(f);
+    (void)hipFuncSetAttribute((const void*)k_rows_r2c_ct<T, kChunk, F>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lim);
+    (void)hipFuncSetAttribute((const void*)k_rows_c2r_ct<T, kChunk, true, F>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_rows_c2r_ct<T, kChunk, false, F>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  });
+  for_all_variants<T, 1>([&](auto f) {
+    using F = decltype(f);
+    (void)hipFuncSetAttribute((const void*)k_colpass_ct<T, kChunk, F>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lim);
+    (void)hipFuncSetAttribute((const void*)k_colpass_adj_ct<T, kChunk, F>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  });
+}
+
+void conv_ct_init_kernels() {
+  raise_lds_limits_ct<float>();
+  raise_lds_limits_ct<double>();
+}
+
+#define WCT_INST(T)                                                                                              \
+  template hipError_t launch_rows_r2c_ct<T>(const T*, int64_t, cx<T>*, int64_t, int, int, int, int, int,         \
+                                            const FftPlan&, const cx<T>*, const cx<T>*, int, hipStream_t);      \
+  template hipError_t launch_colpass_ct<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int, int,  \
+                                           int, const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);        \
+  template hipError_t launch_colpass_adj_ct<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int,   \
+                                               int, int, const FftPlan&, const cx<T>*, const cx<T>*,             \
+                                               hipStream_t);                                                     \
+  template hipError_t launch_rows_c2r_ct<T>(const cx<T>*, int64_t, T*, int64_t, int, bool, int, int, int, int,   \
+                                            const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);
+WCT_INST(float)
+WCT_INST(double)
+#undef WCT_INST
+
+}  // namespace wct

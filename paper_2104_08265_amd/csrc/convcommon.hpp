@@ -1,0 +1,74 @@
+// Helpers shared by the transform kernels (conv.hip: runtime plans; conv_ct.hip:
+// compiled plans).
+#pragma once
+
+#include <type_traits>
+
+#include "fft.hpp"
+#include "fftvariants.hpp"
+#include "kernels.hpp"
+
+namespace wct {
+
+// Blocks are dispatched to the 8 XCDs round-robin; map them so that consecutive
+// logical indices share an XCD (and its L2).
+__device__ __forceinline__ int xcd_remap(int b, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7;
+  const int xcd = b & 7, pos = b >> 3;
+  return xcd < r ? xcd * (q + 1) + pos : r * (q + 1) + (xcd - r) * q + pos;
+}
+
+// 16-byte vector of the real type (4 floats or 2 doubles) for row loads: a clang vector,
+// so register arrays of it stay in registers.
+template <typename T>
+struct Vec16 {
+  static constexpr int n = 16 / sizeof(T);
+  typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
+};
+
+// Complex value as a clang 2-vector for register arrays (aggregates there can end up in
+// scratch memory).
+template <typename T>
+using cv2 = T __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ cv2<T> to_v(cx<T> a) {
+  cv2<T> r;
+  r.x = a.x;
+  r.y = a.y;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cx<T> from_v(cv2<T> a) { return mk(a.x, a.y); }
+
+// Persistent grid: as many workgroups as fit on the device at once (LDS and waves).
+inline int persistent_blocks(int n_cu, size_t lds, int threads, int work) {
+  int per_cu = (int)((160 * 1024) / (lds > 0 ? lds : 1));
+  const int waves = (threads + 63) / 64;
+  if (per_cu * waves > 32) per_cu = 32 / waves;
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu > 8) per_cu = 8;
+  const int g = n_cu * per_cu;
+  return work < g ? work : g;
+}
+
+
+// Launchers of the compiled-plan kernels (conv_ct.hip), selected by plan.variant.
+template <typename T>
+hipError_t launch_rows_r2c_ct(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt,
+                              int nphase, int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
+                              const cx<T>* post, int n_cu, hipStream_t st);
+template <typename T>
+hipError_t launch_colpass_ct(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtil, cx<T>* mhat,
+                             int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
+                             const FftPlan& plan, const cx<T>* tw, const cx<T>* tw_rev, hipStream_t st);
+template <typename T>
+hipError_t launch_colpass_adj_ct(const cx<T>* ghat, int64_t ghat_ev_stride, const cx<T>* rtil, cx<T>* hhat,
+                                 int64_t hhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
+                                 const FftPlan& plan, const cx<T>* tw, const cx<T>* tw_rev, hipStream_t st);
+template <typename T>
+hipError_t launch_rows_c2r_ct(const cx<T>* src, int64_t src_ev_stride, T* dst, int64_t dst_ev_stride, int nt,
+                              bool tiled, int nphase, int nper, int nchunk, int n_events, const FftPlan& plan,
+                              const cx<T>* tw, const cx<T>* post, hipStream_t st);
+void conv_ct_init_kernels();
+
+}  // namespace wct

@@ -114,35 +114,70 @@ __host__ __device__ __forceinline__ void dft8(cx<T>* v) {
   v[7] = e[3] - o3;
 }
 
-// exp(-2 pi i m / N) for the composite codelets (N = 6, 9, 10), 22-digit literals.
+// cos and sin of 2 pi m / n, evaluated at compile time: the angle is reduced exactly to
+// a quarter turn and then to [0, pi/4], where short Taylor series are accurate to the
+// last bit of a double.
+constexpr double ct_sin_small(double a) {
+  const double a2 = a * a;
+  double t = a, s = a;
+  for (int k = 1; k <= 12; ++k) {
+    t = -t * a2 / (double)((2 * k) * (2 * k + 1));
+    s += t;
+  }
+  return s;
+}
+constexpr double ct_cos_small(double a) {
+  const double a2 = a * a;
+  double t = 1.0, s = 1.0;
+  for (int k = 1; k <= 12; ++k) {
+    t = -t * a2 / (double)((2 * k - 1) * (2 * k));
+    s += t;
+  }
+  return s;
+}
+struct CtCis {
+  double c, s;
+};
+constexpr CtCis ct_cis(long m, long n) {
+  m %= n;
+  if (m < 0) m += n;
+  const long q = (4 * m) / n;  // quarter turn
+  const long r = 4 * m - q * n;  // angle within it: (pi/2) r / n
+  constexpr double kHalfPi = 1.5707963267948966;
+  double c = 0, s = 0;
+  if (2 * r <= n) {
+    const double a = kHalfPi * ((double)r / (double)n);
+    c = ct_cos_small(a);
+    s = ct_sin_small(a);
+  } else {
+    const double a = kHalfPi * ((double)(n - r) / (double)n);
+    c = ct_sin_small(a);
+    s = ct_cos_small(a);
+  }
+  if (q == 0) return CtCis{c, s};
+  if (q == 1) return CtCis{-s, c};
+  if (q == 2) return CtCis{-c, -s};
+  return CtCis{s, -c};
+}
+
+// exp(-2 pi i m / N), m < N, for the composite codelets.
 template <int N>
-struct WTab;
-template <>
-struct WTab<6> {
-  static constexpr double re[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
-  static constexpr double im[6] = {0.0, -8.660254037844386467637e-1, -8.660254037844386467637e-1, 0.0,
-                                   8.660254037844386467637e-1, 8.660254037844386467637e-1};
+struct WTabData {
+  double re[N], im[N];
 };
-template <>
-struct WTab<9> {
-  static constexpr double re[9] = {1.0, 7.660444431189780352024e-1, 1.736481776669303488517e-1, -0.5,
-                                   -9.396926207859083840541e-1, -9.396926207859083840541e-1, -0.5,
-                                   1.736481776669303488517e-1, 7.660444431189780352024e-1};
-  static constexpr double im[9] = {0.0, -6.427876096865393263226e-1, -9.848077530122080593667e-1,
-                                   -8.660254037844386467637e-1, -3.420201433256687330441e-1,
-                                   3.420201433256687330441e-1, 8.660254037844386467637e-1,
-                                   9.848077530122080593667e-1, 6.427876096865393263226e-1};
-};
-template <>
-struct WTab<10> {
-  static constexpr double re[10] = {1.0, 8.090169943749474241023e-1, 3.090169943749474241023e-1,
-                                    -3.090169943749474241023e-1, -8.090169943749474241023e-1, -1.0,
-                                    -8.090169943749474241023e-1, -3.090169943749474241023e-1,
-                                    3.090169943749474241023e-1, 8.090169943749474241023e-1};
-  static constexpr double im[10] = {0.0, -5.877852522924731291687e-1, -9.510565162951535721164e-1,
-                                    -9.510565162951535721164e-1, -5.877852522924731291687e-1, 0.0,
-                                    5.877852522924731291687e-1, 9.510565162951535721164e-1,
-                                    9.510565162951535721164e-1, 5.877852522924731291687e-1};
+template <int N>
+constexpr WTabData<N> make_wtab() {
+  WTabData<N> d{};
+  for (int m = 0; m < N; ++m) {
+    const CtCis e = ct_cis(m, N);
+    d.re[m] = e.c;
+    d.im[m] = -e.s;
+  }
+  return d;
+}
+template <int N>
+struct WTab {
+  static constexpr WTabData<N> d = make_wtab<N>();
 };
 // a * W_N^m (forward) or a * W_N^-m (inverse) for a compile-time m after unrolling.
 template <typename T, bool INV, int N>
@@ -152,8 +187,8 @@ __host__ __device__ __forceinline__ cx<T> wmul(cx<T> a, int m) {
   if (4 * m == N) return rot<T, INV>(a);
   if (2 * m == N) return mk(-a.x, -a.y);
   if (4 * m == 3 * N) return rot<T, !INV>(a);
-  const T c = (T)WTab<N>::re[m];
-  const T s = INV ? -(T)WTab<N>::im[m] : (T)WTab<N>::im[m];
+  const T c = (T)WTab<N>::d.re[m];
+  const T s = INV ? -(T)WTab<N>::d.im[m] : (T)WTab<N>::d.im[m];
   return mk(a.x * c - a.y * s, a.x * s + a.y * c);
 }
 
@@ -186,34 +221,49 @@ __host__ __device__ __forceinline__ void dft_comp(cx<T>* v) {
   }
 }
 
+// Split of a composite radix R = R1 * R2: the largest of 10, 9, 8, 5, 4, 3, 2 below R
+// that divides it.
+constexpr int comp_split(int R) {
+  constexpr int c[7] = {10, 9, 8, 5, 4, 3, 2};
+  for (int k = 0; k < 7; ++k)
+    if (c[k] < R && R % c[k] == 0) return c[k];
+  return 0;
+}
+
 template <int R, typename T, bool INV>
 __host__ __device__ __forceinline__ void dftR(cx<T>* v) {
   if constexpr (R == 2) dft2<T, INV>(v);
   else if constexpr (R == 3) dft3<T, INV>(v);
   else if constexpr (R == 4) dft4<T, INV>(v);
   else if constexpr (R == 5) dft5<T, INV>(v);
-  else if constexpr (R == 6) dft_comp<T, INV, 3, 2>(v);
   else if constexpr (R == 8) dft8<T, INV>(v);
-  else if constexpr (R == 9) dft_comp<T, INV, 3, 3>(v);
-  else dft_comp<T, INV, 5, 2>(v);  // 10
+  else {
+    static_assert(comp_split(R) > 0, "radix must be a product of 2, 3 and 5");
+    dft_comp<T, INV, comp_split(R), R / comp_split(R)>(v);
+  }
 }
 
 // Butterfly idx of a Stockham pass (radix R, stride Ns) over C interleaved sequences:
-// the load half and the twiddle + DFT + store half.  Shared by the device pass and the
-// host check of the transforms.
+// the load half, the twiddle load and the twiddle + DFT + store half.  Shared by the
+// device pass and the host check of the transforms.
 template <int R, typename T, int C>
 __host__ __device__ __forceinline__ void bf_load(const cx<T>* buf, int idx, int nr, cx<T>* v) {
   const int c = idx % C, j = idx / C;
 #pragma unroll
   for (int r = 0; r < R; ++r) v[r] = buf[(j + r * nr) * C + c];
 }
+template <int R, typename T, int C>
+__host__ __device__ __forceinline__ void bf_twiddles(int idx, int Ns, const cx<T>* __restrict__ tw, cx<T>* w) {
+  const int k = (idx / C) % Ns;
+  const cx<T>* p = tw + k * (R - 1);
+#pragma unroll
+  for (int r = 0; r < R - 1; ++r) w[r] = p[r];
+}
 template <int R, typename T, bool INV, int C>
-__host__ __device__ __forceinline__ void bf_store(cx<T>* buf, int idx, int Ns, const cx<T>* __restrict__ tw,
-                                                  cx<T>* v) {
+__host__ __device__ __forceinline__ void bf_store(cx<T>* buf, int idx, int Ns, const cx<T>* w, cx<T>* v) {
   const int c = idx % C, j = idx / C;
   const int k = j % Ns;
   if (Ns > 1) {
-    const cx<T>* w = tw + k * (R - 1);
 #pragma unroll
     for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], w[r - 1]) : cmul(v[r], w[r - 1]);
   }
@@ -223,23 +273,32 @@ __host__ __device__ __forceinline__ void bf_store(cx<T>* buf, int idx, int Ns, c
   for (int r = 0; r < R; ++r) buf[(base + r * Ns) * C + c] = v[r];
 }
 
-// One Stockham pass over C interleaved sequences of length n in LDS.
-template <int R, typename T, bool INV, int C, int E>
+// One Stockham pass over C interleaved sequences of length n in LDS.  The twiddles do
+// not depend on the LDS contents; with TWPF they are requested before the barrier (at
+// the cost of holding them across it).
+template <int R, typename T, bool INV, int C, int E, bool TWPF>
 __device__ __forceinline__ void stockham_pass(cx<T>* buf, int n, int Ns, const cx<T>* __restrict__ tw) {
   constexpr int MAXB = (E + R - 1) / R;
   const int nr = n / R;
   const int nbf = nr * C;
   cx<T> v[MAXB][R];
+  cx<T> w[MAXB][R - 1];
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
     const int idx = threadIdx.x + q * blockDim.x;
-    if (idx < nbf) bf_load<R, T, C>(buf, idx, nr, v[q]);
+    if (idx < nbf) {
+      if (TWPF && Ns > 1) bf_twiddles<R, T, C>(idx, Ns, tw, w[q]);
+      bf_load<R, T, C>(buf, idx, nr, v[q]);
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
     const int idx = threadIdx.x + q * blockDim.x;
-    if (idx < nbf) bf_store<R, T, INV, C>(buf, idx, Ns, tw, v[q]);
+    if (idx < nbf) {
+      if (!TWPF && Ns > 1) bf_twiddles<R, T, C>(idx, Ns, tw, w[q]);
+      bf_store<R, T, INV, C>(buf, idx, Ns, w[q], v[q]);
+    }
   }
   __syncthreads();
 }
@@ -254,17 +313,257 @@ __device__ __forceinline__ void fft_lds(cx<T>* buf, const FftPlan& plan, const c
     const int R = plan.radix[p];
     const cx<T>* twp = tw + plan.tw_off[p];
     switch (R) {
-      case 2: stockham_pass<2, T, INV, C, E>(buf, plan.n, Ns, twp); break;
-      case 3: stockham_pass<3, T, INV, C, E>(buf, plan.n, Ns, twp); break;
-      case 4: stockham_pass<4, T, INV, C, E>(buf, plan.n, Ns, twp); break;
-      case 5: stockham_pass<5, T, INV, C, E>(buf, plan.n, Ns, twp); break;
-      case 6: stockham_pass<6, T, INV, C, E>(buf, plan.n, Ns, twp); break;
-      case 8: stockham_pass<8, T, INV, C, E>(buf, plan.n, Ns, twp); break;
-      case 9: stockham_pass<9, T, INV, C, E>(buf, plan.n, Ns, twp); break;
-      default: stockham_pass<10, T, INV, C, E>(buf, plan.n, Ns, twp); break;
+      case 2: stockham_pass<2, T, INV, C, E, (C == 1)>(buf, plan.n, Ns, twp); break;
+      case 3: stockham_pass<3, T, INV, C, E, (C == 1)>(buf, plan.n, Ns, twp); break;
+      case 4: stockham_pass<4, T, INV, C, E, (C == 1)>(buf, plan.n, Ns, twp); break;
+      case 5: stockham_pass<5, T, INV, C, E, (C == 1)>(buf, plan.n, Ns, twp); break;
+      case 6: stockham_pass<6, T, INV, C, E, (C == 1)>(buf, plan.n, Ns, twp); break;
+      case 8: stockham_pass<8, T, INV, C, E, (C == 1)>(buf, plan.n, Ns, twp); break;
+      case 9: stockham_pass<9, T, INV, C, E, (C == 1)>(buf, plan.n, Ns, twp); break;
+      default: stockham_pass<10, T, INV, C, E, (C == 1)>(buf, plan.n, Ns, twp); break;
     }
     Ns *= R;
   }
 }
+
+// ---------------------------------------------------------------------------
+// Compile-time plans.  For the transform lengths of the shipped geometries the radix
+// sequence, the thread count and the interleave are template parameters: strides,
+// twiddle offsets and divisions fold into constants, LDS addresses into instruction
+// offsets, and each thread's butterflies of a pass are a fixed unrolled set.  The
+// butterflies are the runtime pass's (same codelets, same index formulas), with the
+// twiddle table laid out as build_fft lays it out for the same radices.
+// ---------------------------------------------------------------------------
+template <int R, typename T, int C, int NR>
+__host__ __device__ __forceinline__ void bfc_load(const cx<T>* buf, int idx, cx<T>* v) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = buf[idx + r * NR * C];
+}
+template <int R, typename T, int C, int NS>
+__host__ __device__ __forceinline__ void bfc_twiddles(int idx, const cx<T>* __restrict__ tw, cx<T>* w) {
+  const int k = (idx / C) % NS;
+  const cx<T>* p = tw + k * (R - 1);
+#pragma unroll
+  for (int r = 0; r < R - 1; ++r) w[r] = p[r];
+}
+// Same twiddles from one table entry, W^k, and its powers by squaring and multiplying
+// (depth <= log2 R products; relative error grows to about R rounding errors of the
+// entry).  Holds one value across the barrier instead of R - 1.
+template <int R, typename T, int C, int NS>
+__host__ __device__ __forceinline__ void bfc_twiddles_pow(int idx, const cx<T>* __restrict__ tw, cx<T>* w) {
+  const int k = (idx / C) % NS;
+  w[0] = tw[k * (R - 1)];
+#pragma unroll
+  for (int r = 2; r < R; ++r) w[r - 1] = (r % 2 == 0) ? cmul(w[r / 2 - 1], w[r / 2 - 1]) : cmul(w[r - 2], w[0]);
+}
+template <int R, typename T, bool INV, int C, int NS>
+__host__ __device__ __forceinline__ void bfc_store(cx<T>* buf, int idx, const cx<T>* w, cx<T>* v) {
+  const int c = idx % C, j = idx / C;
+  const int k = j % NS;
+  if constexpr (NS > 1) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], w[r - 1]) : cmul(v[r], w[r - 1]);
+  }
+  dftR<R, T, INV>(v);
+  const int base = ((j - k) * R + k) * C + c;
+#pragma unroll
+  for (int r = 0; r < R; ++r) buf[base + r * NS * C] = v[r];
+}
+
+// Twiddle policy of the compiled passes: row transforms (C = 1) request the table
+// entries before the barrier; column transforms, which hold many values per thread,
+// load one entry per butterfly after it and form the powers.
+template <typename T, bool INV, int C, int NT, int N, int R, int NS>
+__device__ __forceinline__ void ct_pass(cx<T>* buf, const cx<T>* __restrict__ tw) {
+  constexpr bool TWPF = C == 1;
+  constexpr int NR = N / R, NB = NR * C, MB = (NB + NT - 1) / NT;
+  constexpr bool FULL = NB % NT == 0;
+  cx<T> v[MB][R];
+  cx<T> w[MB][R - 1];
+#pragma unroll
+  for (int q = 0; q < MB; ++q) {
+    const int idx = (int)threadIdx.x + q * NT;
+    if (FULL || idx < NB) {
+      if constexpr (TWPF && NS > 1) bfc_twiddles<R, T, C, NS>(idx, tw, w[q]);
+      bfc_load<R, T, C, NR>(buf, idx, v[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MB; ++q) {
+    const int idx = (int)threadIdx.x + q * NT;
+    if (FULL || idx < NB) {
+      if constexpr (!TWPF && NS > 1) bfc_twiddles_pow<R, T, C, NS>(idx, tw, w[q]);
+      bfc_store<R, T, INV, C, NS>(buf, idx, w[q], v[q]);
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, bool INV, int C, int NT, int N, int NS, int TWO, int R, int... Rest>
+__device__ __forceinline__ void ct_fft(cx<T>* buf, const cx<T>* __restrict__ tw) {
+  ct_pass<T, INV, C, NT, N, R, NS>(buf, tw + TWO);
+  if constexpr (sizeof...(Rest) > 0) ct_fft<T, INV, C, NT, N, NS * R, TWO + NS * (R - 1), Rest...>(buf, tw);
+}
+
+// Chains with register input and output.  The first pass (stride 1) needs no twiddles
+// and reads, for butterfly idx, the elements idx + r (N/R0) C; a caller that holds
+// exactly those values in registers skips the LDS write and read before it.  The last
+// pass (stride N/RL) writes every output back to the position it read it from, so its
+// results can stay in the registers that held its inputs.
+template <typename T, bool INV, int C, int NT, int N, int R, int NS>
+__device__ __forceinline__ void ct_last_to_regs(cx<T>* buf, const cx<T>* __restrict__ tw, cx<T>* out) {
+  constexpr int NR = N / R, NB = NR * C, MB = (NB + NT - 1) / NT;
+  constexpr bool FULL = NB % NT == 0;
+  constexpr bool TWPF = C == 1;
+  cx<T> w[MB][R - 1];
+#pragma unroll
+  for (int q = 0; q < MB; ++q) {
+    const int idx = (int)threadIdx.x + q * NT;
+    if (FULL || idx < NB) {
+      if constexpr (TWPF && NS > 1) bfc_twiddles<R, T, C, NS>(idx, tw, w[q]);
+      bfc_load<R, T, C, NR>(buf, idx, &out[q * R]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MB; ++q) {
+    const int idx = (int)threadIdx.x + q * NT;
+    if (FULL || idx < NB) {
+      if constexpr (!TWPF && NS > 1) bfc_twiddles_pow<R, T, C, NS>(idx, tw, w[q]);
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r)
+          out[q * R + r] = INV ? cmulc(out[q * R + r], w[q][r - 1]) : cmul(out[q * R + r], w[q][r - 1]);
+      }
+      dftR<R, T, INV>(&out[q * R]);
+    }
+  }
+}
+
+template <typename T, bool INV, int C, int NT, int N, bool OREG, int NS, int TWO, int R, int... Rest>
+__device__ __forceinline__ void ct_rest(cx<T>* buf, const cx<T>* __restrict__ tw, cx<T>* out) {
+  if constexpr (sizeof...(Rest) == 0) {
+    if constexpr (OREG) ct_last_to_regs<T, INV, C, NT, N, R, NS>(buf, tw + TWO, out);
+    else ct_pass<T, INV, C, NT, N, R, NS>(buf, tw + TWO);
+  } else {
+    ct_pass<T, INV, C, NT, N, R, NS>(buf, tw + TWO);
+    ct_rest<T, INV, C, NT, N, OREG, NS * R, TWO + NS * (R - 1), Rest...>(buf, tw, out);
+  }
+}
+
+// in: first-pass inputs (consumed); out: last-pass outputs (OREG) or natural order in
+// LDS.  hook() runs once the inputs are no longer needed (to start the next loads).
+template <typename T, bool INV, int C, int NT, int N, bool OREG, typename Hook, int R0, int... Rest>
+__device__ __forceinline__ void ct_chain(cx<T>* buf, const cx<T>* __restrict__ tw, cx<T>* in, cx<T>* out,
+                                         Hook& hook) {
+  constexpr int NB = (N / R0) * C, MB = (NB + NT - 1) / NT;
+  constexpr bool FULL = NB % NT == 0;
+  if constexpr (sizeof...(Rest) == 0) {
+#pragma unroll
+    for (int q = 0; q < MB; ++q) {
+      const int idx = (int)threadIdx.x + q * NT;
+      if (FULL || idx < NB) {
+        if constexpr (OREG) {
+          dftR<R0, T, INV>(&in[q * R0]);
+#pragma unroll
+          for (int r = 0; r < R0; ++r) out[q * R0 + r] = in[q * R0 + r];
+        } else {
+          bfc_store<R0, T, INV, C, 1>(buf, idx, nullptr, &in[q * R0]);
+        }
+      }
+    }
+    hook();
+    if constexpr (!OREG) __syncthreads();
+  } else {
+#pragma unroll
+    for (int q = 0; q < MB; ++q) {
+      const int idx = (int)threadIdx.x + q * NT;
+      if (FULL || idx < NB) bfc_store<R0, T, INV, C, 1>(buf, idx, nullptr, &in[q * R0]);
+    }
+    hook();
+    __syncthreads();
+    ct_rest<T, INV, C, NT, N, OREG, R0, R0 - 1, Rest...>(buf, tw, out);
+  }
+}
+
+template <int... Rs>
+struct IntList {};
+template <typename L, typename A = IntList<>>
+struct RevList;
+template <int R, int... Rs, int... A>
+struct RevList<IntList<R, Rs...>, IntList<A...>> {
+  using type = typename RevList<IntList<Rs...>, IntList<R, A...>>::type;
+};
+template <int... A>
+struct RevList<IntList<>, IntList<A...>> {
+  using type = IntList<A...>;
+};
+template <int... Rs>
+constexpr int first_of() {
+  constexpr int r[] = {Rs...};
+  return r[0];
+}
+template <int... Rs>
+constexpr int last_of() {
+  constexpr int r[] = {Rs...};
+  return r[sizeof...(Rs) - 1];
+}
+
+// Transform policies the kernels are written against.
+//  RtFft: runtime plan (any 2,3,5-smooth length), E values per thread, any block size.
+//  CtFft: compile-time plan with radices Rs..., exactly NT threads per block; besides the
+//         LDS-to-LDS run() it offers the register-input chains rr() and rl().
+template <typename T, int C, int E_>
+struct RtFft {
+  static constexpr int E = E_;
+  static constexpr int kBound = LaunchBound<T, E_>::value;
+  FftPlan p;
+  __device__ __forceinline__ int n() const { return p.n; }
+  __device__ __forceinline__ int nthr() const { return (int)blockDim.x; }
+  template <bool INV>
+  __device__ __forceinline__ void run(cx<T>* buf, const cx<T>* __restrict__ tw) const {
+    fft_lds<T, INV, C, E_>(buf, p, tw);
+  }
+};
+template <typename T, int C, int NT, typename L>
+struct CtFftOf;
+template <typename T, int C, int NT, int... Rs>
+struct CtFft {
+  static constexpr int N = (1 * ... * Rs);
+  static constexpr int E = (N * C + NT - 1) / NT;
+  static constexpr int kBound = NT;
+  static constexpr int kThreads = NT;
+  static constexpr int R0 = first_of<Rs...>(), RL = last_of<Rs...>();
+  static constexpr int NB0 = (N / R0) * C, NBL = (N / RL) * C;  // butterflies of the first / last pass
+  static constexpr int MB0 = (NB0 + NT - 1) / NT, MBL = (NBL + NT - 1) / NT;
+  static constexpr int IN = MB0 * R0, OUT = MBL * RL;  // register values per thread
+  // same radices in reverse order: its first pass reads what this one's last pass leaves
+  using Reverse = typename CtFftOf<T, C, NT, typename RevList<IntList<Rs...>>::type>::type;
+  __device__ __forceinline__ constexpr int n() const { return N; }
+  __device__ __forceinline__ constexpr int nthr() const { return NT; }
+  // element held in register slot (q, r): first-pass and last-pass arrangement
+  __device__ __forceinline__ static int in_elem(int q, int r) { return (int)threadIdx.x + q * NT + r * NB0; }
+  __device__ __forceinline__ static bool in_ok(int q) { return NB0 % NT == 0 || (int)threadIdx.x + q * NT < NB0; }
+  __device__ __forceinline__ static int out_elem(int q, int r) { return (int)threadIdx.x + q * NT + r * NBL; }
+  __device__ __forceinline__ static bool out_ok(int q) { return NBL % NT == 0 || (int)threadIdx.x + q * NT < NBL; }
+  template <bool INV>
+  __device__ __forceinline__ void run(cx<T>* buf, const cx<T>* __restrict__ tw) const {
+    ct_fft<T, INV, C, NT, N, 1, 0, Rs...>(buf, tw);
+  }
+  template <bool INV, typename Hook>
+  __device__ __forceinline__ static void rr(cx<T>* buf, const cx<T>* __restrict__ tw, cx<T>* in, cx<T>* out,
+                                            Hook&& hook) {
+    ct_chain<T, INV, C, NT, N, true, Hook, Rs...>(buf, tw, in, out, hook);
+  }
+  template <bool INV, typename Hook>
+  __device__ __forceinline__ static void rl(cx<T>* buf, const cx<T>* __restrict__ tw, cx<T>* in, Hook&& hook) {
+    ct_chain<T, INV, C, NT, N, false, Hook, Rs...>(buf, tw, in, nullptr, hook);
+  }
+};
+template <typename T, int C, int NT, int... Rs>
+struct CtFftOf<T, C, NT, IntList<Rs...>> {
+  using type = CtFft<T, C, NT, Rs...>;
+};
 
 }  // namespace wct

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "fftvariants.hpp"
 
 namespace wct {
 
@@ -79,13 +80,17 @@ inline bool plan_radices(int n, int policy, std::vector<int>& out) {
   return (int)out.size() <= kMaxPass;
 }
 
-// Stockham plan and its twiddle table: pass p with stride Ns and radix R keeps
-// W_{Ns R}^{r k} for k < Ns, 1 <= r < R at tw_off[p] + k (R-1) + r - 1.
-inline bool build_fft(int n, int policy, FftPlan& fp, std::vector<cx<double>>& tw) {
+// Stockham plan for the radices `rad` (in pass order) and its twiddle table: pass p
+// with stride Ns and radix R keeps W_{Ns R}^{r k} for k < Ns, 1 <= r < R at
+// tw_off[p] + k (R-1) + r - 1.
+inline bool build_fft_radices(int n, const std::vector<int>& rad, FftPlan& fp, std::vector<cx<double>>& tw) {
   std::memset(&fp, 0, sizeof(fp));
   fp.n = n;
-  std::vector<int> rad;
-  if (!plan_radices(n, policy, rad)) return false;
+  fp.variant = -1;
+  if (rad.empty() || (int)rad.size() > kMaxPass) return false;
+  int64_t prod = 1;
+  for (int r : rad) prod *= r;
+  if (prod != n) return false;
   tw.clear();
   int Ns = 1;
   fp.npass = (int)rad.size();
@@ -98,6 +103,21 @@ inline bool build_fft(int n, int policy, FftPlan& fp, std::vector<cx<double>>& t
     Ns *= R;
   }
   if (tw.empty()) tw.push_back(mk(1.0, 0.0));
+  return true;
+}
+
+// Runtime plan of a radix policy.
+inline bool build_fft(int n, int policy, FftPlan& fp, std::vector<cx<double>>& tw) {
+  std::vector<int> rad;
+  if (!plan_radices(n, policy, rad)) return false;
+  return build_fft_radices(n, rad, fp, tw);
+}
+
+// Plan of compiled variant v (fftvariants.hpp).
+inline bool build_fft_variant(const FftVariantDesc& d, int v, FftPlan& fp, std::vector<cx<double>>& tw) {
+  std::vector<int> rad(d.radix, d.radix + d.npass);
+  if (!build_fft_radices(d.n, rad, fp, tw)) return false;
+  fp.variant = v;
   return true;
 }
 

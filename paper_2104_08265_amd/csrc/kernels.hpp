@@ -79,7 +79,8 @@ hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigm
                          ProfHook* prof);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 
-// conv.hip
+// conv.hip.  A plan with variant >= 0 runs the compiled-plan kernels; the column passes
+// of those take a second twiddle table for the same radices in reverse order (tw_rev).
 // Rows are read with 16-byte loads (and the next row prefetched) when their length and base allow it.
 template <typename T>
 hipError_t launch_rows_r2c(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt, int nphase,
@@ -88,11 +89,11 @@ hipError_t launch_rows_r2c(const T* src, int64_t src_ev_stride, cx<T>* dst, int6
 template <typename T>
 hipError_t launch_colpass(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtil, cx<T>* mhat,
                           int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, const FftPlan& plan,
-                          const cx<T>* tw, hipStream_t st);
+                          const cx<T>* tw, const cx<T>* tw_rev, hipStream_t st);
 template <typename T>
 hipError_t launch_colpass_adj(const cx<T>* ghat, int64_t ghat_ev_stride, const cx<T>* rtil, cx<T>* hhat,
                               int64_t hhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
-                              const FftPlan& plan, const cx<T>* tw, hipStream_t st);
+                              const FftPlan& plan, const cx<T>* tw, const cx<T>* tw_rev, hipStream_t st);
 template <typename T>
 hipError_t launch_rows_c2r(const cx<T>* src, int64_t src_ev_stride, T* dst, int64_t dst_ev_stride, int nt,
                            bool tiled, int nphase, int nper, int nchunk, int n_events, const FftPlan& plan,

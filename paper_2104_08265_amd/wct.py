@@ -79,6 +79,22 @@ wct_profile_count = _sig("wct_profile_count", c_int32, [PlanP])
 wct_profile_get = _sig("wct_profile_get", c_int32, [PlanP, c_int32, c_char_p, c_size_t, POINTER(c_double),
                                                    POINTER(c_int64)])
 wct_fluct_spec_version = _sig("wct_fluct_spec_version", c_int32, [])
+wct_fft_variant_count = _sig("wct_fft_variant_count", c_int32, [])
+wct_fft_variant_info = _sig("wct_fft_variant_info", c_int32, [c_int32, POINTER(c_int32)])
+wct_plan_get_fft = _sig("wct_plan_get_fft", c_int32, [PlanP, c_int32, c_int32, POINTER(c_int32)])
+wct_plan_set_fft = _sig("wct_plan_set_fft", c_int32, [PlanP, c_int32, c_int32, c_int32])
+
+
+def fft_variants():
+    """Compiled transform variants: list of dicts (index, kind, dtype, threads, n, radices)."""
+    out = []
+    buf = (c_int32 * 12)()
+    for k in range(wct_fft_variant_count()):
+        check(wct_fft_variant_info(k, buf), "wct_fft_variant_info")
+        v = list(buf)
+        out.append({"index": k, "kind": v[0], "dtype": "f64" if v[1] else "f32", "threads": v[2], "n": v[3],
+                    "radices": v[5:5 + v[4]]})
+    return out
 
 
 class WctError(RuntimeError):
@@ -240,6 +256,23 @@ class Plan:
         check(wct_simulate_backward(self.h, ctypes.byref(d), ctypes.byref(o), _ptr(grad_wave), *[_ptr(x) for x in outs],
                                     _ptr(ws), nb, self._stream()), "wct_simulate_backward")
         return outs
+
+    def get_fft(self, plane, kind):
+        """Transform variant of a plane's tick (kind 0) or wire (kind 1) transforms; -1 = runtime plan."""
+        v = c_int32()
+        check(wct_plan_get_fft(self.h, plane, kind, ctypes.byref(v)), "wct_plan_get_fft")
+        return v.value
+
+    def set_fft(self, plane, kind, variant):
+        check(wct_plan_set_fft(self.h, plane, kind, variant), "wct_plan_set_fft")
+
+    def fft_candidates(self, plane, kind):
+        """Variants applicable to a plane's transform of this kind, runtime plan (-1) last."""
+        info = self.plane_info(plane)
+        n = info["lt"] // 2 if kind == 0 else info["lw"]
+        return [v["index"] for v in fft_variants()
+                if v["kind"] == kind and v["dtype"] == ("f64" if self.dtype == WCT_F64 else "f32")
+                and v["n"] == n] + [-1]
 
     def profile(self, enable=True):
         check(wct_profile_enable(self.h, int(bool(enable))), "wct_profile_enable")

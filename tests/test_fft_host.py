@@ -44,3 +44,15 @@ def test_transform_lengths(checker, n, policy):
 def test_interleaved_batch_of_four(checker, n):
     out = subprocess.run([checker, str(n), "0", "4"], capture_output=True, text=True, check=True).stdout.split()
     assert float(out[0]) < 1e-14 and float(out[1]) < 1e-14 and float(out[2]) < 1e-6
+
+
+def test_compiled_variants(checker):
+    """Every compiled plan (fftvariants.hpp): forward with its table, inverse with the
+    reversed radices, against the long-double DFT (column variants with power twiddles)."""
+    lines = subprocess.run([checker, "variants"], capture_output=True, text=True, check=True).stdout.strip().splitlines()
+    assert len(lines) >= 10
+    for ln in lines:
+        f = ln.split()
+        ef, ei, ef32, ei32 = (float(v) for v in f[3:7])
+        assert ef < 1e-14 and ei < 1e-14, ln
+        assert ef32 < 2e-6 and ei32 < 2e-6, ln
