@@ -27,7 +27,6 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 ROOT = os.path.dirname(os.path.abspath(__file__))
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_JSON = os.path.join(PROFILES, "hbm_traffic.json")
-CSRC = os.path.join(ROOT, "paper_2104_08265_amd", "csrc")
 
 # The commands whose output --summarize reads (run from /tmp on the GPU host, R = repo root).
 PROFILE_COMMANDS = {
@@ -43,15 +42,22 @@ FAMILIES = [("k_tile<float, true", "raster_tile_fluct"), ("k_tile<float, false",
             ("k_big<", "raster_wide_rows")]
 
 
-def sources_digest():
-    """Hash of the kernel sources; counter data are used only while it is unchanged."""
-    import hashlib
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(name.encode() + f.read())
-    return h.hexdigest()
+def built_digest():
+    """Digest of the sources the in-tree libwct.so was built from (written by the build)."""
+    try:
+        with open(os.path.join(ROOT, "paper_2104_08265_amd", "libwct.sha256")) as f:
+            return f.read().strip()
+    except OSError:
+        return None
+
+
+def log_digest(path):
+    """The "build" digest printed in a bench JSON line inside a log file."""
+    with open(path) as f:
+        for line in f:
+            if line.startswith("{") and '"build"' in line:
+                return json.loads(line).get("build")
+    return None
 
 
 def family(kernel_name):
@@ -100,7 +106,10 @@ def summarize(out_dir):
 
     fetch, fs = counters("fetch", "FETCH_SIZE")
     write, ws = counters("write", "WRITE_SIZE")
-    traffic = {"sources_sha256": sources_digest(), "fetch_scale": fs, "write_scale": ws, "kernels": {},
+    digest = log_digest(os.path.join(out_dir, "pmc_fetch.log"))
+    if digest is None or digest != log_digest(os.path.join(out_dir, "pmc_write.log")):
+        raise SystemExit("the two counter runs do not name the same library build")
+    traffic = {"build": digest, "fetch_scale": fs, "write_scale": ws, "kernels": {},
                "commands": {k: PROFILE_COMMANDS[k] for k in ("fetch", "write")}}
     lines = ["# HBM traffic per kernel family: three-plane track workload, one step", "",
              "Commands (separate runs, from /tmp, R = repository root):", "",
@@ -127,7 +136,7 @@ def measured_traffic(kernel):
         t = json.load(open(TRAFFIC_JSON))
     except (OSError, ValueError):
         return None
-    if t.get("sources_sha256") != sources_digest() or kernel not in t.get("kernels", {}):
+    if t.get("build") is None or t.get("build") != built_digest() or kernel not in t.get("kernels", {}):
         return None
     return t["kernels"][kernel]["bytes_per_launch"]
 
@@ -317,6 +326,7 @@ def main():
         "dominant_kernel": dom,
         "kernels": kernels,
         "roofline": roofline,
+        "build": built_digest(),
     }
     plan.close()
     if not args.no_extras:

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define WCT_ABI_VERSION 1
+#define WCT_ABI_VERSION 2
 /* Version of the fluctuation draw stream (counter layout + sampler).  Bumped whenever a
  * change would alter any fluctuated count for the same inputs and seed. */
 #define WCT_FLUCT_SPEC_VERSION 2
@@ -93,15 +93,22 @@ typedef struct {
   const void* sigma_t;    /* [n] longitudinal width, ticks, > 0 */
   const void* sigma_p;    /* [n] transverse width, wire pitches, > 0 */
   const int32_t* plane;   /* [n] plane index in [0, n_planes) */
-  const int32_t* event;   /* [n] event index in [0, n_events) */
+  const int32_t* event;   /* [n] event id >= 0 (NULL: all 0); see wct_opts.event_base */
   const int32_t* depo_id; /* [n] deposition id (fluctuation counter word 1) */
 } wct_depos;
 
+/* Event window.  A call simulates the events event_base .. event_base + n_events - 1:
+ * rows whose event id lies in that range are used, the others ignored (gradients of
+ * ignored rows are written as 0).  Event e fills output slot e - event_base, while its
+ * fluctuation draws are keyed by e itself, so an event gets the same counts whether it
+ * is simulated alone or inside a batch. */
 typedef struct {
-  double nsigma;     /* truncation half-width of the Gaussian patch in sigmas, (0, 8] */
-  int32_t fluctuate; /* 0: mean charge; 1: binomial electron counts (needs nsigma <= 4.2) */
-  int32_t n_events;  /* events in this call, 1..max_events */
-  uint64_t seed;     /* fluctuation key (Philox4x32-10 key words: low, high 32 bits) */
+  double nsigma;      /* truncation half-width of the Gaussian patch in sigmas, (0, 8] */
+  int32_t fluctuate;  /* 0: mean charge; 1: binomial electron counts (needs nsigma <= 4.2) */
+  int32_t n_events;   /* events in this call: 1..max_events (wct_simulate: any >= 1) */
+  uint64_t seed;      /* fluctuation key (Philox4x32-10 key words: low, high 32 bits) */
+  int32_t event_base; /* first event id of the window, >= 0 */
+  int32_t reserved;   /* must be 0 */
 } wct_opts;
 
 /* Geometry of a plane as planned: out[0..9] = N_w, N_t, I, K, T_R, L_w, L_t, F,
@@ -136,9 +143,9 @@ size_t wct_workspace_bytes(const wct_plan* plan, int32_t op, int32_t n_events, i
  * `seed`; cells (b, 2m) and (b, 2m+1) share the counter (b*ceil(N_t/2) + m, depo_id,
  * event, plane << 24), the even tick taking words 0-1 and the odd tick words 2-3; the
  * sampler is that of WCT_FLUCT_SPEC_VERSION (bit-reproducible, independent of
- * scheduling).  Rows with
- * sigma <= 0, Q < 0 or non-finite values contribute nothing.  The whole grid of every
- * event in [0, n_events) is overwritten. */
+ * scheduling and batching; `event` is the row's event id).  Rows with sigma <= 0,
+ * Q < 0 or non-finite values contribute nothing.  The whole grid of every event of the
+ * window is overwritten. */
 int wct_raster(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* grid, void* ws,
                size_t ws_bytes, void* stream);
 
@@ -149,7 +156,11 @@ int wct_raster(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, voi
 int wct_convolve(wct_plan* plan, const void* grid, int32_t n_events, void* wave, void* ws, size_t ws_bytes,
                  void* stream);
 
-/* wct_raster followed by wct_convolve, the grid living in the workspace. */
+/* wct_raster followed by wct_convolve, the grid living in the workspace.  n_events may
+ * exceed the plan's max_events: the events are then processed in consecutive
+ * sub-batches of max_events (one persistent raster launch and one set of batched
+ * transform passes per sub-batch), with the workspace of max_events events
+ * (wct_workspace_bytes(plan, WCT_OP_SIMULATE, n, rows) caps n at max_events). */
 int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* wave, void* ws,
                  size_t ws_bytes, void* stream);
 

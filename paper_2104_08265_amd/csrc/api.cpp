@@ -163,11 +163,12 @@ ProfHook* hook(wct_plan* P) { return P->prof.on ? &P->prof : nullptr; }
     if (e__ != hipSuccess) return hip_fail(e__, what); \
   } while (0)
 
-RasterGeom raster_geom(const wct_plan* P, int n_events) {
+RasterGeom raster_geom(const wct_plan* P, int n_events, int event_base) {
   RasterGeom g;
   std::memset(&g, 0, sizeof(g));
   g.n_planes = P->n_planes;
   g.n_events = n_events;
+  g.event_base = event_base;
   g.ntiles_ev = P->ntiles_ev;
   g.grid_ev_stride = P->grid_elems;
   for (int p = 0; p < P->n_planes; ++p) g.pl[p] = P->geom[p];
@@ -235,10 +236,14 @@ size_t ws_bytes(const wct_plan* P, int op, int n_events, int64_t n_rows) {
 }
 
 // Validation -----------------------------------------------------------------------
-int check_opts(const wct_plan* P, const wct_opts* o, bool need_nsigma) {
+// batched: n_events may exceed max_events (wct_simulate processes sub-batches)
+int check_opts(const wct_plan* P, const wct_opts* o, bool need_nsigma, bool batched = false) {
   if (!o) return fail(WCT_E_INVALID, "opts is NULL");
-  if (o->n_events < 1 || o->n_events > P->max_events)
+  if (o->n_events < 1 || (!batched && o->n_events > P->max_events))
     return fail(WCT_E_INVALID, "n_events %d outside [1, %d]", o->n_events, P->max_events);
+  if (o->event_base < 0 || (int64_t)o->event_base + o->n_events > 0x7fffffffLL)
+    return fail(WCT_E_INVALID, "event window [%d, %d + %d) out of range", o->event_base, o->event_base, o->n_events);
+  if (o->reserved != 0) return fail(WCT_E_INVALID, "opts.reserved must be 0");
   if (need_nsigma && !(o->nsigma > 0.0 && o->nsigma <= 8.0))
     return fail(WCT_E_INVALID, "nsigma %g outside (0, 8]", o->nsigma);
   if (o->fluctuate != 0 && o->fluctuate != 1) return fail(WCT_E_INVALID, "fluctuate must be 0 or 1");
@@ -273,7 +278,7 @@ DepoView<T> view(const wct_depos* d) {
 // Launch sequences -------------------------------------------------------------------
 template <typename T>
 int run_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, T* grid, Carver& cv, hipStream_t st) {
-  const RasterGeom g = raster_geom(P, o->n_events);
+  const RasterGeom g = raster_geom(P, o->n_events, o->event_base);
   const RasterWs ws = carve_raster(P, cv, o->n_events, d->n);
   HIP_TRY(launch_raster<T>(view<T>(d), g, o->nsigma, o->fluctuate, o->seed, grid, ws, P->d_tables, P->n_cu, st,
                            hook(P)),
@@ -337,7 +342,7 @@ int run_backward(wct_plan* P, const wct_depos* d, const wct_opts* o, const T* gw
                 "adjoint inverse row transform launch");
   }
   PROF_LAUNCH(P, "grad_gather", st,
-              launch_grad_gather<T>(view<T>(d), raster_geom(P, ne), o->nsigma, H, gq, gt, gp, gst, gsp, st),
+              launch_grad_gather<T>(view<T>(d), raster_geom(P, ne, o->event_base), o->nsigma, H, gq, gt, gp, gst, gsp, st),
               "gradient gather launch");
   return WCT_OK;
 }
@@ -618,7 +623,9 @@ int wct_plane_info(const wct_plan* plan, int32_t plane, int64_t out[10]) {
 }
 
 size_t wct_workspace_bytes(const wct_plan* plan, int32_t op, int32_t n_events, int64_t n_rows) {
-  if (!plan || n_events < 1 || n_events > plan->max_events || n_rows < 0) return 0;
+  if (!plan || n_events < 1 || n_rows < 0) return 0;
+  if (op == WCT_OP_SIMULATE && n_events > plan->max_events) n_events = plan->max_events;  // sub-batched
+  if (n_events > plan->max_events) return 0;
   return ws_bytes(plan, op, n_events, n_rows);
 }
 
@@ -663,27 +670,39 @@ int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, v
                  void* stream) {
   g_err.clear();
   if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
-  int rc = check_opts(plan, opts, true);
+  int rc = check_opts(plan, opts, true, true);
   if (rc) return rc;
   if ((rc = check_depos(depos))) return rc;
   if (!wave) return fail(WCT_E_INVALID, "wave is NULL");
-  const size_t need = ws_bytes(plan, WCT_OP_SIMULATE, opts->n_events, depos->n);
+  const int batch = opts->n_events < plan->max_events ? opts->n_events : plan->max_events;
+  const size_t need = ws_bytes(plan, WCT_OP_SIMULATE, batch, depos->n);
   if (!ws || ws_size < need) return fail(WCT_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_size, need);
   DeviceGuard dg(plan->device);
   if (!dg.ok) return fail(WCT_E_DEVICE, "hipSetDevice(%d) failed", plan->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   Carver head(ws);
-  void* grid = head.take(plan->esize * (size_t)opts->n_events * plan->grid_elems);
+  void* grid = head.take(plan->esize * (size_t)batch * plan->grid_elems);
   const size_t rest = align_up(head.off, 256);
-  Carver cr(static_cast<char*>(ws) + rest), cc(static_cast<char*>(ws) + rest);
-  if (plan->dtype == WCT_F32) {
-    if ((rc = run_raster<float>(plan, depos, opts, static_cast<float*>(grid), cr, st))) return rc;
-    return run_convolve<float>(plan, static_cast<const float*>(grid), opts->n_events, static_cast<float*>(wave), cc,
+  // sub-batches of up to max_events events: raster into the workspace grid, then the
+  // transform passes write the sub-batch's slots of `wave`
+  for (int e0 = 0; e0 < opts->n_events; e0 += batch) {
+    wct_opts sub = *opts;
+    sub.n_events = opts->n_events - e0 < batch ? opts->n_events - e0 : batch;
+    sub.event_base = opts->event_base + e0;
+    Carver cr(static_cast<char*>(ws) + rest), cc(static_cast<char*>(ws) + rest);
+    char* w = static_cast<char*>(wave) + plan->esize * (size_t)e0 * plan->wave_elems;
+    if (plan->dtype == WCT_F32) {
+      if ((rc = run_raster<float>(plan, depos, &sub, static_cast<float*>(grid), cr, st))) return rc;
+      rc = run_convolve<float>(plan, static_cast<const float*>(grid), sub.n_events, reinterpret_cast<float*>(w), cc,
                                st);
+    } else {
+      if ((rc = run_raster<double>(plan, depos, &sub, static_cast<double*>(grid), cr, st))) return rc;
+      rc = run_convolve<double>(plan, static_cast<const double*>(grid), sub.n_events, reinterpret_cast<double*>(w),
+                                cc, st);
+    }
+    if (rc) return rc;
   }
-  if ((rc = run_raster<double>(plan, depos, opts, static_cast<double*>(grid), cr, st))) return rc;
-  return run_convolve<double>(plan, static_cast<const double*>(grid), opts->n_events, static_cast<double*>(wave), cc,
-                              st);
+  return WCT_OK;
 }
 
 int wct_simulate_backward(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, const void* grad_wave,

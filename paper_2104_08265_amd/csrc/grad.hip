@@ -58,11 +58,12 @@ __global__ void __launch_bounds__(256) k_grad_gather(DepoView<T> d, RasterGeom g
   const int64_t j = (int64_t)blockIdx.x * 4 + wv;
   if (j >= d.n) return;
   const int pl_i = d.plane ? d.plane[j] : 0;
-  const int ev = d.event ? d.event[j] : 0;
+  const int ev_id = d.event ? d.event[j] : 0;
+  const int ev = ev_id - g.event_base;
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
   double q = 0;
   int I = 1;
-  bool ok = pl_i >= 0 && pl_i < g.n_planes && ev >= 0 && ev < g.n_events;
+  bool ok = pl_i >= 0 && pl_i < g.n_planes && ev_id >= 0 && ev >= 0 && ev < g.n_events;
   if (ok) {
     const PlaneGeom& pl = g.pl[pl_i];
     I = pl.I;

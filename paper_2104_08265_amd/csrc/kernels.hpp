@@ -20,6 +20,7 @@ struct DepoView {
 struct RasterGeom {
   int n_planes;
   int n_events;
+  int event_base;          // rows of events [event_base, event_base + n_events) are used
   int ntiles_ev;           // raster tiles per event
   int64_t grid_ev_stride;  // grid elements per event
   PlaneGeom pl[kMaxPlanes];

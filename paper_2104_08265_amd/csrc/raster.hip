@@ -31,7 +31,8 @@ struct RowWin {
   double q, u, su, t, st;
   double ulo, uhi, tlo, thi;
   int b0, b1, k0, k1;  // cell ranges clipped to the grid, [b0, b1) x [k0, k1)
-  int plane, event;
+  int plane, event;  // event: slot in this call's grids (id - event_base)
+  int key_event;     // event id (fluctuation counter word 2)
   bool ok;
 };
 
@@ -44,8 +45,9 @@ template <typename T>
 __device__ __forceinline__ RowWin row_window(const DepoView<T>& d, int64_t j, const RasterGeom& g, double nsigma) {
   RowWin w;
   w.plane = d.plane ? d.plane[j] : 0;
-  w.event = d.event ? d.event[j] : 0;
-  w.ok = w.plane >= 0 && w.plane < g.n_planes && w.event >= 0 && w.event < g.n_events;
+  w.key_event = d.event ? d.event[j] : 0;
+  w.event = w.key_event - g.event_base;
+  w.ok = w.plane >= 0 && w.plane < g.n_planes && w.key_event >= 0 && w.event >= 0 && w.event < g.n_events;
   if (!w.ok) return w;
   const PlaneGeom& pl = g.pl[w.plane];
   w.q = (double)d.q[j];
@@ -449,7 +451,7 @@ __global__ void __launch_bounds__(256, 3) k_tile(DepoView<T> d, RasterGeom g, do
       const int kk0 = max(w.k0, tk0), kk1 = min(w.k1, tk0 + tw);
       if (!w.ok || bb0 >= bb1 || kk0 >= kk1) continue;
       const uint32_t did = d.depo_id ? (uint32_t)d.depo_id[j] : (uint32_t)j;
-      patch_cells<T, FLUCT>(w, bb0, bb1, kk0, kk1, pl.nt, did, (uint32_t)ev, (uint32_t)pi, key0, key1, s_ea[wv],
+      patch_cells<T, FLUCT>(w, bb0, bb1, kk0, kk1, pl.nt, did, (uint32_t)w.key_event, (uint32_t)pi, key0, key1, s_ea[wv],
                             s_eb[wv], q, qn, s_tb, lane, dst, add);
     }
     if (FLUCT) queue_run<T>(q, qn, true, lane, s_tb, add);
@@ -506,7 +508,7 @@ __global__ void __launch_bounds__(256, 3) k_big(DepoView<T> d, RasterGeom g, dou
       const int cb = c / nck, ck = c - (c / nck) * nck;
       const int b0 = w.b0 + cb * CB, b1 = min(b0 + CB, w.b1);
       const int k0 = max(kstart + ck * CK, w.k0), k1 = min(kstart + (ck + 1) * CK, w.k1);
-      patch_cells<T, FLUCT>(w, b0, b1, k0, k1, pl.nt, did, (uint32_t)w.event, (uint32_t)w.plane, key0, key1,
+      patch_cells<T, FLUCT>(w, b0, b1, k0, k1, pl.nt, did, (uint32_t)w.key_event, (uint32_t)w.plane, key0, key1,
                             s_ea[wv], s_eb[wv], q, qn, s_tb, lane, dst, add);
     }
     if (FLUCT) queue_run<T>(q, qn, true, lane, s_tb, add);

@@ -44,7 +44,8 @@ class wct_depos(ctypes.Structure):
 
 
 class wct_opts(ctypes.Structure):
-    _fields_ = [("nsigma", c_double), ("fluctuate", c_int32), ("n_events", c_int32), ("seed", c_uint64)]
+    _fields_ = [("nsigma", c_double), ("fluctuate", c_int32), ("n_events", c_int32), ("seed", c_uint64),
+                ("event_base", c_int32), ("reserved", c_int32)]
 
 
 PlanP = c_void_p
@@ -158,8 +159,10 @@ class DeviceDepos:
                          _ptr(self.plane), _ptr(self.event), _ptr(self.depo_id))
 
 
-def opts(nsigma=3.0, fluctuate=False, n_events=1, seed=0):
-    return wct_opts(float(nsigma), int(bool(fluctuate)), int(n_events), int(seed) & 0xFFFFFFFFFFFFFFFF)
+def opts(nsigma=3.0, fluctuate=False, n_events=1, seed=0, event_base=0):
+    """Run options; the call simulates events event_base .. event_base + n_events - 1."""
+    return wct_opts(float(nsigma), int(bool(fluctuate)), int(n_events), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                    int(event_base), 0)
 
 
 class Plan:

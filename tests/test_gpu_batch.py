@@ -1,0 +1,95 @@
+"""Batched simulation: event windows and sub-batches.
+
+* A call with an event window (event_base, n_events) fills slot e - event_base with event
+  e and keys its fluctuation by e itself: the fluctuated grids equal the oracle's grids of
+  those events bit for bit.
+* wct_simulate over more events than the plan's max_events runs sub-batches; its waves
+  equal one-event-per-call waves bit for bit (integer grids, deterministic transforms).
+* The same on the batched workload's geometry (three planes, 9600 ticks), first events.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import device_depos, make_plan, rel_l2, say, to_np
+from oracle import convolve as OC
+from oracle import fluct as OF
+from paper_2104_08265_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL32 = 1e-5
+
+
+def five_events():
+    """Five events of different sizes on a reduced three-plane geometry."""
+    wl = synth.config2(n_depos=1500, n_tracks=5, n_ticks=960, wires=(240, 240, 346), fluctuate=True)
+    rng = np.random.default_rng(4)
+    ev = rng.choice(5, size=len(wl.depos), p=[0.05, 0.4, 0.1, 0.3, 0.15]).astype(np.int32)
+    order = np.argsort(ev, kind="stable")
+    d = wl.depos.select(order)
+    d.event = ev[order]
+    return wl, d
+
+
+def test_event_window_matches_oracle(wct):
+    wl, d = five_events()
+    plan = make_plan(wct, wl, max_events=2)
+    say("event window 3..4 of 5", len(d))
+    grid = plan.raster(device_depos(wct, wl, d), wct.opts(3.0, True, 2, 21, event_base=3))
+    ref = OF.raster_fluct(d, wl.planes, seed=21, n_events=5)
+    for slot, e in enumerate((3, 4)):
+        for k, g in enumerate(plan.grid_view(grid, slot)):
+            assert np.array_equal(to_np(g), ref[e][k]), (e, k)
+    wave = plan.convolve(grid, 2)
+    R = [r.astype(np.float64) for r in synth.round_responses(wl)]
+    for slot, e in enumerate((3, 4)):
+        for k, w in enumerate(plan.wave_view(wave, slot)):
+            assert rel_l2(to_np(w), OC.convolve_fft(ref[e][k], R[k], wl.planes[k].n_impacts)) < TOL32, (e, k)
+    plan.close()
+
+
+def test_subbatches_equal_single_event_calls(wct):
+    import torch
+    wl, d = five_events()
+    plan = make_plan(wct, wl, max_events=2)
+    dd = device_depos(wct, wl, d)
+    say("five events in sub-batches of two vs five single calls")
+    batched = plan.simulate(dd, wct.opts(3.0, True, 5, 21)).clone()
+    singles = [plan.simulate(dd, wct.opts(3.0, True, 1, 21, event_base=e)).clone() for e in range(5)]
+    torch.cuda.synchronize()
+    assert torch.equal(batched, torch.cat(singles))
+    # an event window that starts inside the batch: slots shift, contents do not
+    part = plan.simulate(dd, wct.opts(3.0, True, 3, 21, event_base=2))
+    torch.cuda.synchronize()
+    assert torch.equal(part, torch.cat(singles[2:]))
+    plan.close()
+
+
+def test_batched_geometry_first_events(wct):
+    """First four events of the 64-event workload, sub-batches of two, against single calls;
+    sampled fluctuated cells of event 1 against the oracle."""
+    import torch
+    wl = synth.config5(n_events=4)
+    plan = make_plan(wct, wl, max_events=2)
+    dd = device_depos(wct, wl)
+    say("batched workload, 4 events", len(wl.depos))
+    batched = plan.simulate(dd, wct.opts(3.0, True, 4, wl.seed))
+    torch.cuda.synchronize()
+    for e in range(4):
+        single = plan.simulate(dd, wct.opts(3.0, True, 1, wl.seed, event_base=e))
+        torch.cuda.synchronize()
+        assert torch.equal(batched[e * plan.wave_elems:(e + 1) * plan.wave_elems], single), e
+        del single
+    del batched
+    grid = plan.raster(dd, wct.opts(3.0, True, 1, wl.seed, event_base=1))
+    rng = np.random.default_rng(8)
+    for k, pl in enumerate(wl.planes):
+        g = to_np(plan.grid_view(grid)[k])
+        hot = np.argsort(g.ravel())[::-1][:4]
+        for f in hot:
+            b, t = divmod(int(f), pl.n_ticks)
+            b0 = min(max(b - 4, 0), g.shape[0] - 8)
+            t0 = min(max(t - 4, 0), g.shape[1] - 8)
+            rr, kk = np.meshgrid(np.arange(b0, b0 + 8), np.arange(t0, t0 + 8), indexing="ij")
+            ref = OF.raster_fluct_at(wl.depos, k, pl, rr.ravel(), kk.ravel(), seed=wl.seed, event=1)
+            assert np.array_equal(g[b0:b0 + 8, t0:t0 + 8].ravel(), ref.astype(np.float64)), (k, b0, t0)
+    plan.close()
