@@ -222,13 +222,82 @@ def fwd_bwd_ratio(wct, synth, steps=10):
             "workload": "256 wires x 1024 ticks, 2e4 track depositions, FP32, no fluctuation"}
 
 
+def graph_of(fn):
+    """Captures fn's launches (on torch's capture stream) into a HIP graph."""
+    import torch
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    return g
+
+
+def batch_bench(wct, synth, sub_batch=16, reps=2):
+    """The 64-event workload (three-plane geometry, log-uniform event sizes): per-event time of
+    one batched call (sub-batches of `sub_batch` events: one persistent raster and one set of
+    batched transform passes each) against a loop of one-event calls on each event's own rows,
+    both eager and replayed from a HIP graph; outputs of the two are compared bit for bit."""
+    import numpy as np
+    import torch
+    wl = synth.config5()
+    n_ev = wl.n_events
+    plan = wct.Plan(wl.planes, synth.round_responses(wl), dtype="f32", max_events=sub_batch)
+    dd = wct.DeviceDepos.from_numpy(wl.depos, "cuda:0", torch.float32)
+    starts = np.searchsorted(wl.depos.event, np.arange(n_ev + 1))
+    we = plan.wave_elems
+    wave_b = plan.new_wave(n_ev)
+    wave_l = plan.new_wave(n_ev)
+    plan.workspace(wct.OP_SIMULATE, sub_batch, dd.n)
+    o_all = wct.opts(wl.nsigma, True, n_ev, wl.seed)
+    singles = [(dd.slice(int(starts[e]), int(starts[e + 1])), wct.opts(wl.nsigma, True, 1, wl.seed, event_base=e),
+                wave_l[e * we:(e + 1) * we]) for e in range(n_ev)]
+
+    def batched():
+        plan.simulate(dd, o_all, wave_b)
+
+    def loop():
+        for d, o, w in singles:
+            plan.simulate(d, o, w)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"events": n_ev, "depos": int(wl.n_depos), "sub_batch": sub_batch}
+    out["batched_ms_per_event"] = timed(batched) / n_ev
+    out["loop_ms_per_event"] = timed(loop) / n_ev
+    out["bitwise_equal"] = bool(torch.equal(wave_b, wave_l))
+    gb = graph_of(batched)
+    out["batched_graph_ms_per_event"] = timed(gb.replay) / n_ev
+    gl = graph_of(loop)
+    out["loop_graph_ms_per_event"] = timed(gl.replay) / n_ev
+    torch.cuda.synchronize()
+    out["graph_replay_bitwise_equal"] = bool(torch.equal(wave_b, wave_l))
+    del gb, gl
+    plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the backward-ratio measurement")
+    ap.add_argument("--no-extras", action="store_true", help="skip the backward-ratio and batching measurements")
     ap.add_argument("--summarize", metavar="DIR", help="write profiles/ summaries from rocprofv3 output in DIR")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run 3 plain device copies of this many MiB (a known-size reference for "
@@ -331,6 +400,7 @@ def main():
     plan.close()
     if not args.no_extras:
         out["fwd_bwd"] = fwd_bwd_ratio(wct, synth)
+        out["batch"] = batch_bench(wct, synth)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl)
         cb["cores_available"] = os.cpu_count()

@@ -202,6 +202,18 @@ int wct_fft_variant_info(int32_t idx, int32_t* out);
 int wct_plan_get_fft(const wct_plan* plan, int32_t plane, int32_t kind, int32_t* variant);
 int wct_plan_set_fft(wct_plan* plan, int32_t plane, int32_t kind, int32_t variant);
 
+/* Autotuning of the transform variants: for every plane and kind, times the
+ * convolution of n_events zero-filled events (HIP events on `stream`, after a warm-up)
+ * with each applicable compiled variant and with the runtime plan, and keeps the
+ * fastest.  cache_path (HOST string, NULL = none) names a text file of earlier choices:
+ * lines "wct-fft <dtype> <N_w> <N_t> <I> <K> <T_R> kind <k> -> <threads> <radices...>"
+ * (or "-> runtime"); choices found there for this library's variants are applied
+ * without timing, new ones are appended.  ws: wct_tune_workspace_bytes(plan, n_events)
+ * bytes (grid, waveform and convolution workspace).  A set-up call: allocates twiddle
+ * tables and synchronises. */
+size_t wct_tune_workspace_bytes(const wct_plan* plan, int32_t n_events);
+int wct_plan_tune(wct_plan* plan, int32_t n_events, const char* cache_path, void* ws, size_t ws_bytes, void* stream);
+
 /* Thread-local text of the last error on this thread ("" if none). */
 const char* wct_last_error(void);
 

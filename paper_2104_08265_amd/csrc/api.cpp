@@ -484,6 +484,116 @@ int plan_tables(wct_plan* P, const wct_plan_desc* desc) {
   return WCT_OK;
 }
 
+// Autotuning of the transform variants -------------------------------------------------
+// Cache file: one line per (geometry, dtype, kind) with the chosen variant's threads and
+// radices ("runtime" for the runtime plan), e.g.
+//   wct-fft f32 2400 9600 10 10 200 kind 1 -> 540 9 9 5 6
+std::string tune_key(const wct_plan* P, int p, int kind) {
+  const PlaneGeom& G = P->geom[p];
+  char b[160];
+  std::snprintf(b, sizeof(b), "wct-fft %s %d %d %d %d %d kind %d", P->dtype == WCT_F32 ? "f32" : "f64", G.nw, G.nt,
+                G.I, G.K, G.TR, kind);
+  return b;
+}
+std::string variant_text(int v) {
+  if (v < 0) return "runtime";
+  int cnt = 0;
+  const FftVariantDesc* d = fft_variants(&cnt);
+  std::string s = std::to_string(d[v].threads);
+  for (int k = 0; k < d[v].npass; ++k) s += " " + std::to_string(d[v].radix[k]);
+  return s;
+}
+std::map<std::string, std::string> read_tune_cache(const char* path) {
+  std::map<std::string, std::string> m;
+  if (!path) return m;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return m;
+  char line[512];
+  while (std::fgets(line, sizeof(line), f)) {
+    std::string l(line);
+    while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+    const size_t a = l.find(" -> ");
+    if (a != std::string::npos) m[l.substr(0, a)] = l.substr(a + 4);
+  }
+  std::fclose(f);
+  return m;
+}
+
+template <typename T>
+int run_tune(wct_plan* P, int n_events, const char* cache_path, void* ws, hipStream_t st) {
+  Carver cv(ws);
+  T* grid = static_cast<T*>(cv.take(P->esize * (size_t)n_events * P->grid_elems));
+  T* wave = static_cast<T*>(cv.take(P->esize * (size_t)n_events * P->wave_elems));
+  const size_t conv_off = align_up(cv.off, 256);
+  HIP_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(grid), (int64_t)(P->esize / 4) * n_events * P->grid_elems, 0,
+                          st),
+          "tune grid fill");
+  auto cache = read_tune_cache(cache_path);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "event create");
+  HIP_TRY(hipEventCreate(&e1), "event create");
+  auto time_conv = [&](float* ms) -> int {
+    for (int rep = 0; rep < 4; ++rep) {
+      if (rep == 1) HIP_TRY(hipEventRecord(e0, st), "event record");
+      Carver cc(static_cast<char*>(ws) + conv_off);
+      const int rc = run_convolve<T>(P, grid, n_events, wave, cc, st);
+      if (rc) return rc;
+    }
+    HIP_TRY(hipEventRecord(e1, st), "event record");
+    HIP_TRY(hipEventSynchronize(e1), "event sync");
+    HIP_TRY(hipEventElapsedTime(ms, e0, e1), "event time");
+    return WCT_OK;
+  };
+  int cnt = 0;
+  const FftVariantDesc* vd = fft_variants(&cnt);
+  std::string appended;
+  int rc = WCT_OK;
+  for (int p = 0; p < P->n_planes && rc == WCT_OK; ++p) {
+    for (int kind = 0; kind < 2 && rc == WCT_OK; ++kind) {
+      const int n = kind == 0 ? P->geom[p].M : P->geom[p].lw;
+      std::vector<int> cand;
+      for (int v = 0; v < cnt; ++v)
+        if (vd[v].kind == kind && vd[v].dbl == (int)(sizeof(T) == 8) && vd[v].n == n) cand.push_back(v);
+      cand.push_back(-1);
+      const std::string key = tune_key(P, p, kind);
+      auto it = cache.find(key);
+      int best = -2;
+      if (it != cache.end())
+        for (int v : cand)
+          if (variant_text(v) == it->second) best = v;
+      if (best == -2) {
+        float best_ms = 0.f;
+        for (int v : cand) {
+          if ((rc = set_fft<T>(P, p, kind, v))) break;
+          float ms = 0.f;
+          if ((rc = time_conv(&ms))) break;
+          if (best == -2 || ms < best_ms) best = v, best_ms = ms;
+        }
+        if (rc) break;
+        appended += key + " -> " + variant_text(best) + "\n";
+      }
+      rc = set_fft<T>(P, p, kind, best);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if (cache_path && !appended.empty()) {
+    FILE* f = std::fopen(cache_path, "a");
+    if (!f) return fail(WCT_E_INVALID, "cannot append to tune cache %s", cache_path);
+    std::fputs(appended.c_str(), f);
+    std::fclose(f);
+  }
+  return WCT_OK;
+}
+
+size_t tune_ws_bytes(const wct_plan* P, int n_events) {
+  Carver a(nullptr);
+  a.take(P->esize * (size_t)n_events * P->grid_elems);
+  a.take(P->esize * (size_t)n_events * P->wave_elems);
+  return align_up(a.off, 256) + ws_bytes(P, WCT_OP_CONVOLVE, n_events, 0);
+}
+
 }  // namespace
 
 extern "C" {
@@ -773,6 +883,29 @@ int wct_plan_set_fft(wct_plan* plan, int32_t plane, int32_t kind, int32_t varian
   if (e != hipSuccess) return hip_fail(e, "synchronise before replacing twiddle tables");
   return plan->dtype == WCT_F32 ? set_fft<float>(plan, plane, kind, variant < 0 ? -1 : variant)
                                 : set_fft<double>(plan, plane, kind, variant < 0 ? -1 : variant);
+}
+
+size_t wct_tune_workspace_bytes(const wct_plan* plan, int32_t n_events) {
+  if (!plan || n_events < 1 || n_events > plan->max_events) return 0;
+  return tune_ws_bytes(plan, n_events);
+}
+
+int wct_plan_tune(wct_plan* plan, int32_t n_events, const char* cache_path, void* ws, size_t ws_size, void* stream) {
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  if (n_events < 1 || n_events > plan->max_events)
+    return fail(WCT_E_INVALID, "n_events %d outside [1, %d]", n_events, plan->max_events);
+  const size_t need = tune_ws_bytes(plan, n_events);
+  if (!ws || ws_size < need) return fail(WCT_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_size, need);
+  DeviceGuard dg(plan->device);
+  if (!dg.ok) return fail(WCT_E_DEVICE, "hipSetDevice(%d) failed", plan->device);
+  const bool prof = plan->prof.on;
+  plan->prof.on = false;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int rc = plan->dtype == WCT_F32 ? run_tune<float>(plan, n_events, cache_path, ws, st)
+                                        : run_tune<double>(plan, n_events, cache_path, ws, st);
+  plan->prof.on = prof;
+  return rc;
 }
 
 int wct_profile_enable(wct_plan* plan, int32_t enable) {

@@ -84,6 +84,8 @@ wct_fft_variant_count = _sig("wct_fft_variant_count", c_int32, [])
 wct_fft_variant_info = _sig("wct_fft_variant_info", c_int32, [c_int32, POINTER(c_int32)])
 wct_plan_get_fft = _sig("wct_plan_get_fft", c_int32, [PlanP, c_int32, c_int32, POINTER(c_int32)])
 wct_plan_set_fft = _sig("wct_plan_set_fft", c_int32, [PlanP, c_int32, c_int32, c_int32])
+wct_tune_workspace_bytes = _sig("wct_tune_workspace_bytes", c_size_t, [PlanP, c_int32])
+wct_plan_tune = _sig("wct_plan_tune", c_int32, [PlanP, c_int32, c_char_p, c_void_p, c_size_t, c_void_p])
 
 
 def fft_variants():
@@ -153,6 +155,12 @@ class DeviceDepos:
         f = lambda a: torch.as_tensor(a).to(device=device, dtype=dtype).contiguous()
         i = lambda a: torch.as_tensor(a.astype("int32")).to(device=device).contiguous()
         return DeviceDepos(f(d.q), f(d.t), f(d.p), f(d.sigma_t), f(d.sigma_p), i(d.plane), i(d.event), i(d.depo_id))
+
+    def slice(self, a, b):
+        """Rows a..b-1 as views (no copy)."""
+        f = lambda x: x[a:b]
+        return DeviceDepos(f(self.q), f(self.t), f(self.p), f(self.sigma_t), f(self.sigma_p), f(self.plane),
+                           f(self.event), f(self.depo_id))
 
     def c(self):
         return wct_depos(self.n, _ptr(self.q), _ptr(self.t), _ptr(self.p), _ptr(self.sigma_t), _ptr(self.sigma_p),
@@ -268,6 +276,17 @@ class Plan:
 
     def set_fft(self, plane, kind, variant):
         check(wct_plan_set_fft(self.h, plane, kind, variant), "wct_plan_set_fft")
+
+    def tune(self, n_events=1, cache_path=None):
+        """Pick the fastest transform variant per plane and kind (optionally via a cache file)."""
+        torch = _torch()
+        need = int(wct_tune_workspace_bytes(self.h, n_events))
+        if need == 0:
+            raise WctError(WCT_E_INVALID, "wct_tune_workspace_bytes")
+        ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
+        path = None if cache_path is None else str(cache_path).encode()
+        check(wct_plan_tune(self.h, n_events, path, _ptr(ws), need, self._stream()), "wct_plan_tune")
+        return {(p, k): self.get_fft(p, k) for p in range(self.n_planes) for k in (0, 1)}
 
     def fft_candidates(self, plane, kind):
         """Variants applicable to a plane's transform of this kind, runtime plan (-1) last."""

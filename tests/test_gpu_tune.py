@@ -1,0 +1,65 @@
+"""Transform variants and their autotuner.
+
+* Every compiled variant that applies to a plane gives the convolution the runtime plan
+  gives (same transform, different rounding: relative L2 1e-6 in FP32).
+* wct_plan_tune picks a variant per plane and kind, writes the cache file, and a second
+  plan reading the cache makes the same choices without timing.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import make_plan, say
+from paper_2104_08265_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    import torch
+    return float(torch.linalg.norm((a - b).double()) / torch.linalg.norm(b.double()))
+
+
+@pytest.mark.parametrize("name", ["config2", "config3"])
+def test_variants_agree_with_runtime_plan(wct, name):
+    import torch
+    wl = synth.config2(n_depos=10) if name == "config2" else synth.config3(n_depos=10)
+    plan = make_plan(wct, wl)
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(3)
+    g = torch.rand(plan.grid_elems, device="cuda:0", generator=gen, dtype=plan.torch_dtype)
+    g[torch.rand(plan.grid_elems, device="cuda:0", generator=gen) < 0.9] = 0
+    for p in range(plan.n_planes):
+        for k in (0, 1):
+            plan.set_fft(p, k, -1)
+    ref = plan.convolve(g, 1).clone()
+    for p in range(plan.n_planes):
+        for k in (0, 1):
+            for v in plan.fft_candidates(p, k)[:-1]:
+                say(name, "plane", p, "kind", k, "variant", v)
+                plan.set_fft(p, k, v)
+                w = plan.convolve(g, 1)
+                assert rel(w, ref) < 1e-6, (p, k, v)
+            plan.set_fft(p, k, -1)
+    plan.close()
+
+
+def test_tune_and_cache(wct, tmp_path):
+    import torch
+    wl = synth.config2(n_depos=10)
+    cache = tmp_path / "fft.tune"
+    plan = make_plan(wct, wl)
+    say("tune config2 geometry")
+    choice = plan.tune(1, cache)
+    lines = cache.read_text().strip().splitlines()
+    assert len(lines) == 2 * plan.n_planes
+    for (p, k), v in choice.items():
+        assert v in plan.fft_candidates(p, k)
+    plan2 = make_plan(wct, wl)
+    assert plan2.tune(1, cache) == choice
+    assert cache.read_text().strip().splitlines() == lines  # nothing appended
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(5)
+    g = torch.rand(plan.grid_elems, device="cuda:0", generator=gen, dtype=plan.torch_dtype)
+    assert rel(plan.convolve(g, 1), plan2.convolve(g, 1)) == 0.0
+    plan.close()
+    plan2.close()
