@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(F::kBound) k_rows_r2c(const T* __restrict__ sr
 template <typename T, int C, typename F, bool PF>
 __global__ void __launch_bounds__(F::kBound) k_colpass(const cx<T>* __restrict__ shat, int64_t shat_ev_stride,
                                                   const cx<T>* __restrict__ rtil, cx<T>* __restrict__ mhat,
-                                                  int64_t mhat_ev_stride, int nw, int nphase, int nchunk,
+                                                  int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
                                                   F f, const cx<T>* __restrict__ tw) {
   constexpr int E = F::E;
   const int nthr = f.nthr();
@@ -124,12 +124,13 @@ __global__ void __launch_bounds__(F::kBound) k_colpass(const cx<T>* __restrict__
   const int lw = f.n();
   const int ne = lw * C;
   const int nin = nw * C;
-  const int ch = blockIdx.x;
+  int ch, ev;
+  colpass_block(n_events, ch, ev);
   constexpr bool PFS = PF;
   cv2<T> acc[E], rreg[PF ? E : 1], sreg[PFS ? E : 1];
 #pragma unroll
   for (int q = 0; q < E; ++q) acc[q] = to_v(mk(T(0), T(0)));
-  const cx<T>* src = shat + blockIdx.y * shat_ev_stride + (int64_t)ch * nphase * nin;
+  const cx<T>* src = shat + ev * shat_ev_stride + (int64_t)ch * nphase * nin;
   const cx<T>* rt = rtil + (int64_t)ch * nphase * ne;
   if (PFS) {
 #pragma unroll
@@ -178,7 +179,7 @@ __global__ void __launch_bounds__(F::kBound) k_colpass(const cx<T>* __restrict__
   }
   __syncthreads();
   f.template run<true>(buf, tw);
-  cx<T>* dst = mhat + blockIdx.y * mhat_ev_stride;
+  cx<T>* dst = mhat + ev * mhat_ev_stride;
   const int fpad = nchunk * C;
   for (int idx = threadIdx.x; idx < nin; idx += nthr) {
     const int w = idx / C, cc = idx - (idx / C) * C;
@@ -193,7 +194,7 @@ __global__ void __launch_bounds__(F::kBound) k_colpass(const cx<T>* __restrict__
 template <typename T, int C, typename F>
 __global__ void __launch_bounds__(F::kBound) k_colpass_adj(const cx<T>* __restrict__ ghat, int64_t ghat_ev_stride,
                                                       const cx<T>* __restrict__ rtil, cx<T>* __restrict__ hhat,
-                                                      int64_t hhat_ev_stride, int nw, int nphase, int nchunk,
+                                                      int64_t hhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
                                                       F f, const cx<T>* __restrict__ tw) {
   constexpr int E = F::E;
   const int nthr = f.nthr();
@@ -202,8 +203,9 @@ __global__ void __launch_bounds__(F::kBound) k_colpass_adj(const cx<T>* __restri
   const int lw = f.n();
   const int ne = lw * C;
   const int nin = nw * C;
-  const int ch = blockIdx.x;
-  const cx<T>* s = ghat + blockIdx.y * ghat_ev_stride + (int64_t)ch * nin;
+  int ch, ev;
+  colpass_block(n_events, ch, ev);
+  const cx<T>* s = ghat + ev * ghat_ev_stride + (int64_t)ch * nin;
   for (int idx = threadIdx.x; idx < ne; idx += nthr) buf[idx] = idx < nin ? s[idx] : mk(T(0), T(0));
   __syncthreads();
   f.template run<false>(buf, tw);
@@ -215,7 +217,7 @@ __global__ void __launch_bounds__(F::kBound) k_colpass_adj(const cx<T>* __restri
   }
   __syncthreads();
   const cx<T>* rt = rtil + (int64_t)ch * nphase * ne;
-  cx<T>* dst = hhat + blockIdx.y * hhat_ev_stride + (int64_t)ch * nphase * nin;
+  cx<T>* dst = hhat + ev * hhat_ev_stride + (int64_t)ch * nphase * nin;
   for (int i = 0; i < nphase; ++i) {
     const cx<T>* r = rt + (int64_t)i * ne;
 #pragma unroll
@@ -361,11 +363,11 @@ hipError_t launch_colpass(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>
     return launch_colpass_ct<T>(shat, shat_ev_stride, rtil, mhat, mhat_ev_stride, nw, nphase, nchunk, n_events, plan,
                                 tw, tw_rev, st);
   const size_t lds = sizeof(cx<T>) * plan.n * kChunk;
-  const dim3 grid(nchunk, n_events);
+  const dim3 grid(nchunk * n_events);
   const hipError_t e = with_fft<T, 1>(plan, [&](auto f, int thr) {
     using F = decltype(f);
     hipLaunchKernelGGL((k_colpass<T, kChunk, F, colpass_prefetch<T, F>()>), grid, dim3(thr), lds, st, shat,
-                       shat_ev_stride, rtil, mhat, mhat_ev_stride, nw, nphase, nchunk, f, tw);
+                       shat_ev_stride, rtil, mhat, mhat_ev_stride, nw, nphase, nchunk, n_events, f, tw);
   });
   return e != hipSuccess ? e : hipGetLastError();
 }
@@ -378,11 +380,11 @@ hipError_t launch_colpass_adj(const cx<T>* ghat, int64_t ghat_ev_stride, const c
     return launch_colpass_adj_ct<T>(ghat, ghat_ev_stride, rtil, hhat, hhat_ev_stride, nw, nphase, nchunk, n_events,
                                     plan, tw, tw_rev, st);
   const size_t lds = sizeof(cx<T>) * plan.n * kChunk;
-  const dim3 grid(nchunk, n_events);
+  const dim3 grid(nchunk * n_events);
   const hipError_t e = with_fft<T, 1>(plan, [&](auto f, int thr) {
     using F = decltype(f);
     hipLaunchKernelGGL((k_colpass_adj<T, kChunk, F>), grid, dim3(thr), lds, st, ghat, ghat_ev_stride, rtil, hhat,
-                       hhat_ev_stride, nw, nphase, nchunk, f, tw);
+                       hhat_ev_stride, nw, nphase, nchunk, n_events, f, tw);
   });
   return e != hipSuccess ? e : hipGetLastError();
 }

@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(F::kThreads) k_rows_r2c_ct(const T* __restrict
 template <typename T, int C, typename F>
 __global__ void __launch_bounds__(F::kThreads) k_colpass_ct(const cx<T>* __restrict__ shat, int64_t shat_ev_stride,
                                                             const cx<T>* __restrict__ rtil, cx<T>* __restrict__ mhat,
-                                                            int64_t mhat_ev_stride, int nw, int nphase, int nchunk,
+                                                            int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
                                                             const cx<T>* __restrict__ tw,
                                                             const cx<T>* __restrict__ tw_rev) {
   using FI = typename F::Reverse;
@@ -108,8 +108,9 @@ __global__ void __launch_bounds__(F::kThreads) k_colpass_ct(const cx<T>* __restr
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int nin = nw * C;
-  const int ch = blockIdx.x;
-  const cx<T>* src = shat + blockIdx.y * shat_ev_stride + (int64_t)ch * nphase * nin;
+  int ch, ev;
+  colpass_block(n_events, ch, ev);
+  const cx<T>* src = shat + ev * shat_ev_stride + (int64_t)ch * nphase * nin;
   const cx<T>* rt = rtil + (int64_t)ch * nphase * NE;
   cx<T> in[F::IN], out[F::OUT], acc[F::OUT];
 #pragma unroll
@@ -140,7 +141,7 @@ __global__ void __launch_bounds__(F::kThreads) k_colpass_ct(const cx<T>* __restr
   }
   cx<T> res[FI::OUT];
   FI::template rr<true>(buf, tw_rev, acc, res, []() {});
-  cx<T>* dst = mhat + blockIdx.y * mhat_ev_stride;
+  cx<T>* dst = mhat + ev * mhat_ev_stride;
   const int fpad = nchunk * C;
 #pragma unroll
   for (int q = 0; q < FI::MBL; ++q) {
@@ -162,7 +163,7 @@ __global__ void __launch_bounds__(F::kThreads) k_colpass_adj_ct(const cx<T>* __r
                                                                 int64_t ghat_ev_stride,
                                                                 const cx<T>* __restrict__ rtil,
                                                                 cx<T>* __restrict__ hhat, int64_t hhat_ev_stride,
-                                                                int nw, int nphase, int nchunk,
+                                                                int nw, int nphase, int nchunk, int n_events,
                                                                 const cx<T>* __restrict__ tw,
                                                                 const cx<T>* __restrict__ tw_rev) {
   using FI = typename F::Reverse;
@@ -171,8 +172,9 @@ __global__ void __launch_bounds__(F::kThreads) k_colpass_adj_ct(const cx<T>* __r
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int nin = nw * C;
-  const int ch = blockIdx.x;
-  const cx<T>* s = ghat + blockIdx.y * ghat_ev_stride + (int64_t)ch * nin;
+  int ch, ev;
+  colpass_block(n_events, ch, ev);
+  const cx<T>* s = ghat + ev * ghat_ev_stride + (int64_t)ch * nin;
   cx<T> in[F::IN], g[F::OUT];
 #pragma unroll
   for (int q = 0; q < F::MB0; ++q) {
@@ -185,7 +187,7 @@ __global__ void __launch_bounds__(F::kThreads) k_colpass_adj_ct(const cx<T>* __r
   }
   F::template rr<false>(buf, tw, in, g, []() {});
   const cx<T>* rt = rtil + (int64_t)ch * nphase * NE;
-  cx<T>* dst = hhat + blockIdx.y * hhat_ev_stride + (int64_t)ch * nphase * nin;
+  cx<T>* dst = hhat + ev * hhat_ev_stride + (int64_t)ch * nphase * nin;
   for (int i = 0; i < nphase; ++i) {
     const cx<T>* r = rt + (int64_t)i * NE;
     cx<T> h[FI::IN], res[FI::OUT];
@@ -323,8 +325,8 @@ hipError_t launch_colpass_ct(const cx<T>* shat, int64_t shat_ev_stride, const cx
   const size_t lds = sizeof(cx<T>) * plan.n * kChunk;
   const hipError_t e = with_variant<T, 1>(plan.variant, [&](auto f) {
     using F = decltype(f);
-    hipLaunchKernelGGL((k_colpass_ct<T, kChunk, F>), dim3(nchunk, n_events), dim3(F::kThreads), lds, st, shat,
-                       shat_ev_stride, rtil, mhat, mhat_ev_stride, nw, nphase, nchunk, tw, tw_rev);
+    hipLaunchKernelGGL((k_colpass_ct<T, kChunk, F>), dim3(nchunk * n_events), dim3(F::kThreads), lds, st, shat,
+                       shat_ev_stride, rtil, mhat, mhat_ev_stride, nw, nphase, nchunk, n_events, tw, tw_rev);
   });
   return e != hipSuccess ? e : hipGetLastError();
 }
@@ -336,8 +338,8 @@ hipError_t launch_colpass_adj_ct(const cx<T>* ghat, int64_t ghat_ev_stride, cons
   const size_t lds = sizeof(cx<T>) * plan.n * kChunk;
   const hipError_t e = with_variant<T, 1>(plan.variant, [&](auto f) {
     using F = decltype(f);
-    hipLaunchKernelGGL((k_colpass_adj_ct<T, kChunk, F>), dim3(nchunk, n_events), dim3(F::kThreads), lds, st, ghat,
-                       ghat_ev_stride, rtil, hhat, hhat_ev_stride, nw, nphase, nchunk, tw, tw_rev);
+    hipLaunchKernelGGL((k_colpass_adj_ct<T, kChunk, F>), dim3(nchunk * n_events), dim3(F::kThreads), lds, st,
+                       ghat, ghat_ev_stride, rtil, hhat, hhat_ev_stride, nw, nphase, nchunk, n_events, tw, tw_rev);
   });
   return e != hipSuccess ? e : hipGetLastError();
 }

@@ -18,6 +18,15 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk) {
   return xcd < r ? xcd * (q + 1) + pos : r * (q + 1) + (xcd - r) * q + pos;
 }
 
+// Column-pass block -> (chunk, event).  Events vary fastest and consecutive logical
+// blocks share an XCD, so the blocks of one chunk, which read the same slice of R~, run
+// together on one L2.
+__device__ __forceinline__ void colpass_block(int n_events, int& ch, int& ev) {
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  ch = L / n_events;
+  ev = L - ch * n_events;
+}
+
 // 16-byte vector of the real type (4 floats or 2 doubles) for row loads: a clang vector,
 // so register arrays of it stay in registers.
 template <typename T>
