@@ -31,15 +31,28 @@ TRAFFIC_JSON = os.path.join(PROFILES, "hbm_traffic.json")
 # The commands whose output --summarize reads (run from /tmp on the GPU host, R = repo root).
 PROFILE_COMMANDS = {
     "trace": "rocprofv3 --kernel-trace --stats -f csv -d $R/gpurun_out/prof_cfg2 -o cfg2 -- "
-             "python3 $R/bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-extras",
+             "python3 $R/bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-extras --tune-cache $R/gpurun_out/fft.tune",
     "fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d $R/gpurun_out/pmc_fetch -o fetch -- "
-             "python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --copy-calibration-mib 1024",
+             "python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --copy-calibration-mib 1024 "
+             "--tune-cache $R/gpurun_out/fft.tune",
     "write": "rocprofv3 --pmc WRITE_SIZE -f csv -d $R/gpurun_out/pmc_write -o write -- "
-             "python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --copy-calibration-mib 1024",
+             "python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --copy-calibration-mib 1024 "
+             "--tune-cache $R/gpurun_out/fft.tune",
 }
-FAMILIES = [("k_tile<float, true", "raster_tile_fluct"), ("k_tile<float, false", "raster_tile_mean"),
-            ("k_rows_r2c<", "rows_r2c"), ("k_colpass<", "colpass"), ("k_rows_c2r<float, 4, false", "rows_c2r"),
-            ("k_big<", "raster_wide_rows")]
+def family(kernel_name):
+    """Kernel family (the names of the per-kernel table) of a device kernel symbol."""
+    n = kernel_name.split("(")[0]
+    if "k_tile<" in n:
+        return "raster_tile_fluct" if ", true," in n else "raster_tile_mean"
+    if "k_big<" in n:
+        return "raster_wide_rows"
+    if "k_rows_r2c" in n:
+        return "rows_r2c"
+    if "k_colpass" in n and "adj" not in n:
+        return "colpass"
+    if "k_rows_c2r" in n and ", false," in n:
+        return "rows_c2r"
+    return None
 
 
 def built_digest():
@@ -57,13 +70,6 @@ def log_digest(path):
         for line in f:
             if line.startswith("{") and '"build"' in line:
                 return json.loads(line).get("build")
-    return None
-
-
-def family(kernel_name):
-    for prefix, fam in FAMILIES:
-        if prefix in kernel_name:
-            return fam
     return None
 
 
@@ -299,6 +305,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward-ratio and batching measurements")
     ap.add_argument("--summarize", metavar="DIR", help="write profiles/ summaries from rocprofv3 output in DIR")
+    ap.add_argument("--tune-cache", metavar="FILE", help="transform-variant choices: read from / appended to FILE")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run 3 plain device copies of this many MiB (a known-size reference for "
                          "hardware byte counters)")
@@ -325,6 +332,11 @@ def main():
 
     wl = synth.config2()
     plan = wct.Plan(wl.planes, synth.round_responses(wl), dtype="f32")
+    fft_choice = plan.tune(1, args.tune_cache)  # transform variant per plane and axis, timed on this GPU
+    variants = {v["index"]: v for v in wct.fft_variants()}
+    fft_desc = {f"plane{p}_{'ticks' if k == 0 else 'wires'}":
+                ("runtime" if v < 0 else f"{variants[v]['threads']} threads, radices {variants[v]['radices']}")
+                for (p, k), v in sorted(fft_choice.items())}
     dd = wct.DeviceDepos.from_numpy(wl.depos, "cuda:0", torch.float32)
     o = wct.opts(wl.nsigma, True, 1, wl.seed)
     wave = plan.new_wave(1)
@@ -395,6 +407,7 @@ def main():
         "dominant_kernel": dom,
         "kernels": kernels,
         "roofline": roofline,
+        "fft_plans": fft_desc,
         "build": built_digest(),
     }
     plan.close()

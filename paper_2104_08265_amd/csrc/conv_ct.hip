@@ -20,7 +20,7 @@ namespace wct {
 // requested as soon as the current row's first pass has consumed its registers.
 // ---------------------------------------------------------------------------
 template <typename T, int C, typename F>
-__global__ void __launch_bounds__(F::kThreads) k_rows_r2c_ct(const T* __restrict__ src, int64_t src_ev_stride,
+__global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_ct(const T* __restrict__ src, int64_t src_ev_stride,
                                                              cx<T>* __restrict__ dst, int64_t dst_ev_stride, int nt,
                                                              int nphase, int nper, int nchunk, int n_events,
                                                              const cx<T>* __restrict__ tw,
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(F::kThreads) k_rows_r2c_ct(const T* __restrict
 // sum in registers, inverse transform with the reversed plan.
 // ---------------------------------------------------------------------------
 template <typename T, int C, typename F>
-__global__ void __launch_bounds__(F::kThreads) k_colpass_ct(const cx<T>* __restrict__ shat, int64_t shat_ev_stride,
+__global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_colpass_ct(const cx<T>* __restrict__ shat, int64_t shat_ev_stride,
                                                             const cx<T>* __restrict__ rtil, cx<T>* __restrict__ mhat,
                                                             int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
                                                             const cx<T>* __restrict__ tw,
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(F::kThreads) k_colpass_ct(const cx<T>* __restr
 // conj(R~_i) and an inverse transform with the reversed plan, written from registers.
 // ---------------------------------------------------------------------------
 template <typename T, int C, typename F>
-__global__ void __launch_bounds__(F::kThreads) k_colpass_adj_ct(const cx<T>* __restrict__ ghat,
+__global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_colpass_adj_ct(const cx<T>* __restrict__ ghat,
                                                                 int64_t ghat_ev_stride,
                                                                 const cx<T>* __restrict__ rtil,
                                                                 cx<T>* __restrict__ hhat, int64_t hhat_ev_stride,
@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(F::kThreads) k_colpass_adj_ct(const cx<T>* __r
 // Pass C (compiled plan): pre-twiddled half spectrum -> registers -> real row.
 // ---------------------------------------------------------------------------
 template <typename T, int C, bool TILED, typename F>
-__global__ void __launch_bounds__(F::kThreads) k_rows_c2r_ct(const cx<T>* __restrict__ src, int64_t src_ev_stride,
+__global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_c2r_ct(const cx<T>* __restrict__ src, int64_t src_ev_stride,
                                                              T* __restrict__ dst, int64_t dst_ev_stride, int nt,
                                                              int nphase, int nper, int nchunk,
                                                              const cx<T>* __restrict__ tw,

@@ -534,6 +534,10 @@ struct CtFft {
   static constexpr int E = (N * C + NT - 1) / NT;
   static constexpr int kBound = NT;
   static constexpr int kThreads = NT;
+  // waves per SIMD the register allocation must allow: row transforms (small LDS
+  // buffers) keep two 8-wave blocks per CU resident; column transforms take what the
+  // LDS allows anyway
+  static constexpr int kMinWaves = (C == 1 && E <= 12) ? 4 : 1;
   static constexpr int R0 = first_of<Rs...>(), RL = last_of<Rs...>();
   static constexpr int NB0 = (N / R0) * C, NBL = (N / RL) * C;  // butterflies of the first / last pass
   static constexpr int MB0 = (NB0 + NT - 1) / NT, MBL = (NBL + NT - 1) / NT;

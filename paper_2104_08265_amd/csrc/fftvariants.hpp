@@ -2,8 +2,9 @@
 // fft.hpp).  One line per variant: X(kind, real type, threads per block, radices...).
 //  kind 0: tick rows, one sequence per block (passes A and C);
 //  kind 1: wire columns, kChunk interleaved sequences per block (pass B).
-// A plan uses the first variant whose kind, type and length match (the tuner may pick
-// another); lengths without a variant run the runtime plan.  The radices of a variant
+// A plan uses the first variant whose kind, type and length match (listed fastest
+// first as measured on MI355X; the tuner may pick another); lengths without a variant
+// run the runtime plan.  The radices of a variant
 // are its Stockham passes in order; its twiddle table is built by build_fft for them.
 #pragma once
 
@@ -18,13 +19,13 @@
   X(0, float, 128, 5, 5, 5, 5)               \
   X(0, double, 128, 5, 5, 5, 5)              \
   /* wire lengths: 2430, 3600 (2400 / 3456 wires), 810, 972 (800 / 960), 270 (256) */ \
-  X(1, float, 540, 9, 9, 5, 6)               \
   X(1, float, 648, 9, 9, 10, 3)              \
+  X(1, float, 540, 9, 9, 5, 6)               \
   X(1, float, 384, 27, 9, 10)                \
-  X(1, float, 800, 10, 10, 9, 4)             \
   X(1, float, 720, 10, 9, 8, 5)              \
-  X(1, float, 360, 9, 9, 10)                 \
+  X(1, float, 800, 10, 10, 9, 4)             \
   X(1, float, 180, 9, 9, 10)                 \
+  X(1, float, 360, 9, 9, 10)                 \
   X(1, float, 216, 9, 9, 12)                 \
   X(1, float, 128, 9, 5, 6)                  \
   X(1, double, 128, 9, 5, 6)

@@ -71,6 +71,8 @@ __device__ __forceinline__ double uniform53(uint32_t w0, uint32_t w1) {
 __device__ __forceinline__ double det_erf(double x, const double* __restrict__ inv) {
   const double mx2 = -(x * x);
   double term = x, acc = x;
+  // rolled loops: unrolled, the compiler would keep every table entry in registers
+#pragma unroll 1
   for (int j = 1; j < kErfTerms; ++j) {
     term = (term * mx2) * inv[j];
     acc = acc + term * inv[2 * j + 1];
@@ -88,6 +90,7 @@ __device__ __forceinline__ double det_log(double x, const double* __restrict__ i
   const double s = (m - 1.0) / (m + 1.0);
   const double s2 = s * s;
   double poly = inv[23];
+#pragma unroll 1
   for (int j = 10; j >= 0; --j) poly = poly * s2 + inv[2 * j + 1];
   return (s * poly) * 2.0 + (double)e * kLn2;
 }
@@ -96,6 +99,7 @@ __device__ __forceinline__ double det_exp(double x, const DetTables& tb) {
   const double n = rint(x * kLog2e);
   const double r = x - n * kLn2;
   double poly = tb.inv_fact[16];
+#pragma unroll 1
   for (int j = 15; j >= 0; --j) poly = poly * r + tb.inv_fact[j];
   return ldexp(poly, (int)n);
 }
