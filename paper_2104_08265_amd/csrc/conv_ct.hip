@@ -74,7 +74,11 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_ct(const
     });
     cx<T>* out = dst + ev * dst_ev_stride;
     const int fpad = nchunk * C;
-    for (int k = threadIdx.x; k < fpad; k += NT) {
+    // frequency k goes to [k / C][i][c][k % C]; with NT a multiple of C a thread keeps
+    // k % C and advances by NT / C chunks per step
+    const int64_t cstride = (int64_t)nphase * nper * C;
+    cx<T>* o = out + ((int64_t)i * nper + c) * C;
+    auto post_twiddle = [&](int k) {
       cx<T> X = mk(T(0), T(0));
       if (k <= M) {
         const cx<T> A = z[k == M ? 0 : k];
@@ -84,8 +88,13 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_ct(const
         const cx<T> O = mk(D.y, -D.x);  // (A - B) / (2i)
         X = Ev + cmul(post[k], O);
       }
-      const int ch = k / C, cc = k - (k / C) * C;
-      out[(((int64_t)ch * nphase + i) * nper + c) * C + cc] = X;
+      return X;
+    };
+    if constexpr (NT % C == 0) {
+      cx<T>* op = o + (int64_t)(threadIdx.x / C) * cstride + threadIdx.x % C;
+      for (int k = threadIdx.x; k < fpad; k += NT, op += (NT / C) * cstride) *op = post_twiddle(k);
+    } else {
+      for (int k = threadIdx.x; k < fpad; k += NT) o[(int64_t)(k / C) * cstride + k % C] = post_twiddle(k);
     }
     __syncthreads();
     L = Ln;
