@@ -22,12 +22,32 @@
 
 namespace wct {
 
-// Small tables, filled on the host with correctly rounded divisions.
+// Small tables, filled on the host with correctly rounded divisions (kept in LDS for
+// the loops that index them at run time).
 struct DetTables {
   double inv[256];      // inv[j] = 1/j (inv[0] = 0)
   double inv_fact[17];  // 1/j!
   double fact[19];      // j! (exact)
 };
+
+// The same values as compile-time constants for the fully unrolled series (erf, log,
+// exp): each entry is one correctly rounded division, as on the host, and unrolled use
+// keeps them out of vector registers.
+constexpr DetTables make_det_const() {
+  DetTables t{};
+  t.inv[0] = 0.0;
+  for (int j = 1; j < 256; ++j) t.inv[j] = 1.0 / (double)j;
+  double f = 1.0;
+  t.fact[0] = 1.0;
+  t.inv_fact[0] = 1.0;
+  for (int j = 1; j < 19; ++j) {
+    f = f * (double)j;
+    t.fact[j] = f;
+    if (j <= 16) t.inv_fact[j] = 1.0 / f;
+  }
+  return t;
+}
+constexpr DetTables kDet = make_det_const();
 
 constexpr double kTwoOverSqrtPi = 1.1283791670955126;
 constexpr double kSqrt2 = 1.4142135623730951;
@@ -68,19 +88,18 @@ __device__ __forceinline__ double uniform53(uint32_t w0, uint32_t w1) {
   return ((double)(w0 >> 6) * 134217728.0 + (double)(w1 >> 5)) * 0x1p-53;
 }
 
-__device__ __forceinline__ double det_erf(double x, const double* __restrict__ inv) {
+__device__ __forceinline__ double det_erf(double x) {
   const double mx2 = -(x * x);
   double term = x, acc = x;
-  // rolled loops: unrolled, the compiler would keep every table entry in registers
-#pragma unroll 1
+#pragma unroll
   for (int j = 1; j < kErfTerms; ++j) {
-    term = (term * mx2) * inv[j];
-    acc = acc + term * inv[2 * j + 1];
+    term = (term * mx2) * kDet.inv[j];
+    acc = acc + term * kDet.inv[2 * j + 1];
   }
   return kTwoOverSqrtPi * acc;
 }
 
-__device__ __forceinline__ double det_log(double x, const double* __restrict__ inv) {
+__device__ __forceinline__ double det_log(double x) {
   int e;
   double m = frexp(x, &e);
   if (m < kSqrtHalf) {
@@ -89,28 +108,30 @@ __device__ __forceinline__ double det_log(double x, const double* __restrict__ i
   }
   const double s = (m - 1.0) / (m + 1.0);
   const double s2 = s * s;
-  double poly = inv[23];
-#pragma unroll 1
-  for (int j = 10; j >= 0; --j) poly = poly * s2 + inv[2 * j + 1];
+  double poly = kDet.inv[23];
+#pragma unroll
+  for (int j = 10; j >= 0; --j) poly = poly * s2 + kDet.inv[2 * j + 1];
   return (s * poly) * 2.0 + (double)e * kLn2;
 }
 
-__device__ __forceinline__ double det_exp(double x, const DetTables& tb) {
+__device__ __forceinline__ double det_exp(double x) {
   const double n = rint(x * kLog2e);
   const double r = x - n * kLn2;
-  double poly = tb.inv_fact[16];
-#pragma unroll 1
-  for (int j = 15; j >= 0; --j) poly = poly * r + tb.inv_fact[j];
+  double poly = kDet.inv_fact[16];
+#pragma unroll
+  for (int j = 15; j >= 0; --j) poly = poly * r + kDet.inv_fact[j];
   return ldexp(poly, (int)n);
 }
 
 __device__ __forceinline__ double det_lfact(int64_t n, const DetTables& tb) {
-  if (n <= 18) return det_log(tb.fact[n], tb.inv);
+  // one det_log call site: the argument is n! (exact) for small n, else n
   const double x = (double)n;
+  const double lg = det_log(n <= 18 ? tb.fact[n] : x);
+  if (n <= 18) return lg;
   const double r = 1.0 / x;
   const double r2 = r * r;
   const double series = r * ((1.0 / 12.0) - r2 * ((1.0 / 360.0) - r2 * ((1.0 / 1260.0) - r2 * (1.0 / 1680.0))));
-  return (x + 0.5) * det_log(x, tb.inv) - x + kHalfLn2Pi + series;
+  return (x + 0.5) * lg - x + kHalfLn2Pi + series;
 }
 
 __device__ __forceinline__ int64_t binom_inversion(int64_t N, double pp, double q, double u, const DetTables& tb) {
@@ -135,9 +156,9 @@ __device__ __forceinline__ int64_t binom_chopdown(int64_t N, double pp, double q
   const double Nf = (double)N;
   int64_t m = (int64_t)floor((Nf + 1.0) * pp);
   if (m > N) m = N;
-  const double x = det_lfact(N, tb) - det_lfact(m, tb) - det_lfact(N - m, tb) + (double)m * det_log(pp, tb.inv) +
-                   (double)(N - m) * det_log(q, tb.inv);
-  const double pm = det_exp(x, tb);
+  const double x = det_lfact(N, tb) - det_lfact(m, tb) - det_lfact(N - m, tb) + (double)m * det_log(pp) +
+                   (double)(N - m) * det_log(q);
+  const double pm = det_exp(x);
   double v = u - pm;
   if (v < 0.0) return m;
   int64_t lo = m, hi = m;

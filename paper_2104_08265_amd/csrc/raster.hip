@@ -87,12 +87,12 @@ __device__ __forceinline__ int find_plane(const RasterGeom& g, int tin) {
 // computed from the same doubles the oracle uses, with one erf per edge.
 template <bool FLUCT>
 __device__ __forceinline__ void edge_fill(double* __restrict__ e, int k0, int k1, double mu, double sigma, double lo,
-                                          double hi, const double* __restrict__ inv, int lane) {
+                                          double hi, int lane) {
   const int n = k1 - k0;
   const double s2 = sigma * kSqrt2;
   for (int x = lane; x <= n; x += 64) {
     const double edge = x == 0 ? fmax((double)k0, lo) : (x == n ? fmin((double)k1, hi) : (double)(k0 + x));
-    e[x] = FLUCT ? det_erf((edge - mu) / s2, inv) : erf((edge - mu) / s2);
+    e[x] = FLUCT ? det_erf((edge - mu) / s2) : erf((edge - mu) / s2);
   }
 }
 __device__ __forceinline__ double edge_weight(const double* e, int x) { return 0.5 * (e[x + 1] - e[x]); }
@@ -177,8 +177,8 @@ __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int
                                             double* __restrict__ ea, double* __restrict__ eb, SampleQueue& q,
                                             int& qn, const DetTables& tb, int lane, Dst dst, Add add) {
   const int nbr = b1 - b0, nkr = k1 - k0;
-  edge_fill<FLUCT>(ea, b0, b1, w.u, w.su, w.ulo, w.uhi, tb.inv, lane);
-  edge_fill<FLUCT>(eb, k0, k1, w.t, w.st, w.tlo, w.thi, tb.inv, lane);
+  edge_fill<FLUCT>(ea, b0, b1, w.u, w.su, w.ulo, w.uhi, lane);
+  edge_fill<FLUCT>(eb, k0, k1, w.t, w.st, w.tlo, w.thi, lane);
   wave_sync();
   if (!FLUCT) {
     const float rd = 1.0f / (float)nkr;
