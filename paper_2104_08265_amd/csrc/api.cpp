@@ -134,6 +134,7 @@ struct wct_plan {
   std::vector<FftPlan> fp_t, fp_w;
   std::vector<void*> tw_t, post_t, tw_w, tw_w_rev, rtil;
   DetTables* d_tables = nullptr;
+  double* d_lfact = nullptr;  // ln(n!), n < kLfactTable, for the chop-down sampler
   std::vector<void*> allocs;
   int64_t grid_elems = 0, wave_elems = 0, shat_elems = 0, mhat_elems = 0;
   int ntiles_ev = 0;
@@ -280,7 +281,8 @@ template <typename T>
 int run_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, T* grid, Carver& cv, hipStream_t st) {
   const RasterGeom g = raster_geom(P, o->n_events, o->event_base);
   const RasterWs ws = carve_raster(P, cv, o->n_events, d->n);
-  HIP_TRY(launch_raster<T>(view<T>(d), g, o->nsigma, o->fluctuate, o->seed, grid, ws, P->d_tables, P->n_cu, st,
+  HIP_TRY(launch_raster<T>(view<T>(d), g, o->nsigma, o->fluctuate, o->seed, grid, ws, P->d_tables, P->d_lfact,
+                           P->n_cu, st,
                            hook(P)),
           "raster launch");
   return WCT_OK;
@@ -707,6 +709,13 @@ int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
   if (e != hipSuccess) {
     delete P;
     return hip_fail(e, "table upload");
+  }
+  P->d_lfact = static_cast<double*>(P->dalloc(sizeof(double) * kLfactTable, &e));
+  if (e == hipSuccess) e = launch_lfact_table(P->d_lfact, kLfactTable, P->d_tables, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    delete P;
+    return hip_fail(e, "log-factorial table");
   }
   *out = P;
   return WCT_OK;

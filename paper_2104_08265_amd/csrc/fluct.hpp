@@ -152,11 +152,19 @@ __device__ __forceinline__ int64_t binom_inversion(int64_t N, double pp, double 
   return k;
 }
 
-__device__ __forceinline__ int64_t binom_chopdown(int64_t N, double pp, double q, double u, const DetTables& tb) {
+// ln(n!) for n < kLfactTable is read from a table the plan fills with det_lfact itself
+// (same code, same bits); larger n are evaluated.
+constexpr int kLfactTable = 1 << 17;
+__device__ __forceinline__ double lfact_of(int64_t n, const double* __restrict__ lf, const DetTables& tb) {
+  return (lf && n < kLfactTable) ? lf[n] : det_lfact(n, tb);
+}
+
+__device__ __forceinline__ int64_t binom_chopdown(int64_t N, double pp, double q, double u, const DetTables& tb,
+                                                  const double* __restrict__ lf = nullptr) {
   const double Nf = (double)N;
   int64_t m = (int64_t)floor((Nf + 1.0) * pp);
   if (m > N) m = N;
-  const double x = det_lfact(N, tb) - det_lfact(m, tb) - det_lfact(N - m, tb) + (double)m * det_log(pp) +
+  const double x = lfact_of(N, lf, tb) - lfact_of(m, lf, tb) - lfact_of(N - m, lf, tb) + (double)m * det_log(pp) +
                    (double)(N - m) * det_log(q);
   const double pm = det_exp(x);
   double v = u - pm;
@@ -198,6 +206,24 @@ __device__ __forceinline__ int64_t binomial(int64_t N, double p, double u, const
   // (1 - mu) - (1e-12 + 2.5e-16 N) implies u < F(0) and the inversion would return 0.
   if (!flip && mu < kMuSwitch && u < (1.0 - mu) - (1.0e-12 + (double)N * 2.5e-16)) return 0;
   const int64_t k = mu < kMuSwitch ? binom_inversion(N, pp, q, u, tb) : binom_chopdown(N, pp, q, u, tb);
+  return flip ? N - k : k;
+}
+
+// The two regimes of binomial() as separate entry points, for callers that sort cells by
+// regime first.  Both require N > 0 and 0 < p < 1; binom_regime(N, p) names the one
+// binomial() takes (0: inversion, N p' < 10; 1: chop-down), and binom_regime_draw(r, ...)
+// returns exactly what binomial() returns for the same arguments.
+__device__ __forceinline__ int binom_regime(int64_t N, double p) {
+  const double pp = p > 0.5 ? 1.0 - p : p;
+  return (double)N * pp < kMuSwitch ? 0 : 1;
+}
+template <int REGIME>
+__device__ __forceinline__ int64_t binom_regime_draw(int64_t N, double p, double u, const DetTables& tb,
+                                                     const double* __restrict__ lf) {
+  const bool flip = p > 0.5;
+  const double pp = flip ? 1.0 - p : p;
+  const double q = 1.0 - pp;
+  const int64_t k = REGIME == 0 ? binom_inversion(N, pp, q, u, tb) : binom_chopdown(N, pp, q, u, tb, lf);
   return flip ? N - k : k;
 }
 

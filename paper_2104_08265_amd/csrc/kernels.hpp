@@ -74,10 +74,12 @@ struct ProfHook {
 };
 
 // raster.hip
+// lfact: ln(n!) for n < kLfactTable (launch_lfact_table), or NULL (evaluated per cell).
 template <typename T>
 hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigma, int fluctuate, uint64_t seed,
-                         T* grid, const RasterWs& ws, const DetTables* tables, int n_cu, hipStream_t st,
-                         ProfHook* prof);
+                         T* grid, const RasterWs& ws, const DetTables* tables, const double* lfact, int n_cu,
+                         hipStream_t st, ProfHook* prof);
+hipError_t launch_lfact_table(double* out, int n, const DetTables* tables, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 
 // conv.hip.  A plan with variant >= 0 runs the compiled-plan kernels; the column passes

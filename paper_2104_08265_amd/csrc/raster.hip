@@ -105,10 +105,10 @@ __device__ __forceinline__ int div_small(int x, int d, float rd) {
   return q;
 }
 
-// Per-wave queue of cells whose count needs the full sampler.  Cells whose count follows
-// from the cheap tests (p <= 0, p >= 1, or the exact zero shortcut) never enter it, so
-// the expensive inversion / chop-down paths run with all 64 lanes on queued cells
-// instead of diverging inside every wave.
+// Per-wave queues of cells whose count needs the full sampler, one per regime of the
+// sampler (inversion, chop-down).  Cells whose count follows from the cheap tests (p = 0,
+// p = 1, or the exact zero bound) never enter them; a batch of 64 queued cells then runs
+// one regime's code with all lanes, instead of every wave diverging over both.
 constexpr int kQCap = 128;  // up to 63 left over + 64 pushed
 struct SampleQueue {
   double p[kQCap];
@@ -117,24 +117,20 @@ struct SampleQueue {
   uint32_t dst[kQCap];
 };
 
-__device__ __forceinline__ int binom_quick(int64_t N, double p, double u) {
-  if (N <= 0) return 0;
-  if (p >= 1.0) return -1;  // rare: the full path returns N
-  if (!(p > 0.0)) return 0;
+// The cell's count when the cheap tests decide it (>= 0), else -1 - (regime of the
+// full sampler).
+__device__ __forceinline__ int64_t binom_quick(int64_t N, double p, double u) {
+  if (N <= 0 || !(p > 0.0)) return 0;
+  if (p >= 1.0) return N;
   if (p <= 0.5) {
     const double mu = (double)N * p;
     if (mu < kMuSwitch && u < (1.0 - mu) - (1.0e-12 + (double)N * 2.5e-16)) return 0;
   }
-  return -1;
+  return -1 - binom_regime(N, p);
 }
 
 __device__ __forceinline__ int lanes_below(uint64_t mask, int lane) {
   return __popcll(mask & ((1ull << lane) - 1ull));
-}
-
-// The full sampler for one queued cell.
-__device__ __forceinline__ int sample_queued(const SampleQueue* q, int at, const DetTables* tb) {
-  return (int)binomial((int64_t)q->n[at], q->p[at], q->u[at], *tb);
 }
 
 __device__ __forceinline__ void queue_push(SampleQueue& q, int& qn, bool need, double p, double u, int64_t N,
@@ -150,21 +146,41 @@ __device__ __forceinline__ void queue_push(SampleQueue& q, int& qn, bool need, d
   qn += __popcll(mask);
 }
 
-// Samples queued cells with all lanes, 64 at a time from the top of the queue: full
-// batches only (all = false, inside the cell loop) or everything (all = true).
-template <typename T, typename Add>
-__device__ __forceinline__ void queue_run(SampleQueue& q, int& qn, bool all, int lane, const DetTables& tb, Add add) {
+// Samples queued cells of one regime with all lanes, 64 at a time from the top of the
+// queue: full batches only (all = false, inside the cell loop) or everything (all = true).
+template <typename T, int REGIME, typename Add>
+__device__ __forceinline__ void queue_run(SampleQueue& q, int& qn, bool all, int lane, const DetTables& tb,
+                                          const double* __restrict__ lf, Add add) {
   wave_sync();
   while (qn >= 64 || (all && qn > 0)) {
     const int take = qn < 64 ? qn : 64;
     if (lane < take) {
       const int at = qn - take + lane;
-      const int n = sample_queued(&q, at, &tb);
+      const int64_t n = binom_regime_draw<REGIME>((int64_t)q.n[at], q.p[at], q.u[at], tb, lf);
       if (n) add(q.dst[at], (T)n);
     }
     qn -= take;
     wave_sync();
   }
+}
+
+// A cell's outcome of the cheap tests: added at once, queued for its regime, or nothing.
+template <typename T, typename Add>
+__device__ __forceinline__ void cell_route(SampleQueue* q, int* qn, int64_t quick, double p, double u, int64_t N,
+                                           uint32_t dst, int lane, const DetTables& tb,
+                                           const double* __restrict__ lf, Add add) {
+  if (quick > 0) add(dst, (T)quick);
+  queue_push(q[0], qn[0], quick == -1, p, u, N, dst, lane);
+  if (qn[0] >= 64) queue_run<T, 0>(q[0], qn[0], false, lane, tb, lf, add);
+  queue_push(q[1], qn[1], quick == -2, p, u, N, dst, lane);
+  if (qn[1] >= 64) queue_run<T, 1>(q[1], qn[1], false, lane, tb, lf, add);
+}
+
+template <typename T, typename Add>
+__device__ __forceinline__ void queues_flush(SampleQueue* q, int* qn, int lane, const DetTables& tb,
+                                             const double* __restrict__ lf, Add add) {
+  queue_run<T, 0>(q[0], qn[0], true, lane, tb, lf, add);
+  queue_run<T, 1>(q[1], qn[1], true, lane, tb, lf, add);
 }
 
 // One wave rasterises the cells [b0, b1) x [k0, k1) of a row; `dst(b, k)` names a cell and
@@ -174,8 +190,9 @@ __device__ __forceinline__ void queue_run(SampleQueue& q, int& qn, bool all, int
 template <typename T, bool FLUCT, typename Dst, typename Add>
 __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int k0, int k1, int nt, uint32_t did,
                                             uint32_t ev, uint32_t plane, uint32_t key0, uint32_t key1,
-                                            double* __restrict__ ea, double* __restrict__ eb, SampleQueue& q,
-                                            int& qn, const DetTables& tb, int lane, Dst dst, Add add) {
+                                            double* __restrict__ ea, double* __restrict__ eb, SampleQueue* q,
+                                            int* qn, const DetTables& tb, const double* __restrict__ lf, int lane,
+                                            Dst dst, Add add) {
   const int nbr = b1 - b0, nkr = k1 - k0;
   edge_fill<FLUCT>(ea, b0, b1, w.u, w.su, w.ulo, w.uhi, lane);
   edge_fill<FLUCT>(eb, k0, k1, w.t, w.st, w.tlo, w.thi, lane);
@@ -195,7 +212,7 @@ __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int
       const int total = nbr * np;
       for (int base = 0; base < total; base += 64) {
         const int x = base + lane;
-        bool need_e = false, need_o = false;
+        int64_t quick_e = 0, quick_o = 0;
         double pe = 0.0, po = 0.0, ue = 0.0, uo = 0.0;
         uint32_t de = 0, dodd = 0;
         if (x < total) {
@@ -208,19 +225,17 @@ __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int
             pe = a * edge_weight(eb, ke - k0);
             ue = uniform53(ph.w0, ph.w1);
             de = dst(b, ke);
-            need_e = binom_quick(N, pe, ue) != 0;
+            quick_e = binom_quick(N, pe, ue);
           }
           if (ko < k1) {
             po = a * edge_weight(eb, ko - k0);
             uo = uniform53(ph.w2, ph.w3);
             dodd = dst(b, ko);
-            need_o = binom_quick(N, po, uo) != 0;
+            quick_o = binom_quick(N, po, uo);
           }
         }
-        queue_push(q, qn, need_e, pe, ue, N, de, lane);
-        if (qn >= 64) queue_run<T>(q, qn, false, lane, tb, add);
-        queue_push(q, qn, need_o, po, uo, N, dodd, lane);
-        if (qn >= 64) queue_run<T>(q, qn, false, lane, tb, add);
+        cell_route<T>(q, qn, quick_e, pe, ue, N, de, lane, tb, lf, add);
+        cell_route<T>(q, qn, quick_o, po, uo, N, dodd, lane, tb, lf, add);
       }
     }
   }
@@ -404,12 +419,12 @@ __global__ void __launch_bounds__(256, 3) k_tile(DepoView<T> d, RasterGeom g, do
                                               T* __restrict__ grid, const int32_t* __restrict__ list,
                                               const int32_t* __restrict__ offs, const int32_t* __restrict__ items,
                                               const int32_t* __restrict__ item_off, int32_t* __restrict__ ctrl,
-                                              const DetTables* __restrict__ tables) {
+                                              const DetTables* __restrict__ tables, const double* __restrict__ lf) {
   constexpr int NWAVE = 4;
   __shared__ T tile[TH * TW];
   __shared__ double s_ea[NWAVE][TH + 1];
   __shared__ double s_eb[NWAVE][TW + 1];
-  __shared__ SampleQueue s_q[FLUCT ? NWAVE : 1];
+  __shared__ SampleQueue s_q[FLUCT ? NWAVE : 1][FLUCT ? 2 : 1];
   __shared__ DetTables s_tb;
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -439,8 +454,8 @@ __global__ void __launch_bounds__(256, 3) k_tile(DepoView<T> d, RasterGeom g, do
     __syncthreads();
     const int r0 = offs[t] + chunk * kRowsPerItem;
     const int r1 = min(offs[t] + (chunk + 1) * kRowsPerItem, offs[t + 1]);
-    int qn = 0;
-    SampleQueue& q = s_q[FLUCT ? wv : 0];
+    int qn[2] = {0, 0};
+    SampleQueue* q = s_q[FLUCT ? wv : 0];
     auto dst = [&](int b, int k) { return (uint32_t)((b - tb0) * TW + (k - tk0)); };
     auto add = [&](uint32_t o, T v) { atomicAdd(&tile[o], v); };
     for (int r = r0 + wv; r < r1; r += NWAVE) {
@@ -452,9 +467,9 @@ __global__ void __launch_bounds__(256, 3) k_tile(DepoView<T> d, RasterGeom g, do
       if (!w.ok || bb0 >= bb1 || kk0 >= kk1) continue;
       const uint32_t did = d.depo_id ? (uint32_t)d.depo_id[j] : (uint32_t)j;
       patch_cells<T, FLUCT>(w, bb0, bb1, kk0, kk1, pl.nt, did, (uint32_t)w.key_event, (uint32_t)pi, key0, key1, s_ea[wv],
-                            s_eb[wv], q, qn, s_tb, lane, dst, add);
+                            s_eb[wv], q, qn, s_tb, lf, lane, dst, add);
     }
-    if (FLUCT) queue_run<T>(q, qn, true, lane, s_tb, add);
+    if (FLUCT) queues_flush<T>(q, qn, lane, s_tb, lf, add);
     __syncthreads();
     T* gp = grid + (int64_t)ev * g.grid_ev_stride + pl.grid_off;
     for (int x = threadIdx.x; x < th * TW; x += blockDim.x) {
@@ -475,11 +490,12 @@ __global__ void __launch_bounds__(256, 3) k_tile(DepoView<T> d, RasterGeom g, do
 template <typename T, bool FLUCT>
 __global__ void __launch_bounds__(256, 3) k_big(DepoView<T> d, RasterGeom g, double nsigma, uint64_t seed,
                                              T* __restrict__ grid, const int32_t* __restrict__ big,
-                                             const int32_t* __restrict__ ctrl, const DetTables* __restrict__ tables) {
+                                             const int32_t* __restrict__ ctrl, const DetTables* __restrict__ tables,
+                                             const double* __restrict__ lf) {
   constexpr int NWAVE = 4, CB = 64, CK = 64;
   __shared__ double s_ea[NWAVE][CB + 1];
   __shared__ double s_eb[NWAVE][CK + 1];
-  __shared__ SampleQueue s_q[FLUCT ? NWAVE : 1];
+  __shared__ SampleQueue s_q[FLUCT ? NWAVE : 1][FLUCT ? 2 : 1];
   __shared__ DetTables s_tb;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (FLUCT) {
@@ -499,8 +515,8 @@ __global__ void __launch_bounds__(256, 3) k_big(DepoView<T> d, RasterGeom g, dou
     const uint32_t did = d.depo_id ? (uint32_t)d.depo_id[j] : (uint32_t)j;
     const int kstart = w.k0 & ~1;  // chunks start on even ticks: a Philox pair never straddles two
     const int ncb = (w.b1 - w.b0 + CB - 1) / CB, nck = (w.k1 - kstart + CK - 1) / CK;
-    int qn = 0;
-    SampleQueue& q = s_q[FLUCT ? wv : 0];
+    int qn[2] = {0, 0};
+    SampleQueue* q = s_q[FLUCT ? wv : 0];
     const int nt = pl.nt;
     auto dst = [&](int b, int k) { return (uint32_t)((int64_t)b * nt + k); };
     auto add = [&](uint32_t o, T v) { atomicAdd(gp + o, v); };
@@ -509,9 +525,9 @@ __global__ void __launch_bounds__(256, 3) k_big(DepoView<T> d, RasterGeom g, dou
       const int b0 = w.b0 + cb * CB, b1 = min(b0 + CB, w.b1);
       const int k0 = max(kstart + ck * CK, w.k0), k1 = min(kstart + (ck + 1) * CK, w.k1);
       patch_cells<T, FLUCT>(w, b0, b1, k0, k1, pl.nt, did, (uint32_t)w.key_event, (uint32_t)w.plane, key0, key1,
-                            s_ea[wv], s_eb[wv], q, qn, s_tb, lane, dst, add);
+                            s_ea[wv], s_eb[wv], q, qn, s_tb, lf, lane, dst, add);
     }
-    if (FLUCT) queue_run<T>(q, qn, true, lane, s_tb, add);
+    if (FLUCT) queues_flush<T>(q, qn, lane, s_tb, lf, add);
   }
 }
 
@@ -532,8 +548,8 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigma, int fluctuate, uint64_t seed,
-                         T* grid, const RasterWs& ws, const DetTables* tables, int n_cu, hipStream_t st,
-                         ProfHook* prof) {
+                         T* grid, const RasterWs& ws, const DetTables* tables, const double* lfact, int n_cu,
+                         hipStream_t st, ProfHook* prof) {
   constexpr int TH = TileShape<T>::TH, TW = TileShape<T>::TW;
   const int64_t nt = ws.ntiles;
   if (prof) prof->begin("raster_bin", st);
@@ -568,27 +584,39 @@ hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigm
   if (prof) prof->begin(fluctuate ? "raster_tile_fluct" : "raster_tile_mean", st);
   if (fluctuate)
     hipLaunchKernelGGL((k_tile<T, true, TH, TW>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.list,
-                       ws.offs, ws.items, ws.item_off, ws.ctrl, tables);
+                       ws.offs, ws.items, ws.item_off, ws.ctrl, tables, lfact);
   else
     hipLaunchKernelGGL((k_tile<T, false, TH, TW>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid,
-                       ws.list, ws.offs, ws.items, ws.item_off, ws.ctrl, tables);
+                       ws.list, ws.offs, ws.items, ws.item_off, ws.ctrl, tables, lfact);
   WCT_CHECK_LAUNCH();
   if (prof) prof->end(st);
   if (prof) prof->begin("raster_wide_rows", st);
   if (fluctuate)
     hipLaunchKernelGGL((k_big<T, true>), dim3(256), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.big, ws.ctrl,
-                       tables);
+                       tables, lfact);
   else
     hipLaunchKernelGGL((k_big<T, false>), dim3(256), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.big, ws.ctrl,
-                       tables);
+                       tables, lfact);
   WCT_CHECK_LAUNCH();
   if (prof) prof->end(st);
   return hipSuccess;
 }
 
 template hipError_t launch_raster<float>(const DepoView<float>&, const RasterGeom&, double, int, uint64_t, float*,
-                                         const RasterWs&, const DetTables*, int, hipStream_t, ProfHook*);
+                                         const RasterWs&, const DetTables*, const double*, int, hipStream_t,
+                                         ProfHook*);
 template hipError_t launch_raster<double>(const DepoView<double>&, const RasterGeom&, double, int, uint64_t, double*,
-                                          const RasterWs&, const DetTables*, int, hipStream_t, ProfHook*);
+                                          const RasterWs&, const DetTables*, const double*, int, hipStream_t,
+                                          ProfHook*);
+
+// ln(n!) table for the chop-down sampler, filled with the sampler's own det_lfact.
+__global__ void k_lfact_table(double* __restrict__ out, int n, const DetTables* __restrict__ tables) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = det_lfact((int64_t)i, *tables);
+}
+hipError_t launch_lfact_table(double* out, int n, const DetTables* tables, hipStream_t st) {
+  hipLaunchKernelGGL(k_lfact_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, out, n, tables);
+  return hipGetLastError();
+}
 
 }  // namespace wct
