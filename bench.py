@@ -147,6 +147,58 @@ def measured_traffic(kernel):
     return t["kernels"][kernel]["bytes_per_launch"]
 
 
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # lane operations per second: 256 CUs x 4 SIMD16 x 2.4 GHz
+
+
+def raster_alu_ops(wl, sample_rows=3000, nsigma=3.0, seed=0):
+    """Algorithmic lane operations of one fluctuated raster of the workload (a cost model).
+
+    Per cell of a row's window: half a Philox4x32-10 block (10 rounds of two 32x32->64
+    products and two xors, key bumps: 78 ops per block), the 53-bit uniform (7), the
+    probability and address (3), the zero bound (6).  Cells that need the full sampler
+    add, in the inversion regime (N p' < 10), the set-up (4), the square-and-multiply
+    power (bit length + popcount of N) and 6 ops per search step (k steps, E[k] = N p');
+    in the chop-down regime the set-up (3 table reads, two logs, one exp: 110) and 7 ops
+    per side step (about 2 |k - m| + 1, E|k - m| ~ 0.8 sigma).  Expectations are taken
+    over a seeded sample of the workload's rows and scaled to all rows.
+    """
+    import numpy as np
+    from scipy.special import erf
+    d = wl.depos
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(len(d.q), min(sample_rows, len(d.q)), replace=False)
+    total = 0.0
+
+    def axis(mu, sig, n):
+        lo, hi = mu - nsigma * sig, mu + nsigma * sig
+        k = np.arange(np.floor(lo), np.ceil(hi))
+        k = k[(k >= 0) & (k < n)]
+        e0, e1 = np.maximum(k, lo), np.minimum(k + 1, hi)
+        return 0.5 * (erf((e1 - mu) / (sig * np.sqrt(2))) - erf((e0 - mu) / (sig * np.sqrt(2))))
+
+    for j in idx:
+        pl = wl.planes[int(d.plane[j])]
+        a = axis(pl.n_impacts * float(d.p[j]), pl.n_impacts * float(d.sigma_p[j]), pl.n_impacts * pl.n_wires)
+        b = axis(float(d.t[j]), float(d.sigma_t[j]), pl.n_ticks)
+        p = np.outer(a, b).ravel()
+        p = p[p > 0]
+        N = np.floor(float(d.q[j]) + 0.5)
+        if N <= 0 or p.size == 0:
+            continue
+        pp = np.minimum(p, 1 - p)
+        mu = N * pp
+        ops = p.size * (39 + 7 + 3 + 6)
+        inv = mu < 10
+        full_inv = inv * np.clip(mu, 0, 1) + inv * (mu >= 1) * (1 - np.clip(mu, 0, 1))  # P(not the zero bound)
+        nbits = int(N).bit_length() + bin(int(N)).count("1")
+        ops += float(np.sum(full_inv * (4 + nbits + 6 * mu)))
+        chop = ~inv
+        sig = np.sqrt(N * pp * (1 - pp))
+        ops += float(np.sum(chop * (110 + 7 * (2 * 0.8 * sig + 1))))
+        total += ops
+    return total * len(d.q) / len(idx)
+
+
 def algorithmic_bytes(plan, esize=4):
     """Bytes each kernel family must move per event (sum over planes) by design."""
     out = {"rows_r2c": 0, "colpass": 0, "rows_c2r": 0, "raster_tile_fluct": 0, "raster_tile_mean": 0}
@@ -371,14 +423,25 @@ def main():
     t_raster = sum(v["ms_per_step"] for k, v in kernels.items() if k.startswith("raster"))
     t_conv = sum(v["ms_per_step"] for k, v in kernels.items() if k in ("rows_r2c", "colpass", "rows_c2r"))
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-    # roofline of the dominant HBM-bound kernel family (FFT passes move the data)
+    # roofline of the dominant kernel: the fluctuated raster is bound by lane arithmetic
+    # (Philox products and the FP64 sampler), the transform passes by HBM
     fft_dom = max(("rows_r2c", "colpass", "rows_c2r"), key=lambda k: kernels.get(k, {}).get("ms_per_step", 0))
     kd = kernels[fft_dom]
-    roofline = {"kernel": fft_dom, "bound": "hbm", "achieved": kd["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": kd["GBps"] / HBM_PEAK_GBS, "traffic": measured_traffic(fft_dom),
-                "alg_bytes_per_launch": alg[fft_dom] / n_planes,
-                "avg_launch_ms": kd["ms_per_step"] / kd["launches_per_step"],
-                "note": "algorithmic bytes / mean launch time from HIP events on the launch stream"}
+    roofline_fft = {"kernel": fft_dom, "bound": "hbm", "achieved": kd["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": kd["GBps"] / HBM_PEAK_GBS, "traffic": measured_traffic(fft_dom),
+                    "alg_bytes_per_launch": alg[fft_dom] / n_planes,
+                    "avg_launch_ms": kd["ms_per_step"] / kd["launches_per_step"]}
+    if dom == "raster_tile_fluct":
+        ops = raster_alu_ops(wl)
+        t = kernels[dom]["ms_per_step"] * 1e-3
+        roofline = {"kernel": dom, "bound": "alu", "achieved": ops / t / 1e12, "peak": ALU_PEAK_TOPS,
+                    "unit": "Tops/s", "frac": ops / t / 1e12 / ALU_PEAK_TOPS, "traffic": measured_traffic(dom),
+                    "alg_ops_per_launch": ops, "avg_launch_ms": kernels[dom]["ms_per_step"],
+                    "note": "algorithmic lane operations (bench.raster_alu_ops cost model) / mean launch time "
+                            "from HIP events on the launch stream; peak = 256 CUs x 64 lanes x 2.4 GHz"}
+    else:
+        roofline = dict(roofline_fft)
+    roofline_fft["note"] = "algorithmic bytes / mean launch time from HIP events on the launch stream"
     conv_bytes = sum(alg[k] for k in ("rows_r2c", "colpass", "rows_c2r"))
     grid_bytes = 4 * sum(i["n_impacts"] * i["n_wires"] * i["n_ticks"] for i in plan.info)
     wave_bytes = 4 * sum(i["n_wires"] * i["n_ticks"] for i in plan.info)
@@ -407,6 +470,7 @@ def main():
         "dominant_kernel": dom,
         "kernels": kernels,
         "roofline": roofline,
+        "roofline_fft": roofline_fft,
         "fft_plans": fft_desc,
         "build": built_digest(),
     }
