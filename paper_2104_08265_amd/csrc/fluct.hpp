@@ -49,6 +49,13 @@ constexpr DetTables make_det_const() {
 }
 constexpr DetTables kDet = make_det_const();
 
+// The part of the tables the sampler indexes at run time (inversion: 1/(k+1) for
+// k < kInversionCap; ln(n!) for n <= 18), small enough for LDS next to a raster tile.
+struct DetTablesSmall {
+  double inv[129];
+  double fact[19];
+};
+
 constexpr double kTwoOverSqrtPi = 1.1283791670955126;
 constexpr double kSqrt2 = 1.4142135623730951;
 constexpr double kSqrtHalf = 0.7071067811865476;
@@ -123,7 +130,8 @@ __device__ __forceinline__ double det_exp(double x) {
   return ldexp(poly, (int)n);
 }
 
-__device__ __forceinline__ double det_lfact(int64_t n, const DetTables& tb) {
+template <typename Tab>
+__device__ __forceinline__ double det_lfact(int64_t n, const Tab& tb) {
   // one det_log call site: the argument is n! (exact) for small n, else n
   const double x = (double)n;
   const double lg = det_log(n <= 18 ? tb.fact[n] : x);
@@ -134,7 +142,8 @@ __device__ __forceinline__ double det_lfact(int64_t n, const DetTables& tb) {
   return (x + 0.5) * lg - x + kHalfLn2Pi + series;
 }
 
-__device__ __forceinline__ int64_t binom_inversion(int64_t N, double pp, double q, double u, const DetTables& tb) {
+template <typename Tab>
+__device__ __forceinline__ int64_t binom_inversion(int64_t N, double pp, double q, double u, const Tab& tb) {
   double f = 1.0;
   for (int b = 63 - __clzll((unsigned long long)N); b >= 0; --b) {
     f = f * f;
@@ -155,11 +164,13 @@ __device__ __forceinline__ int64_t binom_inversion(int64_t N, double pp, double 
 // ln(n!) for n < kLfactTable is read from a table the plan fills with det_lfact itself
 // (same code, same bits); larger n are evaluated.
 constexpr int kLfactTable = 1 << 17;
-__device__ __forceinline__ double lfact_of(int64_t n, const double* __restrict__ lf, const DetTables& tb) {
+template <typename Tab>
+__device__ __forceinline__ double lfact_of(int64_t n, const double* __restrict__ lf, const Tab& tb) {
   return (lf && n < kLfactTable) ? lf[n] : det_lfact(n, tb);
 }
 
-__device__ __forceinline__ int64_t binom_chopdown(int64_t N, double pp, double q, double u, const DetTables& tb,
+template <typename Tab>
+__device__ __forceinline__ int64_t binom_chopdown(int64_t N, double pp, double q, double u, const Tab& tb,
                                                   const double* __restrict__ lf = nullptr) {
   const double Nf = (double)N;
   int64_t m = (int64_t)floor((Nf + 1.0) * pp);
@@ -217,8 +228,8 @@ __device__ __forceinline__ int binom_regime(int64_t N, double p) {
   const double pp = p > 0.5 ? 1.0 - p : p;
   return (double)N * pp < kMuSwitch ? 0 : 1;
 }
-template <int REGIME>
-__device__ __forceinline__ int64_t binom_regime_draw(int64_t N, double p, double u, const DetTables& tb,
+template <int REGIME, typename Tab>
+__device__ __forceinline__ int64_t binom_regime_draw(int64_t N, double p, double u, const Tab& tb,
                                                      const double* __restrict__ lf) {
   const bool flip = p > 0.5;
   const double pp = flip ? 1.0 - p : p;

@@ -105,17 +105,16 @@ __device__ __forceinline__ int div_small(int x, int d, float rd) {
   return q;
 }
 
-// Per-wave queues of cells whose count needs the full sampler, one per regime of the
-// sampler (inversion, chop-down).  Cells whose count follows from the cheap tests (p = 0,
-// p = 1, or the exact zero bound) never enter them; a batch of 64 queued cells then runs
-// one regime's code with all lanes, instead of every wave diverging over both.
-constexpr int kQCap = 128;  // up to 63 left over + 64 pushed
-struct SampleQueue {
-  double p[kQCap];
-  double u[kQCap];
-  int n[kQCap];
-  uint32_t dst[kQCap];
-};
+// Cells whose count needs the full sampler wait in per-wave queues, one per regime of the
+// sampler (inversion, chop-down), so that a batch of 64 runs one regime's code with all
+// lanes instead of every wave diverging over both.  Cells whose count follows from the
+// cheap tests (p = 0, p = 1, or the exact zero bound) never enter them.
+//
+// A queue lives in registers: position e (< 128) is held by lane e & 63 in slot e >> 6.
+// A push moves each new entry to its lane with one ds_permute per 32-bit word; a run
+// takes slot 0 (positions 0..63) and slot 1 moves down.  The queues are emptied at the
+// end of every row's sub-patch, so a batch shares the row's electron count N (a
+// wave-uniform value: the sampler's power loop then runs under scalar control).
 
 // The cell's count when the cheap tests decide it (>= 0), else -1 - (regime of the
 // full sampler).
@@ -133,54 +132,78 @@ __device__ __forceinline__ int lanes_below(uint64_t mask, int lane) {
   return __popcll(mask & ((1ull << lane) - 1ull));
 }
 
-__device__ __forceinline__ void queue_push(SampleQueue& q, int& qn, bool need, double p, double u, int64_t N,
-                                           uint32_t dst, int lane) {
-  const uint64_t mask = __ballot(need);
-  if (need) {
-    const int at = qn + lanes_below(mask, lane);
-    q.p[at] = p;
-    q.u[at] = u;
-    q.n[at] = (int)N;
-    q.dst[at] = dst;
-  }
-  qn += __popcll(mask);
+__device__ __forceinline__ uint32_t lo32(double v) { return (uint32_t)__double_as_longlong(v); }
+__device__ __forceinline__ uint32_t hi32(double v) { return (uint32_t)((uint64_t)__double_as_longlong(v) >> 32); }
+__device__ __forceinline__ double mkd(uint32_t lo, uint32_t hi) {
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ uint32_t permute_to(int lane_dst, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_ds_permute(lane_dst << 2, (int)v);
 }
 
-// Samples queued cells of one regime with all lanes, 64 at a time from the top of the
-// queue: full batches only (all = false, inside the cell loop) or everything (all = true).
-template <typename T, int REGIME, typename Add>
-__device__ __forceinline__ void queue_run(SampleQueue& q, int& qn, bool all, int lane, const DetTables& tb,
-                                          const double* __restrict__ lf, Add add) {
-  wave_sync();
-  while (qn >= 64 || (all && qn > 0)) {
-    const int take = qn < 64 ? qn : 64;
-    if (lane < take) {
-      const int at = qn - take + lane;
-      const int64_t n = binom_regime_draw<REGIME>((int64_t)q.n[at], q.p[at], q.u[at], tb, lf);
-      if (n) add(q.dst[at], (T)n);
+struct RegQueue {
+  double p0, u0, p1, u1;  // probability and uniform of the entries in slot 0 / slot 1
+  uint32_t d0, d1;        // their tile offsets
+  int n;                  // entries (wave-uniform)
+};
+
+__device__ __forceinline__ void rq_push(RegQueue& q, bool need, double p, double u, uint32_t dst, int lane) {
+  const uint64_t mask = __ballot(need);
+  const int cnt = __popcll(mask);
+  if (cnt == 0) return;
+  // new entries go to positions n .. n+cnt-1; the other lanes fill the rest of the
+  // rotation so that every lane sends and receives exactly one value
+  const int below = lanes_below(mask, lane);
+  const int t = need ? below : cnt + (lane - below);
+  const int to = (q.n + t) & 63;
+  const double rp = mkd(permute_to(to, lo32(p)), permute_to(to, hi32(p)));
+  const double ru = mkd(permute_to(to, lo32(u)), permute_to(to, hi32(u)));
+  const uint32_t rd = permute_to(to, dst);
+  const int off = (lane - q.n) & 63;
+  if (off < cnt) {
+    if (((q.n + off) >> 6) == 0) {
+      q.p0 = rp;
+      q.u0 = ru;
+      q.d0 = rd;
+    } else {
+      q.p1 = rp;
+      q.u1 = ru;
+      q.d1 = rd;
     }
-    qn -= take;
-    wave_sync();
   }
+  q.n += cnt;
+}
+
+// Samples slot 0 (lanes below `take`) with regime REGIME, then moves slot 1 down.
+template <typename T, int REGIME, typename Add>
+__device__ __forceinline__ void rq_run(RegQueue& q, int take, int64_t N, int lane, const DetTablesSmall& tb,
+                                       const double* __restrict__ lf, Add add) {
+  if (lane < take) {
+    const int64_t k = binom_regime_draw<REGIME>(N, q.p0, q.u0, tb, lf);
+    if (k) add(q.d0, (T)k);
+  }
+  q.p0 = q.p1;
+  q.u0 = q.u1;
+  q.d0 = q.d1;
+  q.n -= take;
 }
 
 // A cell's outcome of the cheap tests: added at once, queued for its regime, or nothing.
 template <typename T, typename Add>
-__device__ __forceinline__ void cell_route(SampleQueue* q, int* qn, int64_t quick, double p, double u, int64_t N,
-                                           uint32_t dst, int lane, const DetTables& tb,
-                                           const double* __restrict__ lf, Add add) {
+__device__ __forceinline__ void cell_route(RegQueue* q, int64_t quick, double p, double u, int64_t N, uint32_t dst,
+                                           int lane, const DetTablesSmall& tb, const double* __restrict__ lf, Add add) {
   if (quick > 0) add(dst, (T)quick);
-  queue_push(q[0], qn[0], quick == -1, p, u, N, dst, lane);
-  if (qn[0] >= 64) queue_run<T, 0>(q[0], qn[0], false, lane, tb, lf, add);
-  queue_push(q[1], qn[1], quick == -2, p, u, N, dst, lane);
-  if (qn[1] >= 64) queue_run<T, 1>(q[1], qn[1], false, lane, tb, lf, add);
+  rq_push(q[0], quick == -1, p, u, dst, lane);
+  if (q[0].n >= 64) rq_run<T, 0>(q[0], 64, N, lane, tb, lf, add);
+  rq_push(q[1], quick == -2, p, u, dst, lane);
+  if (q[1].n >= 64) rq_run<T, 1>(q[1], 64, N, lane, tb, lf, add);
 }
 
 template <typename T, typename Add>
-__device__ __forceinline__ void queues_flush(SampleQueue* q, int* qn, int lane, const DetTables& tb,
+__device__ __forceinline__ void queues_flush(RegQueue* q, int64_t N, int lane, const DetTablesSmall& tb,
                                              const double* __restrict__ lf, Add add) {
-  queue_run<T, 0>(q[0], qn[0], true, lane, tb, lf, add);
-  queue_run<T, 1>(q[1], qn[1], true, lane, tb, lf, add);
+  if (q[0].n > 0) rq_run<T, 0>(q[0], q[0].n, N, lane, tb, lf, add);
+  if (q[1].n > 0) rq_run<T, 1>(q[1], q[1].n, N, lane, tb, lf, add);
 }
 
 // One wave rasterises the cells [b0, b1) x [k0, k1) of a row; `dst(b, k)` names a cell and
@@ -190,9 +213,9 @@ __device__ __forceinline__ void queues_flush(SampleQueue* q, int* qn, int lane, 
 template <typename T, bool FLUCT, typename Dst, typename Add>
 __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int k0, int k1, int nt, uint32_t did,
                                             uint32_t ev, uint32_t plane, uint32_t key0, uint32_t key1,
-                                            double* __restrict__ ea, double* __restrict__ eb, SampleQueue* q,
-                                            int* qn, const DetTables& tb, const double* __restrict__ lf, int lane,
-                                            Dst dst, Add add) {
+                                            double* __restrict__ ea, double* __restrict__ eb,
+                                            const DetTablesSmall& tb, const double* __restrict__ lf, int lane, Dst dst,
+                                            Add add) {
   const int nbr = b1 - b0, nkr = k1 - k0;
   edge_fill<FLUCT>(ea, b0, b1, w.u, w.su, w.ulo, w.uhi, lane);
   edge_fill<FLUCT>(eb, k0, k1, w.t, w.st, w.tlo, w.thi, lane);
@@ -204,8 +227,11 @@ __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int
       add(dst(b0 + bi, k0 + ki), (T)(w.q * (edge_weight(ea, bi) * edge_weight(eb, ki))));
     }
   } else {
-    const int64_t N = (int64_t)floor(w.q + 0.5);
+    // the row's electron count, wave-uniform
+    const int64_t N = (int64_t)__builtin_amdgcn_readfirstlane((int)floor(w.q + 0.5));
     if (N > 0) {
+      RegQueue q[2];
+      q[0].n = q[1].n = 0;
       const int j0 = k0 >> 1, np = ((k1 - 1) >> 1) - j0 + 1;
       const uint32_t half_nt = (uint32_t)((nt + 1) >> 1);
       const float rd = 1.0f / (float)np;
@@ -234,9 +260,10 @@ __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int
             quick_o = binom_quick(N, po, uo);
           }
         }
-        cell_route<T>(q, qn, quick_e, pe, ue, N, de, lane, tb, lf, add);
-        cell_route<T>(q, qn, quick_o, po, uo, N, dodd, lane, tb, lf, add);
+        cell_route<T>(q, quick_e, pe, ue, N, de, lane, tb, lf, add);
+        cell_route<T>(q, quick_o, po, uo, N, dodd, lane, tb, lf, add);
       }
+      queues_flush<T>(q, N, lane, tb, lf, add);
     }
   }
   wave_sync();
@@ -415,7 +442,7 @@ __global__ void k_zero_split(RasterGeom g, const int32_t* __restrict__ counts, i
 
 // 4. persistent tile kernel -------------------------------------------------
 template <typename T, bool FLUCT, int TH, int TW>
-__global__ void __launch_bounds__(256, 3) k_tile(DepoView<T> d, RasterGeom g, double nsigma, uint64_t seed,
+__global__ void __launch_bounds__(256, 4) k_tile(DepoView<T> d, RasterGeom g, double nsigma, uint64_t seed,
                                               T* __restrict__ grid, const int32_t* __restrict__ list,
                                               const int32_t* __restrict__ offs, const int32_t* __restrict__ items,
                                               const int32_t* __restrict__ item_off, int32_t* __restrict__ ctrl,
@@ -424,14 +451,12 @@ __global__ void __launch_bounds__(256, 3) k_tile(DepoView<T> d, RasterGeom g, do
   __shared__ T tile[TH * TW];
   __shared__ double s_ea[NWAVE][TH + 1];
   __shared__ double s_eb[NWAVE][TW + 1];
-  __shared__ SampleQueue s_q[FLUCT ? NWAVE : 1][FLUCT ? 2 : 1];
-  __shared__ DetTables s_tb;
+  __shared__ DetTablesSmall s_tb;
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (FLUCT) {
-    const double* src = reinterpret_cast<const double*>(tables);
-    double* dst = reinterpret_cast<double*>(&s_tb);
-    for (int x = threadIdx.x; x < (int)(sizeof(DetTables) / sizeof(double)); x += blockDim.x) dst[x] = src[x];
+    for (int x = threadIdx.x; x < 129; x += blockDim.x) s_tb.inv[x] = tables->inv[x];
+    for (int x = threadIdx.x; x < 19; x += blockDim.x) s_tb.fact[x] = tables->fact[x];
   }
   const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
   for (;;) {
@@ -454,8 +479,6 @@ __global__ void __launch_bounds__(256, 3) k_tile(DepoView<T> d, RasterGeom g, do
     __syncthreads();
     const int r0 = offs[t] + chunk * kRowsPerItem;
     const int r1 = min(offs[t] + (chunk + 1) * kRowsPerItem, offs[t + 1]);
-    int qn[2] = {0, 0};
-    SampleQueue* q = s_q[FLUCT ? wv : 0];
     auto dst = [&](int b, int k) { return (uint32_t)((b - tb0) * TW + (k - tk0)); };
     auto add = [&](uint32_t o, T v) { atomicAdd(&tile[o], v); };
     for (int r = r0 + wv; r < r1; r += NWAVE) {
@@ -467,9 +490,8 @@ __global__ void __launch_bounds__(256, 3) k_tile(DepoView<T> d, RasterGeom g, do
       if (!w.ok || bb0 >= bb1 || kk0 >= kk1) continue;
       const uint32_t did = d.depo_id ? (uint32_t)d.depo_id[j] : (uint32_t)j;
       patch_cells<T, FLUCT>(w, bb0, bb1, kk0, kk1, pl.nt, did, (uint32_t)w.key_event, (uint32_t)pi, key0, key1, s_ea[wv],
-                            s_eb[wv], q, qn, s_tb, lf, lane, dst, add);
+                            s_eb[wv], s_tb, lf, lane, dst, add);
     }
-    if (FLUCT) queues_flush<T>(q, qn, lane, s_tb, lf, add);
     __syncthreads();
     T* gp = grid + (int64_t)ev * g.grid_ev_stride + pl.grid_off;
     for (int x = threadIdx.x; x < th * TW; x += blockDim.x) {
@@ -495,13 +517,11 @@ __global__ void __launch_bounds__(256, 3) k_big(DepoView<T> d, RasterGeom g, dou
   constexpr int NWAVE = 4, CB = 64, CK = 64;
   __shared__ double s_ea[NWAVE][CB + 1];
   __shared__ double s_eb[NWAVE][CK + 1];
-  __shared__ SampleQueue s_q[FLUCT ? NWAVE : 1][FLUCT ? 2 : 1];
-  __shared__ DetTables s_tb;
+  __shared__ DetTablesSmall s_tb;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (FLUCT) {
-    const double* src = reinterpret_cast<const double*>(tables);
-    double* dst = reinterpret_cast<double*>(&s_tb);
-    for (int x = threadIdx.x; x < (int)(sizeof(DetTables) / sizeof(double)); x += blockDim.x) dst[x] = src[x];
+    for (int x = threadIdx.x; x < 129; x += blockDim.x) s_tb.inv[x] = tables->inv[x];
+    for (int x = threadIdx.x; x < 19; x += blockDim.x) s_tb.fact[x] = tables->fact[x];
     __syncthreads();
   }
   const int nbig = ctrl[kCtrlNBig];
@@ -515,8 +535,6 @@ __global__ void __launch_bounds__(256, 3) k_big(DepoView<T> d, RasterGeom g, dou
     const uint32_t did = d.depo_id ? (uint32_t)d.depo_id[j] : (uint32_t)j;
     const int kstart = w.k0 & ~1;  // chunks start on even ticks: a Philox pair never straddles two
     const int ncb = (w.b1 - w.b0 + CB - 1) / CB, nck = (w.k1 - kstart + CK - 1) / CK;
-    int qn[2] = {0, 0};
-    SampleQueue* q = s_q[FLUCT ? wv : 0];
     const int nt = pl.nt;
     auto dst = [&](int b, int k) { return (uint32_t)((int64_t)b * nt + k); };
     auto add = [&](uint32_t o, T v) { atomicAdd(gp + o, v); };
@@ -525,9 +543,8 @@ __global__ void __launch_bounds__(256, 3) k_big(DepoView<T> d, RasterGeom g, dou
       const int b0 = w.b0 + cb * CB, b1 = min(b0 + CB, w.b1);
       const int k0 = max(kstart + ck * CK, w.k0), k1 = min(kstart + (ck + 1) * CK, w.k1);
       patch_cells<T, FLUCT>(w, b0, b1, k0, k1, pl.nt, did, (uint32_t)w.key_event, (uint32_t)w.plane, key0, key1,
-                            s_ea[wv], s_eb[wv], q, qn, s_tb, lf, lane, dst, add);
+                            s_ea[wv], s_eb[wv], s_tb, lf, lane, dst, add);
     }
-    if (FLUCT) queues_flush<T>(q, qn, lane, s_tb, lf, add);
   }
 }
 
@@ -580,7 +597,7 @@ hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigm
   hipLaunchKernelGGL((k_zero_split<T, TH, TW>), dim3(1024), dim3(256), 0, st, g, ws.counts, nt, grid);
   WCT_CHECK_LAUNCH();
   if (prof) prof->end(st);
-  const unsigned pblocks = (unsigned)(n_cu * 3);
+  const unsigned pblocks = (unsigned)(n_cu * 4);  // 4 resident blocks per CU (40 KB of LDS each)
   if (prof) prof->begin(fluctuate ? "raster_tile_fluct" : "raster_tile_mean", st);
   if (fluctuate)
     hipLaunchKernelGGL((k_tile<T, true, TH, TW>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.list,
