@@ -192,7 +192,8 @@ int wct_profile_get(wct_plan* plan, int32_t idx, char* name, size_t name_len, do
  * the runtime plan when none does; every choice computes the same transform (results
  * differ by floating-point rounding only).
  * wct_fft_variant_info(idx, out[12]) fills out = {kind, is_double, threads per block,
- * length, number of passes, radices[0..6] (0-padded)} (HOST buffer).
+ * length, number of passes, radices[0..6] (0-padded)} (HOST buffer); kind 2 is a wire
+ * transform that takes half of a chunk's tick frequencies per block (it serves kind 1).
  * wct_plan_get_fft reports a plane's current choice (-1 = runtime plan);
  * wct_plan_set_fft selects one: -1 or a variant of that kind, dtype and length, else
  * WCT_E_INVALID.  set_fft allocates the new twiddle tables and synchronises the device;

@@ -362,12 +362,16 @@ int upload_table(wct_plan* P, const std::vector<cx<double>>& h, void** out) {
   return WCT_OK;
 }
 
+// Whether a compiled variant of kind `vkind` can run a plane's transforms of `kind`
+// (0 ticks, 1 wires): wire transforms take whole-chunk (1) or half-chunk (2) variants.
+bool kind_fits(int vkind, int kind) { return kind == 0 ? vkind == 0 : (vkind == 1 || vkind == 2); }
+
 // First compiled variant of a kind, precision and length, or -1.
 int find_variant(int kind, bool dbl, int n) {
   int cnt = 0;
   const FftVariantDesc* v = fft_variants(&cnt);
   for (int i = 0; i < cnt; ++i)
-    if (v[i].kind == kind && v[i].dbl == (int)dbl && v[i].n == n) return i;
+    if (kind_fits(v[i].kind, kind) && v[i].dbl == (int)dbl && v[i].n == n) return i;
   return -1;
 }
 
@@ -393,14 +397,14 @@ int set_fft(wct_plan* P, int p, int kind, int v) {
   if (v >= 0) {
     int cnt = 0;
     const FftVariantDesc* vd = fft_variants(&cnt);
-    if (v >= cnt || vd[v].kind != kind || vd[v].dbl != (int)(sizeof(T) == 8) || vd[v].n != n)
+    if (v >= cnt || !kind_fits(vd[v].kind, kind) || vd[v].dbl != (int)(sizeof(T) == 8) || vd[v].n != n)
       return fail(WCT_E_INVALID, "transform variant %d does not apply to plane %d kind %d (length %d)", v, p, kind,
                   n);
     if (!build_fft_variant(vd[v], v, fp, tw)) return fail(WCT_E_INVALID, "transform variant %d: bad plan", v);
     std::vector<int> rad(vd[v].radix, vd[v].radix + vd[v].npass);
     std::reverse(rad.begin(), rad.end());
     FftPlan fr;
-    if (kind == 1 && !build_fft_radices(n, rad, fr, twr))
+    if (kind != 0 && !build_fft_radices(n, rad, fr, twr))
       return fail(WCT_E_INVALID, "transform variant %d: bad reversed plan", v);
   } else if (!build_fft(n, 0, fp, tw)) {
     return fail(WCT_E_UNSUPPORTED, "plane %d: length %d not 2,3,5-smooth", p, n);
@@ -501,7 +505,7 @@ std::string variant_text(int v) {
   if (v < 0) return "runtime";
   int cnt = 0;
   const FftVariantDesc* d = fft_variants(&cnt);
-  std::string s = std::to_string(d[v].threads);
+  std::string s = (d[v].kind == 2 ? "half " : "") + std::to_string(d[v].threads);
   for (int k = 0; k < d[v].npass; ++k) s += " " + std::to_string(d[v].radix[k]);
   return s;
 }
@@ -555,7 +559,7 @@ int run_tune(wct_plan* P, int n_events, const char* cache_path, void* ws, hipStr
       const int n = kind == 0 ? P->geom[p].M : P->geom[p].lw;
       std::vector<int> cand;
       for (int v = 0; v < cnt; ++v)
-        if (vd[v].kind == kind && vd[v].dbl == (int)(sizeof(T) == 8) && vd[v].n == n) cand.push_back(v);
+        if (kind_fits(vd[v].kind, kind) && vd[v].dbl == (int)(sizeof(T) == 8) && vd[v].n == n) cand.push_back(v);
       cand.push_back(-1);
       const std::string key = tune_key(P, p, kind);
       auto it = cache.find(key);

@@ -112,14 +112,22 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_colpass_ct(const 
                                                             const cx<T>* __restrict__ tw,
                                                             const cx<T>* __restrict__ tw_rev) {
   using FI = typename F::Reverse;
-  constexpr int NE = F::N * C, R0 = F::R0, RL = F::RL;
+  constexpr int CI = F::CI, NSUB = C / CI;
+  constexpr int NE = F::N * C, R0 = F::R0, RL = F::RL;  // NE: one phase of R~ (whole chunk)
   static_assert(FI::R0 == RL && FI::IN == F::OUT, "the reversed plan must start where the forward one ends");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  const int nin = nw * C;
-  int ch, ev;
-  colpass_block(n_events, ch, ev);
-  const cx<T>* src = shat + ev * shat_ev_stride + (int64_t)ch * nphase * nin;
+  const int nin = nw * CI;  // elements of this block's sequences inside the grid
+  int ch, ev, h;
+  colpass_block_sub(n_events, NSUB, ch, ev, h);
+  // element tid + K of the block (wire (tid + K) / CI, sequence (tid + K) % CI) in the
+  // chunk layout [wire][C]: with NT and every K multiples of CI this is a per-thread base
+  // plus a compile-time offset
+  static_assert(F::kThreads % CI == 0 && F::NB0 % CI == 0 && F::NBL % CI == 0, "layout offsets");
+  const int tid = (int)threadIdx.x;
+  const int abase = (tid / CI) * C + h * CI + tid % CI;
+  auto at = [&](int K) { return abase + (K / CI) * C; };
+  const cx<T>* src = shat + ev * shat_ev_stride + (int64_t)ch * nphase * nw * C;
   const cx<T>* rt = rtil + (int64_t)ch * nphase * NE;
   cx<T> in[F::IN], out[F::OUT], acc[F::OUT];
 #pragma unroll
@@ -130,20 +138,21 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_colpass_ct(const 
       if (!F::in_ok(q)) continue;
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
-        const int e = F::in_elem(q, r);
-        in[q * R0 + r] = e < nin ? s[e] : mk(T(0), T(0));
+        const int K = F::in_off(q, r);
+        in[q * R0 + r] = tid + K < nin ? s[at(K)] : mk(T(0), T(0));
       }
     }
   };
   for (int i = 0; i < nphase; ++i) {
-    load(src + (int64_t)i * nin);
+    load(src + (int64_t)i * nw * C);
     F::template rr<false>(buf, tw, in, out, []() {});
     const cx<T>* r = rt + (int64_t)i * NE;
 #pragma unroll
     for (int q = 0; q < F::MBL; ++q) {
       if (!F::out_ok(q)) continue;
 #pragma unroll
-      for (int rr = 0; rr < RL; ++rr) acc[q * RL + rr] = acc[q * RL + rr] + cmul(out[q * RL + rr], r[F::out_elem(q, rr)]);
+      for (int rr = 0; rr < RL; ++rr)
+        acc[q * RL + rr] = acc[q * RL + rr] + cmul(out[q * RL + rr], r[at(F::out_off(q, rr))]);
     }
     // keep the next phase's loads behind this product (register budget)
     __builtin_amdgcn_sched_barrier(0);
@@ -158,7 +167,7 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_colpass_ct(const 
 #pragma unroll
     for (int r = 0; r < FI::RL; ++r) {
       const int e = FI::out_elem(q, r);
-      if (e < nin) dst[(int64_t)(e / C) * fpad + ch * C + (e % C)] = res[q * FI::RL + r];
+      if (e < nin) dst[(int64_t)(e / CI) * fpad + ch * C + h * CI + (e % CI)] = res[q * FI::RL + r];  // [w][fpad]
     }
   }
 }
@@ -176,45 +185,50 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_colpass_adj_ct(co
                                                                 const cx<T>* __restrict__ tw,
                                                                 const cx<T>* __restrict__ tw_rev) {
   using FI = typename F::Reverse;
+  constexpr int CI = F::CI, NSUB = C / CI;
   constexpr int NE = F::N * C, R0 = F::R0, RL = F::RL;
   static_assert(FI::R0 == RL && FI::IN == F::OUT, "the reversed plan must start where the forward one ends");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  const int nin = nw * C;
-  int ch, ev;
-  colpass_block(n_events, ch, ev);
-  const cx<T>* s = ghat + ev * ghat_ev_stride + (int64_t)ch * nin;
+  const int nin = nw * CI;
+  int ch, ev, h;
+  colpass_block_sub(n_events, NSUB, ch, ev, h);
+  static_assert(F::kThreads % CI == 0 && F::NB0 % CI == 0 && F::NBL % CI == 0, "layout offsets");
+  const int tid = (int)threadIdx.x;
+  const int abase = (tid / CI) * C + h * CI + tid % CI;
+  auto at = [&](int K) { return abase + (K / CI) * C; };
+  const cx<T>* s = ghat + ev * ghat_ev_stride + (int64_t)ch * nw * C;
   cx<T> in[F::IN], g[F::OUT];
 #pragma unroll
   for (int q = 0; q < F::MB0; ++q) {
     if (!F::in_ok(q)) continue;
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
-      const int e = F::in_elem(q, r);
-      in[q * R0 + r] = e < nin ? s[e] : mk(T(0), T(0));
+      const int K = F::in_off(q, r);
+      in[q * R0 + r] = tid + K < nin ? s[at(K)] : mk(T(0), T(0));
     }
   }
   F::template rr<false>(buf, tw, in, g, []() {});
   const cx<T>* rt = rtil + (int64_t)ch * nphase * NE;
-  cx<T>* dst = hhat + ev * hhat_ev_stride + (int64_t)ch * nphase * nin;
+  cx<T>* dst = hhat + ev * hhat_ev_stride + (int64_t)ch * nphase * nw * C;
   for (int i = 0; i < nphase; ++i) {
     const cx<T>* r = rt + (int64_t)i * NE;
-    cx<T> h[FI::IN], res[FI::OUT];
+    cx<T> hv[FI::IN], res[FI::OUT];
 #pragma unroll
     for (int q = 0; q < F::MBL; ++q) {
       if (!F::out_ok(q)) continue;
 #pragma unroll
-      for (int rr = 0; rr < RL; ++rr) h[q * RL + rr] = cmulc(g[q * RL + rr], r[F::out_elem(q, rr)]);
+      for (int rr = 0; rr < RL; ++rr) hv[q * RL + rr] = cmulc(g[q * RL + rr], r[at(F::out_off(q, rr))]);
     }
-    FI::template rr<true>(buf, tw_rev, h, res, []() {});
-    cx<T>* d = dst + (int64_t)i * nin;
+    FI::template rr<true>(buf, tw_rev, hv, res, []() {});
+    cx<T>* d = dst + (int64_t)i * nw * C;
 #pragma unroll
     for (int q = 0; q < FI::MBL; ++q) {
       if (!FI::out_ok(q)) continue;
 #pragma unroll
       for (int r2 = 0; r2 < FI::RL; ++r2) {
-        const int e = FI::out_elem(q, r2);
-        if (e < nin) d[e] = res[q * FI::RL + r2];
+        const int K = FI::out_off(q, r2);
+        if (tid + K < nin) d[at(K)] = res[q * FI::RL + r2];
       }
     }
   }
@@ -287,13 +301,13 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_c2r_ct(const
 // Calls fn(policy) for compiled variant `v` of kind KIND and type T.
 template <typename T, int KIND, typename Fn>
 static hipError_t with_variant(int v, Fn&& fn) {
-  constexpr int CI = KIND == 0 ? 1 : kChunk;
+  constexpr int CI = KIND == 0 ? 1 : (KIND == 1 ? kChunk : kChunk / 2);
   bool done = false;
   int id = 0;
-#define WCT_VARIANT_CASE(K, TT, NT, ...)                       \
+#define WCT_VARIANT_CASE(K, TT, NT, MW, ...)                   \
   if constexpr (K == KIND && std::is_same<T, TT>::value) {     \
     if (id == v) {                                             \
-      fn(CtFft<T, CI, NT, __VA_ARGS__>{});                     \
+      fn(CtFft<T, CI, NT, MW, __VA_ARGS__>{});                 \
       done = true;                                             \
     }                                                          \
   }                                                            \
@@ -303,11 +317,20 @@ static hipError_t with_variant(int v, Fn&& fn) {
   return done ? hipSuccess : hipErrorInvalidValue;
 }
 
+// Wire-transform variants: kind 1 (whole chunks) and kind 2 (half chunks).
+template <typename T, typename Fn>
+static hipError_t with_wire_variant(int v, Fn&& fn) {
+  int cnt = 0;
+  const FftVariantDesc* d = fft_variants(&cnt);
+  if (v < 0 || v >= cnt) return hipErrorInvalidValue;
+  return d[v].kind == 2 ? with_variant<T, 2>(v, fn) : with_variant<T, 1>(v, fn);
+}
+
 template <typename T, int KIND, typename Fn>
 static void for_all_variants(Fn&& fn) {
-  constexpr int CI = KIND == 0 ? 1 : kChunk;
-#define WCT_VARIANT_ALL(K, TT, NT, ...) \
-  if constexpr (K == KIND && std::is_same<T, TT>::value) fn(CtFft<T, CI, NT, __VA_ARGS__>{});
+  constexpr int CI = KIND == 0 ? 1 : (KIND == 1 ? kChunk : kChunk / 2);
+#define WCT_VARIANT_ALL(K, TT, NT, MW, ...) \
+  if constexpr (K == KIND && std::is_same<T, TT>::value) fn(CtFft<T, CI, NT, MW, __VA_ARGS__>{});
   WCT_FFT_VARIANTS(WCT_VARIANT_ALL)
 #undef WCT_VARIANT_ALL
 }
@@ -331,10 +354,11 @@ template <typename T>
 hipError_t launch_colpass_ct(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtil, cx<T>* mhat,
                              int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
                              const FftPlan& plan, const cx<T>* tw, const cx<T>* tw_rev, hipStream_t st) {
-  const size_t lds = sizeof(cx<T>) * plan.n * kChunk;
-  const hipError_t e = with_variant<T, 1>(plan.variant, [&](auto f) {
+  const hipError_t e = with_wire_variant<T>(plan.variant, [&](auto f) {
     using F = decltype(f);
-    hipLaunchKernelGGL((k_colpass_ct<T, kChunk, F>), dim3(nchunk * n_events), dim3(F::kThreads), lds, st, shat,
+    const size_t lds = sizeof(cx<T>) * plan.n * F::CI;
+    hipLaunchKernelGGL((k_colpass_ct<T, kChunk, F>), dim3(nchunk * n_events * (kChunk / F::CI)), dim3(F::kThreads),
+                       lds, st, shat,
                        shat_ev_stride, rtil, mhat, mhat_ev_stride, nw, nphase, nchunk, n_events, tw, tw_rev);
   });
   return e != hipSuccess ? e : hipGetLastError();
@@ -344,10 +368,11 @@ template <typename T>
 hipError_t launch_colpass_adj_ct(const cx<T>* ghat, int64_t ghat_ev_stride, const cx<T>* rtil, cx<T>* hhat,
                                  int64_t hhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
                                  const FftPlan& plan, const cx<T>* tw, const cx<T>* tw_rev, hipStream_t st) {
-  const size_t lds = sizeof(cx<T>) * plan.n * kChunk;
-  const hipError_t e = with_variant<T, 1>(plan.variant, [&](auto f) {
+  const hipError_t e = with_wire_variant<T>(plan.variant, [&](auto f) {
     using F = decltype(f);
-    hipLaunchKernelGGL((k_colpass_adj_ct<T, kChunk, F>), dim3(nchunk * n_events), dim3(F::kThreads), lds, st,
+    const size_t lds = sizeof(cx<T>) * plan.n * F::CI;
+    hipLaunchKernelGGL((k_colpass_adj_ct<T, kChunk, F>), dim3(nchunk * n_events * (kChunk / F::CI)),
+                       dim3(F::kThreads), lds, st,
                        ghat, ghat_ev_stride, rtil, hhat, hhat_ev_stride, nw, nphase, nchunk, n_events, tw, tw_rev);
   });
   return e != hipSuccess ? e : hipGetLastError();
@@ -383,13 +408,15 @@ static void raise_lds_limits_ct() {
     (void)hipFuncSetAttribute((const void*)k_rows_c2r_ct<T, kChunk, false, F>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   });
-  for_all_variants<T, 1>([&](auto f) {
+  auto wire = [&](auto f) {
     using F = decltype(f);
     (void)hipFuncSetAttribute((const void*)k_colpass_ct<T, kChunk, F>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               lim);
     (void)hipFuncSetAttribute((const void*)k_colpass_adj_ct<T, kChunk, F>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  });
+  };
+  for_all_variants<T, 1>(wire);
+  for_all_variants<T, 2>(wire);
 }
 
 void conv_ct_init_kernels() {

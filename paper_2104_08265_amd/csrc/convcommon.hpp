@@ -26,6 +26,15 @@ __device__ __forceinline__ void colpass_block(int n_events, int& ch, int& ev) {
   ch = L / n_events;
   ev = L - ch * n_events;
 }
+// The same with NSUB blocks per (chunk, event), each taking one part of the chunk's
+// frequencies (the parts of a chunk vary fastest).
+__device__ __forceinline__ void colpass_block_sub(int n_events, int nsub, int& ch, int& ev, int& h) {
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int rest = L / nsub;
+  h = L - rest * nsub;
+  ch = rest / n_events;
+  ev = rest - ch * n_events;
+}
 
 // 16-byte vector of the real type (4 floats or 2 doubles) for row loads: a clang vector,
 // so register arrays of it stay in registers.

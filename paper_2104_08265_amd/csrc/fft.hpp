@@ -512,7 +512,8 @@ constexpr int last_of() {
 
 // Transform policies the kernels are written against.
 //  RtFft: runtime plan (any 2,3,5-smooth length), E values per thread, any block size.
-//  CtFft: compile-time plan with radices Rs..., exactly NT threads per block; besides the
+//  CtFft: compile-time plan with radices Rs..., exactly NT threads per block, registers
+//         budgeted for MINW waves per SIMD; besides the
 //         LDS-to-LDS run() it offers the register-input chains rr() and rl().
 template <typename T, int C, int E_>
 struct RtFft {
@@ -526,28 +527,31 @@ struct RtFft {
     fft_lds<T, INV, C, E_>(buf, p, tw);
   }
 };
-template <typename T, int C, int NT, typename L>
+template <typename T, int C, int NT, int MINW, typename L>
 struct CtFftOf;
-template <typename T, int C, int NT, int... Rs>
+template <typename T, int C, int NT, int MINW, int... Rs>
 struct CtFft {
   static constexpr int N = (1 * ... * Rs);
+  static constexpr int CI = C;  // interleaved sequences
   static constexpr int E = (N * C + NT - 1) / NT;
   static constexpr int kBound = NT;
   static constexpr int kThreads = NT;
-  // waves per SIMD the register allocation must allow: row transforms (small LDS
-  // buffers) keep two 8-wave blocks per CU resident; column transforms take what the
-  // LDS allows anyway
-  static constexpr int kMinWaves = (C == 1 && E <= 12) ? 4 : 1;
+  // waves per SIMD the register allocation must allow (chosen per variant so that the
+  // blocks the LDS admits also fit in the register file)
+  static constexpr int kMinWaves = MINW;
   static constexpr int R0 = first_of<Rs...>(), RL = last_of<Rs...>();
   static constexpr int NB0 = (N / R0) * C, NBL = (N / RL) * C;  // butterflies of the first / last pass
   static constexpr int MB0 = (NB0 + NT - 1) / NT, MBL = (NBL + NT - 1) / NT;
   static constexpr int IN = MB0 * R0, OUT = MBL * RL;  // register values per thread
   // same radices in reverse order: its first pass reads what this one's last pass leaves
-  using Reverse = typename CtFftOf<T, C, NT, typename RevList<IntList<Rs...>>::type>::type;
+  using Reverse = typename CtFftOf<T, C, NT, MINW, typename RevList<IntList<Rs...>>::type>::type;
   __device__ __forceinline__ constexpr int n() const { return N; }
   __device__ __forceinline__ constexpr int nthr() const { return NT; }
   // element held in register slot (q, r): first-pass and last-pass arrangement
   __device__ __forceinline__ static int in_elem(int q, int r) { return (int)threadIdx.x + q * NT + r * NB0; }
+  // the same minus the thread index: a compile-time constant after unrolling
+  __host__ __device__ __forceinline__ static constexpr int in_off(int q, int r) { return q * NT + r * NB0; }
+  __host__ __device__ __forceinline__ static constexpr int out_off(int q, int r) { return q * NT + r * NBL; }
   __device__ __forceinline__ static bool in_ok(int q) { return NB0 % NT == 0 || (int)threadIdx.x + q * NT < NB0; }
   __device__ __forceinline__ static int out_elem(int q, int r) { return (int)threadIdx.x + q * NT + r * NBL; }
   __device__ __forceinline__ static bool out_ok(int q) { return NBL % NT == 0 || (int)threadIdx.x + q * NT < NBL; }
@@ -565,9 +569,9 @@ struct CtFft {
     ct_chain<T, INV, C, NT, N, false, Hook, Rs...>(buf, tw, in, nullptr, hook);
   }
 };
-template <typename T, int C, int NT, int... Rs>
-struct CtFftOf<T, C, NT, IntList<Rs...>> {
-  using type = CtFft<T, C, NT, Rs...>;
+template <typename T, int C, int NT, int MINW, int... Rs>
+struct CtFftOf<T, C, NT, MINW, IntList<Rs...>> {
+  using type = CtFft<T, C, NT, MINW, Rs...>;
 };
 
 }  // namespace wct

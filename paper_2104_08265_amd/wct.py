@@ -292,8 +292,9 @@ class Plan:
         """Variants applicable to a plane's transform of this kind, runtime plan (-1) last."""
         info = self.plane_info(plane)
         n = info["lt"] // 2 if kind == 0 else info["lw"]
+        kinds = (0,) if kind == 0 else (1, 2)  # wire transforms: whole or half chunks per block
         return [v["index"] for v in fft_variants()
-                if v["kind"] == kind and v["dtype"] == ("f64" if self.dtype == WCT_F64 else "f32")
+                if v["kind"] in kinds and v["dtype"] == ("f64" if self.dtype == WCT_F64 else "f32")
                 and v["n"] == n] + [-1]
 
     def profile(self, enable=True):

@@ -149,11 +149,11 @@ static void check_variant(double* ef, double* ei) {
 }
 
 static int run_variants() {
-#define WCT_CHECK_VARIANT(K, TT, NT, ...)                                                        \
+#define WCT_CHECK_VARIANT(K, TT, NT, MW, ...)                                                        \
   {                                                                                              \
     double ef = 0, ei = 0, ef32 = 0, ei32 = 0;                                                   \
-    check_variant<double, (K == 0 ? 1 : kChunk), NT, __VA_ARGS__>(&ef, &ei);                     \
-    check_variant<float, (K == 0 ? 1 : kChunk), NT, __VA_ARGS__>(&ef32, &ei32);                  \
+    check_variant<double, (K == 0 ? 1 : K == 1 ? kChunk : kChunk / 2), NT, __VA_ARGS__>(&ef, &ei);  \
+    check_variant<float, (K == 0 ? 1 : K == 1 ? kChunk : kChunk / 2), NT, __VA_ARGS__>(&ef32, &ei32); \
     std::printf("%d %d %d %.3e %.3e %.3e %.3e %s\n", K, (int)sizeof(TT), NT, ef, ei, ef32, ei32, #__VA_ARGS__); \
   }
   WCT_FFT_VARIANTS(WCT_CHECK_VARIANT)
