@@ -32,9 +32,11 @@ enum RasterCtrl {
   kCtrlNItems = 1,  // number of tile work items
   kCtrlNBig = 2,    // rows whose window covers more than 4 tiles
   kCtrlTotal = 3,   // total (row, tile) pairs
+  kCtrlHeadZero = 4,  // queue head of the groups of tiles the tile kernel clears
   kCtrlWords = 64
 };
 constexpr int kRowsPerItem = 256;  // rows one tile work item processes at most
+constexpr int kZeroGroup = 16;     // tiles per clearing item of the tile kernel
 constexpr int kScanPerBlock = 4096;
 
 // Raster tile shapes (rows x ticks), 32 KB of LDS each.  Tall tiles: a window of up to

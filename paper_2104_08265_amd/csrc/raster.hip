@@ -294,7 +294,8 @@ __global__ void k_count(DepoView<T> d, RasterGeom g, double nsigma, int32_t* __r
 }
 
 // 2. scan of (rows, items) per tile -------------------------------------------
-__device__ __forceinline__ int items_of(int c) { return c > kRowsPerItem ? (c + kRowsPerItem - 1) / kRowsPerItem : 1; }
+// Tiles no row touches get no work item: the tile kernel clears them in groups.
+__device__ __forceinline__ int items_of(int c) { return (c + kRowsPerItem - 1) / kRowsPerItem; }
 
 // Inclusive block scan of int2 over 1024 threads (16 waves of 64).
 __device__ int2 block_scan_incl(int2 v, int2* s_wave) {
@@ -422,48 +423,92 @@ __global__ void k_items(const int32_t* __restrict__ item_off, int64_t ntiles, in
   for (int k = item_off[t]; k < item_off[t + 1]; ++k) items[k] = (int32_t)t;
 }
 
+// Writes zeros over tile t of the grid with the block's threads: 16-byte stores when the
+// tile's rows start on 16-byte boundaries, element stores otherwise.
 template <typename T, int TH, int TW>
-__global__ void k_zero_split(RasterGeom g, const int32_t* __restrict__ counts, int64_t ntiles, T* __restrict__ grid) {
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    if (counts[t] <= kRowsPerItem) continue;
-    const int ev = (int)(t / g.ntiles_ev);
-    const int tin = (int)(t - (int64_t)ev * g.ntiles_ev);
-    const PlaneGeom& pl = g.pl[find_plane(g, tin)];
-    const int tl = tin - pl.tile_off;
-    const int tr = tl / pl.ntc, tc = tl - (tl / pl.ntc) * pl.ntc;
-    const int tb0 = tr * TH, tk0 = tc * TW;
-    T* gp = grid + (int64_t)ev * g.grid_ev_stride + pl.grid_off;
-    for (int x = threadIdx.x; x < TH * TW; x += blockDim.x) {
+__device__ __forceinline__ void zero_tile(const RasterGeom& g, int64_t t, T* __restrict__ grid) {
+  constexpr int V = 16 / (int)sizeof(T);
+  static_assert(TW % V == 0, "tile width must be a whole number of 16-byte vectors");
+  const int ev = (int)(t / g.ntiles_ev);
+  const int tin = (int)(t - (int64_t)ev * g.ntiles_ev);
+  const PlaneGeom& pl = g.pl[find_plane(g, tin)];
+  const int tl = tin - pl.tile_off;
+  const int tr = tl / pl.ntc, tc = tl - (tl / pl.ntc) * pl.ntc;
+  const int tb0 = tr * TH, tk0 = tc * TW;
+  const int th = min(TH, pl.nb - tb0), tw = min(TW, pl.nt - tk0);
+  T* gp = grid + (int64_t)ev * g.grid_ev_stride + pl.grid_off + (int64_t)tb0 * pl.nt + tk0;
+  if (tw == TW && pl.nt % V == 0 && (reinterpret_cast<uintptr_t>(gp) & 15) == 0) {
+    constexpr int VR = TW / V;  // vectors per tile row
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int x = threadIdx.x; x < th * VR; x += blockDim.x) {
+      const int r = x / VR, c = x - (x / VR) * VR;
+      *reinterpret_cast<float4*>(gp + (int64_t)r * pl.nt + c * V) = z;
+    }
+  } else {
+    for (int x = threadIdx.x; x < th * TW; x += blockDim.x) {
       const int r = x / TW, c = x - (x / TW) * TW;
-      if (tb0 + r < pl.nb && tk0 + c < pl.nt) gp[(int64_t)(tb0 + r) * pl.nt + tk0 + c] = T(0);
+      if (c < tw) gp[(int64_t)r * pl.nt + c] = T(0);
     }
   }
 }
 
+// Tiles that several work items accumulate into start from zero.
+template <typename T, int TH, int TW>
+__global__ void k_zero_split(RasterGeom g, const int32_t* __restrict__ counts, int64_t ntiles, T* __restrict__ grid) {
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
+    if (counts[t] > kRowsPerItem) zero_tile<T, TH, TW>(g, t, grid);
+}
+
 // 4. persistent tile kernel -------------------------------------------------
+// Blocks take work from two queues in step: a tile work item (rows of one tile, added
+// in LDS and written out) and a group of kZeroGroup consecutive tiles, of which those no
+// row touches are cleared.  The clearing stores (HBM-bound) then overlap the arithmetic
+// of the rows instead of costing work items of their own.
 template <typename T, bool FLUCT, int TH, int TW>
 __global__ void __launch_bounds__(256, 4) k_tile(DepoView<T> d, RasterGeom g, double nsigma, uint64_t seed,
                                               T* __restrict__ grid, const int32_t* __restrict__ list,
                                               const int32_t* __restrict__ offs, const int32_t* __restrict__ items,
-                                              const int32_t* __restrict__ item_off, int32_t* __restrict__ ctrl,
+                                              const int32_t* __restrict__ item_off, const int32_t* __restrict__ counts,
+                                              int64_t ntiles, int32_t* __restrict__ ctrl,
                                               const DetTables* __restrict__ tables, const double* __restrict__ lf) {
   constexpr int NWAVE = 4;
   __shared__ T tile[TH * TW];
   __shared__ double s_ea[NWAVE][TH + 1];
   __shared__ double s_eb[NWAVE][TW + 1];
   __shared__ DetTablesSmall s_tb;
-  __shared__ int s_item;
+  __shared__ int s_item, s_zero;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (FLUCT) {
     for (int x = threadIdx.x; x < 129; x += blockDim.x) s_tb.inv[x] = tables->inv[x];
     for (int x = threadIdx.x; x < 19; x += blockDim.x) s_tb.fact[x] = tables->fact[x];
   }
   const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
+  const int nzero = (int)((ntiles + kZeroGroup - 1) / kZeroGroup);
+  bool more_items = true, more_zero = true;  // block-uniform
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&ctrl[kCtrlHead], 1);
+    if (threadIdx.x == 0) {
+      s_item = more_items ? atomicAdd(&ctrl[kCtrlHead], 1) : INT_MAX;
+      s_zero = more_zero ? atomicAdd(&ctrl[kCtrlHeadZero], 1) : INT_MAX;
+    }
     __syncthreads();
     const int item = __builtin_amdgcn_readfirstlane(s_item);  // block-uniform: keep it scalar
-    if (item >= ctrl[kCtrlNItems]) break;
+    const int zg = __builtin_amdgcn_readfirstlane(s_zero);
+    more_items = item < ctrl[kCtrlNItems];
+    more_zero = zg < nzero;
+    if (!more_items && !more_zero) break;
+    __syncthreads();  // every thread has read s_item and s_zero
+    // the group is cleared after the item, so that its stores drain while the other
+    // blocks of the CU compute
+    auto clear_group = [&]() {
+      if (!more_zero) return;
+      const int64_t z1 = min((int64_t)(zg + 1) * kZeroGroup, ntiles);
+      for (int64_t t = (int64_t)zg * kZeroGroup; t < z1; ++t)
+        if (counts[t] == 0) zero_tile<T, TH, TW>(g, t, grid);
+    };
+    if (!more_items) {
+      clear_group();
+      continue;
+    }
     const int t = items[item];
     const int chunk = item - item_off[t];
     const bool owned = (item_off[t + 1] - item_off[t]) == 1;
@@ -505,6 +550,7 @@ __global__ void __launch_bounds__(256, 4) k_tile(DepoView<T> d, RasterGeom g, do
       }
     }
     __syncthreads();
+    clear_group();
   }
 }
 
@@ -601,10 +647,10 @@ hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigm
   if (prof) prof->begin(fluctuate ? "raster_tile_fluct" : "raster_tile_mean", st);
   if (fluctuate)
     hipLaunchKernelGGL((k_tile<T, true, TH, TW>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.list,
-                       ws.offs, ws.items, ws.item_off, ws.ctrl, tables, lfact);
+                       ws.offs, ws.items, ws.item_off, ws.counts, nt, ws.ctrl, tables, lfact);
   else
     hipLaunchKernelGGL((k_tile<T, false, TH, TW>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid,
-                       ws.list, ws.offs, ws.items, ws.item_off, ws.ctrl, tables, lfact);
+                       ws.list, ws.offs, ws.items, ws.item_off, ws.counts, nt, ws.ctrl, tables, lfact);
   WCT_CHECK_LAUNCH();
   if (prof) prof->end(st);
   if (prof) prof->begin("raster_wide_rows", st);
