@@ -104,7 +104,9 @@ typedef struct {
  * is simulated alone or inside a batch. */
 typedef struct {
   double nsigma;      /* truncation half-width of the Gaussian patch in sigmas, (0, 8] */
-  int32_t fluctuate;  /* 0: mean charge; 1: binomial electron counts (needs nsigma <= 4.2) */
+  int32_t fluctuate;  /* 0: mean charge; 1: binomial electron counts (needs nsigma <= 4.2;
+                         electron counts are 32-bit: a charge of 2^31 - 1 or more draws
+                         as 2^31 - 1 electrons) */
   int32_t n_events;   /* events in this call: 1..max_events (wct_simulate: any >= 1) */
   uint64_t seed;      /* fluctuation key (Philox4x32-10 key words: low, high 32 bits) */
   int32_t event_base; /* first event id of the window, >= 0 */

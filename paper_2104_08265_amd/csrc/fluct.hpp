@@ -220,21 +220,95 @@ __device__ __forceinline__ int64_t binomial(int64_t N, double p, double u, const
   return flip ? N - k : k;
 }
 
+// The two searches again, for a batch of lanes that share N (0 < N < 2^31), with the
+// same operations on the same values, so the same counts.  Integers enter the
+// arithmetic as doubles kept up to date by exact +-1 steps instead of conversions, and
+// in the inversion every lane still searching has taken the same number of steps, so
+// the step's table entry is one shared read, issued a step ahead.
+template <typename Tab>
+__device__ __forceinline__ int binom_inversion_shared(int N, double pp, double q, double u, const Tab& tb) {
+  double f = 1.0;
+  for (int b = 31 - __clz(N); b >= 0; --b) {
+    f = f * f;
+    if ((N >> b) & 1) f = f * q;
+  }
+  const double r = pp / q;
+  double F = f;
+  const int cap = N < kInversionCap ? N : (int)kInversionCap;
+  double nk = (double)N;  // N - k
+  int k = 0;
+  double inv1 = tb.inv[1], inv2 = tb.inv[2];  // 1 / (s + 1), 1 / (s + 2): reads run two steps ahead
+  for (int s = 0; s < cap; ++s) {  // s: steps taken by every lane still searching
+    if (!(u >= F)) break;
+    const double inv_k = inv1;
+    inv1 = inv2;
+    if (s + 3 <= kInversionCap) inv2 = tb.inv[s + 3];
+    f = (f * (r * nk)) * inv_k;
+    k = s + 1;
+    F = F + f;
+    nk = nk - 1.0;
+  }
+  return k;
+}
+
+template <typename Tab>
+__device__ __forceinline__ int binom_chopdown_shared(int N, double lfN, double pp, double q, double u, const Tab& tb,
+                                                     const double* __restrict__ lf) {
+  const double Nf = (double)N;
+  int m = (int)floor((Nf + 1.0) * pp);
+  if (m > N) m = N;
+  // the table reads go first: their latency overlaps the two logarithms
+  const double lfm = lfact_of(m, lf, tb), lfnm = lfact_of(N - m, lf, tb);
+  const double lp = det_log(pp), lq = det_log(q);
+  const double x = lfN - lfm - lfnm + (double)m * lp + (double)(N - m) * lq;
+  const double pm = det_exp(x);
+  double v = u - pm;
+  if (v < 0.0) return m;
+  int lo = m, hi = m;
+  double plo = pm, phi = pm;
+  double dlo = (double)m, dnlo = (double)(N - m + 1);  // lo, N - lo + 1
+  double dnhi = (double)(N - m), dhi1 = (double)m + 1.0;  // N - hi, hi + 1
+  for (;;) {
+    bool moved = false;
+    if (lo > 0 && plo > 0.0) {
+      plo = plo * (dlo * q) / (dnlo * pp);
+      lo -= 1;
+      dlo = dlo - 1.0;
+      dnlo = dnlo + 1.0;
+      v = v - plo;
+      moved = true;
+      if (v < 0.0) return lo;
+    }
+    if (hi < N && phi > 0.0) {
+      phi = phi * (dnhi * pp) / (dhi1 * q);
+      hi += 1;
+      dnhi = dnhi - 1.0;
+      dhi1 = dhi1 + 1.0;
+      v = v - phi;
+      moved = true;
+      if (v < 0.0) return hi;
+    }
+    if (!moved) return m;
+  }
+}
+
 // The two regimes of binomial() as separate entry points, for callers that sort cells by
-// regime first.  Both require N > 0 and 0 < p < 1; binom_regime(N, p) names the one
-// binomial() takes (0: inversion, N p' < 10; 1: chop-down), and binom_regime_draw(r, ...)
-// returns exactly what binomial() returns for the same arguments.
+// regime first.  Both require 0 < N < 2^31 and 0 < p < 1; binom_regime(N, p) names the
+// one binomial() takes (0: inversion, N p' < 10; 1: chop-down), and
+// binom_regime_draw(r, ...) returns exactly what binomial() returns for the same
+// arguments.  lfN is ln(N!) as lfact_of gives it.
 __device__ __forceinline__ int binom_regime(int64_t N, double p) {
   const double pp = p > 0.5 ? 1.0 - p : p;
   return (double)N * pp < kMuSwitch ? 0 : 1;
 }
 template <int REGIME, typename Tab>
-__device__ __forceinline__ int64_t binom_regime_draw(int64_t N, double p, double u, const Tab& tb,
-                                                     const double* __restrict__ lf) {
+__device__ __forceinline__ int binom_regime_draw(int N, double lfN, double p, double u, const Tab& tb,
+                                                 const double* __restrict__ lf) {
   const bool flip = p > 0.5;
   const double pp = flip ? 1.0 - p : p;
   const double q = 1.0 - pp;
-  const int64_t k = REGIME == 0 ? binom_inversion(N, pp, q, u, tb) : binom_chopdown(N, pp, q, u, tb, lf);
+  const int k =
+      REGIME == 0 ? binom_inversion_shared(N, pp, q, u, tb) : binom_chopdown_shared(N, lfN, pp, q, u, tb, lf);
   return flip ? N - k : k;
 }
 

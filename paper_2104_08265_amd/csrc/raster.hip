@@ -176,10 +176,10 @@ __device__ __forceinline__ void rq_push(RegQueue& q, bool need, double p, double
 
 // Samples slot 0 (lanes below `take`) with regime REGIME, then moves slot 1 down.
 template <typename T, int REGIME, typename Add>
-__device__ __forceinline__ void rq_run(RegQueue& q, int take, int64_t N, int lane, const DetTablesSmall& tb,
+__device__ __forceinline__ void rq_run(RegQueue& q, int take, int N, double lfN, int lane, const DetTablesSmall& tb,
                                        const double* __restrict__ lf, Add add) {
   if (lane < take) {
-    const int64_t k = binom_regime_draw<REGIME>(N, q.p0, q.u0, tb, lf);
+    const int k = binom_regime_draw<REGIME>(N, lfN, q.p0, q.u0, tb, lf);
     if (k) add(q.d0, (T)k);
   }
   q.p0 = q.p1;
@@ -190,20 +190,20 @@ __device__ __forceinline__ void rq_run(RegQueue& q, int take, int64_t N, int lan
 
 // A cell's outcome of the cheap tests: added at once, queued for its regime, or nothing.
 template <typename T, typename Add>
-__device__ __forceinline__ void cell_route(RegQueue* q, int64_t quick, double p, double u, int64_t N, uint32_t dst,
+__device__ __forceinline__ void cell_route(RegQueue* q, int64_t quick, double p, double u, int N, double lfN, uint32_t dst,
                                            int lane, const DetTablesSmall& tb, const double* __restrict__ lf, Add add) {
   if (quick > 0) add(dst, (T)quick);
   rq_push(q[0], quick == -1, p, u, dst, lane);
-  if (q[0].n >= 64) rq_run<T, 0>(q[0], 64, N, lane, tb, lf, add);
+  if (q[0].n >= 64) rq_run<T, 0>(q[0], 64, N, lfN, lane, tb, lf, add);
   rq_push(q[1], quick == -2, p, u, dst, lane);
-  if (q[1].n >= 64) rq_run<T, 1>(q[1], 64, N, lane, tb, lf, add);
+  if (q[1].n >= 64) rq_run<T, 1>(q[1], 64, N, lfN, lane, tb, lf, add);
 }
 
 template <typename T, typename Add>
-__device__ __forceinline__ void queues_flush(RegQueue* q, int64_t N, int lane, const DetTablesSmall& tb,
+__device__ __forceinline__ void queues_flush(RegQueue* q, int N, double lfN, int lane, const DetTablesSmall& tb,
                                              const double* __restrict__ lf, Add add) {
-  if (q[0].n > 0) rq_run<T, 0>(q[0], q[0].n, N, lane, tb, lf, add);
-  if (q[1].n > 0) rq_run<T, 1>(q[1], q[1].n, N, lane, tb, lf, add);
+  if (q[0].n > 0) rq_run<T, 0>(q[0], q[0].n, N, lfN, lane, tb, lf, add);
+  if (q[1].n > 0) rq_run<T, 1>(q[1], q[1].n, N, lfN, lane, tb, lf, add);
 }
 
 // One wave rasterises the cells [b0, b1) x [k0, k1) of a row; `dst(b, k)` names a cell and
@@ -227,9 +227,11 @@ __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int
       add(dst(b0 + bi, k0 + ki), (T)(w.q * (edge_weight(ea, bi) * edge_weight(eb, ki))));
     }
   } else {
-    // the row's electron count, wave-uniform
-    const int64_t N = (int64_t)__builtin_amdgcn_readfirstlane((int)floor(w.q + 0.5));
+    // the row's electron count, wave-uniform (counts are 32-bit: charges from 2^31 - 1
+    // electrons up draw as 2^31 - 1)
+    const int N = __builtin_amdgcn_readfirstlane((int)floor(fmin(w.q + 0.5, 2147483647.0)));
     if (N > 0) {
+      const double lfN = lfact_of(N, lf, tb);
       RegQueue q[2];
       q[0].n = q[1].n = 0;
       const int j0 = k0 >> 1, np = ((k1 - 1) >> 1) - j0 + 1;
@@ -260,10 +262,10 @@ __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int
             quick_o = binom_quick(N, po, uo);
           }
         }
-        cell_route<T>(q, quick_e, pe, ue, N, de, lane, tb, lf, add);
-        cell_route<T>(q, quick_o, po, uo, N, dodd, lane, tb, lf, add);
+        cell_route<T>(q, quick_e, pe, ue, N, lfN, de, lane, tb, lf, add);
+        cell_route<T>(q, quick_o, po, uo, N, lfN, dodd, lane, tb, lf, add);
       }
-      queues_flush<T>(q, N, lane, tb, lf, add);
+      queues_flush<T>(q, N, lfN, lane, tb, lf, add);
     }
   }
   wave_sync();
