@@ -227,11 +227,19 @@ __device__ __forceinline__ int64_t binomial(int64_t N, double p, double u, const
 // the step's table entry is one shared read, issued a step ahead.
 template <typename Tab>
 __device__ __forceinline__ int binom_inversion_shared(int N, double pp, double q, double u, const Tab& tb) {
-  double f = 1.0;
-  for (int b = 31 - __clz(N); b >= 0; --b) {
-    f = f * f;
-    if ((N >> b) & 1) f = f * q;
+  // q^N by the same square-and-multiply, walked over the set bits of N (shared, so the
+  // control is scalar): the leading bit makes 1 * 1 * q = q exactly; then each lower bit
+  // squares, and each set one multiplies by q
+  double f = q;
+  int b = 31 - __clz(N);
+  for (unsigned rest = (unsigned)N & ~(1u << b); rest != 0;) {
+    const int nb = 31 - __clz(rest);
+    for (int s = b - nb; s > 0; --s) f = f * f;
+    f = f * q;
+    b = nb;
+    rest &= ~(1u << nb);
   }
+  for (int s = b; s > 0; --s) f = f * f;
   const double r = pp / q;
   double F = f;
   const int cap = N < kInversionCap ? N : (int)kInversionCap;

@@ -85,14 +85,22 @@ __device__ __forceinline__ int find_plane(const RasterGeom& g, int tin) {
 // edge n = min(k1, hi), interior edges the integers between.  A cell's weight (the
 // Gaussian's integral over its part inside the window) is then 0.5 (e[x+1] - e[x]),
 // computed from the same doubles the oracle uses, with one erf per edge.
+// Both axes of a patch share one pass over the lanes: the impact edges [b0, b1] first,
+// then the tick edges [k0, k1] (a short tick window would leave most lanes idle in a
+// pass of its own).
 template <bool FLUCT>
-__device__ __forceinline__ void edge_fill(double* __restrict__ e, int k0, int k1, double mu, double sigma, double lo,
-                                          double hi, int lane) {
-  const int n = k1 - k0;
-  const double s2 = sigma * kSqrt2;
-  for (int x = lane; x <= n; x += 64) {
-    const double edge = x == 0 ? fmax((double)k0, lo) : (x == n ? fmin((double)k1, hi) : (double)(k0 + x));
-    e[x] = FLUCT ? det_erf((edge - mu) / s2) : erf((edge - mu) / s2);
+__device__ __forceinline__ void edge_fill2(double* __restrict__ ea, int b0, int b1, double mua, double siga,
+                                           double loa, double hia, double* __restrict__ eb, int k0, int k1,
+                                           double mub, double sigb, double lob, double hib, int lane) {
+  const int na = b1 - b0, nb = k1 - k0;
+  const double s2a = siga * kSqrt2, s2b = sigb * kSqrt2;
+  for (int x = lane; x <= na + 1 + nb; x += 64) {
+    const bool a = x <= na;
+    const int i = a ? x : x - (na + 1), n = a ? na : nb, c0 = a ? b0 : k0, c1 = a ? b1 : k1;
+    const double lo = a ? loa : lob, hi = a ? hia : hib, mu = a ? mua : mub, s2 = a ? s2a : s2b;
+    const double edge = i == 0 ? fmax((double)c0, lo) : (i == n ? fmin((double)c1, hi) : (double)(c0 + i));
+    const double v = FLUCT ? det_erf((edge - mu) / s2) : erf((edge - mu) / s2);
+    (a ? ea : eb)[i] = v;
   }
 }
 __device__ __forceinline__ double edge_weight(const double* e, int x) { return 0.5 * (e[x + 1] - e[x]); }
@@ -217,8 +225,7 @@ __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int
                                             const DetTablesSmall& tb, const double* __restrict__ lf, int lane, Dst dst,
                                             Add add) {
   const int nbr = b1 - b0, nkr = k1 - k0;
-  edge_fill<FLUCT>(ea, b0, b1, w.u, w.su, w.ulo, w.uhi, lane);
-  edge_fill<FLUCT>(eb, k0, k1, w.t, w.st, w.tlo, w.thi, lane);
+  edge_fill2<FLUCT>(ea, b0, b1, w.u, w.su, w.ulo, w.uhi, eb, k0, k1, w.t, w.st, w.tlo, w.thi, lane);
   wave_sync();
   if (!FLUCT) {
     const float rd = 1.0f / (float)nkr;
