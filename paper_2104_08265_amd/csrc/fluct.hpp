@@ -22,6 +22,9 @@
 
 namespace wct {
 
+// Host and device: the host build serves the CPU checks of the sampler.
+#define WCT_HD __host__ __device__ __forceinline__
+
 // Small tables, filled on the host with correctly rounded divisions (kept in LDS for
 // the loops that index them at run time).
 struct DetTables {
@@ -70,7 +73,7 @@ struct Philox4 {
   uint32_t w0, w1, w2, w3;
 };
 
-__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+WCT_HD Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                                  uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
@@ -91,11 +94,11 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
   return Philox4{c0, c1, c2, c3};
 }
 
-__device__ __forceinline__ double uniform53(uint32_t w0, uint32_t w1) {
+WCT_HD double uniform53(uint32_t w0, uint32_t w1) {
   return ((double)(w0 >> 6) * 134217728.0 + (double)(w1 >> 5)) * 0x1p-53;
 }
 
-__device__ __forceinline__ double det_erf(double x) {
+WCT_HD double det_erf(double x) {
   const double mx2 = -(x * x);
   double term = x, acc = x;
 #pragma unroll
@@ -106,7 +109,7 @@ __device__ __forceinline__ double det_erf(double x) {
   return kTwoOverSqrtPi * acc;
 }
 
-__device__ __forceinline__ double det_log(double x) {
+WCT_HD double det_log(double x) {
   int e;
   double m = frexp(x, &e);
   if (m < kSqrtHalf) {
@@ -121,7 +124,7 @@ __device__ __forceinline__ double det_log(double x) {
   return (s * poly) * 2.0 + (double)e * kLn2;
 }
 
-__device__ __forceinline__ double det_exp(double x) {
+WCT_HD double det_exp(double x) {
   const double n = rint(x * kLog2e);
   const double r = x - n * kLn2;
   double poly = kDet.inv_fact[16];
@@ -131,7 +134,7 @@ __device__ __forceinline__ double det_exp(double x) {
 }
 
 template <typename Tab>
-__device__ __forceinline__ double det_lfact(int64_t n, const Tab& tb) {
+WCT_HD double det_lfact(int64_t n, const Tab& tb) {
   // one det_log call site: the argument is n! (exact) for small n, else n
   const double x = (double)n;
   const double lg = det_log(n <= 18 ? tb.fact[n] : x);
@@ -142,110 +145,66 @@ __device__ __forceinline__ double det_lfact(int64_t n, const Tab& tb) {
   return (x + 0.5) * lg - x + kHalfLn2Pi + series;
 }
 
-template <typename Tab>
-__device__ __forceinline__ int64_t binom_inversion(int64_t N, double pp, double q, double u, const Tab& tb) {
-  double f = 1.0;
-  for (int b = 63 - __clzll((unsigned long long)N); b >= 0; --b) {
-    f = f * f;
-    if ((N >> b) & 1) f = f * q;
-  }
-  const double r = pp / q;
-  double F = f;
-  int64_t k = 0;
-  const int64_t cap = N < kInversionCap ? N : kInversionCap;
-  while (u >= F && k < cap) {
-    f = (f * (r * (double)(N - k))) * tb.inv[k + 1];
-    k += 1;
-    F = F + f;
-  }
-  return k;
-}
-
 // ln(n!) for n < kLfactTable is read from a table the plan fills with det_lfact itself
 // (same code, same bits); larger n are evaluated.
 constexpr int kLfactTable = 1 << 17;
 template <typename Tab>
-__device__ __forceinline__ double lfact_of(int64_t n, const double* __restrict__ lf, const Tab& tb) {
+WCT_HD double lfact_of(int64_t n, const double* __restrict__ lf, const Tab& tb) {
   return (lf && n < kLfactTable) ? lf[n] : det_lfact(n, tb);
 }
 
-template <typename Tab>
-__device__ __forceinline__ int64_t binom_chopdown(int64_t N, double pp, double q, double u, const Tab& tb,
-                                                  const double* __restrict__ lf = nullptr) {
-  const double Nf = (double)N;
-  int64_t m = (int64_t)floor((Nf + 1.0) * pp);
-  if (m > N) m = N;
-  const double x = lfact_of(N, lf, tb) - lfact_of(m, lf, tb) - lfact_of(N - m, lf, tb) + (double)m * det_log(pp) +
-                   (double)(N - m) * det_log(q);
-  const double pm = det_exp(x);
-  double v = u - pm;
-  if (v < 0.0) return m;
-  int64_t lo = m, hi = m;
-  double plo = pm, phi = pm;
-  for (;;) {
-    bool moved = false;
-    if (lo > 0 && plo > 0.0) {
-      plo = plo * ((double)lo * q) / ((double)(N - lo + 1) * pp);
-      lo -= 1;
-      v = v - plo;
-      moved = true;
-      if (v < 0.0) return lo;
-    }
-    if (hi < N && phi > 0.0) {
-      phi = phi * ((double)(N - hi) * pp) / (((double)hi + 1.0) * q);
-      hi += 1;
-      v = v - phi;
-      moved = true;
-      if (v < 0.0) return hi;
-    }
-    if (!moved) return m;
-  }
+// Count k of Binomial(N, p) from the uniform u: inversion from k = 0 when N p' < 10
+// (p' = min(p, 1 - p)), else a chop-down search that starts at the mode and alternates a
+// step below with a step above; p > 1/2 is drawn as N minus a draw with 1 - p.  The
+// cheap cases are decided first (binom_quick), the two searches are separate entry
+// points (binom_regime_draw), so that a caller can gather the cells of one regime and
+// run them together.  Lanes that run a search together share N (0 < N < 2^31):
+// integers enter the arithmetic as doubles kept up to date by exact +-1 steps, and in
+// the inversion every lane still searching has taken the same number of steps, so the
+// step's table entry is one shared read, issued two steps ahead.
+WCT_HD int binom_regime(int64_t N, double p) {
+  const double pp = p > 0.5 ? 1.0 - p : p;
+  return (double)N * pp < kMuSwitch ? 0 : 1;
 }
 
-__device__ __forceinline__ int64_t binomial(int64_t N, double p, double u, const DetTables& tb) {
-  if (N <= 0) return 0;
+// The count when the cheap tests decide it (>= 0), else -1 - (regime of the search).
+// Zero bound: the inversion returns 0 when u < F(0), the computed q^N.  The rounded q is
+// at least 1 - (p + 2^-53), so by Bernoulli's inequality the exact power of it is at
+// least 1 - N p - N 2^-53; the square-and-multiply adds at most 128 roundings (< 2e-14)
+// and mu = N p carries < 2e-15.  Hence u below (1 - mu) - (1e-12 + 2.5e-16 N) implies
+// u < F(0): the search would return 0.
+WCT_HD int64_t binom_quick(int64_t N, double p, double u) {
+  if (N <= 0 || !(p > 0.0)) return 0;
   if (p >= 1.0) return N;
-  if (!(p > 0.0)) return 0;
-  const bool flip = p > 0.5;
-  const double pp = flip ? 1.0 - p : p;
-  const double q = 1.0 - pp;
-  const double mu = (double)N * pp;
-  // Shortcut with the same result: inversion returns 0 when u < F(0), the computed q^N.
-  // The rounded q is at least 1 - (p + 2^-53), so by Bernoulli's inequality the exact
-  // power of it is at least 1 - N p - N 2^-53; the square-and-multiply adds at most 128
-  // roundings (< 2e-14) and mu = N p carries < 2e-15.  Hence u below
-  // (1 - mu) - (1e-12 + 2.5e-16 N) implies u < F(0) and the inversion would return 0.
-  if (!flip && mu < kMuSwitch && u < (1.0 - mu) - (1.0e-12 + (double)N * 2.5e-16)) return 0;
-  const int64_t k = mu < kMuSwitch ? binom_inversion(N, pp, q, u, tb) : binom_chopdown(N, pp, q, u, tb);
-  return flip ? N - k : k;
+  if (p <= 0.5) {
+    const double mu = (double)N * p;
+    if (mu < kMuSwitch && u < (1.0 - mu) - (1.0e-12 + (double)N * 2.5e-16)) return 0;
+  }
+  return -1 - binom_regime(N, p);
 }
 
-// The two searches again, for a batch of lanes that share N (0 < N < 2^31), with the
-// same operations on the same values, so the same counts.  Integers enter the
-// arithmetic as doubles kept up to date by exact +-1 steps instead of conversions, and
-// in the inversion every lane still searching has taken the same number of steps, so
-// the step's table entry is one shared read, issued a step ahead.
 template <typename Tab>
-__device__ __forceinline__ int binom_inversion_shared(int N, double pp, double q, double u, const Tab& tb) {
-  // q^N by the same square-and-multiply, walked over the set bits of N (shared, so the
-  // control is scalar): the leading bit makes 1 * 1 * q = q exactly; then each lower bit
-  // squares, and each set one multiplies by q
+WCT_HD int binom_inversion_shared(int N, double pp, double q, double u, const Tab& tb) {
+  // q^N by left-to-right square-and-multiply, walked over the set bits of N (shared, so
+  // the control is scalar): the leading bit gives 1 * 1 * q = q exactly; then each lower
+  // bit squares, and each set one multiplies by q
   double f = q;
-  int b = 31 - __clz(N);
+  int b = 31 - __builtin_clz((unsigned)N);
   for (unsigned rest = (unsigned)N & ~(1u << b); rest != 0;) {
-    const int nb = 31 - __clz(rest);
+    const int nb = 31 - __builtin_clz(rest);
     for (int s = b - nb; s > 0; --s) f = f * f;
     f = f * q;
     b = nb;
     rest &= ~(1u << nb);
   }
   for (int s = b; s > 0; --s) f = f * f;
+  // F(k) = F(k-1) + f(k), f(k) = f(k-1) * (r (N - k + 1)) / k, while u >= F and k < cap
   const double r = pp / q;
   double F = f;
   const int cap = N < kInversionCap ? N : (int)kInversionCap;
   double nk = (double)N;  // N - k
   int k = 0;
-  double inv1 = tb.inv[1], inv2 = tb.inv[2];  // 1 / (s + 1), 1 / (s + 2): reads run two steps ahead
+  double inv1 = tb.inv[1], inv2 = tb.inv[2];  // 1 / (s + 1), 1 / (s + 2)
   for (int s = 0; s < cap; ++s) {  // s: steps taken by every lane still searching
     if (!(u >= F)) break;
     const double inv_k = inv1;
@@ -260,8 +219,9 @@ __device__ __forceinline__ int binom_inversion_shared(int N, double pp, double q
 }
 
 template <typename Tab>
-__device__ __forceinline__ int binom_chopdown_shared(int N, double lfN, double pp, double q, double u, const Tab& tb,
-                                                     const double* __restrict__ lf) {
+WCT_HD int binom_chopdown_shared(int N, double lfN, double pp, double q, double u, const Tab& tb,
+                                 const double* __restrict__ lf) {
+  // mode m = floor((N + 1) p'), P(m) = exp(ln N! - ln m! - ln (N - m)! + m ln p' + (N - m) ln q)
   const double Nf = (double)N;
   int m = (int)floor((Nf + 1.0) * pp);
   if (m > N) m = N;
@@ -274,10 +234,11 @@ __device__ __forceinline__ int binom_chopdown_shared(int N, double lfN, double p
   if (v < 0.0) return m;
   int lo = m, hi = m;
   double plo = pm, phi = pm;
-  double dlo = (double)m, dnlo = (double)(N - m + 1);  // lo, N - lo + 1
+  double dlo = (double)m, dnlo = (double)(N - m + 1);     // lo, N - lo + 1
   double dnhi = (double)(N - m), dhi1 = (double)m + 1.0;  // N - hi, hi + 1
   for (;;) {
     bool moved = false;
+    // a step below while the lower side is neither at 0 nor underflowed
     if (lo > 0 && plo > 0.0) {
       plo = plo * (dlo * q) / (dnlo * pp);
       lo -= 1;
@@ -287,6 +248,7 @@ __device__ __forceinline__ int binom_chopdown_shared(int N, double lfN, double p
       moved = true;
       if (v < 0.0) return lo;
     }
+    // then a step above, same rule
     if (hi < N && phi > 0.0) {
       phi = phi * (dnhi * pp) / (dhi1 * q);
       hi += 1;
@@ -296,22 +258,15 @@ __device__ __forceinline__ int binom_chopdown_shared(int N, double lfN, double p
       moved = true;
       if (v < 0.0) return hi;
     }
+    // both sides exhausted before u was reached: the mode
     if (!moved) return m;
   }
 }
 
-// The two regimes of binomial() as separate entry points, for callers that sort cells by
-// regime first.  Both require 0 < N < 2^31 and 0 < p < 1; binom_regime(N, p) names the
-// one binomial() takes (0: inversion, N p' < 10; 1: chop-down), and
-// binom_regime_draw(r, ...) returns exactly what binomial() returns for the same
-// arguments.  lfN is ln(N!) as lfact_of gives it.
-__device__ __forceinline__ int binom_regime(int64_t N, double p) {
-  const double pp = p > 0.5 ? 1.0 - p : p;
-  return (double)N * pp < kMuSwitch ? 0 : 1;
-}
+// The search of regime REGIME (binom_regime) for 0 < N < 2^31 and 0 < p < 1; lfN is
+// ln(N!) as lfact_of gives it.
 template <int REGIME, typename Tab>
-__device__ __forceinline__ int binom_regime_draw(int N, double lfN, double p, double u, const Tab& tb,
-                                                 const double* __restrict__ lf) {
+WCT_HD int binom_regime_draw(int N, double lfN, double p, double u, const Tab& tb, const double* __restrict__ lf) {
   const bool flip = p > 0.5;
   const double pp = flip ? 1.0 - p : p;
   const double q = 1.0 - pp;

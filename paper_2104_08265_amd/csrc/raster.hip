@@ -124,18 +124,6 @@ __device__ __forceinline__ int div_small(int x, int d, float rd) {
 // end of every row's sub-patch, so a batch shares the row's electron count N (a
 // wave-uniform value: the sampler's power loop then runs under scalar control).
 
-// The cell's count when the cheap tests decide it (>= 0), else -1 - (regime of the
-// full sampler).
-__device__ __forceinline__ int64_t binom_quick(int64_t N, double p, double u) {
-  if (N <= 0 || !(p > 0.0)) return 0;
-  if (p >= 1.0) return N;
-  if (p <= 0.5) {
-    const double mu = (double)N * p;
-    if (mu < kMuSwitch && u < (1.0 - mu) - (1.0e-12 + (double)N * 2.5e-16)) return 0;
-  }
-  return -1 - binom_regime(N, p);
-}
-
 __device__ __forceinline__ int lanes_below(uint64_t mask, int lane) {
   return __popcll(mask & ((1ull << lane) - 1ull));
 }
