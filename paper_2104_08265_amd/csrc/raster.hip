@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(256, 4) k_tile(DepoView<T> d, RasterGeom g, do
   __shared__ double s_ea[NWAVE][TH + 1];
   __shared__ double s_eb[NWAVE][TW + 1];
   __shared__ DetTablesSmall s_tb;
-  __shared__ int s_item, s_zero;
+  __shared__ int s_item, s_zero, s_row;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (FLUCT) {
     for (int x = threadIdx.x; x < 129; x += blockDim.x) s_tb.inv[x] = tables->inv[x];
@@ -517,15 +517,22 @@ __global__ void __launch_bounds__(256, 4) k_tile(DepoView<T> d, RasterGeom g, do
     const int tr = tl / pl.ntc, tc = tl - (tl / pl.ntc) * pl.ntc;
     const int tb0 = tr * TH, tk0 = tc * TW;
     const int th = min(TH, pl.nb - tb0), tw = min(TW, pl.nt - tk0);
-    for (int x = threadIdx.x; x < TH * TW; x += blockDim.x) tile[x] = T(0);
-    __syncthreads();
     const int r0 = offs[t] + chunk * kRowsPerItem;
     const int r1 = min(offs[t] + (chunk + 1) * kRowsPerItem, offs[t + 1]);
+    for (int x = threadIdx.x; x < TH * TW; x += blockDim.x) tile[x] = T(0);
+    if (threadIdx.x == 0) s_row = r0;
+    __syncthreads();
     auto dst = [&](int b, int k) { return (uint32_t)((b - tb0) * TW + (k - tk0)); };
     auto add = [&](uint32_t o, T v) { atomicAdd(&tile[o], v); };
-    for (int r = r0 + wv; r < r1; r += NWAVE) {
+    // the waves claim rows one at a time, so that they finish the item together
+    auto claim = [&]() {
+      int r = 0;
+      if (lane == 0) r = atomicAdd(&s_row, 1);
+      return __builtin_amdgcn_readfirstlane(r);
+    };
+    for (int r = claim(); r < r1; r = claim()) {
       // the row is wave-uniform: a scalar index makes its parameters scalar loads and registers
-      const int64_t j = __builtin_amdgcn_readfirstlane(list[__builtin_amdgcn_readfirstlane(r)]);
+      const int64_t j = __builtin_amdgcn_readfirstlane(list[r]);
       const RowWin w = row_window(d, j, g, nsigma);
       const int bb0 = max(w.b0, tb0), bb1 = min(w.b1, tb0 + th);
       const int kk0 = max(w.k0, tk0), kk1 = min(w.k1, tk0 + tw);
