@@ -34,6 +34,7 @@ SOURCES = {
     "raster.hip": ["-ffp-contract=off"],
     "conv.hip": [],
     "conv_ct.hip": [],
+    "wiredirect.hip": [],
     "plan.hip": [],
     "grad.hip": [],
 }

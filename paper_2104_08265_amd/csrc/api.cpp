@@ -133,6 +133,8 @@ struct wct_plan {
   std::vector<PlaneGeom> geom;
   std::vector<FftPlan> fp_t, fp_w;
   std::vector<void*> tw_t, post_t, tw_w, tw_w_rev, rtil;
+  std::vector<void*> rtick;      // direct wire pass coefficients, [F padded][I][2K+1]
+  std::vector<int> wire_direct;  // forward wire pass as direct sums (the adjoint keeps fp_w)
   DetTables* d_tables = nullptr;
   double* d_lfact = nullptr;  // ln(n!), n < kLfactTable, for the chop-down sampler
   std::vector<void*> allocs;
@@ -303,11 +305,17 @@ int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, 
                 launch_rows_r2c<T>(grid + G.grid_off, P->grid_elems, shat + G.shat_off, P->shat_elems, G.nt, G.I,
                                    G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, P->n_cu, st),
                 "row transform launch");
-    PROF_LAUNCH(P, "colpass", st,
-                launch_colpass<T>(shat + G.shat_off, P->shat_elems, static_cast<const cx<T>*>(P->rtil[p]),
-                                  mhat + G.mhat_off, P->mhat_elems, G.nw, G.I, G.nchunk, n_events, P->fp_w[p], tw_w,
-                                  tw_wr, st),
-                "column pass launch");
+    if (P->wire_direct[p])
+      PROF_LAUNCH(P, "colpass", st,
+                  launch_colpass_direct<T>(shat + G.shat_off, P->shat_elems, static_cast<const cx<T>*>(P->rtick[p]),
+                                           mhat + G.mhat_off, P->mhat_elems, G.nw, G.I, G.nchunk, n_events, st),
+                  "column pass launch");
+    else
+      PROF_LAUNCH(P, "colpass", st,
+                  launch_colpass<T>(shat + G.shat_off, P->shat_elems, static_cast<const cx<T>*>(P->rtil[p]),
+                                    mhat + G.mhat_off, P->mhat_elems, G.nw, G.I, G.nchunk, n_events, P->fp_w[p], tw_w,
+                                    tw_wr, st),
+                  "column pass launch");
     PROF_LAUNCH(P, "rows_c2r", st,
                 launch_rows_c2r<T>(mhat + G.mhat_off, P->mhat_elems, wave + G.wave_off, P->wave_elems, G.nt, false,
                                    1, G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, st),
@@ -391,6 +399,15 @@ void free_table(wct_plan* P, void* d) {
 template <typename T>
 int set_fft(wct_plan* P, int p, int kind, int v) {
   const PlaneGeom& G = P->geom[p];
+  if (v == WCT_WIRE_DIRECT) {
+    if (kind != 1) return fail(WCT_E_INVALID, "the direct sum applies to the wire pass (kind 1) only");
+    if (!colpass_direct_fits(G.K))
+      return fail(WCT_E_UNSUPPORTED, "plane %d: direct wire pass needs a response of 21 wires (K = 10), K = %d", p,
+                  G.K);
+    P->wire_direct[p] = 1;
+    return WCT_OK;
+  }
+  if (v < 0) v = -1;
   const int n = kind == 0 ? G.M : G.lw;
   FftPlan fp;
   std::vector<cx<double>> tw, twr;
@@ -427,6 +444,7 @@ int set_fft(wct_plan* P, int p, int kind, int v) {
     P->fp_w[p] = fp;
     P->tw_w[p] = d;
     P->tw_w_rev[p] = dr;
+    P->wire_direct[p] = 0;
   }
   return WCT_OK;
 }
@@ -445,6 +463,7 @@ int plan_tables(wct_plan* P, const wct_plan_desc* desc) {
     P->tw_t.push_back(nullptr);
     P->tw_w.push_back(nullptr);
     P->tw_w_rev.push_back(nullptr);
+    P->wire_direct.push_back(0);
     int rc = set_fft<T>(P, p, 0, find_variant(0, sizeof(T) == 8, G.M));
     if (rc) return rc;
     rc = set_fft<T>(P, p, 1, find_variant(1, sizeof(T) == 8, G.lw));
@@ -472,13 +491,17 @@ int plan_tables(wct_plan* P, const wct_plan_desc* desc) {
     if (e == hipSuccess) e = hipMalloc(&dtlw, sizeof(cx<double>) * G.lw);
     if (e == hipSuccess) e = hipMalloc(&drt, sizeof(cx<double>) * (size_t)nk * G.I * G.F);
     void* rtil = nullptr;
+    void* rtick = nullptr;
     if (e == hipSuccess) rtil = P->dalloc(sizeof(cx<T>) * (size_t)G.nchunk * G.I * G.lw * kChunk, &e);
+    if (e == hipSuccess) rtick = P->dalloc(sizeof(cx<T>) * (size_t)G.nchunk * kChunk * G.I * nk, &e);
     if (e == hipSuccess) e = hipMemcpy(dR, R.data(), sizeof(double) * nr, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dtlt, tlt.data(), sizeof(cx<double>) * G.lt, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dtlw, tlw.data(), sizeof(cx<double>) * G.lw, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_resp_tick(dR, nk, G.I, G.TR, G.lt, G.F, dtlt, drt, nullptr);
     if (e == hipSuccess)
       e = launch_resp_wire<T>(drt, G.K, G.I, G.F, G.lw, G.lt, G.nchunk, dtlw, static_cast<cx<T>*>(rtil), nullptr);
+    if (e == hipSuccess)
+      e = launch_resp_tick_pack<T>(drt, G.K, G.I, G.F, G.nchunk * kChunk, G.lt, static_cast<cx<T>*>(rtick), nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     (void)hipFree(dR);
     (void)hipFree(dtlt);
@@ -486,6 +509,7 @@ int plan_tables(wct_plan* P, const wct_plan_desc* desc) {
     (void)hipFree(drt);
     if (e != hipSuccess) return hip_fail(e, "response spectrum");
     P->rtil.push_back(rtil);
+    P->rtick.push_back(rtick);
   }
   return WCT_OK;
 }
@@ -502,6 +526,7 @@ std::string tune_key(const wct_plan* P, int p, int kind) {
   return b;
 }
 std::string variant_text(int v) {
+  if (v == WCT_WIRE_DIRECT) return "direct";
   if (v < 0) return "runtime";
   int cnt = 0;
   const FftVariantDesc* d = fft_variants(&cnt);
@@ -561,24 +586,30 @@ int run_tune(wct_plan* P, int n_events, const char* cache_path, void* ws, hipStr
       for (int v = 0; v < cnt; ++v)
         if (kind_fits(vd[v].kind, kind) && vd[v].dbl == (int)(sizeof(T) == 8) && vd[v].n == n) cand.push_back(v);
       cand.push_back(-1);
+      if (kind == 1 && colpass_direct_fits(P->geom[p].K)) cand.push_back(WCT_WIRE_DIRECT);
       const std::string key = tune_key(P, p, kind);
       auto it = cache.find(key);
-      int best = -2;
+      constexpr int kNone = -1000;
+      int best = kNone, best_fft = kNone;  // best_fft: the transform plan the adjoint keeps
       if (it != cache.end())
         for (int v : cand)
           if (variant_text(v) == it->second) best = v;
-      if (best == -2) {
-        float best_ms = 0.f;
+      if (best == kNone) {
+        float best_ms = 0.f, best_fft_ms = 0.f;
         for (int v : cand) {
           if ((rc = set_fft<T>(P, p, kind, v))) break;
           float ms = 0.f;
           if ((rc = time_conv(&ms))) break;
-          if (best == -2 || ms < best_ms) best = v, best_ms = ms;
+          if (best == kNone || ms < best_ms) best = v, best_ms = ms;
+          if (v != WCT_WIRE_DIRECT && (best_fft == kNone || ms < best_fft_ms)) best_fft = v, best_fft_ms = ms;
         }
         if (rc) break;
         appended += key + " -> " + variant_text(best) + "\n";
       }
-      rc = set_fft<T>(P, p, kind, best);
+      // the direct sum replaces the forward wire pass only: the adjoint runs the fastest
+      // transform plan timed (or, from the cache, the plane's current one)
+      if (best == WCT_WIRE_DIRECT && best_fft != kNone) rc = set_fft<T>(P, p, kind, best_fft);
+      if (rc == WCT_OK) rc = set_fft<T>(P, p, kind, best);
     }
   }
   (void)hipEventDestroy(e0);
@@ -882,7 +913,8 @@ int wct_plan_get_fft(const wct_plan* plan, int32_t plane, int32_t kind, int32_t*
   if (!plan || !variant) return fail(WCT_E_INVALID, "plan or variant is NULL");
   if (plane < 0 || plane >= plan->n_planes || (kind != 0 && kind != 1))
     return fail(WCT_E_INVALID, "plane %d / kind %d out of range", plane, kind);
-  *variant = kind == 0 ? plan->fp_t[plane].variant : plan->fp_w[plane].variant;
+  *variant = kind == 0 ? plan->fp_t[plane].variant
+                      : (plan->wire_direct[plane] ? WCT_WIRE_DIRECT : plan->fp_w[plane].variant);
   return WCT_OK;
 }
 
@@ -894,8 +926,8 @@ int wct_plan_set_fft(wct_plan* plan, int32_t plane, int32_t kind, int32_t varian
   DeviceGuard dg(plan->device);
   const hipError_t e = hipDeviceSynchronize();  // tables may be in use by queued work
   if (e != hipSuccess) return hip_fail(e, "synchronise before replacing twiddle tables");
-  return plan->dtype == WCT_F32 ? set_fft<float>(plan, plane, kind, variant < 0 ? -1 : variant)
-                                : set_fft<double>(plan, plane, kind, variant < 0 ? -1 : variant);
+  return plan->dtype == WCT_F32 ? set_fft<float>(plan, plane, kind, variant)
+                                : set_fft<double>(plan, plane, kind, variant);
 }
 
 size_t wct_tune_workspace_bytes(const wct_plan* plan, int32_t n_events) {

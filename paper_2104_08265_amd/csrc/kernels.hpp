@@ -95,6 +95,11 @@ template <typename T>
 hipError_t launch_colpass(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtil, cx<T>* mhat,
                           int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, const FftPlan& plan,
                           const cx<T>* tw, const cx<T>* tw_rev, hipStream_t st);
+// wiredirect.hip: pass B as direct sums over the response's 2K+1 wires (K = 10 only)
+bool colpass_direct_fits(int K);
+template <typename T>
+hipError_t launch_colpass_direct(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtick, cx<T>* mhat,
+                                 int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, hipStream_t st);
 template <typename T>
 hipError_t launch_colpass_adj(const cx<T>* ghat, int64_t ghat_ev_stride, const cx<T>* rtil, cx<T>* hhat,
                               int64_t hhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
@@ -113,6 +118,9 @@ hipError_t launch_resp_tick(const double* R, int nk, int I, int TR, int lt, int 
 template <typename T>
 hipError_t launch_resp_wire(const cx<double>* rt, int K, int I, int F, int lw, int lt, int nchunk,
                             const cx<double>* tw_lw, cx<T>* rtil, hipStream_t st);
+template <typename T>
+hipError_t launch_resp_tick_pack(const cx<double>* rt, int K, int I, int F, int fpad, int lt, cx<T>* rtick,
+                                 hipStream_t st);
 
 // grad.hip
 template <typename T>

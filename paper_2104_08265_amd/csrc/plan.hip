@@ -59,6 +59,40 @@ __global__ void k_resp_wire(const cx<double>* __restrict__ rt, int K, int I, int
   rtil[idx] = mk((T)ax, (T)ay);
 }
 
+// Coefficients of the direct wire pass: R^_t[k][i](w_t) / L_t in the layout
+// [w_t (padded to the chunks)][i][k + K], zero for w_t >= F.
+template <typename T>
+__global__ void k_resp_tick_pack(const cx<double>* __restrict__ rt, int K, int I, int F, int fpad, int lt,
+                                 cx<T>* __restrict__ out) {
+  const int nk = 2 * K + 1;
+  const int64_t total = (int64_t)fpad * I * nk;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int kk = (int)(idx % nk);
+  const int64_t rest = idx / nk;
+  const int i = (int)(rest % I);
+  const int wt = (int)(rest / I);
+  cx<double> a = mk(0.0, 0.0);
+  if (wt < F) {
+    a = rt[((int64_t)kk * I + i) * F + wt];
+    const double s = 1.0 / (double)lt;
+    a = mk(a.x * s, a.y * s);
+  }
+  out[idx] = mk((T)a.x, (T)a.y);
+}
+
+template <typename T>
+hipError_t launch_resp_tick_pack(const cx<double>* rt, int K, int I, int F, int fpad, int lt, cx<T>* rtick,
+                                 hipStream_t st) {
+  const int64_t n = (int64_t)fpad * I * (2 * K + 1);
+  hipLaunchKernelGGL((k_resp_tick_pack<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rt, K, I, F, fpad, lt,
+                     rtick);
+  return hipGetLastError();
+}
+template hipError_t launch_resp_tick_pack<float>(const cx<double>*, int, int, int, int, int, cx<float>*, hipStream_t);
+template hipError_t launch_resp_tick_pack<double>(const cx<double>*, int, int, int, int, int, cx<double>*,
+                                                  hipStream_t);
+
 hipError_t launch_resp_tick(const double* R, int nk, int I, int TR, int lt, int F, const cx<double>* tw_lt,
                             cx<double>* out, hipStream_t st) {
   const int64_t n = (int64_t)nk * I * F;

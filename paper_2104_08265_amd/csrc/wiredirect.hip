@@ -1,0 +1,151 @@
+// Pass B as direct sums along wires, an alternative to the wire transforms of conv.hip /
+// conv_ct.hip for responses 2K+1 = 21 wires wide (arXiv:2104.08265 Eq. 1; Eq. 2 with the
+// tick axis transformed only).  With the response's tick spectrum R^_t[k][i](w_t) (plan
+// data, scaled by 1/L_t for the inverse tick transform of pass C),
+//
+//   M^(w, w_t) = sum_{k=-K..K} sum_{i<I} R^_t[k][i](w_t) S^(I (w + k) + i, w_t),
+//
+// rows outside the grid being zero: along wires the signal is a correlation with 2K+1
+// taps per phase, which the column transforms evaluate through a length-L_w transform
+// pair and a product with the full 2D spectrum R~; here it is summed as it stands.
+// Work per output: (2K+1) I complex products (FP32: 840 FMAs), against the transforms'
+// 10 forward and one inverse transform per (frequency, wire column) plus the read of R~
+// (10 complex per output); the direct sum reads only S^ and 21 I coefficients per
+// frequency.
+#include "convcommon.hpp"
+
+namespace wct {
+
+namespace {
+
+constexpr int kDirectK = 10;                // response half-width the kernel is compiled for
+constexpr int kDirectWL = 8;                // output wires per lane
+constexpr int kDirectWT = 64 * kDirectWL;   // output wires per block
+constexpr int kDirectSpan = kDirectWT + 2 * kDirectK;  // S^ wires staged per phase
+// LDS stride of one frequency's staged wires: one pad element every kDirectWL wires, so
+// that lanes reading wires kDirectWL apart hit distinct banks
+constexpr int kDirectPstr = kDirectSpan + kDirectSpan / kDirectWL + 1;
+
+// One block: kChunk tick frequencies (one per wave, so a wave's coefficients are
+// uniform: scalar loads) x kDirectWT consecutive wires of one (chunk, event).  Phases are
+// staged through LDS in two buffers: the next phase's global loads are in flight while
+// the current one is summed.
+template <typename T>
+__global__ void __launch_bounds__(64 * kChunk) k_colpass_direct(const cx<T>* __restrict__ shat, int64_t shat_ev_stride,
+                                                               const cx<T>* __restrict__ rtick, cx<T>* __restrict__ mhat,
+                                                               int64_t mhat_ev_stride, int nw, int nphase, int nchunk,
+                                                               int ntile, int n_events) {
+  constexpr int K = kDirectK, NK = 2 * K + 1, WL = kDirectWL, WT = kDirectWT;
+  constexpr int SPAN = kDirectSpan, PSTR = kDirectPstr, C = kChunk;
+  constexpr int CPV = 16 / (int)sizeof(cx<T>);  // complex values per 16-byte load
+  constexpr int VPW = C / CPV;                  // 16-byte loads per staged wire
+  constexpr int NE = SPAN * VPW, NPT = (NE + 64 * C - 1) / (64 * C);
+  using V = typename Vec16<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);  // [2][C][PSTR]
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = L % ntile, rest = L / ntile;
+  const int ev = rest % n_events, ch = rest / n_events;
+  const int w0 = tile * WT;
+  const int tid = (int)threadIdx.x, lane = tid & 63;
+  const int f = __builtin_amdgcn_readfirstlane(tid >> 6);  // this wave's frequency in the chunk
+  const cx<T>* src = shat + ev * shat_ev_stride + (int64_t)ch * nphase * nw * C;
+
+  V stage[NPT];
+  auto load = [&](int i) {
+    const cx<T>* s = src + (int64_t)i * nw * C;
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+      const int e = tid + u * 64 * C;
+      const int w = w0 - K + e / VPW;
+      V v = {};
+      if (e < NE && w >= 0 && w < nw) v = *reinterpret_cast<const V*>(s + (int64_t)w * C + (e % VPW) * CPV);
+      stage[u] = v;
+    }
+  };
+  auto store = [&](int b) {
+    cx<T>* d = lds + b * C * PSTR;
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+      const int e = tid + u * 64 * C;
+      if (e < NE) {
+        const int x = e / VPW, f0 = (e % VPW) * CPV;
+#pragma unroll
+        for (int q = 0; q < CPV; ++q) d[(f0 + q) * PSTR + x + x / WL] = mk(stage[u][2 * q], stage[u][2 * q + 1]);
+      }
+    }
+  };
+
+  T ax[WL], ay[WL];
+#pragma unroll
+  for (int o = 0; o < WL; ++o) ax[o] = ay[o] = T(0);
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int i = 0; i < nphase; ++i) {
+    if (i + 1 < nphase) load(i + 1);
+    const cx<T>* coef = rtick + ((int64_t)(ch * C + f) * nphase + i) * NK;  // uniform: scalar loads
+    cx<T> r[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) r[k] = coef[k];
+    // staged wire x = WL lane + j (j < WL + 2K) sits at (WL + 1) lane + j + j / WL
+    const cx<T>* s = lds + (i & 1) * C * PSTR + f * PSTR + (WL + 1) * lane;
+#pragma unroll
+    for (int j = 0; j < WL + 2 * K; ++j) {
+      const cx<T> v = s[j + j / WL];
+#pragma unroll
+      for (int o = 0; o < WL; ++o) {
+        if (j - o < 0 || j - o > 2 * K) continue;  // output wire w0 + WL lane + o, tap k = j - o - K
+        const cx<T> c = r[j - o];
+        ax[o] = fma(c.x, v.x, ax[o]);
+        ax[o] = fma(-c.y, v.y, ax[o]);
+        ay[o] = fma(c.x, v.y, ay[o]);
+        ay[o] = fma(c.y, v.x, ay[o]);
+      }
+    }
+    if (i + 1 < nphase) store((i + 1) & 1);
+    __syncthreads();
+  }
+  cx<T>* dst = mhat + ev * mhat_ev_stride;
+  const int fpad = nchunk * C;
+#pragma unroll
+  for (int o = 0; o < WL; ++o) {
+    const int w = w0 + WL * lane + o;
+    if (w < nw) dst[(int64_t)w * fpad + ch * C + f] = mk(ax[o], ay[o]);  // [w][fpad]
+  }
+}
+
+template <typename T>
+size_t direct_lds() {
+  return sizeof(cx<T>) * 2 * kChunk * kDirectPstr;
+}
+
+}  // namespace
+
+bool colpass_direct_fits(int K) { return K == kDirectK; }
+
+template <typename T>
+hipError_t launch_colpass_direct(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtick, cx<T>* mhat,
+                                 int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, hipStream_t st) {
+  static_assert(kChunk == 4, "one wave per frequency of a chunk");
+  const int ntile = (nw + kDirectWT - 1) / kDirectWT;
+  const int64_t nblk = (int64_t)nchunk * n_events * ntile;
+  if (nblk <= 0) return hipSuccess;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  const size_t lds = direct_lds<T>();
+  if (lds > 64 * 1024) {
+    static const hipError_t once = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colpass_direct<T>),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (once != hipSuccess) return once;
+  }
+  hipLaunchKernelGGL((k_colpass_direct<T>), dim3((unsigned)nblk), dim3(64 * kChunk), lds, st, shat, shat_ev_stride,
+                     rtick, mhat, mhat_ev_stride, nw, nphase, nchunk, ntile, n_events);
+  return hipGetLastError();
+}
+
+template hipError_t launch_colpass_direct<float>(const cx<float>*, int64_t, const cx<float>*, cx<float>*, int64_t, int,
+                                                 int, int, int, hipStream_t);
+template hipError_t launch_colpass_direct<double>(const cx<double>*, int64_t, const cx<double>*, cx<double>*, int64_t,
+                                                  int, int, int, int, hipStream_t);
+
+}  // namespace wct

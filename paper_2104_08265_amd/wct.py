@@ -22,6 +22,7 @@ if not os.path.exists(LIB_PATH):
 lib = ctypes.CDLL(LIB_PATH)
 
 WCT_F32, WCT_F64 = 0, 1
+WCT_WIRE_DIRECT = -2  # wct_plan_set_fft kind 1: direct sums over the response's 21 wires
 WCT_OK, WCT_E_INVALID, WCT_E_WORKSPACE, WCT_E_DEVICE, WCT_E_UNSUPPORTED, WCT_E_NOMEM = 0, -1, -2, -3, -4, -5
 OP_RASTER, OP_CONVOLVE, OP_SIMULATE, OP_BACKWARD = 0, 1, 2, 3
 STATUS = {0: "WCT_OK", -1: "WCT_E_INVALID", -2: "WCT_E_WORKSPACE", -3: "WCT_E_DEVICE", -4: "WCT_E_UNSUPPORTED",
@@ -293,9 +294,12 @@ class Plan:
         info = self.plane_info(plane)
         n = info["lt"] // 2 if kind == 0 else info["lw"]
         kinds = (0,) if kind == 0 else (1, 2)  # wire transforms: whole or half chunks per block
-        return [v["index"] for v in fft_variants()
+        comp = [v["index"] for v in fft_variants()
                 if v["kind"] in kinds and v["dtype"] == ("f64" if self.dtype == WCT_F64 else "f32")
-                and v["n"] == n] + [-1]
+                and v["n"] == n]
+        # wires: the direct sum over the response's 21 wires when the response has them
+        direct = [WCT_WIRE_DIRECT] if kind == 1 and info["half_wires"] == 10 else []
+        return comp + direct + [-1]
 
     def profile(self, enable=True):
         check(wct_profile_enable(self.h, int(bool(enable))), "wct_profile_enable")
