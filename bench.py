@@ -201,13 +201,17 @@ def raster_alu_ops(wl, sample_rows=3000, nsigma=3.0, seed=0):
 
 def algorithmic_bytes(plan, esize=4):
     """Bytes each kernel family must move per event (sum over planes) by design."""
+    from paper_2104_08265_amd import wct
     out = {"rows_r2c": 0, "colpass": 0, "rows_c2r": 0, "raster_tile_fluct": 0, "raster_tile_mean": 0}
-    for inf in plan.info:
+    for p, inf in enumerate(plan.info):
         nb = inf["n_impacts"] * inf["n_wires"]
         nw, nt, F, lw, I = inf["n_wires"], inf["n_ticks"], inf["F"], inf["lw"], inf["n_impacts"]
         c = 2 * esize  # one complex value
         out["rows_r2c"] += esize * nb * nt + c * nb * F          # read S, write S-hat
-        out["colpass"] += c * nb * F + c * I * lw * F + c * nw * F  # read S-hat and R~, write M-hat
+        if plan.get_fft(p, 1) == wct.WCT_WIRE_DIRECT:  # read S-hat and the 21 I coefficients, write M-hat
+            out["colpass"] += c * nb * F + c * I * (2 * inf["half_wires"] + 1) * F + c * nw * F
+        else:  # read S-hat and R~, write M-hat
+            out["colpass"] += c * nb * F + c * I * lw * F + c * nw * F
         out["rows_c2r"] += c * nw * F + esize * nw * nt          # read M-hat, write M
         out["raster_tile_fluct"] += esize * nb * nt              # write S once
         out["raster_tile_mean"] += esize * nb * nt
@@ -387,7 +391,8 @@ def main():
     fft_choice = plan.tune(1, args.tune_cache)  # transform variant per plane and axis, timed on this GPU
     variants = {v["index"]: v for v in wct.fft_variants()}
     fft_desc = {f"plane{p}_{'ticks' if k == 0 else 'wires'}":
-                ("runtime" if v < 0 else f"{variants[v]['threads']} threads, radices {variants[v]['radices']}")
+                ("direct 21-wire sums" if v == wct.WCT_WIRE_DIRECT else "runtime" if v < 0
+                 else f"{variants[v]['threads']} threads, radices {variants[v]['radices']}")
                 for (p, k), v in sorted(fft_choice.items())}
     dd = wct.DeviceDepos.from_numpy(wl.depos, "cuda:0", torch.float32)
     o = wct.opts(wl.nsigma, True, 1, wl.seed)

@@ -213,7 +213,8 @@ int wct_plan_get_fft(const wct_plan* plan, int32_t plane, int32_t kind, int32_t*
 int wct_plan_set_fft(wct_plan* plan, int32_t plane, int32_t kind, int32_t variant);
 
 /* Autotuning of the transform variants: for every plane and kind, times the
- * convolution of n_events zero-filled events (HIP events on `stream`, after a warm-up)
+ * convolution of n_events events of constant charge (HIP events on `stream`, after a
+ * warm-up)
  * with each applicable compiled variant and with the runtime plan (wires: and the
  * direct sum, which when fastest keeps the fastest transform plan for the adjoint), and
  * keeps the fastest.  cache_path (HOST string, NULL = none) names a text file of earlier choices:

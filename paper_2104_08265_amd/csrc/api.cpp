@@ -556,8 +556,10 @@ int run_tune(wct_plan* P, int n_events, const char* cache_path, void* ws, hipStr
   T* grid = static_cast<T*>(cv.take(P->esize * (size_t)n_events * P->grid_elems));
   T* wave = static_cast<T*>(cv.take(P->esize * (size_t)n_events * P->wave_elems));
   const size_t conv_off = align_up(cv.off, 256);
-  HIP_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(grid), (int64_t)(P->esize / 4) * n_events * P->grid_elems, 0,
-                          st),
+  // every cell nonzero (0x3ff00000 in each 32-bit word: 1.875f, or about 1.0 as a
+  // double), so that no row transform is skipped as empty while timing
+  HIP_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(grid), (int64_t)(P->esize / 4) * n_events * P->grid_elems,
+                          0x3ff00000, st),
           "tune grid fill");
   auto cache = read_tune_cache(cache_path);
   hipEvent_t e0, e1;

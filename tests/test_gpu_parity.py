@@ -206,3 +206,31 @@ def test_multi_event(wct):
         ref_w = oracle_wave(wl, ref[e])
         for k, w in enumerate(plan.wave_view(wave, e)):
             assert rel_l2(to_np(w), ref_w[k]) < TOL32, (e, k)
+
+
+def test_zero_rows(wct):
+    """Grids with empty impact rows (every other row, and a run of 33): the waveform equals
+    the oracle's for every tick-transform choice (compiled and runtime), and a zero grid
+    gives a zero waveform."""
+    import torch
+    wl = synth.config2(n_depos=10, n_ticks=1024, wires=(240, 240, 346))  # L_t = 1250: compiled tick plans exist
+    plan = make_plan(wct, wl)
+    assert len(plan.fft_candidates(0, 0)) > 1
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(17)
+    g = torch.rand(plan.grid_elems, device="cuda:0", generator=gen, dtype=plan.torch_dtype)
+    R = [r.astype(np.float64) for r in synth.round_responses(wl)]
+    for k, v in enumerate(plan.grid_view(g)):
+        v[::2] = 0  # every other impact row empty
+        v[7:40] = 0
+    ref = [OC.convolve_fft(to_np(v), R[k], wl.planes[k].n_impacts) for k, v in enumerate(plan.grid_view(g))]
+    for choice in plan.fft_candidates(0, 0):
+        for p in range(plan.n_planes):
+            plan.set_fft(p, 0, choice)
+        say("zero rows, tick plan", choice)
+        w = plan.convolve(g, 1)
+        for k, wv in enumerate(plan.wave_view(w)):
+            assert rel_l2(to_np(wv), ref[k]) < TOL32, (choice, k)
+    w = plan.convolve(torch.zeros_like(g), 1)
+    assert float(torch.abs(w).max()) == 0.0
+    plan.close()
