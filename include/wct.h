@@ -191,7 +191,7 @@ int wct_profile_get(wct_plan* plan, int32_t idx, char* name, size_t name_len, do
  * pass B, length L_w) run either a runtime plan (any 2,3,5-smooth length) or one of the
  * plans compiled into the library, whose radices and block size are fixed at build
  * time.  A plan starts with the first compiled variant that matches each length, or
- * the runtime plan when none does; every choice computes the same transform (results
+ * the runtime plan when none does (the forward wire pass: see WCT_WIRE_DIRECT below); every choice computes the same transform (results
  * differ by floating-point rounding only).
  * wct_fft_variant_info(idx, out[12]) fills out = {kind, is_double, threads per block,
  * length, number of passes, radices[0..6] (0-padded)} (HOST buffer); kind 2 is a wire
@@ -205,7 +205,7 @@ int wct_profile_get(wct_plan* plan, int32_t idx, char* name, size_t name_len, do
  * transformed; needs K = 10, else WCT_E_UNSUPPORTED), the same convolution up to
  * rounding.  The adjoint (wct_simulate_backward) keeps running the plane's transform
  * plan, the one last selected with -1 or a variant index; get_fft then reports
- * WCT_WIRE_DIRECT. */
+ * WCT_WIRE_DIRECT.  A new plan starts with the direct sum wherever it applies. */
 #define WCT_WIRE_DIRECT (-2)
 int wct_fft_variant_count(void);
 int wct_fft_variant_info(int32_t idx, int32_t* out);

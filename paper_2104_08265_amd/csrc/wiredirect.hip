@@ -26,6 +26,8 @@ constexpr int kDirectSpan = kDirectWT + 2 * kDirectK;  // S^ wires staged per ph
 // that lanes reading wires kDirectWL apart hit distinct banks
 constexpr int kDirectPstr = kDirectSpan + kDirectSpan / kDirectWL + 1;
 
+}  // namespace
+
 // One block: kChunk tick frequencies (one per wave, so a wave's coefficients are
 // uniform: scalar loads) x kDirectWT consecutive wires of one (chunk, event).  Phases are
 // staged through LDS in two buffers: the next phase's global loads are in flight while
@@ -115,11 +117,11 @@ __global__ void __launch_bounds__(64 * kChunk) k_colpass_direct(const cx<T>* __r
   }
 }
 
+namespace {
 template <typename T>
 size_t direct_lds() {
   return sizeof(cx<T>) * 2 * kChunk * kDirectPstr;
 }
-
 }  // namespace
 
 bool colpass_direct_fits(int K) { return K == kDirectK; }
