@@ -200,12 +200,12 @@ int wct_profile_get(wct_plan* plan, int32_t idx, char* name, size_t name_len, do
  * wct_plan_set_fft selects one: -1 or a variant of that kind, dtype and length, else
  * WCT_E_INVALID.  set_fft allocates the new twiddle tables and synchronises the device;
  * it is a set-up call (for example for an autotuner), not a run call.
- * Kind 1 also takes WCT_WIRE_DIRECT: the forward wire pass as direct sums over the
- * response's 2K+1 wires in the tick-frequency domain (Eq. 1 with only the tick axis
- * transformed; needs K = 10, else WCT_E_UNSUPPORTED), the same convolution up to
- * rounding.  The adjoint (wct_simulate_backward) keeps running the plane's transform
- * plan, the one last selected with -1 or a variant index; get_fft then reports
- * WCT_WIRE_DIRECT.  A new plan starts with the direct sum wherever it applies. */
+ * Kind 1 also takes WCT_WIRE_DIRECT: the wire pass (forward, and the adjoint of
+ * wct_simulate_backward) as direct sums over the response's 2K+1 wires in the
+ * tick-frequency domain (Eq. 1 with only the tick axis transformed; needs K = 10, else
+ * WCT_E_UNSUPPORTED), the same convolution up to rounding; get_fft then reports
+ * WCT_WIRE_DIRECT, and a later -1 or variant index returns to a transform plan.  A new
+ * plan starts with the direct sum wherever it applies. */
 #define WCT_WIRE_DIRECT (-2)
 int wct_fft_variant_count(void);
 int wct_fft_variant_info(int32_t idx, int32_t* out);
@@ -216,8 +216,7 @@ int wct_plan_set_fft(wct_plan* plan, int32_t plane, int32_t kind, int32_t varian
  * convolution of n_events events of constant charge (HIP events on `stream`, after a
  * warm-up)
  * with each applicable compiled variant and with the runtime plan (wires: and the
- * direct sum, which when fastest keeps the fastest transform plan for the adjoint), and
- * keeps the fastest.  cache_path (HOST string, NULL = none) names a text file of earlier choices:
+ * direct sum), and keeps the fastest.  cache_path (HOST string, NULL = none) names a text file of earlier choices:
  * lines "wct-fft <dtype> <N_w> <N_t> <I> <K> <T_R> kind <k> -> <threads> <radices...>"
  * (or "-> runtime", "-> direct"); choices found there for this library's variants are applied
  * without timing, new ones are appended.  ws: wct_tune_workspace_bytes(plan, n_events)

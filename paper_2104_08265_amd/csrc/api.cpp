@@ -134,7 +134,7 @@ struct wct_plan {
   std::vector<FftPlan> fp_t, fp_w;
   std::vector<void*> tw_t, post_t, tw_w, tw_w_rev, rtil;
   std::vector<void*> rtick;      // direct wire pass coefficients, [F padded][I][2K+1]
-  std::vector<int> wire_direct;  // forward wire pass as direct sums (the adjoint keeps fp_w)
+  std::vector<int> wire_direct;  // wire pass (forward and adjoint) as direct sums, else fp_w
   DetTables* d_tables = nullptr;
   double* d_lfact = nullptr;  // ln(n!), n < kLfactTable, for the chop-down sampler
   std::vector<void*> allocs;
@@ -341,11 +341,18 @@ int run_backward(wct_plan* P, const wct_depos* d, const wct_opts* o, const T* gw
                 launch_rows_r2c<T>(gw + G.wave_off, P->wave_elems, ghat + G.mhat_off, P->mhat_elems, G.nt, 1, G.nw,
                                    G.nchunk, ne, P->fp_t[p], tw_t, post, P->n_cu, st),
                 "adjoint row transform launch");
-    PROF_LAUNCH(P, "adj_colpass", st,
-                launch_colpass_adj<T>(ghat + G.mhat_off, P->mhat_elems, static_cast<const cx<T>*>(P->rtil[p]),
-                                      hhat + G.shat_off, P->shat_elems, G.nw, G.I, G.nchunk, ne, P->fp_w[p], tw_w,
-                                      tw_wr, st),
-                "adjoint column pass launch");
+    if (P->wire_direct[p])
+      PROF_LAUNCH(P, "adj_colpass", st,
+                  launch_colpass_adj_direct<T>(ghat + G.mhat_off, P->mhat_elems,
+                                               static_cast<const cx<T>*>(P->rtick[p]), hhat + G.shat_off,
+                                               P->shat_elems, G.nw, G.I, G.nchunk, ne, st),
+                  "adjoint column pass launch");
+    else
+      PROF_LAUNCH(P, "adj_colpass", st,
+                  launch_colpass_adj<T>(ghat + G.mhat_off, P->mhat_elems, static_cast<const cx<T>*>(P->rtil[p]),
+                                        hhat + G.shat_off, P->shat_elems, G.nw, G.I, G.nchunk, ne, P->fp_w[p], tw_w,
+                                        tw_wr, st),
+                  "adjoint column pass launch");
     PROF_LAUNCH(P, "adj_rows_c2r", st,
                 launch_rows_c2r<T>(hhat + G.shat_off, P->shat_elems, H + G.grid_off, P->grid_elems, G.nt, true, G.I,
                                    G.nw, G.nchunk, ne, P->fp_t[p], tw_t, post, st),
@@ -468,8 +475,8 @@ int plan_tables(wct_plan* P, const wct_plan_desc* desc) {
     if (rc) return rc;
     rc = set_fft<T>(P, p, 1, find_variant(1, sizeof(T) == 8, G.lw));
     if (rc) return rc;
-    // the forward wire pass defaults to the direct sums where the response allows them
-    // (about twice as fast as the transform pair on MI355X); the adjoint keeps fp_w
+    // the wire pass (forward and adjoint) defaults to the direct sums where the response
+    // allows them (about twice as fast as the transform pair on MI355X)
     if (colpass_direct_fits(G.K)) P->wire_direct[p] = 1;
     std::vector<cx<double>> post(G.M + 1);
     for (int k = 0; k <= G.M; ++k) post[k] = wexp(k, G.lt);
@@ -611,8 +618,8 @@ int run_tune(wct_plan* P, int n_events, const char* cache_path, void* ws, hipStr
         if (rc) break;
         appended += key + " -> " + variant_text(best) + "\n";
       }
-      // the direct sum replaces the forward wire pass only: the adjoint runs the fastest
-      // transform plan timed (or, from the cache, the plane's current one)
+      // with the direct sums chosen, the plane keeps the fastest transform plan timed
+      // (or, from the cache, its current one) for a later set_fft of -1 or a variant
       if (best == WCT_WIRE_DIRECT && best_fft != kNone) rc = set_fft<T>(P, p, kind, best_fft);
       if (rc == WCT_OK) rc = set_fft<T>(P, p, kind, best);
     }

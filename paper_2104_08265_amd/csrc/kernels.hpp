@@ -101,6 +101,10 @@ template <typename T>
 hipError_t launch_colpass_direct(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtick, cx<T>* mhat,
                                  int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, hipStream_t st);
 template <typename T>
+hipError_t launch_colpass_adj_direct(const cx<T>* ghat, int64_t ghat_ev_stride, const cx<T>* rtick, cx<T>* hhat,
+                                     int64_t hhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
+                                     hipStream_t st);
+template <typename T>
 hipError_t launch_colpass_adj(const cx<T>* ghat, int64_t ghat_ev_stride, const cx<T>* rtil, cx<T>* hhat,
                               int64_t hhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
                               const FftPlan& plan, const cx<T>* tw, const cx<T>* tw_rev, hipStream_t st);

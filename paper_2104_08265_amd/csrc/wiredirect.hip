@@ -117,6 +117,70 @@ __global__ void __launch_bounds__(64 * kChunk) k_colpass_direct(const cx<T>* __r
   }
 }
 
+// Adjoint of the direct pass: H^(I c + i, w_t) = sum_k conj(R^_t[k][i](w_t)) G^(c - k, w_t)
+// (the correlation's transpose; G^ rows outside the wires are zero).  One staged window
+// of G^ serves all I phases: each lane keeps its 8 + 2K values in registers and runs the
+// 21 taps once per phase with that phase's coefficients.
+template <typename T>
+__global__ void __launch_bounds__(64 * kChunk) k_colpass_adj_direct(const cx<T>* __restrict__ ghat,
+                                                                   int64_t ghat_ev_stride,
+                                                                   const cx<T>* __restrict__ rtick,
+                                                                   cx<T>* __restrict__ hhat, int64_t hhat_ev_stride,
+                                                                   int nw, int nphase, int nchunk, int ntile,
+                                                                   int n_events) {
+  constexpr int K = kDirectK, NK = 2 * K + 1, WL = kDirectWL, WT = kDirectWT;
+  constexpr int SPAN = kDirectSpan, PSTR = kDirectPstr, C = kChunk;
+  constexpr int CPV = 16 / (int)sizeof(cx<T>);
+  constexpr int VPW = C / CPV;
+  constexpr int NE = SPAN * VPW;
+  using V = typename Vec16<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);  // [C][PSTR]
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = L % ntile, rest = L / ntile;
+  const int ev = rest % n_events, ch = rest / n_events;
+  const int w0 = tile * WT;
+  const int tid = (int)threadIdx.x, lane = tid & 63;
+  const int f = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const cx<T>* src = ghat + ev * ghat_ev_stride + (int64_t)ch * nw * C;  // [chunk][wire][C]
+  for (int e = tid; e < NE; e += 64 * C) {
+    const int w = w0 - K + e / VPW;
+    V v = {};
+    if (w >= 0 && w < nw) v = *reinterpret_cast<const V*>(src + (int64_t)w * C + (e % VPW) * CPV);
+    const int x = e / VPW, f0 = (e % VPW) * CPV;
+#pragma unroll
+    for (int q = 0; q < CPV; ++q) lds[(f0 + q) * PSTR + x + x / WL] = mk(v[2 * q], v[2 * q + 1]);
+  }
+  __syncthreads();
+  // G^ of wires w0 + WL lane - K + j, j < WL + 2K
+  cx<T> g[WL + 2 * K];
+  const cx<T>* s = lds + f * PSTR + (WL + 1) * lane;
+#pragma unroll
+  for (int j = 0; j < WL + 2 * K; ++j) g[j] = s[j + j / WL];
+  cx<T>* dst = hhat + ev * hhat_ev_stride + (int64_t)ch * nphase * nw * C;  // [chunk][i][wire][C]
+  for (int i = 0; i < nphase; ++i) {
+    const cx<T>* coef = rtick + ((int64_t)(ch * C + f) * nphase + i) * NK;  // uniform: scalar loads
+    cx<T> r[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) r[k] = coef[k];
+#pragma unroll
+    for (int o = 0; o < WL; ++o) {
+      // output wire c = w0 + WL lane + o takes G^(c - k) = g[o + K - k], k = -K..K
+      T ax = T(0), ay = T(0);
+#pragma unroll
+      for (int kk = 0; kk < NK; ++kk) {
+        const cx<T> c = r[kk], v = g[o + 2 * K - kk];  // conj(c) * v
+        ax = fma(c.x, v.x, ax);
+        ax = fma(c.y, v.y, ax);
+        ay = fma(c.x, v.y, ay);
+        ay = fma(-c.y, v.x, ay);
+      }
+      const int w = w0 + WL * lane + o;
+      if (w < nw) dst[((int64_t)i * nw + w) * C + f] = mk(ax, ay);
+    }
+  }
+}
+
 namespace {
 template <typename T>
 size_t direct_lds() {
@@ -145,6 +209,24 @@ hipError_t launch_colpass_direct(const cx<T>* shat, int64_t shat_ev_stride, cons
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_colpass_adj_direct(const cx<T>* ghat, int64_t ghat_ev_stride, const cx<T>* rtick, cx<T>* hhat,
+                                     int64_t hhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
+                                     hipStream_t st) {
+  const int ntile = (nw + kDirectWT - 1) / kDirectWT;
+  const int64_t nblk = (int64_t)nchunk * n_events * ntile;
+  if (nblk <= 0) return hipSuccess;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  const size_t lds = direct_lds<T>() / 2;  // one buffer
+  hipLaunchKernelGGL((k_colpass_adj_direct<T>), dim3((unsigned)nblk), dim3(64 * kChunk), lds, st, ghat,
+                     ghat_ev_stride, rtick, hhat, hhat_ev_stride, nw, nphase, nchunk, ntile, n_events);
+  return hipGetLastError();
+}
+
+template hipError_t launch_colpass_adj_direct<float>(const cx<float>*, int64_t, const cx<float>*, cx<float>*, int64_t,
+                                                     int, int, int, int, hipStream_t);
+template hipError_t launch_colpass_adj_direct<double>(const cx<double>*, int64_t, const cx<double>*, cx<double>*,
+                                                      int64_t, int, int, int, int, hipStream_t);
 template hipError_t launch_colpass_direct<float>(const cx<float>*, int64_t, const cx<float>*, cx<float>*, int64_t, int,
                                                  int, int, int, hipStream_t);
 template hipError_t launch_colpass_direct<double>(const cx<double>*, int64_t, const cx<double>*, cx<double>*, int64_t,
