@@ -101,6 +101,96 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_ct(const
   }
 }
 
+// Pass A over row pairs (wires c, c + 1 of one phase, c even; needs an even wire count):
+// the first row's spectrum waits in LDS while the second is transformed, then both are
+// written together, so each chunk of C frequencies goes out as 2C contiguous values
+// (64 bytes in FP32) instead of two separate C-value pieces.  LDS: the transform buffer
+// plus one staged spectrum.
+template <typename T, int C, typename F>
+__global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(const T* __restrict__ src,
+                                                                  int64_t src_ev_stride, cx<T>* __restrict__ dst,
+                                                                  int64_t dst_ev_stride, int nt, int nphase, int nper,
+                                                                  int nchunk, int n_events,
+                                                                  const cx<T>* __restrict__ tw,
+                                                                  const cx<T>* __restrict__ post) {
+  constexpr int M = F::N, NT = F::kThreads, R0 = F::R0;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* z = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* stg = z + M;  // the pair's first spectrum, [fpad]
+  const int rows = nphase * nper;
+  const int pairs = rows / 2 * n_events;
+  const int fpad = nchunk * C;
+  const bool v2 = (nt % 2) == 0 && (reinterpret_cast<uintptr_t>(src) % (2 * sizeof(T))) == 0 &&
+                  (src_ev_stride % 2) == 0;
+  cx<T> in[F::IN];
+  // row r (0 or 1) of pair P: event, phase, wire
+  auto row_of = [&](int P, int r, int& ev, int& i, int& c) {
+    const int L = 2 * P + r;
+    ev = L / rows;
+    const int rin = L - ev * rows;
+    i = rin / nper;
+    c = rin - i * nper;
+  };
+  auto load = [&](int P, int r) {
+    int ev, i, c;
+    row_of(P, r, ev, i, c);
+    const T* s = src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt;
+#pragma unroll
+    for (int q = 0; q < F::MB0; ++q) {
+      if (!F::in_ok(q)) continue;
+#pragma unroll
+      for (int rr = 0; rr < R0; ++rr) {
+        const int m = F::in_elem(q, rr);
+        if (v2) {
+          if (2 * m < nt) {
+            const cv2<T> p = *reinterpret_cast<const cv2<T>*>(s + 2 * m);
+            in[q * R0 + rr] = mk(p.x, p.y);
+          } else {
+            in[q * R0 + rr] = mk(T(0), T(0));
+          }
+        } else {
+          in[q * R0 + rr] = mk(2 * m < nt ? s[2 * m] : T(0), 2 * m + 1 < nt ? s[2 * m + 1] : T(0));
+        }
+      }
+    }
+  };
+  auto post_twiddle = [&](int k) {
+    cx<T> X = mk(T(0), T(0));
+    if (k <= M) {
+      const cx<T> A = z[k == M ? 0 : k];
+      const cx<T> B = conj(z[k == 0 ? 0 : M - k]);
+      const cx<T> Ev = scale(A + B, T(0.5));
+      const cx<T> D = scale(A - B, T(0.5));
+      const cx<T> O = mk(D.y, -D.x);  // (A - B) / (2i)
+      X = Ev + cmul(post[k], O);
+    }
+    return X;
+  };
+  int P = xcd_remap(blockIdx.x, gridDim.x);
+  if (P < pairs) load(P, 0);
+  while (P < pairs) {
+    const int Pn = P + gridDim.x;
+    F::template rl<false>(z, tw, in, [&]() { load(P, 1); });
+    for (int k = threadIdx.x; k < fpad; k += NT) stg[k] = post_twiddle(k);
+    __syncthreads();
+    F::template rl<false>(z, tw, in, [&]() {
+      if (Pn < pairs) load(Pn, 0);
+    });
+    int ev, i, c;
+    row_of(P, 0, ev, i, c);
+    // chunk q of the pair: [q][i][c .. c + 1][C], 2C contiguous values
+    cx<T>* o = dst + ev * dst_ev_stride + ((int64_t)i * nper + c) * C;
+    const int64_t cstride = (int64_t)nphase * nper * C;
+    for (int x = threadIdx.x; x < 2 * fpad; x += NT) {
+      const int q = x / (2 * C), e = x - q * (2 * C);
+      const int k = q * C + (e < C ? e : e - C);
+      o[(int64_t)q * cstride + e] = e < C ? stg[k] : post_twiddle(k);
+    }
+    __syncthreads();
+    P = Pn;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Pass B (compiled plan): phase transforms along wires, product with R~_i and phase
 // sum in registers, inverse transform with the reversed plan.
@@ -340,12 +430,20 @@ hipError_t launch_rows_r2c_ct(const T* src, int64_t src_ev_stride, cx<T>* dst, i
                               int nphase, int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
                               const cx<T>* post, int n_cu, hipStream_t st) {
   const size_t lds = sizeof(cx<T>) * plan.n;
+  const size_t lds_pair = lds + sizeof(cx<T>) * nchunk * kChunk;
   const int total = nphase * nper * n_events;
+  // wire pairs when the wires pair up and the staged spectrum fits beside the buffer
+  const bool pair = nper % 2 == 0 && lds_pair <= 160 * 1024;
   const hipError_t e = with_variant<T, 0>(plan.variant, [&](auto f) {
     using F = decltype(f);
-    hipLaunchKernelGGL((k_rows_r2c_ct<T, kChunk, F>), dim3(persistent_blocks(n_cu, lds, F::kThreads, total)),
-                       dim3(F::kThreads), lds, st, src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk,
-                       n_events, tw, post);
+    if (pair)
+      hipLaunchKernelGGL((k_rows_r2c_pair_ct<T, kChunk, F>),
+                         dim3(persistent_blocks(n_cu, lds_pair, F::kThreads, total / 2)), dim3(F::kThreads), lds_pair,
+                         st, src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, n_events, tw, post);
+    else
+      hipLaunchKernelGGL((k_rows_r2c_ct<T, kChunk, F>), dim3(persistent_blocks(n_cu, lds, F::kThreads, total)),
+                         dim3(F::kThreads), lds, st, src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk,
+                         n_events, tw, post);
   });
   return e != hipSuccess ? e : hipGetLastError();
 }
@@ -403,6 +501,8 @@ static void raise_lds_limits_ct() {
     using F = decltype(f);
     (void)hipFuncSetAttribute((const void*)k_rows_r2c_ct<T, kChunk, F>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               lim);
+    (void)hipFuncSetAttribute((const void*)k_rows_r2c_pair_ct<T, kChunk, F>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)k_rows_c2r_ct<T, kChunk, true, F>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)k_rows_c2r_ct<T, kChunk, false, F>,
