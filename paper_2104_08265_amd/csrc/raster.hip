@@ -184,34 +184,57 @@ __device__ __forceinline__ void rq_run(RegQueue& q, int take, int N, double lfN,
   q.n -= take;
 }
 
-// A cell's outcome of the cheap tests: added at once, queued for its regime, or nothing.
-template <typename T, typename Add>
-__device__ __forceinline__ void cell_route(RegQueue* q, int64_t quick, double p, double u, int N, double lfN, uint32_t dst,
-                                           int lane, const DetTablesSmall& tb, const double* __restrict__ lf, Add add) {
-  if (quick > 0) add(dst, (T)quick);
-  rq_push(q[0], quick == -1, p, u, dst, lane);
-  if (q[0].n >= 64) rq_run<T, 0>(q[0], 64, N, lfN, lane, tb, lf, add);
-  rq_push(q[1], quick == -2, p, u, dst, lane);
-  if (q[1].n >= 64) rq_run<T, 1>(q[1], 64, N, lfN, lane, tb, lf, add);
-}
+// The chop-down queue may outlive a row: the tile kernel keeps one per wave for a whole
+// work item, so that its batches fill up across rows.  Its entries then carry their
+// row's electron count in the bits of the offset above kDstBits (tile offsets are below
+// 2^13); a count of 0 there stands for `rowN`, the count of the row being rasterised,
+// which is how rows with 2^19 or more electrons (and the wide-row kernel, whose offsets
+// need all the bits) enqueue: such a row empties the queue when it ends.
+constexpr int kDstBits = 13;
+constexpr int kPackN = 1 << (32 - kDstBits);
 
 template <typename T, typename Add>
-__device__ __forceinline__ void queues_flush(RegQueue* q, int N, double lfN, int lane, const DetTablesSmall& tb,
-                                             const double* __restrict__ lf, Add add) {
-  if (q[0].n > 0) rq_run<T, 0>(q[0], q[0].n, N, lfN, lane, tb, lf, add);
-  if (q[1].n > 0) rq_run<T, 1>(q[1], q[1].n, N, lfN, lane, tb, lf, add);
+__device__ __forceinline__ void rq_run_chop(RegQueue& q, int take, int rowN, bool packed, int lane,
+                                            const DetTablesSmall& tb, const double* __restrict__ lf, Add add) {
+  if (lane < take) {
+    const uint32_t e = q.d0;
+    const int fieldN = packed ? (int)(e >> kDstBits) : 0;
+    const int N = fieldN ? fieldN : rowN;
+    const uint32_t d = packed ? (e & ((1u << kDstBits) - 1u)) : e;
+    const int k = binom_regime_draw<1>(N, lfact_of(N, lf, tb), q.p0, q.u0, tb, lf);
+    if (k) add(d, (T)k);
+  }
+  q.p0 = q.p1;
+  q.u0 = q.u1;
+  q.d0 = q.d1;
+  q.n -= take;
+}
+
+// A cell's outcome of the cheap tests: added at once, queued for its regime, or nothing.
+// `tagN` is what the chop-down entry carries (the row's count, or 0 for `rowN`).
+template <typename T, typename Add>
+__device__ __forceinline__ void cell_route(RegQueue& qi, RegQueue& qc, bool packed, int tagN, int64_t quick,
+                                           double p, double u, int N, double lfN, uint32_t dst, int lane,
+                                           const DetTablesSmall& tb, const double* __restrict__ lf, Add add) {
+  if (quick > 0) add(dst, (T)quick);
+  rq_push(qi, quick == -1, p, u, dst, lane);
+  if (qi.n >= 64) rq_run<T, 0>(qi, 64, N, lfN, lane, tb, lf, add);
+  rq_push(qc, quick == -2, p, u, packed ? dst | ((uint32_t)tagN << kDstBits) : dst, lane);
+  if (qc.n >= 64) rq_run_chop<T>(qc, 64, N, packed, lane, tb, lf, add);
 }
 
 // One wave rasterises the cells [b0, b1) x [k0, k1) of a row; `dst(b, k)` names a cell and
 // `add(dst, value)` accumulates a nonzero contribution.  Fluctuated cells are drawn in
 // tick pairs: cells (b, 2m), (b, 2m+1) share one Philox4x32-10 block (counter
 // b*ceil(N_t/2) + m), words 0-1 for the even tick and 2-3 for the odd one.
-template <typename T, bool FLUCT, typename Dst, typename Add>
+// PACKED: `qc` is the caller's chop-down queue of a whole work item (entries carry their
+// count; the caller empties it at the item's end); otherwise it is emptied here.
+template <typename T, bool FLUCT, bool PACKED, typename Dst, typename Add>
 __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int k0, int k1, int nt, uint32_t did,
                                             uint32_t ev, uint32_t plane, uint32_t key0, uint32_t key1,
                                             double* __restrict__ ea, double* __restrict__ eb,
                                             const DetTablesSmall& tb, const double* __restrict__ lf, int lane, Dst dst,
-                                            Add add) {
+                                            Add add, RegQueue& qc) {
   const int nbr = b1 - b0, nkr = k1 - k0;
   edge_fill2<FLUCT>(ea, b0, b1, w.u, w.su, w.ulo, w.uhi, eb, k0, k1, w.t, w.st, w.tlo, w.thi, lane);
   wave_sync();
@@ -227,8 +250,9 @@ __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int
     const int N = __builtin_amdgcn_readfirstlane((int)floor(fmin(w.q + 0.5, 2147483647.0)));
     if (N > 0) {
       const double lfN = lfact_of(N, lf, tb);
-      RegQueue q[2];
-      q[0].n = q[1].n = 0;
+      const int tagN = N < kPackN ? N : 0;  // 0: the entry stands for this row's count
+      RegQueue qi;
+      qi.n = 0;
       const int j0 = k0 >> 1, np = ((k1 - 1) >> 1) - j0 + 1;
       const uint32_t half_nt = (uint32_t)((nt + 1) >> 1);
       const float rd = 1.0f / (float)np;
@@ -257,10 +281,12 @@ __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int
             quick_o = binom_quick(N, po, uo);
           }
         }
-        cell_route<T>(q, quick_e, pe, ue, N, lfN, de, lane, tb, lf, add);
-        cell_route<T>(q, quick_o, po, uo, N, lfN, dodd, lane, tb, lf, add);
+        cell_route<T>(qi, qc, PACKED, tagN, quick_e, pe, ue, N, lfN, de, lane, tb, lf, add);
+        cell_route<T>(qi, qc, PACKED, tagN, quick_o, po, uo, N, lfN, dodd, lane, tb, lf, add);
       }
-      queues_flush<T>(q, N, lfN, lane, tb, lf, add);
+      if (qi.n > 0) rq_run<T, 0>(qi, qi.n, N, lfN, lane, tb, lf, add);
+      // entries that stand for this row's count cannot outlive it
+      if ((!PACKED || tagN == 0) && qc.n > 0) rq_run_chop<T>(qc, qc.n, N, PACKED, lane, tb, lf, add);
     }
   }
   wave_sync();
@@ -530,6 +556,8 @@ __global__ void __launch_bounds__(256, 4) k_tile(DepoView<T> d, RasterGeom g, do
       if (lane == 0) r = atomicAdd(&s_row, 1);
       return __builtin_amdgcn_readfirstlane(r);
     };
+    RegQueue qc;  // this wave's chop-down queue for the item
+    qc.n = 0;
     for (int r = claim(); r < r1; r = claim()) {
       // the row is wave-uniform: a scalar index makes its parameters scalar loads and registers
       const int64_t j = __builtin_amdgcn_readfirstlane(list[r]);
@@ -538,9 +566,10 @@ __global__ void __launch_bounds__(256, 4) k_tile(DepoView<T> d, RasterGeom g, do
       const int kk0 = max(w.k0, tk0), kk1 = min(w.k1, tk0 + tw);
       if (!w.ok || bb0 >= bb1 || kk0 >= kk1) continue;
       const uint32_t did = d.depo_id ? (uint32_t)d.depo_id[j] : (uint32_t)j;
-      patch_cells<T, FLUCT>(w, bb0, bb1, kk0, kk1, pl.nt, did, (uint32_t)w.key_event, (uint32_t)pi, key0, key1, s_ea[wv],
-                            s_eb[wv], s_tb, lf, lane, dst, add);
+      patch_cells<T, FLUCT, true>(w, bb0, bb1, kk0, kk1, pl.nt, did, (uint32_t)w.key_event, (uint32_t)pi, key0, key1,
+                                  s_ea[wv], s_eb[wv], s_tb, lf, lane, dst, add, qc);
     }
+    if (FLUCT && qc.n > 0) rq_run_chop<T>(qc, qc.n, 0, true, lane, s_tb, lf, add);
     __syncthreads();
     T* gp = grid + (int64_t)ev * g.grid_ev_stride + pl.grid_off;
     for (int x = threadIdx.x; x < th * TW; x += blockDim.x) {
@@ -592,8 +621,10 @@ __global__ void __launch_bounds__(256, 3) k_big(DepoView<T> d, RasterGeom g, dou
       const int cb = c / nck, ck = c - (c / nck) * nck;
       const int b0 = w.b0 + cb * CB, b1 = min(b0 + CB, w.b1);
       const int k0 = max(kstart + ck * CK, w.k0), k1 = min(kstart + (ck + 1) * CK, w.k1);
-      patch_cells<T, FLUCT>(w, b0, b1, k0, k1, pl.nt, did, (uint32_t)w.key_event, (uint32_t)w.plane, key0, key1,
-                            s_ea[wv], s_eb[wv], s_tb, lf, lane, dst, add);
+      RegQueue qc;
+      qc.n = 0;
+      patch_cells<T, FLUCT, false>(w, b0, b1, k0, k1, pl.nt, did, (uint32_t)w.key_event, (uint32_t)w.plane, key0, key1,
+                                   s_ea[wv], s_eb[wv], s_tb, lf, lane, dst, add, qc);
     }
   }
 }
