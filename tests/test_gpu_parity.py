@@ -234,3 +234,26 @@ def test_zero_rows(wct):
     w = plan.convolve(torch.zeros_like(g), 1)
     assert float(torch.abs(w).max()) == 0.0
     plan.close()
+
+
+def test_odd_wire_count(wct):
+    """An odd number of wires (no wire pairs for the row transform: single-row kernel) and a
+    wire count that is not a multiple of the direct pass's 512-wire tile: waveforms equal
+    the oracle's, with the compiled tick plan and the runtime one."""
+    import torch
+    wl = synth.config2(n_depos=600, n_tracks=3, n_ticks=1024, wires=(241, 163, 347), fluctuate=True)
+    plan = make_plan(wct, wl)
+    say("odd wire counts 241/163/347", len(wl.depos))
+    grid = plan.raster(device_depos(wct, wl), wct.opts(3.0, True, 1, wl.seed))
+    ref = OF.raster_fluct(wl.depos, wl.planes, seed=wl.seed)[0]
+    for k, g in enumerate(plan.grid_view(grid)):
+        assert np.array_equal(to_np(g), ref[k]), k
+    R = [r.astype(np.float64) for r in synth.round_responses(wl)]
+    waves = [OC.convolve_fft(ref[k], R[k], wl.planes[k].n_impacts) for k in range(len(wl.planes))]
+    for choice in plan.fft_candidates(0, 0):
+        for p in range(plan.n_planes):
+            plan.set_fft(p, 0, choice)
+        w = plan.convolve(grid, 1)
+        for k, wv in enumerate(plan.wave_view(w)):
+            assert rel_l2(to_np(wv), waves[k]) < TOL32, (choice, k)
+    plan.close()
