@@ -23,7 +23,9 @@
  *
  * Memory.  Every pointer argument of the run calls is a DEVICE pointer unless it is
  * marked HOST.  The caller owns depositions, grids, waveforms, gradients and the
- * workspace; the plan owns only its response spectra and twiddle tables.  Outputs are
+ * workspace; the plan owns only its response spectra and twiddle tables (the 2D
+ * spectrum the wire transforms use, I L_w F complex values per plane, only once a
+ * plane's wire pass is set to a transform plan).  Outputs are
  * overwritten, never accumulated.  Grids and waveforms of one event pack the planes
  * back to back (offsets from wct_plane_info); events follow one another.
  *
@@ -32,7 +34,8 @@
  * negative WCT_E_* code; wct_last_error() then describes it.  Invalid arguments are
  * detected on the host before anything is enqueued.  Faults inside kernels surface at
  * the caller's next synchronisation, as HIP specifies.  Only wct_plan_create and the
- * set-up call wct_plan_set_fft allocate device memory or synchronise.  One plan must
+ * set-up calls wct_plan_set_fft and wct_plan_tune allocate device memory or
+ * synchronise.  One plan must
  * not be used by two threads at once; separate plans are independent.
  */
 #ifndef WCT_H

@@ -134,6 +134,8 @@ struct wct_plan {
   std::vector<FftPlan> fp_t, fp_w;
   std::vector<void*> tw_t, post_t, tw_w, tw_w_rev, rtil;
   std::vector<void*> rtick;      // direct wire pass coefficients, [F padded][I][2K+1]
+  std::vector<void*> rt64;       // FP64 tick spectrum of the response, [2K+1][I][F]: R~ is built
+                                 // from it when a wire transform plan is first selected
   std::vector<int> wire_direct;  // wire pass (forward and adjoint) as direct sums, else fp_w
   DetTables* d_tables = nullptr;
   double* d_lfact = nullptr;  // ln(n!), n < kLfactTable, for the chop-down sampler
@@ -400,6 +402,34 @@ void free_table(wct_plan* P, void* d) {
     }
 }
 
+// R~ of plane p (the wire transforms' 2D spectrum, 1/(L_w L_t) folded in), built from the
+// plan's FP64 tick spectrum the first time a wire transform plan is selected: a plan
+// that only runs the direct wire sums never holds it (3.4 GB on the three-plane
+// geometry).  A set-up step: allocates and synchronises.
+template <typename T>
+int ensure_rtil(wct_plan* P, int p) {
+  if (P->rtil[p]) return WCT_OK;
+  const PlaneGeom& G = P->geom[p];
+  std::vector<cx<double>> tlw(G.lw);
+  for (int m = 0; m < G.lw; ++m) tlw[m] = wexp(m, G.lw);
+  cx<double>* dtlw = nullptr;
+  hipError_t e = hipMalloc(&dtlw, sizeof(cx<double>) * G.lw);
+  void* rtil = nullptr;
+  if (e == hipSuccess) rtil = P->dalloc(sizeof(cx<T>) * (size_t)G.nchunk * G.I * G.lw * kChunk, &e);
+  if (e == hipSuccess) e = hipMemcpy(dtlw, tlw.data(), sizeof(cx<double>) * G.lw, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = launch_resp_wire<T>(static_cast<const cx<double>*>(P->rt64[p]), G.K, G.I, G.F, G.lw, G.lt, G.nchunk, dtlw,
+                            static_cast<cx<T>*>(rtil), nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  (void)hipFree(dtlw);
+  if (e != hipSuccess) {
+    free_table(P, rtil);
+    return hip_fail(e, "wire transform spectrum");
+  }
+  P->rtil[p] = rtil;
+  return WCT_OK;
+}
+
 // (Re)builds the transform plan and twiddle tables of plane p along ticks (kind 0) or
 // wires (kind 1): compiled variant v, or the runtime plan (v < 0).  Column variants
 // also get the table of their radices reversed (the inverse transform's plan).
@@ -451,7 +481,10 @@ int set_fft(wct_plan* P, int p, int kind, int v) {
     P->fp_w[p] = fp;
     P->tw_w[p] = d;
     P->tw_w_rev[p] = dr;
-    P->wire_direct[p] = 0;
+    if ((size_t)p < P->rtil.size()) {  // set after plan creation: the transforms run now
+      P->wire_direct[p] = 0;
+      return ensure_rtil<T>(P, p);
+    }
   }
   return WCT_OK;
 }
@@ -491,35 +524,31 @@ int plan_tables(wct_plan* P, const wct_plan_desc* desc) {
     const size_t nr = (size_t)nk * G.I * G.TR;
     std::vector<double> R(nr);
     for (size_t i = 0; i < nr; ++i) R[i] = (double)static_cast<const T*>(pd.response)[i];
-    std::vector<cx<double>> tlt(G.lt), tlw(G.lw);
+    std::vector<cx<double>> tlt(G.lt);
     for (int m = 0; m < G.lt; ++m) tlt[m] = wexp(m, G.lt);
-    for (int m = 0; m < G.lw; ++m) tlw[m] = wexp(m, G.lw);
     double* dR = nullptr;
-    cx<double>*dtlt = nullptr, *dtlw = nullptr, *drt = nullptr;
+    cx<double>* dtlt = nullptr;
     hipError_t e = hipMalloc(&dR, sizeof(double) * nr);
     if (e == hipSuccess) e = hipMalloc(&dtlt, sizeof(cx<double>) * G.lt);
-    if (e == hipSuccess) e = hipMalloc(&dtlw, sizeof(cx<double>) * G.lw);
-    if (e == hipSuccess) e = hipMalloc(&drt, sizeof(cx<double>) * (size_t)nk * G.I * G.F);
-    void* rtil = nullptr;
+    void* drt = nullptr;
     void* rtick = nullptr;
-    if (e == hipSuccess) rtil = P->dalloc(sizeof(cx<T>) * (size_t)G.nchunk * G.I * G.lw * kChunk, &e);
+    if (e == hipSuccess) drt = P->dalloc(sizeof(cx<double>) * (size_t)nk * G.I * G.F, &e);
     if (e == hipSuccess) rtick = P->dalloc(sizeof(cx<T>) * (size_t)G.nchunk * kChunk * G.I * nk, &e);
     if (e == hipSuccess) e = hipMemcpy(dR, R.data(), sizeof(double) * nr, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dtlt, tlt.data(), sizeof(cx<double>) * G.lt, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(dtlw, tlw.data(), sizeof(cx<double>) * G.lw, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_resp_tick(dR, nk, G.I, G.TR, G.lt, G.F, dtlt, drt, nullptr);
+    if (e == hipSuccess) e = launch_resp_tick(dR, nk, G.I, G.TR, G.lt, G.F, dtlt, static_cast<cx<double>*>(drt), nullptr);
     if (e == hipSuccess)
-      e = launch_resp_wire<T>(drt, G.K, G.I, G.F, G.lw, G.lt, G.nchunk, dtlw, static_cast<cx<T>*>(rtil), nullptr);
-    if (e == hipSuccess)
-      e = launch_resp_tick_pack<T>(drt, G.K, G.I, G.F, G.nchunk * kChunk, G.lt, static_cast<cx<T>*>(rtick), nullptr);
+      e = launch_resp_tick_pack<T>(static_cast<cx<double>*>(drt), G.K, G.I, G.F, G.nchunk * kChunk, G.lt,
+                                   static_cast<cx<T>*>(rtick), nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     (void)hipFree(dR);
     (void)hipFree(dtlt);
-    (void)hipFree(dtlw);
-    (void)hipFree(drt);
     if (e != hipSuccess) return hip_fail(e, "response spectrum");
-    P->rtil.push_back(rtil);
+    P->rt64.push_back(drt);
     P->rtick.push_back(rtick);
+    P->rtil.push_back(nullptr);
+    // the 2D spectrum of the wire transforms only where they run
+    if (!P->wire_direct[p] && (rc = ensure_rtil<T>(P, p))) return rc;
   }
   return WCT_OK;
 }
@@ -617,6 +646,7 @@ int run_tune(wct_plan* P, int n_events, const char* cache_path, void* ws, hipStr
         }
         if (rc) break;
         appended += key + " -> " + variant_text(best) + "\n";
+        cache[key] = variant_text(best);  // planes of the same geometry take the same choice
       }
       // with the direct sums chosen, the plane keeps the fastest transform plan timed
       // (or, from the cache, its current one) for a later set_fft of -1 or a variant

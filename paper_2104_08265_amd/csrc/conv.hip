@@ -434,6 +434,7 @@ void conv_init_kernels() {
   raise_lds_limits<float>();
   raise_lds_limits<double>();
   conv_ct_init_kernels();
+  wiredirect_init_kernels();
 }
 
 #define WCT_INST(T)                                                                                            \

@@ -97,6 +97,7 @@ hipError_t launch_colpass(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>
                           const cx<T>* tw, const cx<T>* tw_rev, hipStream_t st);
 // wiredirect.hip: pass B as direct sums over the response's 2K+1 wires (K = 10 only)
 bool colpass_direct_fits(int K);
+void wiredirect_init_kernels();
 template <typename T>
 hipError_t launch_colpass_direct(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtick, cx<T>* mhat,
                                  int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, hipStream_t st);

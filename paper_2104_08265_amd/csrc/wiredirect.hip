@@ -190,6 +190,17 @@ size_t direct_lds() {
 
 bool colpass_direct_fits(int K) { return K == kDirectK; }
 
+// Dynamic LDS above the default 64 KB for the direct kernels (on the current device).
+void wiredirect_init_kernels() {
+  const int lim = 160 * 1024;
+  (void)hipFuncSetAttribute((const void*)k_colpass_direct<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void*)k_colpass_direct<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void*)k_colpass_adj_direct<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lim);
+  (void)hipFuncSetAttribute((const void*)k_colpass_adj_direct<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lim);
+}
+
 template <typename T>
 hipError_t launch_colpass_direct(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtick, cx<T>* mhat,
                                  int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, hipStream_t st) {
@@ -198,12 +209,7 @@ hipError_t launch_colpass_direct(const cx<T>* shat, int64_t shat_ev_stride, cons
   const int64_t nblk = (int64_t)nchunk * n_events * ntile;
   if (nblk <= 0) return hipSuccess;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  const size_t lds = direct_lds<T>();
-  if (lds > 64 * 1024) {
-    static const hipError_t once = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colpass_direct<T>),
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (once != hipSuccess) return once;
-  }
+  const size_t lds = direct_lds<T>();  // FP64: above 64 KB, allowed by wiredirect_init_kernels
   hipLaunchKernelGGL((k_colpass_direct<T>), dim3((unsigned)nblk), dim3(64 * kChunk), lds, st, shat, shat_ev_stride,
                      rtick, mhat, mhat_ev_stride, nw, nphase, nchunk, ntile, n_events);
   return hipGetLastError();

@@ -51,7 +51,9 @@ def test_tune_and_cache(wct, tmp_path):
     say("tune config2 geometry")
     choice = plan.tune(1, cache)
     lines = cache.read_text().strip().splitlines()
-    assert len(lines) == 2 * plan.n_planes
+    # one line per distinct (geometry, kind): planes 0 and 1 share a geometry and a choice
+    assert len(lines) == 2 * 2 and len({ln.split(" -> ")[0] for ln in lines}) == len(lines)
+    assert choice[(0, 0)] == choice[(1, 0)] and choice[(0, 1)] == choice[(1, 1)]
     for (p, k), v in choice.items():
         assert v in plan.fft_candidates(p, k)
     plan2 = make_plan(wct, wl)
