@@ -495,6 +495,7 @@ __global__ void __launch_bounds__(256, 4) k_tile(DepoView<T> d, RasterGeom g, do
                                               int64_t ntiles, int32_t* __restrict__ ctrl,
                                               const DetTables* __restrict__ tables, const double* __restrict__ lf) {
   constexpr int NWAVE = 4;
+  static_assert(TH * TW <= (1 << kDstBits), "tile offsets must fit below the packed electron count");
   __shared__ T tile[TH * TW];
   __shared__ double s_ea[NWAVE][TH + 1];
   __shared__ double s_eb[NWAVE][TW + 1];
