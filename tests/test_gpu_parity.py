@@ -169,6 +169,28 @@ def test_crowded_tile_split(wct):
     assert rel_l2(to_np(plan.grid_view(grid)[0]), ref) < TOL32
 
 
+def test_chopdown_queue_across_rows(wct):
+    """Rows of one raster tile share each wave's chop-down queue; rows of 2^19 electrons or
+    more (their count does not fit beside the tile offset) empty it at their end.  A tile
+    whose rows mix such counts with ordinary ones: the fluctuated grid equals the oracle's
+    bit for bit."""
+    pl = synth.Plane(40, 300, 10, 2, 12)
+    rng = np.random.default_rng(21)
+    n = 80
+    q = np.where(rng.random(n) < 0.25, rng.uniform(6.0e5, 3.0e6, n), rng.lognormal(8.0, 1.0, n))
+    d = synth.Depos(q, rng.uniform(10, 50, n), rng.uniform(2, 10, n), rng.uniform(1.0, 3.0, n),
+                    rng.uniform(0.1, 0.5, n), np.zeros(n, np.int32), np.zeros(n, np.int32),
+                    np.arange(n, dtype=np.int32))
+    wl = synth.Workload("bigN", [pl], [synth.make_response(pl, rng)], synth._finish(d, "f32"), dtype="f32", seed=4)
+    assert np.sum(np.floor(wl.depos.q + 0.5) >= 2 ** 19) >= 10
+    say("tile rows with counts above and below 2^19", n)
+    plan = make_plan(wct, wl)
+    grid = plan.raster(device_depos(wct, wl), wct.opts(3.0, True, 1, 4))
+    reff = OF.raster_fluct(wl.depos, wl.planes, seed=4)[0][0]
+    assert reff.max() < 2 ** 24
+    assert np.array_equal(to_np(plan.grid_view(grid)[0]), reff)
+
+
 def test_delta_response(wct):
     """R = delta(k=0, tau=0) for every phase: the waveform is the sum of each wire's impact rows."""
     import torch
