@@ -141,6 +141,7 @@ struct wct_plan {
   double* d_lfact = nullptr;  // ln(n!), n < kLfactTable, for the chop-down sampler
   std::vector<void*> allocs;
   int64_t grid_elems = 0, wave_elems = 0, shat_elems = 0, mhat_elems = 0;
+  int64_t rows_ev = 0;  // impact rows per event, all planes
   int ntiles_ev = 0;
 
   void* dalloc(size_t bytes, hipError_t* e) {
@@ -176,6 +177,7 @@ RasterGeom raster_geom(const wct_plan* P, int n_events, int event_base) {
   g.event_base = event_base;
   g.ntiles_ev = P->ntiles_ev;
   g.grid_ev_stride = P->grid_elems;
+  g.rows_ev = P->rows_ev;
   for (int p = 0; p < P->n_planes; ++p) g.pl[p] = P->geom[p];
   return g;
 }
@@ -228,7 +230,8 @@ size_t ws_bytes(const wct_plan* P, int op, int n_events, int64_t n_rows) {
     Carver r(nullptr), c(nullptr);
     carve_raster(P, r, n_events, n_rows);
     carve_conv(P, c, n_events);
-    return head + align_up(r.off > c.off ? r.off : c.off, 256);
+    // the row flags go last, so the grid and the transform buffers keep their places
+    return head + align_up(r.off > c.off ? r.off : c.off, 256) + align_up((size_t)n_events * P->rows_ev, 256);
   }
   if (op == WCT_OP_BACKWARD) {
     Carver a(nullptr);
@@ -282,9 +285,11 @@ DepoView<T> view(const wct_depos* d) {
 
 // Launch sequences -------------------------------------------------------------------
 template <typename T>
-int run_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, T* grid, Carver& cv, hipStream_t st) {
+int run_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, T* grid, Carver& cv, hipStream_t st,
+               uint8_t* live = nullptr) {
   const RasterGeom g = raster_geom(P, o->n_events, o->event_base);
-  const RasterWs ws = carve_raster(P, cv, o->n_events, d->n);
+  RasterWs ws = carve_raster(P, cv, o->n_events, d->n);
+  ws.live = live;
   HIP_TRY(launch_raster<T>(view<T>(d), g, o->nsigma, o->fluctuate, o->seed, grid, ws, P->d_tables, P->d_lfact,
                            P->n_cu, st,
                            hook(P)),
@@ -292,8 +297,11 @@ int run_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, T* grid, Carv
   return WCT_OK;
 }
 
+// live (optional): the raster's row flags of these events; the row transform then skips
+// the work (not the zero output) of row pairs no window reached.
 template <typename T>
-int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, hipStream_t st) {
+int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, hipStream_t st,
+                 const uint8_t* live = nullptr) {
   const ConvWs c = carve_conv(P, cv, n_events);
   cx<T>* shat = static_cast<cx<T>*>(c.shat);
   cx<T>* mhat = static_cast<cx<T>*>(c.mhat);
@@ -303,9 +311,10 @@ int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, 
     const cx<T>* post = static_cast<const cx<T>*>(P->post_t[p]);
     const cx<T>* tw_w = static_cast<const cx<T>*>(P->tw_w[p]);
     const cx<T>* tw_wr = static_cast<const cx<T>*>(P->tw_w_rev[p]);
+    const uint8_t* lv = live ? live + G.row_off : nullptr;
     PROF_LAUNCH(P, "rows_r2c", st,
                 launch_rows_r2c<T>(grid + G.grid_off, P->grid_elems, shat + G.shat_off, P->shat_elems, G.nt, G.I,
-                                   G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, P->n_cu, st),
+                                   G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, P->n_cu, st, lv, P->rows_ev),
                 "row transform launch");
     if (P->wire_direct[p])
       PROF_LAUNCH(P, "colpass", st,
@@ -703,7 +712,7 @@ int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
   P->esize = desc->dtype == WCT_F32 ? 4 : 8;
   const int TH = desc->dtype == WCT_F32 ? TileShape<float>::TH : TileShape<double>::TH;
   const int TW = desc->dtype == WCT_F32 ? TileShape<float>::TW : TileShape<double>::TW;
-  int64_t goff = 0, woff = 0, soff = 0, moff = 0, toff = 0;
+  int64_t goff = 0, woff = 0, soff = 0, moff = 0, toff = 0, roff = 0;
   for (int p = 0; p < P->n_planes; ++p) {
     const wct_plane_desc& pd = desc->planes[p];
     if (pd.n_wires < 1 || pd.n_ticks < 1 || pd.n_impacts < 1 || pd.half_wires < 0 || pd.resp_ticks < 1 ||
@@ -734,6 +743,7 @@ int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
     G.shat_off = soff;
     G.mhat_off = moff;
     G.tile_off = toff;
+    G.row_off = roff;
     G.ntr = (G.nb + TH - 1) / TH;
     G.ntc = (G.nt + TW - 1) / TW;
     goff += nbt;
@@ -741,8 +751,10 @@ int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
     soff += (int64_t)G.nchunk * kChunk * G.nb;
     moff += (int64_t)G.nw * G.nchunk * kChunk;
     toff += (int64_t)G.ntr * G.ntc;
+    roff += G.nb;
     P->geom.push_back(G);
   }
+  P->rows_ev = roff;
   P->grid_elems = goff;
   P->wave_elems = woff;
   P->shat_elems = soff;
@@ -879,6 +891,7 @@ int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, v
   Carver head(ws);
   void* grid = head.take(plan->esize * (size_t)batch * plan->grid_elems);
   const size_t rest = align_up(head.off, 256);
+  uint8_t* live = static_cast<uint8_t*>(ws) + need - align_up((size_t)batch * plan->rows_ev, 256);
   // sub-batches of up to max_events events: raster into the workspace grid, then the
   // transform passes write the sub-batch's slots of `wave`
   for (int e0 = 0; e0 < opts->n_events; e0 += batch) {
@@ -888,13 +901,13 @@ int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, v
     Carver cr(static_cast<char*>(ws) + rest), cc(static_cast<char*>(ws) + rest);
     char* w = static_cast<char*>(wave) + plan->esize * (size_t)e0 * plan->wave_elems;
     if (plan->dtype == WCT_F32) {
-      if ((rc = run_raster<float>(plan, depos, &sub, static_cast<float*>(grid), cr, st))) return rc;
+      if ((rc = run_raster<float>(plan, depos, &sub, static_cast<float*>(grid), cr, st, live))) return rc;
       rc = run_convolve<float>(plan, static_cast<const float*>(grid), sub.n_events, reinterpret_cast<float*>(w), cc,
-                               st);
+                               st, live);
     } else {
-      if ((rc = run_raster<double>(plan, depos, &sub, static_cast<double*>(grid), cr, st))) return rc;
+      if ((rc = run_raster<double>(plan, depos, &sub, static_cast<double*>(grid), cr, st, live))) return rc;
       rc = run_convolve<double>(plan, static_cast<const double*>(grid), sub.n_events, reinterpret_cast<double*>(w),
-                                cc, st);
+                                cc, st, live);
     }
     if (rc) return rc;
   }

@@ -74,6 +74,7 @@ struct PlaneGeom {
   int64_t shat_off;   // complex offset within an event's S-hat work array
   int64_t mhat_off;   // complex offset within an event's M-hat work array
   int64_t tile_off;   // raster tile index offset within an event
+  int64_t row_off;    // impact-row offset of the plane within an event (row flags)
   int ntr, ntc;       // raster tiles along rows and ticks
 };
 

@@ -341,10 +341,10 @@ static void for_all_fft(Fn&& fn) {
 template <typename T>
 hipError_t launch_rows_r2c(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt, int nphase,
                            int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
-                           const cx<T>* post, int n_cu, hipStream_t st) {
+                           const cx<T>* post, int n_cu, hipStream_t st, const uint8_t* live, int64_t live_ev) {
   if (plan.variant >= 0)
     return launch_rows_r2c_ct<T>(src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, n_events, plan, tw,
-                                 post, n_cu, st);
+                                 post, n_cu, st, live, live_ev);
   const size_t lds = sizeof(cx<T>) * plan.n;
   const int total = nphase * nper * n_events;
   const hipError_t e = with_fft<T, 0>(plan, [&](auto f, int thr) {
@@ -439,7 +439,8 @@ void conv_init_kernels() {
 
 #define WCT_INST(T)                                                                                            \
   template hipError_t launch_rows_r2c<T>(const T*, int64_t, cx<T>*, int64_t, int, int, int, int, int,          \
-                                         const FftPlan&, const cx<T>*, const cx<T>*, int, hipStream_t);       \
+                                         const FftPlan&, const cx<T>*, const cx<T>*, int, hipStream_t,        \
+                                         const uint8_t*, int64_t);       \
   template hipError_t launch_colpass<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int, int,   \
                                         int, const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);         \
   template hipError_t launch_colpass_adj<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int,    \

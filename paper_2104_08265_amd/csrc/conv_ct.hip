@@ -106,13 +106,14 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_ct(const
 // written together, so each chunk of C frequencies goes out as 2C contiguous values
 // (64 bytes in FP32) instead of two separate C-value pieces.  LDS: the transform buffer
 // plus one staged spectrum.
-template <typename T, int C, typename F>
+template <typename T, int C, typename F, bool FLAGS>
 __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(const T* __restrict__ src,
                                                                   int64_t src_ev_stride, cx<T>* __restrict__ dst,
                                                                   int64_t dst_ev_stride, int nt, int nphase, int nper,
                                                                   int nchunk, int n_events,
                                                                   const cx<T>* __restrict__ tw,
-                                                                  const cx<T>* __restrict__ post) {
+                                                                  const cx<T>* __restrict__ post,
+                                                                  const uint8_t* __restrict__ live, int64_t live_ev) {
   constexpr int M = F::N, NT = F::kThreads, R0 = F::R0;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* z = reinterpret_cast<cx<T>*>(smem_raw);
@@ -166,21 +167,65 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
     }
     return X;
   };
+  // With row flags (FLAGS), a pair whose two rows no window reached is neither loaded nor
+  // transformed: its zero spectrum is written directly.  Each wave reads the flags of its
+  // block's next kSpan pairs at once (lane j: the pair j iterations on) and keeps the
+  // answers as a ballot mask, so the per-pair test is a bit of a scalar register.  kSpan is
+  // the lane count of the block's last wave, which is partial when NT is not a multiple of 64.
+  constexpr int kSpan = NT % 64 == 0 ? 64 : NT % 64;
+  auto pair_live = [&](int Q) {
+    int ev, i, c;
+    row_of(Q, 0, ev, i, c);
+    const uint8_t* f = live + ev * live_ev;
+    return (f[(int64_t)c * nphase + i] | f[(int64_t)(c + 1) * nphase + i]) != 0;
+  };
+  unsigned long long mask = 0;
+  int left = 0;  // unused bits of mask
+  auto live_at = [&](int Q) -> bool {  // called once per iteration, in order; Q: its pair
+    if constexpr (!FLAGS) {
+      return true;
+    } else {
+      if (left == 0) {
+        const int lane = threadIdx.x & 63;
+        const int Ql = Q + lane * (int)gridDim.x;
+        mask = __ballot(lane < kSpan && Ql < pairs && pair_live(Ql));
+        left = kSpan;
+      }
+      const bool b = mask & 1ull;
+      mask >>= 1;
+      --left;
+      return b;
+    }
+  };
   int P = xcd_remap(blockIdx.x, gridDim.x);
-  if (P < pairs) load(P, 0);
+  bool liveP = P < pairs && live_at(P);
+  if (liveP) load(P, 0);
   while (P < pairs) {
     const int Pn = P + gridDim.x;
-    F::template rl<false>(z, tw, in, [&]() { load(P, 1); });
-    for (int k = threadIdx.x; k < fpad; k += NT) stg[k] = post_twiddle(k);
-    __syncthreads();
-    F::template rl<false>(z, tw, in, [&]() {
-      if (Pn < pairs) load(Pn, 0);
-    });
+    const bool liveN = Pn < pairs && live_at(Pn);
     int ev, i, c;
     row_of(P, 0, ev, i, c);
     // chunk q of the pair: [q][i][c .. c + 1][C], 2C contiguous values
     cx<T>* o = dst + ev * dst_ev_stride + ((int64_t)i * nper + c) * C;
     const int64_t cstride = (int64_t)nphase * nper * C;
+    if constexpr (FLAGS) {
+      if (!liveP) {
+        if (liveN) load(Pn, 0);
+        for (int x = threadIdx.x; x < 2 * fpad; x += NT) {
+          const int q = x / (2 * C), e = x - q * (2 * C);
+          o[(int64_t)q * cstride + e] = mk(T(0), T(0));
+        }
+        P = Pn;
+        liveP = liveN;
+        continue;
+      }
+    }
+    F::template rl<false>(z, tw, in, [&]() { load(P, 1); });
+    for (int k = threadIdx.x; k < fpad; k += NT) stg[k] = post_twiddle(k);
+    __syncthreads();
+    F::template rl<false>(z, tw, in, [&]() {
+      if (liveN) load(Pn, 0);
+    });
     for (int x = threadIdx.x; x < 2 * fpad; x += NT) {
       const int q = x / (2 * C), e = x - q * (2 * C);
       const int k = q * C + (e < C ? e : e - C);
@@ -188,6 +233,7 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
     }
     __syncthreads();
     P = Pn;
+    liveP = liveN;
   }
 }
 
@@ -428,7 +474,7 @@ static void for_all_variants(Fn&& fn) {
 template <typename T>
 hipError_t launch_rows_r2c_ct(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt,
                               int nphase, int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
-                              const cx<T>* post, int n_cu, hipStream_t st) {
+                              const cx<T>* post, int n_cu, hipStream_t st, const uint8_t* live, int64_t live_ev) {
   const size_t lds = sizeof(cx<T>) * plan.n;
   const size_t lds_pair = lds + sizeof(cx<T>) * nchunk * kChunk;
   const int total = nphase * nper * n_events;
@@ -436,10 +482,15 @@ hipError_t launch_rows_r2c_ct(const T* src, int64_t src_ev_stride, cx<T>* dst, i
   const bool pair = nper % 2 == 0 && lds_pair <= 160 * 1024;
   const hipError_t e = with_variant<T, 0>(plan.variant, [&](auto f) {
     using F = decltype(f);
-    if (pair)
-      hipLaunchKernelGGL((k_rows_r2c_pair_ct<T, kChunk, F>),
-                         dim3(persistent_blocks(n_cu, lds_pair, F::kThreads, total / 2)), dim3(F::kThreads), lds_pair,
-                         st, src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, n_events, tw, post);
+    const dim3 pgrid(persistent_blocks(n_cu, lds_pair, F::kThreads, total / 2));
+    if (pair && live)
+      hipLaunchKernelGGL((k_rows_r2c_pair_ct<T, kChunk, F, true>), pgrid, dim3(F::kThreads), lds_pair, st, src,
+                         src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, n_events, tw, post, live,
+                         live_ev);
+    else if (pair)
+      hipLaunchKernelGGL((k_rows_r2c_pair_ct<T, kChunk, F, false>), pgrid, dim3(F::kThreads), lds_pair, st, src,
+                         src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, n_events, tw, post, live,
+                         live_ev);
     else
       hipLaunchKernelGGL((k_rows_r2c_ct<T, kChunk, F>), dim3(persistent_blocks(n_cu, lds, F::kThreads, total)),
                          dim3(F::kThreads), lds, st, src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk,
@@ -501,7 +552,9 @@ static void raise_lds_limits_ct() {
     using F = decltype(f);
     (void)hipFuncSetAttribute((const void*)k_rows_r2c_ct<T, kChunk, F>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               lim);
-    (void)hipFuncSetAttribute((const void*)k_rows_r2c_pair_ct<T, kChunk, F>,
+    (void)hipFuncSetAttribute((const void*)k_rows_r2c_pair_ct<T, kChunk, F, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_rows_r2c_pair_ct<T, kChunk, F, false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)k_rows_c2r_ct<T, kChunk, true, F>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
@@ -526,7 +579,8 @@ void conv_ct_init_kernels() {
 
 #define WCT_INST(T)                                                                                              \
   template hipError_t launch_rows_r2c_ct<T>(const T*, int64_t, cx<T>*, int64_t, int, int, int, int, int,         \
-                                            const FftPlan&, const cx<T>*, const cx<T>*, int, hipStream_t);      \
+                                            const FftPlan&, const cx<T>*, const cx<T>*, int, hipStream_t,       \
+                                            const uint8_t*, int64_t);                                           \
   template hipError_t launch_colpass_ct<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int, int,  \
                                            int, const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);        \
   template hipError_t launch_colpass_adj_ct<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int,   \

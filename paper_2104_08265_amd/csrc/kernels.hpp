@@ -23,6 +23,7 @@ struct RasterGeom {
   int event_base;          // rows of events [event_base, event_base + n_events) are used
   int ntiles_ev;           // raster tiles per event
   int64_t grid_ev_stride;  // grid elements per event
+  int64_t rows_ev;         // impact rows per event (all planes)
   PlaneGeom pl[kMaxPlanes];
 };
 
@@ -66,6 +67,7 @@ struct RasterWs {
   int32_t* blocks;    // [2 * nscan_blocks]
   int64_t ntiles;
   int64_t max_items;
+  uint8_t* live = nullptr;  // optional [event][rows_ev]: 1 where some window reaches the row
 };
 
 // Optional kernel timing: begin/end bracket a launch group with events on the stream.
@@ -88,9 +90,13 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 // of those take a second twiddle table for the same radices in reverse order (tw_rev).
 // Rows are read with 16-byte loads (and the next row prefetched) when their length and base allow it.
 template <typename T>
+// live (optional, [event][live_ev] row flags of this plane): the wire-pair kernel
+// neither loads nor transforms a pair of rows no window reached and writes its zero
+// spectrum directly; the other kernels transform every row.
 hipError_t launch_rows_r2c(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt, int nphase,
                            int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
-                           const cx<T>* post, int n_cu, hipStream_t st);
+                           const cx<T>* post, int n_cu, hipStream_t st, const uint8_t* live = nullptr,
+                           int64_t live_ev = 0);
 template <typename T>
 hipError_t launch_colpass(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtil, cx<T>* mhat,
                           int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, const FftPlan& plan,

@@ -300,12 +300,18 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
 // 1. tiles per row ---------------------------------------------------------
 template <typename T, int TH, int TW>
 __global__ void k_count(DepoView<T> d, RasterGeom g, double nsigma, int32_t* __restrict__ counts,
-                        int32_t* __restrict__ big, int32_t* __restrict__ ctrl) {
+                        int32_t* __restrict__ big, int32_t* __restrict__ ctrl, uint8_t* __restrict__ live) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= d.n) return;
   const RowWin w = row_window(d, j, g, nsigma);
   if (!w.ok) return;
   const PlaneGeom& pl = g.pl[w.plane];
+  if (live) {  // the impact rows this window reaches are not empty (most are marked already:
+               // test first, so neighbouring depositions do not contend for the same lines)
+    uint8_t* f = live + (int64_t)w.event * g.rows_ev + pl.row_off;
+    for (int b = w.b0; b < w.b1; ++b)
+      if (!f[b]) f[b] = 1;
+  }
   const int tr0 = w.b0 / TH, tr1 = (w.b1 - 1) / TH, tc0 = w.k0 / TW, tc1 = (w.k1 - 1) / TW;
   if ((tr1 - tr0 + 1) * (tc1 - tc0 + 1) > 4) {
     big[atomicAdd(&ctrl[kCtrlNBig], 1)] = (int32_t)j;
@@ -655,10 +661,14 @@ hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigm
   // control words, counts and cursors are contiguous
   hipError_t e = launch_fill_i32(ws.ctrl, kCtrlWords + 2 * nt, 0, st);
   if (e != hipSuccess) return e;
+  if (ws.live) {
+    e = launch_fill_i32(reinterpret_cast<int32_t*>(ws.live), (g.n_events * g.rows_ev + 3) / 4, 0, st);
+    if (e != hipSuccess) return e;
+  }
   const unsigned rblocks = (unsigned)((d.n + 255) / 256);
   if (d.n > 0) {
     hipLaunchKernelGGL((k_count<T, TH, TW>), dim3(rblocks), dim3(256), 0, st, d, g, nsigma, ws.counts, ws.big,
-                       ws.ctrl);
+                       ws.ctrl, ws.live);
     WCT_CHECK_LAUNCH();
   }
   const int nsb = (int)((nt + kScanPerBlock - 1) / kScanPerBlock);

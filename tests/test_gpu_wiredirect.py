@@ -114,3 +114,37 @@ def test_direct_needs_21_wire_response(wct):
     assert e.value.code == wct.WCT_E_UNSUPPORTED
     assert wct.WCT_WIRE_DIRECT not in plan.fft_candidates(0, 1)
     plan.close()
+
+
+def test_simulate_skips_empty_rows_exactly(wct):
+    """wct_simulate passes the raster's row flags to the row transform, which then writes
+    the zero spectrum of a pair of empty rows without loading or transforming it: a sparse
+    event (most impact rows empty) gives the same waveforms, bit for bit, as wct_raster
+    followed by wct_convolve (every row transformed), for every compiled tick transform
+    (block sizes with and without a partial last wave), and the flags of an earlier, denser
+    call leave nothing behind."""
+    import torch
+    for n_ticks in (1024, 9600):
+        wl = synth.config2(n_depos=60, n_tracks=2, n_ticks=n_ticks, wires=(240, 240, 346), fluctuate=True)
+        plan = make_plan(wct, wl, max_events=2)
+        cands = plan.fft_candidates(0, 0)
+        assert len(cands) > 1  # compiled tick plans (wire-pair kernel)
+        dd = device_depos(wct, wl)
+        o = wct.opts(3.0, True, 1, wl.seed)
+        dense_dd = device_depos(wct, synth.config2(n_depos=3000, n_tracks=8, n_ticks=n_ticks, wires=(240, 240, 346)))
+        for v in cands:
+            for p in range(plan.n_planes):
+                plan.set_fft(p, 0, v)
+            say(f"simulate with row flags vs raster + convolve, sparse event, {n_ticks} ticks, tick plan {v}")
+            dense = plan.simulate(dense_dd, o).clone()
+            w1 = plan.simulate(dd, o).clone()  # after a dense call: rows it reached must not leak in
+            w2 = plan.convolve(plan.raster(dd, o), 1)
+            torch.cuda.synchronize()
+            assert torch.equal(w1, w2), (n_ticks, v)
+            assert not torch.equal(w1, dense)
+        if n_ticks == 1024:
+            ref = OF.raster_fluct(wl.depos, wl.planes, seed=wl.seed)[0]
+            R = [r.astype(np.float64) for r in synth.round_responses(wl)]
+            for k, w in enumerate(plan.wave_view(w1)):
+                assert rel_l2(to_np(w), OC.convolve_fft(ref[k], R[k], wl.planes[k].n_impacts)) < TOL32, k
+        plan.close()
