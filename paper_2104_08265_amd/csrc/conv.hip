@@ -25,14 +25,19 @@ namespace wct {
 // ---------------------------------------------------------------------------
 // Pass A: real rows -> half spectra, column-chunk layout.  Persistent: a workgroup
 // walks rows L = first + k * gridDim.x; the next row is loaded into registers while the
-// current one is transformed, so HBM reads overlap the LDS work.
+// current one is transformed, so HBM reads overlap the LDS work.  With row flags (FLAGS:
+// the raster's mark per impact row, [event][row], row = wire * nphase + phase), a row no
+// deposition window reached is neither loaded nor transformed: its zero spectrum is
+// written directly.  Each wave reads the flags of its block's next rows at once, one per
+// lane, and keeps them as a ballot mask.
 // ---------------------------------------------------------------------------
-template <typename T, int C, typename F>
+template <typename T, int C, typename F, bool FLAGS>
 __global__ void __launch_bounds__(F::kBound) k_rows_r2c(const T* __restrict__ src, int64_t src_ev_stride,
                                                    cx<T>* __restrict__ dst, int64_t dst_ev_stride, int nt,
                                                    int nphase, int nper, int nchunk, int n_events, F f,
                                                    const cx<T>* __restrict__ tw,
-                                                   const cx<T>* __restrict__ post) {
+                                                   const cx<T>* __restrict__ post,
+                                                   const uint8_t* __restrict__ live, int64_t live_ev) {
   using V = typename Vec16<T>::type;
   constexpr int VN = Vec16<T>::n;
   constexpr int PF = (2 * F::E + VN - 1) / VN;  // 16-byte loads per thread: a row has <= 2 E reals per thread
@@ -49,8 +54,35 @@ __global__ void __launch_bounds__(F::kBound) k_rows_r2c(const T* __restrict__ sr
   const bool vec = (nt % VN) == 0 && (reinterpret_cast<uintptr_t>(src) % 16) == 0 && (src_ev_stride % VN) == 0;
   const int ntv = vec ? nt / VN : 0;
   V pre[PF];
+  // lanes of the block's last wave (partial when the block is not a multiple of 64)
+  const int span = blockDim.x % 64 == 0 ? 64 : (int)(blockDim.x % 64);
+  unsigned long long mask = 0;
+  int left = 0;  // unused bits of mask
+  auto live_at = [&](int Q) -> bool {  // called once per iteration, in order; Q: its row
+    if constexpr (!FLAGS) {
+      return true;
+    } else {
+      if (left == 0) {
+        const int lane = threadIdx.x & 63;
+        const int Ql = Q + lane * (int)gridDim.x;
+        bool l = false;
+        if (lane < span && Ql < total) {
+          const int ev = Ql / rows, rin = Ql - (Ql / rows) * rows;
+          const int i = rin / nper, c = rin - (rin / nper) * nper;
+          l = live[ev * live_ev + (int64_t)c * nphase + i] != 0;
+        }
+        mask = __ballot(l);
+        left = span;
+      }
+      const bool b = mask & 1ull;
+      mask >>= 1;
+      --left;
+      return b;
+    }
+  };
   int L = xcd_remap(blockIdx.x, gridDim.x);
-  if (vec && L < total) {
+  bool liveL = L < total && live_at(L);
+  if (vec && liveL) {
     const int ev = L / rows, rin = L - (L / rows) * rows;
     const int i = rin / nper, c = rin - (rin / nper) * nper;
     const V* s = reinterpret_cast<const V*>(src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt);
@@ -60,9 +92,34 @@ __global__ void __launch_bounds__(F::kBound) k_rows_r2c(const T* __restrict__ sr
       pre[q] = s[u < ntv ? u : 0];
     }
   }
+  const int fpad = nchunk * C;
   while (L < total) {
     const int ev = L / rows, rin = L - (L / rows) * rows;
     const int i = rin / nper, c = rin - (rin / nper) * nper;
+    const int Ln = L + gridDim.x;
+    const bool liveN = Ln < total && live_at(Ln);
+    cx<T>* out = dst + ev * dst_ev_stride;
+    if constexpr (FLAGS) {
+      if (!liveL) {
+        if (vec && liveN) {
+          const int evn = Ln / rows, rn = Ln - (Ln / rows) * rows;
+          const int in = rn / nper, cn = rn - (rn / nper) * nper;
+          const V* s = reinterpret_cast<const V*>(src + evn * src_ev_stride + ((int64_t)cn * nphase + in) * nt);
+#pragma unroll
+          for (int q = 0; q < PF; ++q) {
+            const int u = threadIdx.x + q * nthr;
+            pre[q] = s[u < ntv ? u : 0];
+          }
+        }
+        for (int k = threadIdx.x; k < fpad; k += nthr) {
+          const int ch = k / C, cc = k - (k / C) * C;
+          out[(((int64_t)ch * nphase + i) * nper + c) * C + cc] = mk(T(0), T(0));
+        }
+        L = Ln;
+        liveL = liveN;
+        continue;
+      }
+    }
     if (vec) {
 #pragma unroll
       for (int q = 0; q < PF; ++q) {
@@ -75,8 +132,7 @@ __global__ void __launch_bounds__(F::kBound) k_rows_r2c(const T* __restrict__ sr
       for (int u = threadIdx.x; u < 2 * M; u += nthr) zr[u] = u < nt ? s[u] : T(0);
     }
     __syncthreads();
-    const int Ln = L + gridDim.x;
-    if (vec && Ln < total) {  // next row in flight during this row's transform
+    if (vec && liveN) {  // next row in flight during this row's transform
       const int evn = Ln / rows, rn = Ln - (Ln / rows) * rows;
       const int in = rn / nper, cn = rn - (rn / nper) * nper;
       const V* s = reinterpret_cast<const V*>(src + evn * src_ev_stride + ((int64_t)cn * nphase + in) * nt);
@@ -87,8 +143,6 @@ __global__ void __launch_bounds__(F::kBound) k_rows_r2c(const T* __restrict__ sr
       }
     }
     f.template run<false>(z, tw);
-    cx<T>* out = dst + ev * dst_ev_stride;
-    const int fpad = nchunk * C;
     for (int k = threadIdx.x; k < fpad; k += nthr) {
       cx<T> X = mk(T(0), T(0));
       if (k <= M) {
@@ -104,6 +158,7 @@ __global__ void __launch_bounds__(F::kBound) k_rows_r2c(const T* __restrict__ sr
     }
     __syncthreads();
     L = Ln;
+    liveL = liveN;
   }
 }
 
@@ -349,8 +404,13 @@ hipError_t launch_rows_r2c(const T* src, int64_t src_ev_stride, cx<T>* dst, int6
   const int total = nphase * nper * n_events;
   const hipError_t e = with_fft<T, 0>(plan, [&](auto f, int thr) {
     using F = decltype(f);
-    hipLaunchKernelGGL((k_rows_r2c<T, kChunk, F>), dim3(persistent_blocks(n_cu, lds, thr, total)), dim3(thr), lds,
-                       st, src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, n_events, f, tw, post);
+    const dim3 grid(persistent_blocks(n_cu, lds, thr, total));
+    if (live)
+      hipLaunchKernelGGL((k_rows_r2c<T, kChunk, F, true>), grid, dim3(thr), lds, st, src, src_ev_stride, dst,
+                         dst_ev_stride, nt, nphase, nper, nchunk, n_events, f, tw, post, live, live_ev);
+    else
+      hipLaunchKernelGGL((k_rows_r2c<T, kChunk, F, false>), grid, dim3(thr), lds, st, src, src_ev_stride, dst,
+                         dst_ev_stride, nt, nphase, nper, nchunk, n_events, f, tw, post, live, live_ev);
   });
   return e != hipSuccess ? e : hipGetLastError();
 }
@@ -415,7 +475,10 @@ static void raise_lds_limits() {
   const int lim = 160 * 1024;
   for_all_fft<T, 0>([&](auto f) {
     using F = decltype(f);
-    (void)hipFuncSetAttribute((const void*)k_rows_r2c<T, kChunk, F>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_rows_r2c<T, kChunk, F, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lim);
+    (void)hipFuncSetAttribute((const void*)k_rows_r2c<T, kChunk, F, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)k_rows_c2r<T, kChunk, true, F>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)k_rows_c2r<T, kChunk, false, F>,
