@@ -38,7 +38,11 @@ PROFILE_COMMANDS = {
     "write": "rocprofv3 --pmc WRITE_SIZE -f csv -d $R/gpurun_out/pmc_write -o write -- "
              "python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --copy-calibration-mib 1024 "
              "--tune-cache $R/gpurun_out/fft.tune",
+    "trace_showers": "rocprofv3 --kernel-trace --stats -f csv -d $R/gpurun_out/prof_cfg3 -o cfg3 -- "
+                     "python3 $R/bench.py --showers-only --steps 3",
 }
+
+
 def family(kernel_name):
     """Kernel family (the names of the per-kernel table) of a device kernel symbol."""
     n = kernel_name.split("(")[0]
@@ -90,6 +94,19 @@ def summarize(out_dir):
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
     open(os.path.join(PROFILES, "simulate_3plane_1e5_kernel_stats.md"), "w").write("\n".join(lines) + "\n")
+    shower = glob.glob(os.path.join(out_dir, "prof_cfg3", "*kernel_stats.csv"))
+    if shower:
+        rows = list(csv.DictReader(open(shower[0])))
+        lines = ["# Kernel time summary: shower workload (two faces, 1e6 depositions, fluctuation on, FP32)", "",
+                 "Command (from /tmp, R = repository root):", "", "    " + PROFILE_COMMANDS["trace_showers"], "",
+                 "3 timed + 1 warm-up calls of wct_simulate (k_tile: one launch per call), plus plan creation "
+                 "(k_resp_*) and the transform tuner's timing runs (the many short transform launches).", "",
+                 "| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
+        for r in rows[:16]:
+            name = r["Name"].split("(")[0].replace("void ", "")
+            lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                         f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
+        open(os.path.join(PROFILES, "simulate_showers_1e6_kernel_stats.md"), "w").write("\n".join(lines) + "\n")
 
     def counters(tag, counter):
         path = glob.glob(os.path.join(out_dir, f"pmc_{tag}", "*counter_collection.csv"))[0]
@@ -353,6 +370,45 @@ def batch_bench(wct, synth, sub_batch=16, reps=2):
     return out
 
 
+def shower_bench(wct, synth, tune_cache=None, steps=3):
+    """The shower workload (two faces x 800+800+960 wires x 6000 ticks, 1e6 depositions in
+    20 EM-shower-like clusters, fluctuation on, FP32): time per event of wct_simulate, the
+    per-kernel split, and the tile raster on the same lane-operation roofline as the
+    three-plane workload."""
+    import torch
+    wl = synth.config3()
+    plan = wct.Plan(wl.planes, synth.round_responses(wl), dtype="f32")
+    plan.tune(1, tune_cache)
+    dd = wct.DeviceDepos.from_numpy(wl.depos, "cuda:0", torch.float32)
+    o = wct.opts(wl.nsigma, True, 1, wl.seed)
+    wave = plan.new_wave(1)
+    plan.workspace(wct.OP_SIMULATE, 1, dd.n)
+    plan.simulate(dd, o, wave)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.profile_reset()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.simulate(dd, o, wave)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    kt = plan.profile_read()
+    plan.profile(False)
+    plan.close()
+    kernels = {k: tot / steps for k, (tot, _) in sorted(kt.items(), key=lambda kv: -kv[1][0])}
+    t_tile = kernels.get("raster_tile_fluct", 0.0)
+    ops = raster_alu_ops(wl)
+    return {"workload": "2 faces x (800+800+960 wires) x 6000 ticks, 10 impacts/pitch, 1e6 depositions in "
+                        "20 seeded showers, binomial fluctuation on, FP32",
+            "ms_per_event": ms, "depos_per_s": wl.n_depos / (ms * 1e-3),
+            "t_raster_ms": sum(v for k, v in kernels.items() if k.startswith("raster")),
+            "t_conv_ms": sum(v for k, v in kernels.items() if k in ("rows_r2c", "colpass", "rows_c2r")),
+            "kernels_ms": kernels,
+            "tile_raster_alu_frac": ops / (t_tile * 1e-3) / 1e12 / ALU_PEAK_TOPS if t_tile > 0 else None}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -360,6 +416,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward-ratio and batching measurements")
+    ap.add_argument("--showers-only", action="store_true",
+                    help="time only the shower workload (two faces, 1e6 depositions) and print its JSON")
     ap.add_argument("--summarize", metavar="DIR", help="write profiles/ summaries from rocprofv3 output in DIR")
     ap.add_argument("--tune-cache", metavar="FILE", help="transform-variant choices: read from / appended to FILE")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -377,6 +435,9 @@ def main():
     import torch
     from paper_2104_08265_amd import synth, wct
 
+    if args.showers_only:
+        print(json.dumps(shower_bench(wct, synth, args.tune_cache, steps=args.steps)), flush=True)
+        return
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda:0")
@@ -483,6 +544,7 @@ def main():
     if not args.no_extras:
         out["fwd_bwd"] = fwd_bwd_ratio(wct, synth)
         out["batch"] = batch_bench(wct, synth)
+        out["showers"] = shower_bench(wct, synth, args.tune_cache)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl)
         cb["cores_available"] = os.cpu_count()
