@@ -189,9 +189,9 @@ RasterWs carve_raster(const wct_plan* P, Carver& cv, int n_events, int64_t n_row
   const int64_t nrow = n_rows > 0 ? n_rows : 1;
   w.max_items = w.ntiles + (4 * nrow + kRowsPerItem - 1) / kRowsPerItem + 1;
   const int64_t nsb = (w.ntiles + kScanPerBlock - 1) / kScanPerBlock;
-  w.ctrl = static_cast<int32_t*>(cv.take(sizeof(int32_t) * (kCtrlWords + 2 * w.ntiles)));
+  w.ctrl = static_cast<int32_t*>(cv.take(sizeof(int32_t) * (kCtrlWords + w.ntiles)));
   w.counts = w.ctrl ? w.ctrl + kCtrlWords : nullptr;
-  w.cursor = w.counts ? w.counts + w.ntiles : nullptr;
+  w.rank = static_cast<int32_t*>(cv.take(sizeof(int32_t) * 4 * nrow));
   w.offs = static_cast<int32_t*>(cv.take(sizeof(int32_t) * (w.ntiles + 1)));
   w.item_off = static_cast<int32_t*>(cv.take(sizeof(int32_t) * (w.ntiles + 1)));
   w.items = static_cast<int32_t*>(cv.take(sizeof(int32_t) * w.max_items));

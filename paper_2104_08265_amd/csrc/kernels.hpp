@@ -58,7 +58,7 @@ struct TileShape<double> {
 struct RasterWs {
   int32_t* ctrl;      // kCtrlWords
   int32_t* counts;    // [ntiles]
-  int32_t* cursor;    // [ntiles]
+  int32_t* rank;      // [4 n]: a row's slot in the row list of each tile it touches
   int32_t* offs;      // [ntiles + 1]
   int32_t* item_off;  // [ntiles + 1]
   int32_t* items;     // [max_items]

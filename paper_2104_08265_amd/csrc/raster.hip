@@ -298,9 +298,13 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
 }
 
 // 1. tiles per row ---------------------------------------------------------
+// The counter's value before a row's increment is that row's slot in the tile's row list,
+// kept in rank[4 j + n] (n-th tile of row j, rows of tiles outer): the list fill then
+// needs no second pass of atomics.
 template <typename T, int TH, int TW>
 __global__ void k_count(DepoView<T> d, RasterGeom g, double nsigma, int32_t* __restrict__ counts,
-                        int32_t* __restrict__ big, int32_t* __restrict__ ctrl, uint8_t* __restrict__ live) {
+                        int32_t* __restrict__ rank, int32_t* __restrict__ big, int32_t* __restrict__ ctrl,
+                        uint8_t* __restrict__ live) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= d.n) return;
   const RowWin w = row_window(d, j, g, nsigma);
@@ -318,8 +322,9 @@ __global__ void k_count(DepoView<T> d, RasterGeom g, double nsigma, int32_t* __r
     return;
   }
   const int64_t base = (int64_t)w.event * g.ntiles_ev + pl.tile_off;
+  int n = 0;
   for (int tr = tr0; tr <= tr1; ++tr)
-    for (int tc = tc0; tc <= tc1; ++tc) atomicAdd(&counts[base + (int64_t)tr * pl.ntc + tc], 1);
+    for (int tc = tc0; tc <= tc1; ++tc) rank[4 * j + n++] = atomicAdd(&counts[base + (int64_t)tr * pl.ntc + tc], 1);
 }
 
 // 2. scan of (rows, items) per tile -------------------------------------------
@@ -430,7 +435,7 @@ __global__ void __launch_bounds__(1024) k_scan_apply(const int32_t* __restrict__
 // 3. rows into tile slices; 4a. item -> tile map; 4b. clear split tiles -------
 template <typename T, int TH, int TW>
 __global__ void k_fill(DepoView<T> d, RasterGeom g, double nsigma, const int32_t* __restrict__ offs,
-                       int32_t* __restrict__ cursor, int32_t* __restrict__ list) {
+                       const int32_t* __restrict__ rank, int32_t* __restrict__ list) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= d.n) return;
   const RowWin w = row_window(d, j, g, nsigma);
@@ -439,10 +444,11 @@ __global__ void k_fill(DepoView<T> d, RasterGeom g, double nsigma, const int32_t
   const int tr0 = w.b0 / TH, tr1 = (w.b1 - 1) / TH, tc0 = w.k0 / TW, tc1 = (w.k1 - 1) / TW;
   if ((tr1 - tr0 + 1) * (tc1 - tc0 + 1) > 4) return;
   const int64_t base = (int64_t)w.event * g.ntiles_ev + pl.tile_off;
+  int n = 0;
   for (int tr = tr0; tr <= tr1; ++tr)
     for (int tc = tc0; tc <= tc1; ++tc) {
       const int64_t t = base + (int64_t)tr * pl.ntc + tc;
-      list[offs[t] + atomicAdd(&cursor[t], 1)] = (int32_t)j;
+      list[offs[t] + rank[4 * j + n++]] = (int32_t)j;
     }
 }
 
@@ -658,8 +664,8 @@ hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigm
   constexpr int TH = TileShape<T>::TH, TW = TileShape<T>::TW;
   const int64_t nt = ws.ntiles;
   if (prof) prof->begin("raster_bin", st);
-  // control words, counts and cursors are contiguous
-  hipError_t e = launch_fill_i32(ws.ctrl, kCtrlWords + 2 * nt, 0, st);
+  // control words and counts are contiguous
+  hipError_t e = launch_fill_i32(ws.ctrl, kCtrlWords + nt, 0, st);
   if (e != hipSuccess) return e;
   if (ws.live) {
     e = launch_fill_i32(reinterpret_cast<int32_t*>(ws.live), (g.n_events * g.rows_ev + 3) / 4, 0, st);
@@ -667,8 +673,8 @@ hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigm
   }
   const unsigned rblocks = (unsigned)((d.n + 255) / 256);
   if (d.n > 0) {
-    hipLaunchKernelGGL((k_count<T, TH, TW>), dim3(rblocks), dim3(256), 0, st, d, g, nsigma, ws.counts, ws.big,
-                       ws.ctrl, ws.live);
+    hipLaunchKernelGGL((k_count<T, TH, TW>), dim3(rblocks), dim3(256), 0, st, d, g, nsigma, ws.counts, ws.rank,
+                       ws.big, ws.ctrl, ws.live);
     WCT_CHECK_LAUNCH();
   }
   const int nsb = (int)((nt + kScanPerBlock - 1) / kScanPerBlock);
@@ -680,7 +686,7 @@ hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigm
   hipLaunchKernelGGL(k_scan_apply, dim3(nsb), dim3(1024), 0, st, ws.counts, nt, blocks, ws.offs, ws.item_off);
   WCT_CHECK_LAUNCH();
   if (d.n > 0) {
-    hipLaunchKernelGGL((k_fill<T, TH, TW>), dim3(rblocks), dim3(256), 0, st, d, g, nsigma, ws.offs, ws.cursor,
+    hipLaunchKernelGGL((k_fill<T, TH, TW>), dim3(rblocks), dim3(256), 0, st, d, g, nsigma, ws.offs, ws.rank,
                        ws.list);
     WCT_CHECK_LAUNCH();
   }
