@@ -298,7 +298,7 @@ int run_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, T* grid, Carv
 }
 
 // live (optional): the raster's row flags of these events; the row transform then skips
-// the work (not the zero output) of row pairs no window reached.
+// the work (not the zero output) of rows, or row pairs, that no window reached.
 template <typename T>
 int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, hipStream_t st,
                  const uint8_t* live = nullptr) {

@@ -4,16 +4,19 @@
 //
 // Scatter adding goes through LDS-privatised tiles of TH x TW cells:
 //  1. k_count    - each row counts the tiles its window overlaps (<= 4; wider rows go
-//                  to a separate list handled in 64 x 64 chunks with global atomics, k_big);
+//                  to a separate list handled in 64 x 64 chunks with global atomics, k_big)
+//                  and keeps the value each increment returns, its slot in that tile's
+//                  row list; optionally it marks the impact rows its window reaches;
 //  2. scan       - exclusive prefix sums give each tile its slice of a row list and
-//                  a number of work items (ceil(rows / kRowsPerItem), at least 1);
-//  3. k_fill     - rows are written into their tiles' slices;
-//  4. k_tile     - a persistent kernel pops work items from an atomic queue; a work
-//                  item accumulates its rows' in-tile sub-patches with LDS atomics and
-//                  then writes the tile: plain stores when the tile has one item (the
-//                  tile is owned, so empty tiles write zeros and the grid needs no
-//                  clearing), global atomic adds when a crowded tile was split across
-//                  items (those tiles are cleared first by k_zero_split).
+//                  a number of work items (ceil(rows / kRowsPerItem); 0 for an empty tile);
+//  3. k_fill     - rows are written into their tiles' slices at their slots (plain stores);
+//  4. k_tile     - a persistent kernel takes, in step, a work item and a group of
+//                  kZeroGroup consecutive tiles from two atomic queues; a work item
+//                  accumulates its rows' in-tile sub-patches with LDS atomics and then
+//                  writes the tile: plain stores when the tile has one item, global atomic
+//                  adds when a crowded tile was split across items (those tiles are cleared
+//                  first by k_zero_split); a group's tiles that no row touches are cleared
+//                  with plain stores, so the grid needs no separate clearing.
 // Window bounds are formed in FP64 exactly as the oracle forms them, so both sides
 // agree on which cells a row touches; fluctuated counts use the deterministic
 // Philox + binomial chain of fluct.hpp (this file is compiled with contraction off).
