@@ -301,33 +301,70 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
 }
 
 // 1. tiles per row ---------------------------------------------------------
-// The counter's value before a row's increment is that row's slot in the tile's row list,
-// kept in rank[4 j + n] (n-th tile of row j, rows of tiles outer): the list fill then
-// needs no second pass of atomics.
+// A row's slot in a tile's row list is the tile counter's value before its increment,
+// kept in rank[4 j + n] (n-th tile of row j, rows of tiles outer), so the list fill
+// needs no second pass of atomics.  The block first counts its rows per tile in an LDS
+// table (open addressing: 2048 slots for at most 4 x 256 tiles, so every probe sequence
+// ends at a free or matching slot) and then makes one global atomic add per distinct
+// tile: rows of a shower or a track that share tiles no longer queue on one counter.
+constexpr int kCountBlock = 256;
+constexpr int kCountSlots = 2048;
 template <typename T, int TH, int TW>
-__global__ void k_count(DepoView<T> d, RasterGeom g, double nsigma, int32_t* __restrict__ counts,
-                        int32_t* __restrict__ rank, int32_t* __restrict__ big, int32_t* __restrict__ ctrl,
-                        uint8_t* __restrict__ live) {
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j >= d.n) return;
-  const RowWin w = row_window(d, j, g, nsigma);
-  if (!w.ok) return;
-  const PlaneGeom& pl = g.pl[w.plane];
-  if (live) {  // the impact rows this window reaches are not empty (most are marked already:
-               // test first, so neighbouring depositions do not contend for the same lines)
-    uint8_t* f = live + (int64_t)w.event * g.rows_ev + pl.row_off;
-    for (int b = w.b0; b < w.b1; ++b)
-      if (!f[b]) f[b] = 1;
+__global__ void __launch_bounds__(kCountBlock) k_count(DepoView<T> d, RasterGeom g, double nsigma,
+                                                       int32_t* __restrict__ counts, int32_t* __restrict__ rank,
+                                                       int32_t* __restrict__ big, int32_t* __restrict__ ctrl,
+                                                       uint8_t* __restrict__ live) {
+  static_assert(kCountSlots > 4 * kCountBlock && (kCountSlots & (kCountSlots - 1)) == 0, "count table size");
+  __shared__ int32_t s_key[kCountSlots];  // tile index, -1 = free
+  __shared__ int32_t s_cnt[kCountSlots];  // rows of this block in the tile, then their first slot
+  __shared__ int32_t s_pack[4 * kCountBlock];  // per (thread, n): table slot | (rank in the block) << 11
+  for (int e = threadIdx.x; e < kCountSlots; e += kCountBlock) {
+    s_key[e] = -1;
+    s_cnt[e] = 0;
   }
-  const int tr0 = w.b0 / TH, tr1 = (w.b1 - 1) / TH, tc0 = w.k0 / TW, tc1 = (w.k1 - 1) / TW;
-  if ((tr1 - tr0 + 1) * (tc1 - tc0 + 1) > 4) {
-    big[atomicAdd(&ctrl[kCtrlNBig], 1)] = (int32_t)j;
-    return;
+  __syncthreads();
+  const int64_t j = blockIdx.x * (int64_t)kCountBlock + threadIdx.x;
+  int nt = 0;
+  if (j < d.n) {
+    const RowWin w = row_window(d, j, g, nsigma);
+    if (w.ok) {
+      const PlaneGeom& pl = g.pl[w.plane];
+      if (live) {  // the impact rows this window reaches are not empty (most are marked
+                   // already: test first, so neighbouring depositions do not contend)
+        uint8_t* f = live + (int64_t)w.event * g.rows_ev + pl.row_off;
+        for (int b = w.b0; b < w.b1; ++b)
+          if (!f[b]) f[b] = 1;
+      }
+      const int tr0 = w.b0 / TH, tr1 = (w.b1 - 1) / TH, tc0 = w.k0 / TW, tc1 = (w.k1 - 1) / TW;
+      if ((tr1 - tr0 + 1) * (tc1 - tc0 + 1) > 4) {
+        big[atomicAdd(&ctrl[kCtrlNBig], 1)] = (int32_t)j;
+      } else {
+        const int64_t base = (int64_t)w.event * g.ntiles_ev + pl.tile_off;
+        for (int tr = tr0; tr <= tr1; ++tr)
+          for (int tc = tc0; tc <= tc1; ++tc) {
+            const int32_t key = (int32_t)(base + (int64_t)tr * pl.ntc + tc);
+            uint32_t h = ((uint32_t)key * 2654435761u) >> 21;  // 11 bits
+            for (int probe = 0; probe < kCountSlots; ++probe) {
+              const int32_t old = atomicCAS(&s_key[h], -1, key);
+              if (old == -1 || old == key) break;
+              h = (h + 1) & (kCountSlots - 1);
+            }
+            const int loc = atomicAdd(&s_cnt[h], 1);
+            s_pack[4 * threadIdx.x + nt++] = (int32_t)h | (loc << 11);
+          }
+      }
+    }
   }
-  const int64_t base = (int64_t)w.event * g.ntiles_ev + pl.tile_off;
-  int n = 0;
-  for (int tr = tr0; tr <= tr1; ++tr)
-    for (int tc = tc0; tc <= tc1; ++tc) rank[4 * j + n++] = atomicAdd(&counts[base + (int64_t)tr * pl.ntc + tc], 1);
+  __syncthreads();
+  for (int e = threadIdx.x; e < kCountSlots; e += kCountBlock) {
+    const int c = s_cnt[e];
+    if (c > 0) s_cnt[e] = atomicAdd(&counts[s_key[e]], c);
+  }
+  __syncthreads();
+  for (int n = 0; n < nt; ++n) {
+    const int32_t pk = s_pack[4 * threadIdx.x + n];
+    rank[4 * j + n] = s_cnt[pk & (kCountSlots - 1)] + (pk >> 11);
+  }
 }
 
 // 2. scan of (rows, items) per tile -------------------------------------------
@@ -666,6 +703,7 @@ hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigm
                          hipStream_t st, ProfHook* prof) {
   constexpr int TH = TileShape<T>::TH, TW = TileShape<T>::TW;
   const int64_t nt = ws.ntiles;
+  if (nt >= INT32_MAX) return hipErrorInvalidValue;  // tile indices and list offsets are int32
   if (prof) prof->begin("raster_bin", st);
   // control words and counts are contiguous
   hipError_t e = launch_fill_i32(ws.ctrl, kCtrlWords + nt, 0, st);
@@ -676,8 +714,8 @@ hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigm
   }
   const unsigned rblocks = (unsigned)((d.n + 255) / 256);
   if (d.n > 0) {
-    hipLaunchKernelGGL((k_count<T, TH, TW>), dim3(rblocks), dim3(256), 0, st, d, g, nsigma, ws.counts, ws.rank,
-                       ws.big, ws.ctrl, ws.live);
+    hipLaunchKernelGGL((k_count<T, TH, TW>), dim3((unsigned)((d.n + kCountBlock - 1) / kCountBlock)),
+                       dim3(kCountBlock), 0, st, d, g, nsigma, ws.counts, ws.rank, ws.big, ws.ctrl, ws.live);
     WCT_CHECK_LAUNCH();
   }
   const int nsb = (int)((nt + kScanPerBlock - 1) / kScanPerBlock);
