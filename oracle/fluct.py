@@ -14,9 +14,21 @@ It fixes neither the generator nor the sampler.  This module takes the reading:
   cells (b, 2m) and (b, 2m+1) share the block with counter
   (b*ceil(N_t/2) + m, depo_id, event, plane << 24), the even tick using output words
   0-1 and the odd tick words 2-3 (draw-stream version 2);
-* the variate is mapped to a count by a fixed two-regime sampler (inversion from 0
-  when N*p' < 10, otherwise a chop-down search centred on the mode), where
-  p' = min(p, 1-p).
+* the variate is mapped to a count by a fixed two-regime sampler, where
+  p' = min(p, 1-p), q = 1 - p' and a draw with p > 1/2 is N minus the draw with p':
+  - N = 0 or p <= 0 gives 0, p >= 1 gives N;
+  - inversion from 0 when N*p' < 10: f = q^N by left-to-right square-and-multiply,
+    F = f, k = 0; while u >= F and k < min(N, 128): f = f * (r * (N - k)) * (1/(k+1))
+    with r = p'/q and 1/(k+1) a correctly rounded table entry, k = k + 1, F = F + f.
+    The step cap INVERSION_CAP = 128 is part of the stream: with N*p' < 10 the exact
+    probability of a count >= 128 is below 1e-70, so the cap only decides the rare u
+    that exceed the rounded sum F (which can saturate just below 1), and those return
+    min(N, 128);
+  - otherwise a chop-down search from the mode m = min(floor((N+1) p'), N) with
+    P(m) = exp(ln N! - ln m! - ln (N-m)! + m ln p' + (N-m) ln q), v = u - P(m), then
+    alternately one step below (while the lower side is above 0 and its probability
+    has not underflowed) and one step above, subtracting each new probability from v,
+    returning the first index where v < 0 (m if both sides are exhausted).
 
 Because the sampler is part of the specification, every step uses only IEEE-754
 double +, -, *, / (no fused multiply-add, no library transcendental), in a fixed order,
@@ -37,7 +49,7 @@ import math
 
 import numpy as np
 
-from .raster import rows_touching, window
+from .raster import rows_touching, valid_row, window
 
 # ---------------------------------------------------------------------------
 # Philox4x32-10 (Salmon et al., SC'11): 10 rounds, two 32x32->64 multiplies per round,
@@ -317,8 +329,11 @@ def fluct_patch(q, t, p, sigma_t, sigma_p, plane, event, depo_id, n_impacts, n_r
     """Counts of one depo-plane row: (rows, ticks, n[b, k]) as int64.
 
     box = (b_lo, b_hi, k_lo, k_hi) restricts the evaluation to those cells (same values).
+    An invalid row (``raster.valid_row``) draws nothing.
     """
     q, t, p, st, sp = (float(v) for v in (q, t, p, sigma_t, sigma_p))
+    if not valid_row(q, t, p, st, sp):
+        return np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros((0, 0), np.int64)
     N = electrons(q)
     b_lo, b_hi, k_lo, k_hi = box if box is not None else (0, None, 0, None)
     rows, a = det_axis_probs(n_impacts * p, n_impacts * sp, nsigma, n_rows, b_lo, b_hi)

@@ -24,7 +24,7 @@ import math
 import numpy as np
 from scipy.special import erf
 
-from .raster import window
+from .raster import valid_row, window
 
 SQRT2 = math.sqrt(2.0)
 INV_SQRT_2PI = 1.0 / math.sqrt(2.0 * math.pi)
@@ -51,8 +51,13 @@ def axis_weights_and_derivs(mu, sigma, nsigma, n_bins):
 
 
 def row_gradients(H, q, t, p, sigma_t, sigma_p, n_impacts, nsigma=3.0):
-    """(g_q, g_t, g_p, g_sigma_t, g_sigma_p) of one depo-plane row given H = dL/dS of its plane."""
+    """(g_q, g_t, g_p, g_sigma_t, g_sigma_p) of one depo-plane row given H = dL/dS of its plane.
+
+    An invalid row (``raster.valid_row``) contributes nothing to S, so all five are 0.
+    """
     q, t, p, st, sp = (float(v) for v in (q, t, p, sigma_t, sigma_p))
+    if not valid_row(q, t, p, st, sp):
+        return 0.0, 0.0, 0.0, 0.0, 0.0
     I = n_impacts
     rows, a, da_du, da_dsu = axis_weights_and_derivs(I * p, I * sp, nsigma, H.shape[0])
     ticks, b, db_dt, db_dst = axis_weights_and_derivs(t, st, nsigma, H.shape[1])

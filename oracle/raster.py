@@ -9,7 +9,10 @@ this oracle takes the reading:
   truncated to the rectangle mu +- nsigma*sigma on each axis;
 * each cell receives the Gaussian's integral over the part of the cell inside the
   rectangle: an erf difference per axis, the patch is the outer product;
-* cells outside the grid are dropped (their charge is lost), no normalisation.
+* cells outside the grid are dropped (their charge is lost), no normalisation;
+* a row whose values are not a deposition (Q < 0, sigma_t <= 0, sigma_p <= 0, or any of
+  Q, t, p, sigma_t, sigma_p not finite) contributes nothing: the paper states the method
+  for physical depositions only and is silent on such input (``valid_row``).
 
 Everything is FP64.  Window bounds are formed as ``u = I*p``, ``su = I*sigma_p``,
 ``half = nsigma*su``, ``lo = u - half``, ``hi = u + half`` (same for time without the
@@ -23,6 +26,25 @@ import numpy as np
 from scipy.special import erf
 
 SQRT2 = math.sqrt(2.0)
+
+
+def valid_row(q, t, p, sigma_t, sigma_p) -> bool:
+    """Whether a depo-plane row describes a deposition: Q >= 0, both widths > 0, all finite.
+
+    Rows failing this contribute nothing to the grid (and get zero gradients); the paper
+    is silent on such input, this is the reading taken.
+    """
+    v = [float(x) for x in (q, t, p, sigma_t, sigma_p)]
+    return all(math.isfinite(x) for x in v) and v[0] >= 0.0 and v[3] > 0.0 and v[4] > 0.0
+
+
+def valid_rows(depos) -> np.ndarray:
+    """``valid_row`` element-wise over a Depos structure of arrays."""
+    q, t, p = (np.asarray(a, np.float64) for a in (depos.q, depos.t, depos.p))
+    st, sp = (np.asarray(a, np.float64) for a in (depos.sigma_t, depos.sigma_p))
+    fin = np.isfinite(q) & np.isfinite(t) & np.isfinite(p) & np.isfinite(st) & np.isfinite(sp)
+    with np.errstate(invalid="ignore"):
+        return fin & (q >= 0.0) & (st > 0.0) & (sp > 0.0)
 
 
 def window(mu: float, sigma: float, nsigma: float):
@@ -52,8 +74,10 @@ def axis_weights(mu: float, sigma: float, nsigma: float, n_bins: int):
 
 
 def patch(q, t, p, sigma_t, sigma_p, n_impacts, n_rows, n_ticks, nsigma=3.0):
-    """Mean patch of one depo-plane row: (rows, ticks, Q * A_b * B_k)."""
+    """Mean patch of one depo-plane row: (rows, ticks, Q * A_b * B_k); empty for an invalid row."""
     q, t, p, st, sp = (float(v) for v in (q, t, p, sigma_t, sigma_p))
+    if not valid_row(q, t, p, st, sp):
+        return np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros((0, 0))
     u = n_impacts * p
     su = n_impacts * sp
     rows, a = axis_weights(u, su, nsigma, n_rows)
@@ -80,10 +104,11 @@ def raster(depos, planes, nsigma=3.0, n_events=1):
 def rows_touching(depos, plane_idx, plane, b_lo, b_hi, k_lo, k_hi, nsigma=3.0, event=0):
     """Indices of the depo rows of one plane whose window meets rows [b_lo, b_hi) x ticks [k_lo, k_hi).
 
-    Window bounds are formed element-wise exactly as ``window`` forms them.
+    Window bounds are formed element-wise exactly as ``window`` forms them; invalid rows
+    (``valid_row``) touch nothing.
     """
     I = plane.n_impacts
-    m = (depos.plane == plane_idx) & (depos.event == event)
+    m = (depos.plane == plane_idx) & (depos.event == event) & valid_rows(depos)
     p = depos.p.astype(np.float64)
     sp = depos.sigma_p.astype(np.float64)
     t = depos.t.astype(np.float64)
@@ -91,11 +116,12 @@ def rows_touching(depos, plane_idx, plane, b_lo, b_hi, k_lo, k_hi, nsigma=3.0, e
     u = float(I) * p
     hu = nsigma * (float(I) * sp)
     ht = nsigma * st
-    b0 = np.floor(u - hu)
-    b1 = np.ceil(u + hu)
-    k0 = np.floor(t - ht)
-    k1 = np.ceil(t + ht)
-    m &= (b0 < b_hi) & (b1 > b_lo) & (k0 < k_hi) & (k1 > k_lo)
+    with np.errstate(invalid="ignore"):
+        b0 = np.floor(u - hu)
+        b1 = np.ceil(u + hu)
+        k0 = np.floor(t - ht)
+        k1 = np.ceil(t + ht)
+        m &= (b0 < b_hi) & (b1 > b_lo) & (k0 < k_hi) & (k1 > k_lo)
     return np.nonzero(m)[0]
 
 

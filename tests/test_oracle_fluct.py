@@ -183,3 +183,46 @@ def test_fluct_at_matches_full_raster():
     ticks = rng.integers(0, g.shape[1], 300)
     v = F.raster_fluct_at(wl.depos, 0, wl.planes[0], rows, ticks, seed=77)
     assert np.array_equal(v, g[rows, ticks].astype(np.int64))
+
+
+@pytest.mark.parametrize("N,p,expect", [(1000, 0.0099, 128), (200, 0.049, 128), (129, 0.07, 128),
+                                         (128, 0.07, 128), (127, 0.07, 127)])
+def test_inversion_cap(N, p, expect):
+    """The inversion search stops after min(N, 128) steps.  At the largest uniform,
+    1 - 2^-53, these cases' rounded cumulative sums stay below u for every k, so the
+    draw is the cap itself: 128 when N >= 128, else N.  Mathematically the cap changes
+    nothing else: with N p < 10 the exact probability of 128 or more is below 1e-70."""
+    u = np.nextafter(1.0, 0.0)
+    assert N * p < F.MU_SWITCH and F.INVERSION_CAP == 128
+    assert int(F.binomial(N, np.array([p]), np.array([u]))[0]) == expect
+    # the exact law puts no visible mass at or beyond the cap
+    assert stats.binom.sf(127, N, p) < 1e-70
+    # one ulp below a u that the sum reaches, the same cases draw what the inverse CDF gives
+    for uu in (0.5, 0.999, 1 - 1e-12):
+        k = int(F.binomial(N, np.array([p]), np.array([uu]))[0])
+        assert k == int(stats.binom.ppf(uu, N, p)) or abs(stats.binom.cdf(k, N, p) - uu) < 1e-12
+
+
+def test_invalid_rows_draw_nothing():
+    """Rows that are not depositions (Q < 0, a width <= 0, a non-finite value) add no count:
+    a fluctuated raster with them equals the raster of the valid rows alone, bit for bit."""
+    from paper_2104_08265_amd import synth
+    pl = synth.Plane(12, 200, 10, 2, 12)
+    rng = np.random.default_rng(4)
+    good = [(float(rng.lognormal(7, 1)), float(rng.uniform(10, 190)), float(rng.uniform(1, 11)),
+             float(rng.uniform(0.5, 3)), float(rng.uniform(0.1, 1))) for _ in range(12)]
+    bad = [(-500.0, 50.0, 5.0, 1.0, 0.3), (900.0, 50.0, 5.0, 0.0, 0.3), (900.0, 50.0, 5.0, 1.0, -0.2),
+           (900.0, float("nan"), 5.0, 1.0, 0.3), (float("inf"), 50.0, 5.0, 1.0, 0.3),
+           (900.0, 50.0, 5.0, float("inf"), 0.3)]
+    rows = good + bad
+    a = np.array(rows)
+    n = len(a)
+    d = synth.Depos(a[:, 0], a[:, 1], a[:, 2], a[:, 3], a[:, 4], np.zeros(n, np.int32), np.zeros(n, np.int32),
+                    np.arange(n, dtype=np.int32))
+    assert list(RS.valid_rows(d)) == [True] * len(good) + [False] * len(bad)
+    ref = F.raster_fluct(d.select(np.arange(n) < len(good)), [pl], seed=9)[0][0]
+    got = F.raster_fluct(d, [pl], seed=9)[0][0]
+    assert np.array_equal(got, ref) and ref.sum() > 0
+    cells_b, cells_k = np.nonzero(ref)
+    at = F.raster_fluct_at(d, 0, pl, cells_b[:50], cells_k[:50], seed=9)
+    assert np.array_equal(at, ref[cells_b[:50], cells_k[:50]])

@@ -109,3 +109,11 @@ def test_directional_derivative():
     fd = (vals[0] - vals[1]) / 2.0
     an = float(np.sum(g * v * scale))
     assert abs(fd - an) < 1e-5 * abs(an)
+
+
+def test_invalid_rows_have_zero_gradients():
+    """A row that is not a deposition contributes nothing to S, so its five gradients are 0."""
+    H = np.random.default_rng(1).standard_normal((120, 80))
+    for row in [(-5.0, 40.0, 6.0, 1.0, 0.3), (500.0, 40.0, 6.0, 0.0, 0.3), (500.0, 40.0, 6.0, 1.0, -1.0),
+                (500.0, float("nan"), 6.0, 1.0, 0.3), (float("inf"), 40.0, 6.0, 1.0, 0.3)]:
+        assert GR.row_gradients(H, *row, 10) == (0.0, 0.0, 0.0, 0.0, 0.0)

@@ -97,3 +97,28 @@ def test_raster_at_matches_full_grid():
     ticks = rng.integers(0, g.shape[1], 200)
     v = R.raster_at(wl.depos, 0, wl.planes[0], rows, ticks)
     assert np.allclose(v, g[rows, ticks], rtol=1e-14, atol=1e-12)
+
+
+def test_invalid_rows_contribute_nothing():
+    """Rows that are not depositions (Q < 0, sigma_t or sigma_p <= 0, a non-finite value) add
+    nothing: the grid with them equals the grid of the valid rows alone, exactly, and the
+    sampled evaluation skips them too."""
+    pl = synth.Plane(12, 200, 10, 2, 12)
+    rng = np.random.default_rng(5)
+    good = [(float(rng.lognormal(7, 1)), float(rng.uniform(10, 190)), float(rng.uniform(1, 11)),
+             float(rng.uniform(0.5, 3)), float(rng.uniform(0.1, 1))) for _ in range(10)]
+    bad = [(-500.0, 50.0, 5.0, 1.0, 0.3), (900.0, 50.0, 5.0, 0.0, 0.3), (900.0, 50.0, 5.0, 1.0, 0.0),
+           (900.0, 50.0, 5.0, -1.0, 0.3), (900.0, float("nan"), 5.0, 1.0, 0.3),
+           (900.0, 50.0, float("inf"), 1.0, 0.3), (float("nan"), 50.0, 5.0, 1.0, 0.3)]
+    a = np.array(good + bad)
+    n = len(a)
+    d = synth.Depos(a[:, 0], a[:, 1], a[:, 2], a[:, 3], a[:, 4], np.zeros(n, np.int32), np.zeros(n, np.int32),
+                    np.arange(n, dtype=np.int32))
+    for row in bad:
+        rows, ticks, w = R.patch(*row, 10, pl.n_rows, pl.n_ticks)
+        assert rows.size == 0 and ticks.size == 0 and w.size == 0
+    ref = R.raster(d.select(np.arange(n) < len(good)), [pl])[0][0]
+    got = R.raster(d, [pl])[0][0]
+    assert np.isfinite(got).all() and np.array_equal(got, ref)
+    b, k = np.nonzero(ref)
+    assert np.allclose(R.raster_at(d, 0, pl, b[:40], k[:40]), ref[b[:40], k[:40]], rtol=1e-14, atol=0)
