@@ -93,3 +93,39 @@ def test_batched_geometry_first_events(wct):
             ref = OF.raster_fluct_at(wl.depos, k, pl, rr.ravel(), kk.ravel(), seed=wl.seed, event=1)
             assert np.array_equal(g[b0:b0 + 8, t0:t0 + 8].ravel(), ref.astype(np.float64)), (k, b0, t0)
     plan.close()
+
+
+def test_graph_captured_simulate_replays_bitwise(wct):
+    """wct_simulate captured into a HIP graph (torch.cuda.graph on the binding's stream):
+    every replay, with eager calls and synchronisations between the replays, equals the
+    eager call bit for bit (fluctuated grid, deterministic transforms)."""
+    import torch
+    wl, d = five_events()
+    plan = make_plan(wct, wl, max_events=2)
+    dd = device_depos(wct, wl, d)
+    o = wct.opts(3.0, True, 5, 21)
+    wave = plan.new_wave(5)
+    plan.workspace(wct.OP_SIMULATE, 2, dd.n)  # allocated before the capture
+    plan.simulate(dd, o, wave)
+    torch.cuda.synchronize()
+    eager = wave.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.simulate(dd, o, wave)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    say("graph capture of wct_simulate, 5 events in sub-batches of 2")
+    with torch.cuda.graph(g):
+        plan.simulate(dd, o, wave)
+    for rep in range(4):
+        wave.fill_(-1.0)
+        other = plan.simulate(dd, wct.opts(3.0, True, 1, 99, event_base=rep))  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(wave, eager), rep
+        del other
+    del g
+    plan.close()

@@ -123,3 +123,32 @@ def test_autograd_function(wct):
     direct = plan.simulate_backward(dd, wct.opts(3.0, False, 1, 0), (2 * (wave - tgt)).detach().contiguous())
     for p_, d_ in zip(params, direct):
         assert torch.allclose(p_.grad, d_, rtol=1e-12, atol=1e-12)
+
+
+def test_backward_invalid_rows(wct):
+    """Rows that are not depositions (sigma <= 0, Q < 0, non-finite values) get zero
+    gradients, and the other rows' gradients equal the oracle's (FP64)."""
+    import torch
+    wl, tgt = small_fp64()
+    d = wl.depos.astype(np.float64)
+    bad = np.arange(0, 60, 10)
+    d.sigma_t[bad[0]] = 0.0
+    d.sigma_p[bad[1]] = -0.3
+    d.q[bad[2]] = -100.0
+    d.t[bad[3]] = np.nan
+    d.p[bad[4]] = np.inf
+    d.sigma_p[bad[5]] = np.nan
+    wl2 = synth.Workload(wl.name, wl.planes, wl.responses, d, dtype="f64", seed=wl.seed)
+    assert int(np.sum(~OR.valid_rows(d))) == len(bad)
+    R = synth.round_responses(wl2)[0]
+    target = OC.convolve_fft(OR.raster(tgt, wl2.planes)[0][0], R, 10)
+    G, ref = oracle_loss_grad(wl2, target)
+    assert np.all(ref[bad] == 0.0) and np.all(np.isfinite(ref))
+    say("backward fp64 with invalid rows", len(d))
+    plan = make_plan(wct, wl2)
+    g = plan.simulate_backward(device_depos(wct, wl2), wct.opts(3.0, False, 1, 0),
+                               torch.as_tensor(G.ravel()).to("cuda:0"))
+    for c, name in enumerate(NAMES):
+        got = to_np(g[c])
+        assert np.all(got[bad] == 0.0), name
+        assert rel_l2(got, ref[:, c]) < 1e-10, name

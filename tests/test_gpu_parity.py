@@ -103,6 +103,14 @@ def edge_workload(dtype):
         (20000.0, 150.0, 6.0, 50.0, 5.0),  # wider than 4 raster tiles: the separate wide-row path
         (5000.0, 10.0, 3.0, 0.01, 0.002),  # window inside one cell
         (3.0e5, 40.5, 7.5, 2.0, 0.4),      # heavy: chop-down sampler regime
+        # rows that are not depositions contribute nothing (both sides drop them)
+        (3000.0, 50.0, 4.0, 0.0, 0.5),     # sigma_t = 0
+        (3000.0, 60.0, 4.0, 1.0, -0.5),    # sigma_p < 0
+        (-3000.0, 70.0, 4.0, 1.0, 0.5),    # Q < 0
+        (3000.0, np.nan, 4.0, 1.0, 0.5),   # t not a number
+        (3000.0, 80.0, np.inf, 1.0, 0.5),  # p infinite
+        (np.inf, 90.0, 4.0, 1.0, 0.5),     # Q infinite
+        (3000.0, 100.0, 4.0, np.nan, 0.5), # sigma_t not a number
     ]
     for _ in range(20):
         rows.append((float(rng.lognormal(7, 1)), float(rng.uniform(-3, 303)), float(rng.uniform(-1, 13)),
@@ -119,11 +127,13 @@ def edge_workload(dtype):
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_edge_rows(wct, dtype):
     wl = edge_workload(dtype)
-    say("edge rows", dtype)
+    assert int(np.sum(~OR.valid_rows(wl.depos))) == 7
+    say("edge rows (with invalid rows)", dtype)
     plan = make_plan(wct, wl)
     dd = device_depos(wct, wl)
     grid = plan.raster(dd, wct.opts(3.0, False, 1, wl.seed))
     ref = OR.raster(wl.depos, wl.planes)[0][0]
+    assert np.all(np.isfinite(ref))
     assert rel_l2(to_np(plan.grid_view(grid)[0]), ref) < (TOL64 if dtype == "f64" else TOL32)
     grid = plan.raster(dd, wct.opts(3.0, True, 1, wl.seed))
     reff = OF.raster_fluct(wl.depos, wl.planes, seed=wl.seed)[0][0]

@@ -68,6 +68,8 @@ def test_direct_event_batch(wct):
     ref_plan = make_plan(wct, wl, max_events=3)
     for p in range(plan.n_planes):
         plan.set_fft(p, 1, wct.WCT_WIRE_DIRECT)
+        ref_plan.set_fft(p, 1, -1)  # the runtime wire transform, not the direct sums
+        assert ref_plan.get_fft(p, 1) == -1
     gs = [sparse_grid(plan, 11 + e) for e in range(3)]
     say("direct wire pass, 3 events in one call vs 3 calls")
     batched = plan.convolve(torch.cat(gs), 3).clone()
