@@ -154,6 +154,22 @@ size_t wct_workspace_bytes(const wct_plan* plan, int32_t op, int32_t n_events, i
 int wct_raster(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* grid, void* ws,
                size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): wct_raster without a caller workspace.
+ * The raster's scratch (tile counters, per-tile row lists, work items, the wide-row list)
+ * lives instead in a static device array of WCT_NOALLOC_SCRATCH_BYTES that each device the
+ * library runs on holds from its first plan there until the process ends.  Same grid,
+ * same counts and the same kernels as wct_raster.  The call allocates nothing and does
+ * not synchronise; it needs wct_workspace_bytes(plan, WCT_OP_RASTER, n_events, depos->n)
+ * <= WCT_NOALLOC_SCRATCH_BYTES (about 3.5 million rows on the three-plane 2400/2400/3456 x
+ * 9600 geometry), else it returns WCT_E_WORKSPACE before enqueuing anything.  Every call on
+ * one device shares that device's array (it keeps the last call's contents; the counters
+ * that must start at zero are cleared by a kernel at the start of each call): calls that
+ * may overlap in time on one device (several streams or threads) race, and the caller must
+ * order them. */
+#define WCT_NOALLOC_SCRATCH_BYTES (128u << 20)
+int wct_raster_noalloc(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* grid, void* stream);
+
 /* Convolution by FFT (Eq. 2): wave[event][planes packed][N_w][N_t] = R (*) grid for
  * n_events events.  Row transforms along ticks (real-to-complex, length L_t), column
  * transforms along impact rows per phase (length L_w), the product with the

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -120,6 +121,30 @@ struct Profiler final : ProfHook {
   }
 };
 
+// Scratch of wct_raster_noalloc: the raster's tile counters, row lists and work items
+// for callers that cannot allocate.  Each device holds its own copy from the library's
+// first use on it until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: its device address comes from hipGetSymbolAddress, taken
+// once per device with that device current and kept in g_scratch.
+static_assert(WCT_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
+static __device__ __align__(256) char scratch[WCT_NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch;  // device address of `scratch`, by device ordinal
+
+// The device address of `scratch` on device `dev` (which must be current).
+int scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1, nullptr);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return WCT_OK;
+}
+
 }  // namespace
 
 struct wct_plan {
@@ -139,6 +164,7 @@ struct wct_plan {
   std::vector<int> wire_direct;  // wire pass (forward and adjoint) as direct sums, else fp_w
   DetTables* d_tables = nullptr;
   double* d_lfact = nullptr;  // ln(n!), n < kLfactTable, for the chop-down sampler
+  void* scratch = nullptr;    // this device's static scratch (wct_raster_noalloc)
   std::vector<void*> allocs;
   int64_t grid_elems = 0, wave_elems = 0, shat_elems = 0, mhat_elems = 0;
   int64_t rows_ev = 0;  // impact rows per event, all planes
@@ -774,7 +800,12 @@ int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device) == hipSuccess && ncu > 0)
     P->n_cu = ncu;
   conv_init_kernels();
-  int rc = P->dtype == WCT_F32 ? plan_tables<float>(P, desc) : plan_tables<double>(P, desc);
+  int rc = scratch_address(P->device, &P->scratch);
+  if (rc) {
+    delete P;
+    return rc;
+  }
+  rc = P->dtype == WCT_F32 ? plan_tables<float>(P, desc) : plan_tables<double>(P, desc);
   if (rc) {
     delete P;
     return rc;
@@ -850,6 +881,26 @@ int wct_raster(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, voi
   DeviceGuard dg(plan->device);
   if (!dg.ok) return fail(WCT_E_DEVICE, "hipSetDevice(%d) failed", plan->device);
   Carver cv(ws);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return plan->dtype == WCT_F32 ? run_raster<float>(plan, depos, opts, static_cast<float*>(grid), cv, st)
+                                : run_raster<double>(plan, depos, opts, static_cast<double*>(grid), cv, st);
+}
+
+int wct_raster_noalloc(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* grid, void* stream) {
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  int rc = check_opts(plan, opts, true);
+  if (rc) return rc;
+  if ((rc = check_depos(depos))) return rc;
+  if (!grid) return fail(WCT_E_INVALID, "grid is NULL");
+  const size_t need = ws_bytes(plan, WCT_OP_RASTER, opts->n_events, depos->n);
+  if (need > (size_t)WCT_NOALLOC_SCRATCH_BYTES)
+    return fail(WCT_E_WORKSPACE, "wct_raster_noalloc: %lld rows x %d events need %zu bytes of scratch, above its %zu",
+                (long long)depos->n, opts->n_events, need, (size_t)WCT_NOALLOC_SCRATCH_BYTES);
+  if (!plan->scratch) return fail(WCT_E_DEVICE, "wct_raster_noalloc: no scratch address for device %d", plan->device);
+  DeviceGuard dg(plan->device);
+  if (!dg.ok) return fail(WCT_E_DEVICE, "hipSetDevice(%d) failed", plan->device);
+  Carver cv(plan->scratch);  // the kernels get the device address, never `scratch` itself
   hipStream_t st = static_cast<hipStream_t>(stream);
   return plan->dtype == WCT_F32 ? run_raster<float>(plan, depos, opts, static_cast<float*>(grid), cv, st)
                                 : run_raster<double>(plan, depos, opts, static_cast<double*>(grid), cv, st);

@@ -67,6 +67,9 @@ wct_plane_info = _sig("wct_plane_info", c_int32, [PlanP, c_int32, POINTER(c_int6
 wct_workspace_bytes = _sig("wct_workspace_bytes", c_size_t, [PlanP, c_int32, c_int32, c_int64])
 wct_raster = _sig("wct_raster", c_int32, [PlanP, POINTER(wct_depos), POINTER(wct_opts), c_void_p, c_void_p, c_size_t,
                                          c_void_p])
+wct_raster_noalloc = _sig("wct_raster_noalloc", c_int32, [PlanP, POINTER(wct_depos), POINTER(wct_opts), c_void_p,
+                                                         c_void_p])
+NOALLOC_SCRATCH_BYTES = 128 << 20  # WCT_NOALLOC_SCRATCH_BYTES
 wct_convolve = _sig("wct_convolve", c_int32, [PlanP, c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p])
 wct_simulate = _sig("wct_simulate", c_int32, [PlanP, POINTER(wct_depos), POINTER(wct_opts), c_void_p, c_void_p,
                                              c_size_t, c_void_p])
@@ -244,6 +247,13 @@ class Plan:
         d = depos.c()
         check(wct_raster(self.h, ctypes.byref(d), ctypes.byref(o), _ptr(grid), _ptr(ws), nb, self._stream()),
               "wct_raster")
+        return grid
+
+    def raster_noalloc(self, depos: DeviceDepos, o: wct_opts, grid):
+        """wct_raster with the library's static scratch: allocates nothing (grid given)."""
+        d = depos.c()
+        check(wct_raster_noalloc(self.h, ctypes.byref(d), ctypes.byref(o), _ptr(grid), self._stream()),
+              "wct_raster_noalloc")
         return grid
 
     def convolve(self, grid, n_events=1, wave=None):
