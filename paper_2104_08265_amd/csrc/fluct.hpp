@@ -173,47 +173,74 @@ WCT_HD int binom_regime(int64_t N, double p) {
 // least 1 - N p - N 2^-53; the square-and-multiply adds at most 128 roundings (< 2e-14)
 // and mu = N p carries < 2e-15.  Hence u below (1 - mu) - (1e-12 + 2.5e-16 N) implies
 // u < F(0): the search would return 0.
+// The tests are combined without branches (the same comparisons and the same mu).
 WCT_HD int64_t binom_quick(int64_t N, double p, double u) {
-  if (N <= 0 || !(p > 0.0)) return 0;
-  if (p >= 1.0) return N;
-  if (p <= 0.5) {
-    const double mu = (double)N * p;
-    if (mu < kMuSwitch && u < (1.0 - mu) - (1.0e-12 + (double)N * 2.5e-16)) return 0;
+  const double Nf = (double)N;
+  const double mu = Nf * p;  // the zero bound's mean (used where p <= 1/2)
+  const bool none = (N <= 0) | !(p > 0.0);
+  const bool all = p >= 1.0;
+  const bool zero = (p <= 0.5) & (mu < kMuSwitch) & (u < (1.0 - mu) - (1.0e-12 + Nf * 2.5e-16));
+  const int64_t search = -1 - binom_regime(N, p);
+  return none ? 0 : (all ? N : (zero ? 0 : search));
+}
+
+#if defined(WCT_HOST_LOCKSTEP)
+inline thread_local int wct_host_extra_passes = 0;
+#endif
+
+// Whether the predicate holds on any active lane of the wave (on the host: for the one
+// caller).  Loops that end on it have uniform control.
+WCT_HD bool any_lane(bool v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __ballot(v) != 0;
+#else
+#ifdef WCT_HOST_LOCKSTEP
+  // host check of the lockstep property: the caller sets extra passes that a lane takes
+  // after its own search has ended, as it does beside slower lanes of its wave
+  if (wct_host_extra_passes > 0) {
+    --wct_host_extra_passes;
+    return true;
   }
-  return -1 - binom_regime(N, p);
+#endif
+  return v;
+#endif
 }
 
 template <typename Tab>
 WCT_HD int binom_inversion_shared(int N, double pp, double q, double u, const Tab& tb) {
-  // q^N by left-to-right square-and-multiply, walked over the set bits of N (shared, so
-  // the control is scalar): the leading bit gives 1 * 1 * q = q exactly; then each lower
-  // bit squares, and each set one multiplies by q
+  // q^N by left-to-right square-and-multiply: the leading bit of N gives q exactly, then
+  // each lower bit squares, and each set one multiplies by q (N is shared by the lanes, so
+  // the bit tests are scalar)
   double f = q;
-  int b = 31 - __builtin_clz((unsigned)N);
-  for (unsigned rest = (unsigned)N & ~(1u << b); rest != 0;) {
-    const int nb = 31 - __builtin_clz(rest);
-    for (int s = b - nb; s > 0; --s) f = f * f;
-    f = f * q;
-    b = nb;
-    rest &= ~(1u << nb);
+  const int top = 31 - __builtin_clz((unsigned)N);
+#pragma unroll 4
+  for (int i = top - 1; i >= 0; --i) {
+    f = f * f;
+    if ((N >> i) & 1) f = f * q;
   }
-  for (int s = b; s > 0; --s) f = f * f;
-  // F(k) = F(k-1) + f(k), f(k) = f(k-1) * (r (N - k + 1)) / k, while u >= F and k < cap
+  // F(k) = F(k-1) + f(k), f(k) = f(k-1) * (r (N - k + 1)) / k, while u >= F and k < cap.
+  // Every lane takes the shared steps s = 0, 1, ... (the loop ends once no lane has
+  // u >= F, or at the cap) and counts those it takes while u >= F: F never decreases, so
+  // that count is the step at which its own search stops, and each lane's F and f up to
+  // that step are the search's own.  The loop control is then uniform (no per-lane exit),
+  // two steps per pass, and 1/k is a scalar load from the constant table.
   const double r = pp / q;
   double F = f;
   const int cap = N < kInversionCap ? N : (int)kInversionCap;
-  double nk = (double)N;  // N - k
+  double nk = (double)N;  // N - s
   int k = 0;
-  double inv1 = tb.inv[1], inv2 = tb.inv[2];  // 1 / (s + 1), 1 / (s + 2)
-  for (int s = 0; s < cap; ++s) {  // s: steps taken by every lane still searching
-    if (!(u >= F)) break;
-    const double inv_k = inv1;
-    inv1 = inv2;
-    if (s + 3 <= kInversionCap) inv2 = tb.inv[s + 3];
-    f = (f * (r * nk)) * inv_k;
-    k = s + 1;
+  for (int s = 0; s < cap; s += 2) {
+    if (!any_lane(u >= F)) break;
+    k += u >= F ? 1 : 0;
+    f = (f * (r * nk)) * kDet.inv[s + 1];
     F = F + f;
     nk = nk - 1.0;
+    if (s + 1 < cap) {
+      k += u >= F ? 1 : 0;
+      f = (f * (r * nk)) * kDet.inv[s + 2];
+      F = F + f;
+      nk = nk - 1.0;
+    }
   }
   return k;
 }
@@ -231,36 +258,42 @@ WCT_HD int binom_chopdown_shared(int N, double lfN, double pp, double q, double 
   const double x = lfN - lfm - lfnm + (double)m * lp + (double)(N - m) * lq;
   const double pm = det_exp(x);
   double v = u - pm;
-  if (v < 0.0) return m;
   int lo = m, hi = m;
   double plo = pm, phi = pm;
   double dlo = (double)m, dnlo = (double)(N - m + 1);     // lo, N - lo + 1
   double dnhi = (double)(N - m), dhi1 = (double)m + 1.0;  // N - hi, hi + 1
+  // Each pass takes a step below (while the lower side is neither at 0 nor underflowed),
+  // subtracts its probability from v, then a step above under the same rule; the count
+  // is the index at which v first drops below 0 (m if v = u - P(m) already is), or m once
+  // neither side can step.  A side
+  // that cannot step is stepped anyway: at lo = 0 (or hi = N) its factor lo (or N - hi) is
+  // 0, and an underflowed probability stays 0, so the probability added is a zero and v is
+  // unchanged.  A lane whose v is already negative keeps stepping with its count fixed.
+  // So every lane runs the same instructions and the loop ends, for the wave, once no lane
+  // is still searching (uniform control, no per-lane exits).
+  int k = m;
+  bool searching = !(v < 0.0);  // u below P(m): the mode
   for (;;) {
-    bool moved = false;
-    // a step below while the lower side is neither at 0 nor underflowed
-    if (lo > 0 && plo > 0.0) {
-      plo = plo * (dlo * q) / (dnlo * pp);
-      lo -= 1;
-      dlo = dlo - 1.0;
-      dnlo = dnlo + 1.0;
-      v = v - plo;
-      moved = true;
-      if (v < 0.0) return lo;
-    }
-    // then a step above, same rule
-    if (hi < N && phi > 0.0) {
-      phi = phi * (dnhi * pp) / (dhi1 * q);
-      hi += 1;
-      dnhi = dnhi - 1.0;
-      dhi1 = dhi1 + 1.0;
-      v = v - phi;
-      moved = true;
-      if (v < 0.0) return hi;
-    }
-    // both sides exhausted before u was reached: the mode
-    if (!moved) return m;
+    searching = searching & (((lo > 0) & (plo > 0.0)) | ((hi < N) & (phi > 0.0)));
+    if (!any_lane(searching)) break;
+    plo = plo * (dlo * q) / (dnlo * pp);
+    lo -= 1;
+    dlo = dlo - 1.0;
+    dnlo = dnlo + 1.0;
+    v = v - plo;
+    const bool hit_lo = searching & (v < 0.0);
+    k = hit_lo ? lo : k;
+    searching = searching & !hit_lo;
+    phi = phi * (dnhi * pp) / (dhi1 * q);
+    hi += 1;
+    dnhi = dnhi - 1.0;
+    dhi1 = dhi1 + 1.0;
+    v = v - phi;
+    const bool hit_hi = searching & (v < 0.0);
+    k = hit_hi ? hi : k;
+    searching = searching & !hit_hi;
   }
+  return k;
 }
 
 // The search of regime REGIME (binom_regime) for 0 < N < 2^31 and 0 < p < 1; lfN is

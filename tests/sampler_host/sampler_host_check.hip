@@ -4,6 +4,9 @@
 // oracle's.
 // Usage: sampler_host_check binom   stdin lines "N p u" (p, u as C99 hex floats)
 //                                   -> one count per line
+//        sampler_host_check binom_lockstep   the same, each search continuing for
+//                                   (line number mod 9) passes after its own end, as a
+//                                   lane does beside slower lanes of its wave
 //        sampler_host_check philox  stdin lines "c0 c1 c2 c3 k0 k1" (decimal)
 //                                   -> "w0 w1 w2 w3 u_even u_odd" (u as hex floats)
 #include <cstdio>
@@ -25,7 +28,8 @@ int main(int argc, char** argv) {
     }
     return 0;
   }
-  if (std::strcmp(argv[1], "binom") != 0) return 2;
+  const bool lockstep = std::strcmp(argv[1], "binom_lockstep") == 0;
+  if (std::strcmp(argv[1], "binom") != 0 && !lockstep) return 2;
   static const DetTables full = make_det_const();
   DetTablesSmall tb;
   for (int i = 0; i < 129; ++i) tb.inv[i] = full.inv[i];
@@ -36,12 +40,15 @@ int main(int argc, char** argv) {
   long long N;
   double p, u;
   char bp[64], bu[64];
+  long line = 0;
   while (std::scanf("%lld %63s %63s", &N, bp, bu) == 3) {
+    ++line;
     p = std::strtod(bp, nullptr);
     u = std::strtod(bu, nullptr);
     int64_t k = binom_quick(N, p, u);
     if (k < 0) {
       const int n = (int)N;
+      wct_host_extra_passes = lockstep ? (int)(line % 9) : 0;
       const double lfN = lfact_of(n, lf.data(), tb);
       k = k == -1 ? binom_regime_draw<0>(n, lfN, p, u, tb, lf.data()) : binom_regime_draw<1>(n, lfN, p, u, tb, lf.data());
     }

@@ -27,16 +27,17 @@ def checker(tmp_path_factory):
     if not os.path.exists(hipcc):
         pytest.skip("hipcc not available")
     exe = str(tmp_path_factory.mktemp("sampler") / "sampler_host_check")
-    subprocess.run([hipcc, "-std=c++17", "-O2", "-ffp-contract=off", "--offload-arch=gfx950", "-I",
+    subprocess.run([hipcc, "-std=c++17", "-O2", "-ffp-contract=off", "--offload-arch=gfx950", "-DWCT_HOST_LOCKSTEP",
+                    "-I",
                     os.path.join(ROOT, "paper_2104_08265_amd", "csrc"), "-x", "hip",
                     os.path.join(HERE, "sampler_host", "sampler_host_check.hip"), "-o", exe],
                    check=True, capture_output=True)
     return exe
 
 
-def run_binom(exe, N, p, u):
+def run_binom(exe, N, p, u, mode="binom"):
     lines = "".join(f"{int(n)} {float(a).hex()} {float(b).hex()}\n" for n, a, b in zip(N, p, u))
-    out = subprocess.run([exe, "binom"], input=lines, capture_output=True, text=True, check=True).stdout.split()
+    out = subprocess.run([exe, mode], input=lines, capture_output=True, text=True, check=True).stdout.split()
     return np.array([int(v) for v in out], np.int64)
 
 
@@ -108,3 +109,18 @@ def test_philox_words_and_uniforms_equal_oracle(checker):
     got_u = np.array([[float.fromhex(v) for v in r[4:]] for r in got])
     assert np.array_equal(got_w, np.concatenate(ref_w))
     assert np.array_equal(got_u, np.concatenate(ref_u))
+
+
+@pytest.mark.parametrize("seed", [3])
+def test_counts_unchanged_by_lockstep_passes(checker, seed):
+    """On the GPU the searches run with uniform control: a lane whose search has ended keeps
+    taking passes (with its count fixed) while slower lanes of its wave search on.  Here
+    each search continues for up to 8 extra passes after its own end; the counts must still
+    equal the oracle's."""
+    N, p, u = triples(seed, 40000)
+    got = run_binom(checker, N, p, u, mode="binom_lockstep")
+    ref = OF.binomial(N, p, u)
+    bad = np.nonzero(got != ref)[0]
+    assert bad.size == 0, [(int(N[i]), float(p[i]), float(u[i]), int(got[i]), int(ref[i])) for i in bad[:5]]
+    Ne, pe, ue = edge_triples()
+    assert np.array_equal(run_binom(checker, Ne, pe, ue, mode="binom_lockstep"), OF.binomial(Ne, pe, ue))
