@@ -15,6 +15,41 @@
 
 namespace wct {
 
+// A thread's first-pass inputs of the half-length transform of a row of nt reals:
+// complex sample m is (x[2m], x[2m+1]), zero past the row's end.  The choice between
+// 2-vector and element loads is made once for all of them (it is uniform), so the loads
+// of a thread issue back to back with no branch between them; an index past the end reads
+// element 0 and the zero is selected afterwards.
+template <typename F, typename T>
+__device__ __forceinline__ void load_row_inputs(const T* __restrict__ s, int nt, bool v2, cx<T>* in) {
+  constexpr int R0 = F::R0;
+  if (v2) {  // even row length, 8-byte aligned rows
+#pragma unroll
+    for (int q = 0; q < F::MB0; ++q) {
+      if (!F::in_ok(q)) continue;
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int m = F::in_elem(q, r);
+        const bool ok = 2 * m < nt;
+        const cv2<T> p = *reinterpret_cast<const cv2<T>*>(s + (ok ? 2 * m : 0));
+        in[q * R0 + r] = ok ? mk(p.x, p.y) : mk(T(0), T(0));
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < F::MB0; ++q) {
+      if (!F::in_ok(q)) continue;
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int m = F::in_elem(q, r);
+        const bool ok0 = 2 * m < nt, ok1 = 2 * m + 1 < nt;
+        const T a = s[ok0 ? 2 * m : 0], b = s[ok1 ? 2 * m + 1 : 0];
+        in[q * R0 + r] = mk(ok0 ? a : T(0), ok1 ? b : T(0));
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Pass A (compiled plan).  Persistent over rows; the next row's first-pass inputs are
 // requested as soon as the current row's first pass has consumed its registers.
@@ -43,25 +78,7 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_ct(const
   auto load = [&](int L) {
     int ev, i, c;
     row_of(L, ev, i, c);
-    const T* s = src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt;
-#pragma unroll
-    for (int q = 0; q < F::MB0; ++q) {
-      if (!F::in_ok(q)) continue;
-#pragma unroll
-      for (int r = 0; r < R0; ++r) {
-        const int m = F::in_elem(q, r);
-        if (v2) {
-          if (2 * m < nt) {
-            const cv2<T> p = *reinterpret_cast<const cv2<T>*>(s + 2 * m);
-            in[q * R0 + r] = mk(p.x, p.y);
-          } else {
-            in[q * R0 + r] = mk(T(0), T(0));
-          }
-        } else {
-          in[q * R0 + r] = mk(2 * m < nt ? s[2 * m] : T(0), 2 * m + 1 < nt ? s[2 * m + 1] : T(0));
-        }
-      }
-    }
+    load_row_inputs<F>(src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt, nt, v2, in);
   };
   int L = xcd_remap(blockIdx.x, gridDim.x);
   if (L < total) load(L);
@@ -73,12 +90,12 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_ct(const
       if (Ln < total) load(Ln);
     });
     cx<T>* out = dst + ev * dst_ev_stride;
-    const int fpad = nchunk * C;
+    constexpr int fpad = (M + 1 + C - 1) / C * C;  // nchunk * C (checked by the launcher)
     // frequency k goes to [k / C][i][c][k % C]; with NT a multiple of C a thread keeps
     // k % C and advances by NT / C chunks per step
     const int64_t cstride = (int64_t)nphase * nper * C;
     cx<T>* o = out + ((int64_t)i * nper + c) * C;
-    auto post_twiddle = [&](int k) {
+    auto post_twiddle = [&](int k, cx<T> pw) {
       cx<T> X = mk(T(0), T(0));
       if (k <= M) {
         const cx<T> A = z[k == M ? 0 : k];
@@ -86,15 +103,17 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_ct(const
         const cx<T> Ev = scale(A + B, T(0.5));
         const cx<T> D = scale(A - B, T(0.5));
         const cx<T> O = mk(D.y, -D.x);  // (A - B) / (2i)
-        X = Ev + cmul(post[k], O);
+        X = Ev + cmul(pw, O);
       }
       return X;
     };
-    if constexpr (NT % C == 0) {
-      cx<T>* op = o + (int64_t)(threadIdx.x / C) * cstride + threadIdx.x % C;
-      for (int k = threadIdx.x; k < fpad; k += NT, op += (NT / C) * cstride) *op = post_twiddle(k);
-    } else {
-      for (int k = threadIdx.x; k < fpad; k += NT) o[(int64_t)(k / C) * cstride + k % C] = post_twiddle(k);
+    auto post_at = [&](int k) { return k <= M ? post[k] : mk(T(0), T(0)); };
+    cx<T> pw = post_at(threadIdx.x);  // the table entry is loaded a loop trip ahead
+#pragma unroll 1
+    for (int k = threadIdx.x; k < fpad; k += NT) {
+      const cx<T> pn = post_at(k + NT);
+      o[(int64_t)(k / C) * cstride + k % C] = post_twiddle(k, pw);
+      pw = pn;
     }
     __syncthreads();
     L = Ln;
@@ -120,7 +139,9 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
   cx<T>* stg = z + M;  // the pair's first spectrum, [fpad]
   const int rows = nphase * nper;
   const int pairs = rows / 2 * n_events;
-  const int fpad = nchunk * C;
+  // M + 1 frequencies padded to whole chunks (the launcher checks nchunk * C == FPAD)
+  constexpr int FPAD = (M + 1 + C - 1) / C * C;
+  constexpr int fpad = FPAD;
   const bool v2 = (nt % 2) == 0 && (reinterpret_cast<uintptr_t>(src) % (2 * sizeof(T))) == 0 &&
                   (src_ev_stride % 2) == 0;
   cx<T> in[F::IN];
@@ -135,27 +156,10 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
   auto load = [&](int P, int r) {
     int ev, i, c;
     row_of(P, r, ev, i, c);
-    const T* s = src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt;
-#pragma unroll
-    for (int q = 0; q < F::MB0; ++q) {
-      if (!F::in_ok(q)) continue;
-#pragma unroll
-      for (int rr = 0; rr < R0; ++rr) {
-        const int m = F::in_elem(q, rr);
-        if (v2) {
-          if (2 * m < nt) {
-            const cv2<T> p = *reinterpret_cast<const cv2<T>*>(s + 2 * m);
-            in[q * R0 + rr] = mk(p.x, p.y);
-          } else {
-            in[q * R0 + rr] = mk(T(0), T(0));
-          }
-        } else {
-          in[q * R0 + rr] = mk(2 * m < nt ? s[2 * m] : T(0), 2 * m + 1 < nt ? s[2 * m + 1] : T(0));
-        }
-      }
-    }
+    load_row_inputs<F>(src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt, nt, v2, in);
   };
-  auto post_twiddle = [&](int k) {
+  // pw = post[k], loaded by the caller a loop trip ahead (its latency then overlaps a trip)
+  auto post_twiddle = [&](int k, cx<T> pw) {
     cx<T> X = mk(T(0), T(0));
     if (k <= M) {
       const cx<T> A = z[k == M ? 0 : k];
@@ -163,10 +167,11 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
       const cx<T> Ev = scale(A + B, T(0.5));
       const cx<T> D = scale(A - B, T(0.5));
       const cx<T> O = mk(D.y, -D.x);  // (A - B) / (2i)
-      X = Ev + cmul(post[k], O);
+      X = Ev + cmul(pw, O);
     }
     return X;
   };
+  auto post_at = [&](int k) { return k <= M ? post[k] : mk(T(0), T(0)); };
   // With row flags (FLAGS), a pair whose two rows no window reached is neither loaded nor
   // transformed: its zero spectrum is written directly.  Each wave reads the flags of its
   // block's next kSpan pairs at once (lane j: the pair j iterations on) and keeps the
@@ -221,15 +226,34 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
       }
     }
     F::template rl<false>(z, tw, in, [&]() { load(P, 1); });
-    for (int k = threadIdx.x; k < fpad; k += NT) stg[k] = post_twiddle(k);
+    {
+      cx<T> pw = post_at(threadIdx.x);
+#pragma unroll 1
+      for (int k = threadIdx.x; k < FPAD; k += NT) {
+        const cx<T> pn = post_at(k + NT);
+        stg[k] = post_twiddle(k, pw);
+        pw = pn;
+      }
+    }
     __syncthreads();
     F::template rl<false>(z, tw, in, [&]() {
       if (liveN) load(Pn, 0);
     });
-    for (int x = threadIdx.x; x < 2 * fpad; x += NT) {
-      const int q = x / (2 * C), e = x - q * (2 * C);
-      const int k = q * C + (e < C ? e : e - C);
-      o[(int64_t)q * cstride + e] = e < C ? stg[k] : post_twiddle(k);
+    {
+      // entry x of the pair's output: chunk q = x / 2C, position e = x % 2C (e < C: first row)
+      auto k_of = [&](int x) {
+        const int q = x / (2 * C), e = x - q * (2 * C);
+        return q * C + (e < C ? e : e - C);
+      };
+      cx<T> pw = post_at(k_of(threadIdx.x));
+#pragma unroll 1
+      for (int x = threadIdx.x; x < 2 * FPAD; x += NT) {
+        const cx<T> pn = x + NT < 2 * FPAD ? post_at(k_of(x + NT)) : mk(T(0), T(0));
+        const int q = x / (2 * C), e = x - q * (2 * C);
+        const int k = q * C + (e < C ? e : e - C);
+        o[(int64_t)q * cstride + e] = e < C ? stg[k] : post_twiddle(k, pw);
+        pw = pn;
+      }
     }
     __syncthreads();
     P = Pn;
@@ -480,6 +504,7 @@ hipError_t launch_rows_r2c_ct(const T* src, int64_t src_ev_stride, cx<T>* dst, i
   const int total = nphase * nper * n_events;
   // wire pairs when the wires pair up and the staged spectrum fits beside the buffer
   const bool pair = nper % 2 == 0 && lds_pair <= 160 * 1024;
+  if (nchunk * kChunk != (plan.n + 1 + kChunk - 1) / kChunk * kChunk) return hipErrorInvalidValue;
   const hipError_t e = with_variant<T, 0>(plan.variant, [&](auto f) {
     using F = decltype(f);
     const dim3 pgrid(persistent_blocks(n_cu, lds_pair, F::kThreads, total / 2));
