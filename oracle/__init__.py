@@ -18,6 +18,9 @@ Acceleration Solutions for LArTPC Simulation Using Wire-Cell Toolkit"):
                  driven by a counter-based Philox4x32-10 stream (the RNG is factored out
                  of the main loop, Sec. 5) and an exact two-regime binomial sampler
                  that uses IEEE +,-,*,/ only.
+* ``noise``    - Eq. 1's additive noise term N (Sec. 2): stationary noise per wire from
+                 an amplitude spectrum and Philox-keyed complex normals, inverse real
+                 transform along ticks.
 * ``grad``     - adjoint of the convolution and per-deposition gradients of the
                  raster (differentiable mode; a reading beyond the paper, stated in
                  each function).
