@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define WCT_ABI_VERSION 3
+#define WCT_ABI_VERSION 4
 /* Version of the fluctuation draw stream (counter layout + sampler).  Bumped whenever a
  * change would alter any fluctuated count for the same inputs and seed. */
 #define WCT_FLUCT_SPEC_VERSION 2
@@ -113,7 +113,8 @@ typedef struct {
   int32_t n_events;   /* events in this call: 1..max_events (wct_simulate: any >= 1) */
   uint64_t seed;      /* fluctuation key (Philox4x32-10 key words: low, high 32 bits) */
   int32_t event_base; /* first event id of the window, >= 0 */
-  int32_t reserved;   /* must be 0 */
+  int32_t noise;      /* wct_simulate: 1 adds each plane's noise (wct_plan_set_noise) to the
+                         waveforms, 0 none; the other calls ignore it.  0 or 1. */
 } wct_opts;
 
 /* Geometry of a plane as planned: out[0..9] = N_w, N_t, I, K, T_R, L_w, L_t, F,
@@ -169,6 +170,21 @@ int wct_raster(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, voi
  * order them. */
 #define WCT_NOALLOC_SCRATCH_BYTES (128u << 20)
 int wct_raster_noalloc(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* grid, void* stream);
+
+/* Noise (the additive term N of Eq. 1, M = R (*) S + N; Sec. 2 notes it is cheaper to
+ * simulate than the signal).  Sets plane `plane`'s amplitude spectrum: amp (HOST) holds
+ * A[k] >= 0 for the n = F = L_t/2 + 1 frequencies of the plane's tick transform
+ * (wct_plane_info), or is NULL to remove the plane's noise.  With opts.noise = 1,
+ * wct_simulate then adds to every wire w of event e
+ *     n[t] = irfft(A * Z, L_t)[t],  t < N_t,
+ * (irfft: the inverse real transform with the 1/L_t factor) where Z[k] is a complex
+ * normal: the Philox4x32-10 block of counter (k, w, e, plane << 24 | 2^23) under key
+ * `seed` gives u1 = 1 - (53-bit uniform of words 0-1), u2 = (uniform of words 2-3),
+ * r = sqrt(-2 ln u1), theta = 2 pi u2, and Z = r e^{i theta} / sqrt(2), or r cos(theta)
+ * at k = 0 and k = L_t/2.  The noise is added in the frequency domain just before the
+ * inverse row transform (no extra pass over the waveforms); a batch gives each event the
+ * noise it gets alone.  A set-up call: allocates on first use and synchronises. */
+int wct_plan_set_noise(wct_plan* plan, int32_t plane, const double* amp, int64_t n);
 
 /* Convolution by FFT (Eq. 2): wave[event][planes packed][N_w][N_t] = R (*) grid for
  * n_events events.  Row transforms along ticks (real-to-complex, length L_t), column

@@ -52,21 +52,23 @@ def noise_normals(seed, event, plane, wires, ks):
     return r * np.cos(theta), r * np.sin(theta)
 
 
-def noise_spectrum(amp, seed, event, plane, n_wires, L):
-    """X[w][k] = A[k] Z[k] for w < n_wires, k <= L/2 (complex, [n_wires][L/2 + 1])."""
+def noise_spectrum(amp, seed, event, plane, n_wires, L, wires=None):
+    """X[w][k] = A[k] Z[k] for w < n_wires (or the listed wires), k <= L/2 (complex,
+    [wires][L/2 + 1])."""
     F = L // 2 + 1
     amp = np.asarray(amp, np.float64)
     assert amp.shape == (F,), "one amplitude per frequency of the L-point transform"
-    zc, zs = noise_normals(seed, event, plane, np.arange(n_wires)[:, None], np.arange(F)[None, :])
+    w = np.arange(n_wires) if wires is None else np.asarray(wires, np.int64)
+    zc, zs = noise_normals(seed, event, plane, w[:, None], np.arange(F)[None, :])
     Z = (zc + 1j * zs) / np.sqrt(2.0)
     Z[:, 0] = zc[:, 0]
     Z[:, F - 1] = zc[:, F - 1]  # L even: frequency L/2 is real
     return amp[None, :] * Z
 
 
-def noise_waveforms(amp, seed, event, plane, n_wires, n_ticks, L):
-    """Noise of every wire of one plane and event: [n_wires][n_ticks] (FP64)."""
-    X = noise_spectrum(amp, seed, event, plane, n_wires, L)
+def noise_waveforms(amp, seed, event, plane, n_wires, n_ticks, L, wires=None):
+    """Noise of every wire (or the listed wires) of one plane and event: [wires][n_ticks] (FP64)."""
+    X = noise_spectrum(amp, seed, event, plane, n_wires, L, wires)
     return np.fft.irfft(X, n=L, axis=1)[:, :n_ticks]
 
 

@@ -37,6 +37,7 @@ SOURCES = {
     "wiredirect.hip": [],
     "plan.hip": [],
     "grad.hip": [],
+    "probe.cpp": ["-x", "hip"],
 }
 
 

@@ -165,6 +165,7 @@ struct wct_plan {
   DetTables* d_tables = nullptr;
   double* d_lfact = nullptr;  // ln(n!), n < kLfactTable, for the chop-down sampler
   void* scratch = nullptr;    // this device's static scratch (wct_raster_noalloc)
+  std::vector<void*> noise_amp;  // per plane: amplitude spectrum / L_t, [F] in plan dtype (or null)
   std::vector<void*> allocs;
   int64_t grid_elems = 0, wave_elems = 0, shat_elems = 0, mhat_elems = 0;
   int64_t rows_ev = 0;  // impact rows per event, all planes
@@ -277,7 +278,7 @@ int check_opts(const wct_plan* P, const wct_opts* o, bool need_nsigma, bool batc
     return fail(WCT_E_INVALID, "n_events %d outside [1, %d]", o->n_events, P->max_events);
   if (o->event_base < 0 || (int64_t)o->event_base + o->n_events > 0x7fffffffLL)
     return fail(WCT_E_INVALID, "event window [%d, %d + %d) out of range", o->event_base, o->event_base, o->n_events);
-  if (o->reserved != 0) return fail(WCT_E_INVALID, "opts.reserved must be 0");
+  if (o->noise != 0 && o->noise != 1) return fail(WCT_E_INVALID, "noise must be 0 or 1");
   if (need_nsigma && !(o->nsigma > 0.0 && o->nsigma <= 8.0))
     return fail(WCT_E_INVALID, "nsigma %g outside (0, 8]", o->nsigma);
   if (o->fluctuate != 0 && o->fluctuate != 1) return fail(WCT_E_INVALID, "fluctuate must be 0 or 1");
@@ -327,7 +328,7 @@ int run_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, T* grid, Carv
 // the work (not the zero output) of rows, or row pairs, that no window reached.
 template <typename T>
 int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, hipStream_t st,
-                 const uint8_t* live = nullptr) {
+                 const uint8_t* live = nullptr, const wct_opts* noise = nullptr) {
   const ConvWs c = carve_conv(P, cv, n_events);
   cx<T>* shat = static_cast<cx<T>*>(c.shat);
   cx<T>* mhat = static_cast<cx<T>*>(c.mhat);
@@ -353,9 +354,17 @@ int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, 
                                     mhat + G.mhat_off, P->mhat_elems, G.nw, G.I, G.nchunk, n_events, P->fp_w[p], tw_w,
                                     tw_wr, st),
                   "column pass launch");
+    NoiseArgs<T> nz;  // Eq. 1's noise term, added to the half spectra before the inverse
+    if (noise && noise->noise && P->noise_amp[p]) {
+      nz.amp = static_cast<const T*>(P->noise_amp[p]);
+      nz.key0 = (uint32_t)noise->seed;
+      nz.key1 = (uint32_t)(noise->seed >> 32);
+      nz.plane = (uint32_t)p;
+      nz.event_base = noise->event_base;
+    }
     PROF_LAUNCH(P, "rows_c2r", st,
                 launch_rows_c2r<T>(mhat + G.mhat_off, P->mhat_elems, wave + G.wave_off, P->wave_elems, G.nt, false,
-                                   1, G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, st),
+                                   1, G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, st, nz),
                 "inverse row transform launch");
   }
   return WCT_OK;
@@ -780,6 +789,7 @@ int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
     roff += G.nb;
     P->geom.push_back(G);
   }
+  P->noise_amp.assign(P->n_planes, nullptr);
   P->rows_ev = roff;
   P->grid_elems = goff;
   P->wave_elems = woff;
@@ -886,6 +896,47 @@ int wct_raster(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, voi
                                 : run_raster<double>(plan, depos, opts, static_cast<double*>(grid), cv, st);
 }
 
+int wct_plan_set_noise(wct_plan* plan, int32_t plane, const double* amp, int64_t n) {
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  if (plane < 0 || plane >= plan->n_planes) return fail(WCT_E_INVALID, "plane %d of %d", plane, plan->n_planes);
+  const PlaneGeom& G = plan->geom[plane];
+  if (!amp) {  // no noise on this plane (the buffer stays with the plan)
+    if (plan->noise_amp[plane]) {
+      DeviceGuard dg(plan->device);
+      (void)hipDeviceSynchronize();  // queued work may still read it
+    }
+    plan->noise_amp[plane] = nullptr;
+    return WCT_OK;
+  }
+  if (n != G.F) return fail(WCT_E_INVALID, "noise spectrum of %lld values, the plane has %d frequencies", (long long)n, G.F);
+  for (int64_t k = 0; k < n; ++k)
+    if (!(amp[k] >= 0.0) || !std::isfinite(amp[k]))
+      return fail(WCT_E_INVALID, "noise amplitude %lld is negative or not finite", (long long)k);
+  DeviceGuard dg(plan->device);
+  if (!dg.ok) return fail(WCT_E_DEVICE, "hipSetDevice(%d) failed", plan->device);
+  hipError_t e = hipDeviceSynchronize();  // queued work may still read the old values
+  if (e != hipSuccess) return hip_fail(e, "synchronise before the noise upload");
+  void* d = plan->noise_amp[plane];
+  if (!d) {
+    d = plan->dalloc(plan->esize * (size_t)n, &e);
+    if (e != hipSuccess) return fail(WCT_E_NOMEM, "hipMalloc of a noise spectrum failed: %s", hipGetErrorString(e));
+  }
+  // the inverse row transform is unnormalised: store A[k] / L_t
+  if (plan->dtype == WCT_F32) {
+    std::vector<float> v(n);
+    for (int64_t k = 0; k < n; ++k) v[k] = (float)(amp[k] / (double)G.lt);
+    e = hipMemcpy(d, v.data(), sizeof(float) * n, hipMemcpyHostToDevice);
+  } else {
+    std::vector<double> v(n);
+    for (int64_t k = 0; k < n; ++k) v[k] = amp[k] / (double)G.lt;
+    e = hipMemcpy(d, v.data(), sizeof(double) * n, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return hip_fail(e, "noise spectrum upload");
+  plan->noise_amp[plane] = d;
+  return WCT_OK;
+}
+
 int wct_raster_noalloc(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* grid, void* stream) {
   g_err.clear();
   if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
@@ -954,11 +1005,11 @@ int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, v
     if (plan->dtype == WCT_F32) {
       if ((rc = run_raster<float>(plan, depos, &sub, static_cast<float*>(grid), cr, st, live))) return rc;
       rc = run_convolve<float>(plan, static_cast<const float*>(grid), sub.n_events, reinterpret_cast<float*>(w), cc,
-                               st, live);
+                               st, live, &sub);
     } else {
       if ((rc = run_raster<double>(plan, depos, &sub, static_cast<double*>(grid), cr, st, live))) return rc;
       rc = run_convolve<double>(plan, static_cast<const double*>(grid), sub.n_events, reinterpret_cast<double*>(w),
-                                cc, st, live);
+                                cc, st, live, &sub);
     }
     if (rc) return rc;
   }

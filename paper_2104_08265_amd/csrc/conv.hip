@@ -292,12 +292,12 @@ __global__ void __launch_bounds__(F::kBound) k_colpass_adj(const cx<T>* __restri
 // Pass C: half spectra -> real rows.  Input either wire-major rows [w][fpad]
 // (TILED = false) or the column-chunk layout [chunk][phase][c][C] (TILED = true).
 // ---------------------------------------------------------------------------
-template <typename T, int C, bool TILED, typename F>
+template <typename T, int C, bool TILED, typename F, bool NOISE>
 __global__ void __launch_bounds__(F::kBound) k_rows_c2r(const cx<T>* __restrict__ src, int64_t src_ev_stride,
                                                    T* __restrict__ dst, int64_t dst_ev_stride, int nt,
                                                    int nphase, int nper, int nchunk, F f,
                                                    const cx<T>* __restrict__ tw,
-                                                   const cx<T>* __restrict__ post) {
+                                                   const cx<T>* __restrict__ post, NoiseArgs<T> nz) {
   const int nthr = f.nthr();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* z = reinterpret_cast<cx<T>*>(smem_raw);
@@ -310,7 +310,9 @@ __global__ void __launch_bounds__(F::kBound) k_rows_c2r(const cx<T>* __restrict_
   const int fpad = nchunk * C;
   auto X = [&](int k) -> cx<T> {
     if (TILED) return in[(((int64_t)(k / C) * nphase + i) * nper + c) * C + (k % C)];
-    return in[(int64_t)L * fpad + k];
+    cx<T> v = in[(int64_t)L * fpad + k];
+    if constexpr (NOISE) v = v + noise_at(nz, k, M, (uint32_t)L, (uint32_t)(nz.event_base + (int)blockIdx.y));
+    return v;
   };
   for (int k = threadIdx.x; k < M; k += nthr) {
     const cx<T> A = X(k);
@@ -452,20 +454,24 @@ hipError_t launch_colpass_adj(const cx<T>* ghat, int64_t ghat_ev_stride, const c
 template <typename T>
 hipError_t launch_rows_c2r(const cx<T>* src, int64_t src_ev_stride, T* dst, int64_t dst_ev_stride, int nt,
                            bool tiled, int nphase, int nper, int nchunk, int n_events, const FftPlan& plan,
-                           const cx<T>* tw, const cx<T>* post, hipStream_t st) {
+                           const cx<T>* tw, const cx<T>* post, hipStream_t st, const NoiseArgs<T>& nz) {
+  if (tiled && nz.amp) return hipErrorInvalidValue;  // noise belongs to the forward's waveform rows
   if (plan.variant >= 0)
     return launch_rows_c2r_ct<T>(src, src_ev_stride, dst, dst_ev_stride, nt, tiled, nphase, nper, nchunk, n_events,
-                                 plan, tw, post, st);
+                                 plan, tw, post, st, nz);
   const size_t lds = sizeof(cx<T>) * plan.n;
   const dim3 grid(nphase * nper, n_events);
   const hipError_t e = with_fft<T, 0>(plan, [&](auto f, int thr) {
     using F = decltype(f);
     if (tiled)
-      hipLaunchKernelGGL((k_rows_c2r<T, kChunk, true, F>), grid, dim3(thr), lds, st, src, src_ev_stride, dst,
-                         dst_ev_stride, nt, nphase, nper, nchunk, f, tw, post);
+      hipLaunchKernelGGL((k_rows_c2r<T, kChunk, true, F, false>), grid, dim3(thr), lds, st, src, src_ev_stride, dst,
+                         dst_ev_stride, nt, nphase, nper, nchunk, f, tw, post, nz);
+    else if (nz.amp)
+      hipLaunchKernelGGL((k_rows_c2r<T, kChunk, false, F, true>), grid, dim3(thr), lds, st, src, src_ev_stride,
+                         dst, dst_ev_stride, nt, nphase, nper, nchunk, f, tw, post, nz);
     else
-      hipLaunchKernelGGL((k_rows_c2r<T, kChunk, false, F>), grid, dim3(thr), lds, st, src, src_ev_stride, dst,
-                         dst_ev_stride, nt, nphase, nper, nchunk, f, tw, post);
+      hipLaunchKernelGGL((k_rows_c2r<T, kChunk, false, F, false>), grid, dim3(thr), lds, st, src, src_ev_stride,
+                         dst, dst_ev_stride, nt, nphase, nper, nchunk, f, tw, post, nz);
   });
   return e != hipSuccess ? e : hipGetLastError();
 }
@@ -479,9 +485,11 @@ static void raise_lds_limits() {
                               lim);
     (void)hipFuncSetAttribute((const void*)k_rows_r2c<T, kChunk, F, false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)k_rows_c2r<T, kChunk, true, F>,
+    (void)hipFuncSetAttribute((const void*)k_rows_c2r<T, kChunk, true, F, false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)k_rows_c2r<T, kChunk, false, F>,
+    (void)hipFuncSetAttribute((const void*)k_rows_c2r<T, kChunk, false, F, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_rows_c2r<T, kChunk, false, F, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   });
   for_all_fft<T, 1>([&](auto f) {
@@ -509,7 +517,8 @@ void conv_init_kernels() {
   template hipError_t launch_colpass_adj<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int,    \
                                             int, int, const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);\
   template hipError_t launch_rows_c2r<T>(const cx<T>*, int64_t, T*, int64_t, int, bool, int, int, int, int,    \
-                                         const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);
+                                         const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t,              \
+                                         const NoiseArgs<T>&);
 WCT_INST(float)
 WCT_INST(double)
 #undef WCT_INST

@@ -397,12 +397,12 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_colpass_adj_ct(co
 // ---------------------------------------------------------------------------
 // Pass C (compiled plan): pre-twiddled half spectrum -> registers -> real row.
 // ---------------------------------------------------------------------------
-template <typename T, int C, bool TILED, typename F>
+template <typename T, int C, bool TILED, typename F, bool NOISE>
 __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_c2r_ct(const cx<T>* __restrict__ src, int64_t src_ev_stride,
                                                              T* __restrict__ dst, int64_t dst_ev_stride, int nt,
                                                              int nphase, int nper, int nchunk,
                                                              const cx<T>* __restrict__ tw,
-                                                             const cx<T>* __restrict__ post) {
+                                                             const cx<T>* __restrict__ post, NoiseArgs<T> nz) {
   constexpr int M = F::N, R0 = F::R0, RL = F::RL;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* z = reinterpret_cast<cx<T>*>(smem_raw);
@@ -413,7 +413,9 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_c2r_ct(const
   const int fpad = nchunk * C;
   auto X = [&](int k) -> cx<T> {
     if (TILED) return inp[(((int64_t)(k / C) * nphase + i) * nper + c) * C + (k % C)];
-    return inp[(int64_t)L * fpad + k];
+    cx<T> v = inp[(int64_t)L * fpad + k];
+    if constexpr (NOISE) v = v + noise_at(nz, k, M, (uint32_t)L, (uint32_t)(nz.event_base + (int)blockIdx.y));
+    return v;
   };
   cx<T> in[F::IN], out[F::OUT];
 #pragma unroll
@@ -555,17 +557,20 @@ hipError_t launch_colpass_adj_ct(const cx<T>* ghat, int64_t ghat_ev_stride, cons
 template <typename T>
 hipError_t launch_rows_c2r_ct(const cx<T>* src, int64_t src_ev_stride, T* dst, int64_t dst_ev_stride, int nt,
                               bool tiled, int nphase, int nper, int nchunk, int n_events, const FftPlan& plan,
-                              const cx<T>* tw, const cx<T>* post, hipStream_t st) {
+                              const cx<T>* tw, const cx<T>* post, hipStream_t st, const NoiseArgs<T>& nz) {
   const size_t lds = sizeof(cx<T>) * plan.n;
   const dim3 grid(nphase * nper, n_events);
   const hipError_t e = with_variant<T, 0>(plan.variant, [&](auto f) {
     using F = decltype(f);
     if (tiled)
-      hipLaunchKernelGGL((k_rows_c2r_ct<T, kChunk, true, F>), grid, dim3(F::kThreads), lds, st, src, src_ev_stride,
-                         dst, dst_ev_stride, nt, nphase, nper, nchunk, tw, post);
+      hipLaunchKernelGGL((k_rows_c2r_ct<T, kChunk, true, F, false>), grid, dim3(F::kThreads), lds, st, src,
+                         src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, tw, post, nz);
+    else if (nz.amp)
+      hipLaunchKernelGGL((k_rows_c2r_ct<T, kChunk, false, F, true>), grid, dim3(F::kThreads), lds, st, src,
+                         src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, tw, post, nz);
     else
-      hipLaunchKernelGGL((k_rows_c2r_ct<T, kChunk, false, F>), grid, dim3(F::kThreads), lds, st, src,
-                         src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, tw, post);
+      hipLaunchKernelGGL((k_rows_c2r_ct<T, kChunk, false, F, false>), grid, dim3(F::kThreads), lds, st, src,
+                         src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, tw, post, nz);
   });
   return e != hipSuccess ? e : hipGetLastError();
 }
@@ -581,9 +586,11 @@ static void raise_lds_limits_ct() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)k_rows_r2c_pair_ct<T, kChunk, F, false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)k_rows_c2r_ct<T, kChunk, true, F>,
+    (void)hipFuncSetAttribute((const void*)k_rows_c2r_ct<T, kChunk, true, F, false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)k_rows_c2r_ct<T, kChunk, false, F>,
+    (void)hipFuncSetAttribute((const void*)k_rows_c2r_ct<T, kChunk, false, F, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_rows_c2r_ct<T, kChunk, false, F, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   });
   auto wire = [&](auto f) {
@@ -612,7 +619,8 @@ void conv_ct_init_kernels() {
                                                int, int, const FftPlan&, const cx<T>*, const cx<T>*,             \
                                                hipStream_t);                                                     \
   template hipError_t launch_rows_c2r_ct<T>(const cx<T>*, int64_t, T*, int64_t, int, bool, int, int, int, int,   \
-                                            const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);
+                                            const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t,            \
+                                            const NoiseArgs<T>&);
 WCT_INST(float)
 WCT_INST(double)
 #undef WCT_INST

@@ -44,6 +44,26 @@ struct Vec16 {
   typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
 };
 
+// Noise value amp[k] * Z[k] of frequency k (of M + 1) for wire w of `event` (see NoiseArgs):
+// u1 = 1 - (53-bit uniform of words 0-1) in (0, 1], u2 = uniform of words 2-3,
+// r = sqrt(-2 ln u1), theta = 2 pi u2; Z = r e^{i theta} / sqrt(2), or r cos(theta) at
+// k = 0 and k = M.  The transcendental functions run in the plan's precision.
+__device__ __forceinline__ void sincospi_t(float x, float* s, float* c) { sincospif(x, s, c); }
+__device__ __forceinline__ void sincospi_t(double x, double* s, double* c) { sincospi(x, s, c); }
+template <typename T>
+__device__ __forceinline__ cx<T> noise_at(const NoiseArgs<T>& nz, int k, int M, uint32_t wire, uint32_t event) {
+  const Philox4 ph = philox4x32_10((uint32_t)k, wire, event, (nz.plane << 24) | kNoiseStreamBit, nz.key0, nz.key1);
+  const T u1 = (T)(1.0 - uniform53(ph.w0, ph.w1));
+  const T u2 = (T)uniform53(ph.w2, ph.w3);
+  const T r = sqrt(T(-2) * log(u1));
+  T s, c;
+  sincospi_t(T(2) * u2, &s, &c);
+  const T a = nz.amp[k] * r;
+  if (k == 0 || k == M) return mk(a * c, T(0));
+  const T h = a * T(0.70710678118654752);
+  return mk(h * c, h * s);
+}
+
 // Complex value as a clang 2-vector for register arrays (aggregates there can end up in
 // scratch memory).
 template <typename T>
@@ -86,7 +106,7 @@ hipError_t launch_colpass_adj_ct(const cx<T>* ghat, int64_t ghat_ev_stride, cons
 template <typename T>
 hipError_t launch_rows_c2r_ct(const cx<T>* src, int64_t src_ev_stride, T* dst, int64_t dst_ev_stride, int nt,
                               bool tiled, int nphase, int nper, int nchunk, int n_events, const FftPlan& plan,
-                              const cx<T>* tw, const cx<T>* post, hipStream_t st);
+                              const cx<T>* tw, const cx<T>* post, hipStream_t st, const NoiseArgs<T>& nz);
 void conv_ct_init_kernels();
 
 }  // namespace wct

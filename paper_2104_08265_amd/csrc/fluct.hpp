@@ -173,15 +173,18 @@ WCT_HD int binom_regime(int64_t N, double p) {
 // least 1 - N p - N 2^-53; the square-and-multiply adds at most 128 roundings (< 2e-14)
 // and mu = N p carries < 2e-15.  Hence u below (1 - mu) - (1e-12 + 2.5e-16 N) implies
 // u < F(0): the search would return 0.
-// The tests are combined without branches (the same comparisons and the same mu).
-WCT_HD int64_t binom_quick(int64_t N, double p, double u) {
+// The tests are combined without branches (the same comparisons and the same mu).  The
+// kernels call it with 32-bit counts (Int = int), the host checks with int64_t.
+template <typename Int>
+WCT_HD Int binom_quick(Int N, double p, double u) {
   const double Nf = (double)N;
   const double mu = Nf * p;  // the zero bound's mean (used where p <= 1/2)
   const bool none = (N <= 0) | !(p > 0.0);
   const bool all = p >= 1.0;
   const bool zero = (p <= 0.5) & (mu < kMuSwitch) & (u < (1.0 - mu) - (1.0e-12 + Nf * 2.5e-16));
-  const int64_t search = -1 - binom_regime(N, p);
-  return none ? 0 : (all ? N : (zero ? 0 : search));
+  const double pp = p > 0.5 ? 1.0 - p : p;
+  const Int search = Nf * pp < kMuSwitch ? -1 : -2;  // -1 - binom_regime(N, p)
+  return none ? Int(0) : (all ? N : (zero ? Int(0) : search));
 }
 
 #if defined(WCT_HOST_LOCKSTEP)
@@ -229,19 +232,23 @@ WCT_HD int binom_inversion_shared(int N, double pp, double q, double u, const Ta
   const int cap = N < kInversionCap ? N : (int)kInversionCap;
   double nk = (double)N;  // N - s
   int k = 0;
-  for (int s = 0; s < cap; s += 2) {
+  int s = 0;
+  double i1 = kDet.inv[1], i2 = kDet.inv[2];  // 1/(s + 1), 1/(s + 2), loaded a pass ahead
+  for (; s + 2 <= cap; s += 2) {
     if (!any_lane(u >= F)) break;
+    const double n1 = kDet.inv[s + 3], n2 = kDet.inv[s + 4];
     k += u >= F ? 1 : 0;
-    f = (f * (r * nk)) * kDet.inv[s + 1];
+    f = (f * (r * nk)) * i1;
     F = F + f;
     nk = nk - 1.0;
-    if (s + 1 < cap) {
-      k += u >= F ? 1 : 0;
-      f = (f * (r * nk)) * kDet.inv[s + 2];
-      F = F + f;
-      nk = nk - 1.0;
-    }
+    k += u >= F ? 1 : 0;
+    f = (f * (r * nk)) * i2;
+    F = F + f;
+    nk = nk - 1.0;
+    i1 = n1;
+    i2 = n2;
   }
+  if (s < cap) k += u >= F ? 1 : 0;  // an odd cap: one last step (its f is not needed)
   return k;
 }
 

@@ -70,6 +70,21 @@ struct RasterWs {
   uint8_t* live = nullptr;  // optional [event][rows_ev]: 1 where some window reaches the row
 };
 
+// Noise of Eq. 1's N term, added to the half spectra of the inverse row transform (pass
+// C of the forward): frequency k of wire w in event `event_base + slot` receives
+// amp[k] * Z[k], with Z the Box-Muller complex normal of the Philox4x32-10 block of counter
+// (k, w, event, plane << 24 | kNoiseStreamBit) under the run's key (real at k = 0 and
+// k = L_t / 2).  amp holds the plane's amplitude spectrum divided by L_t (the inverse
+// transform is unnormalised), in the plan dtype.
+constexpr uint32_t kNoiseStreamBit = 1u << 23;
+template <typename T>
+struct NoiseArgs {
+  const T* amp = nullptr;  // [L_t / 2 + 1]; nullptr: no noise
+  uint32_t key0 = 0, key1 = 0;
+  uint32_t plane = 0;
+  int event_base = 0;
+};
+
 // Optional kernel timing: begin/end bracket a launch group with events on the stream.
 struct ProfHook {
   virtual void begin(const char* name, hipStream_t st) = 0;
@@ -118,7 +133,8 @@ hipError_t launch_colpass_adj(const cx<T>* ghat, int64_t ghat_ev_stride, const c
 template <typename T>
 hipError_t launch_rows_c2r(const cx<T>* src, int64_t src_ev_stride, T* dst, int64_t dst_ev_stride, int nt,
                            bool tiled, int nphase, int nper, int nchunk, int n_events, const FftPlan& plan,
-                           const cx<T>* tw, const cx<T>* post, hipStream_t st);
+                           const cx<T>* tw, const cx<T>* post, hipStream_t st,
+                           const NoiseArgs<T>& noise = NoiseArgs<T>());
 template <typename T>
 bool conv_fits(int elems);  // a transform of `elems` complex values fits one block
 void conv_init_kernels();

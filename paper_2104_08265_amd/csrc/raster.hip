@@ -216,7 +216,7 @@ __device__ __forceinline__ void rq_run_chop(RegQueue& q, int take, int rowN, boo
 // A cell's outcome of the cheap tests: added at once, queued for its regime, or nothing.
 // `tagN` is what the chop-down entry carries (the row's count, or 0 for `rowN`).
 template <typename T, typename Add>
-__device__ __forceinline__ void cell_route(RegQueue& qi, RegQueue& qc, bool packed, int tagN, int64_t quick,
+__device__ __forceinline__ void cell_route(RegQueue& qi, RegQueue& qc, bool packed, int tagN, int quick,
                                            double p, double u, int N, double lfN, uint32_t dst, int lane,
                                            const DetTablesSmall& tb, const double* __restrict__ lf, Add add) {
   if (quick > 0) add(dst, (T)quick);
@@ -262,7 +262,7 @@ __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int
       const int total = nbr * np;
       for (int base = 0; base < total; base += 64) {
         const int x = base + lane;
-        int64_t quick_e = 0, quick_o = 0;
+        int quick_e = 0, quick_o = 0;
         double pe = 0.0, po = 0.0, ue = 0.0, uo = 0.0;
         uint32_t de = 0, dodd = 0;
         if (x < total) {

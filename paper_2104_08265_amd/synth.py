@@ -418,3 +418,20 @@ def round_responses(wl: Workload):
     """Responses as the plan consumes them: rounded to the working precision once."""
     dt = np.float32 if wl.dtype == F32 else np.float64
     return [np.ascontiguousarray(r.astype(dt)) for r in wl.responses]
+
+
+def noise_amplitude(lt: int, rms: float, shaping_ticks: float = 2.0, white: float = 0.05) -> np.ndarray:
+    """Synthetic noise amplitude spectrum A[k], k = 0..L_t/2, of an L_t-point tick transform.
+
+    Shape (a stand-in for electronics noise after a shaping amplifier; the paper gives no
+    spectrum): s(f) = (f / f0) exp(1 - f / f0) + white, f = k / L_t cycles per tick,
+    f0 = 1 / (2 pi shaping_ticks), zero at DC; scaled so that the noise waveform's RMS is
+    `rms` (Parseval: rms^2 = (A[0]^2 + 2 sum A[k]^2 + A[L/2]^2) / L^2).
+    """
+    F = lt // 2 + 1
+    f = np.arange(F) / lt
+    f0 = 1.0 / (2.0 * np.pi * shaping_ticks)
+    s = (f / f0) * np.exp(1.0 - f / f0) + white
+    s[0] = 0.0
+    power = (s[0] ** 2 + 2.0 * np.sum(s[1:-1] ** 2) + s[-1] ** 2) / lt ** 2
+    return s * (rms / np.sqrt(power))

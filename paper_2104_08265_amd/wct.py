@@ -9,6 +9,8 @@ from __future__ import annotations
 
 import ctypes
 import os
+
+import numpy as np
 from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_size_t, c_uint64, c_void_p
 
 # torch is imported first so that its bundled HIP runtime is the one in the process:
@@ -46,7 +48,7 @@ class wct_depos(ctypes.Structure):
 
 class wct_opts(ctypes.Structure):
     _fields_ = [("nsigma", c_double), ("fluctuate", c_int32), ("n_events", c_int32), ("seed", c_uint64),
-                ("event_base", c_int32), ("reserved", c_int32)]
+                ("event_base", c_int32), ("noise", c_int32)]
 
 
 PlanP = c_void_p
@@ -70,6 +72,9 @@ wct_raster = _sig("wct_raster", c_int32, [PlanP, POINTER(wct_depos), POINTER(wct
 wct_raster_noalloc = _sig("wct_raster_noalloc", c_int32, [PlanP, POINTER(wct_depos), POINTER(wct_opts), c_void_p,
                                                          c_void_p])
 NOALLOC_SCRATCH_BYTES = 128 << 20  # WCT_NOALLOC_SCRATCH_BYTES
+wct_probe_atomic_add = _sig("wct_probe_atomic_add", c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int64,
+                                                              POINTER(c_double), c_void_p])
+wct_probe_last_error = _sig("wct_probe_last_error", c_char_p, [])
 wct_convolve = _sig("wct_convolve", c_int32, [PlanP, c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p])
 wct_simulate = _sig("wct_simulate", c_int32, [PlanP, POINTER(wct_depos), POINTER(wct_opts), c_void_p, c_void_p,
                                              c_size_t, c_void_p])
@@ -88,8 +93,23 @@ wct_fft_variant_count = _sig("wct_fft_variant_count", c_int32, [])
 wct_fft_variant_info = _sig("wct_fft_variant_info", c_int32, [c_int32, POINTER(c_int32)])
 wct_plan_get_fft = _sig("wct_plan_get_fft", c_int32, [PlanP, c_int32, c_int32, POINTER(c_int32)])
 wct_plan_set_fft = _sig("wct_plan_set_fft", c_int32, [PlanP, c_int32, c_int32, c_int32])
+wct_plan_set_noise = _sig("wct_plan_set_noise", c_int32, [PlanP, c_int32, POINTER(c_double), c_int64])
 wct_tune_workspace_bytes = _sig("wct_tune_workspace_bytes", c_size_t, [PlanP, c_int32])
 wct_plan_tune = _sig("wct_plan_tune", c_int32, [PlanP, c_int32, c_char_p, c_void_p, c_size_t, c_void_p])
+
+
+def probe_atomic_add(where, blocks=2048, iters=256, buf_elems=None, device=0):
+    """Peak float atomic adds per second: where = "lds" (into LDS) or "global" (into device
+    memory, performed at L2).  A measurement call: allocates a buffer and synchronises."""
+    torch = _torch()
+    n = blocks * 256 if buf_elems is None else int(buf_elems)
+    buf = torch.zeros(n, dtype=torch.float32, device=f"cuda:{device}")
+    rate = c_double()
+    code = wct_probe_atomic_add(0 if where == "lds" else 1, blocks, iters, _ptr(buf), n, ctypes.byref(rate),
+                                c_void_p(torch.cuda.current_stream(device).cuda_stream))
+    if code != 0:
+        raise WctError(code, f"wct_probe_atomic_add: {wct_probe_last_error().decode()}")
+    return rate.value, buf
 
 
 def fft_variants():
@@ -171,10 +191,11 @@ class DeviceDepos:
                          _ptr(self.plane), _ptr(self.event), _ptr(self.depo_id))
 
 
-def opts(nsigma=3.0, fluctuate=False, n_events=1, seed=0, event_base=0):
-    """Run options; the call simulates events event_base .. event_base + n_events - 1."""
+def opts(nsigma=3.0, fluctuate=False, n_events=1, seed=0, event_base=0, noise=False):
+    """Run options; the call simulates events event_base .. event_base + n_events - 1
+    (noise: wct_simulate adds the planes' noise, see Plan.set_noise)."""
     return wct_opts(float(nsigma), int(bool(fluctuate)), int(n_events), int(seed) & 0xFFFFFFFFFFFFFFFF,
-                    int(event_base), 0)
+                    int(event_base), int(bool(noise)))
 
 
 class Plan:
@@ -287,6 +308,14 @@ class Plan:
 
     def set_fft(self, plane, kind, variant):
         check(wct_plan_set_fft(self.h, plane, kind, variant), "wct_plan_set_fft")
+
+    def set_noise(self, plane, amp):
+        """Noise amplitude spectrum of a plane (host array of F = L_t/2 + 1 values), or None."""
+        if amp is None:
+            check(wct_plan_set_noise(self.h, plane, None, 0), "wct_plan_set_noise")
+            return
+        a = np.ascontiguousarray(amp, dtype=np.float64)
+        check(wct_plan_set_noise(self.h, plane, a.ctypes.data_as(POINTER(c_double)), a.size), "wct_plan_set_noise")
 
     def tune(self, n_events=1, cache_path=None):
         """Pick the fastest transform variant per plane and kind (optionally via a cache file)."""
