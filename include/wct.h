@@ -260,6 +260,31 @@ int wct_plan_set_fft(wct_plan* plan, int32_t plane, int32_t kind, int32_t varian
 size_t wct_tune_workspace_bytes(const wct_plan* plan, int32_t n_events);
 int wct_plan_tune(wct_plan* plan, int32_t n_events, const char* cache_path, void* ws, size_t ws_bytes, void* stream);
 
+/* Raster tile variants.  The raster accumulates each tile of TH impact rows x TW ticks in
+ * LDS (Sec. 2.1.1 scatter adding through privatised tiles); the library compiles a few
+ * shapes per dtype.  wct_tile_variant_info(idx, out[4]) fills out = {is_double, TH, TW,
+ * tile-kernel blocks per CU} (HOST buffer).  A plan starts on the first variant of its
+ * dtype; wct_plan_set_tile selects another (an index of the whole list, of the plan's
+ * dtype, else WCT_E_INVALID) and wct_plan_get_tile reports it.  Every variant gives the
+ * same grid (fluctuated: bit for bit).  The raster workspace depends on the variant:
+ * query wct_workspace_bytes after a change.  Set-up calls: not for use while run calls on
+ * the plan are queued with a workspace sized for another variant. */
+int wct_tile_variant_count(void);
+int wct_tile_variant_info(int32_t idx, int32_t* out);
+int wct_plan_get_tile(const wct_plan* plan, int32_t* variant);
+int wct_plan_set_tile(wct_plan* plan, int32_t variant);
+
+/* Autotuning of the raster tile: times wct_raster of `depos` with `opts` (one warm-up,
+ * three timed runs on `stream`, HIP events) for every tile variant of the plan's dtype and
+ * keeps the fastest.  cache_path (HOST, NULL = none): the same text file as
+ * wct_plan_tune, lines "wct-tile <dtype> <n_planes> (<N_w> <N_t> <I>)... fluct <0|1> ->
+ * <TH> <TW> <blocks>"; a choice found there is applied without timing, a new one is
+ * appended.  ws: wct_tune_raster_workspace_bytes(plan, opts->n_events, depos->n) bytes
+ * (a grid and the largest raster workspace).  A set-up call: synchronises. */
+size_t wct_tune_raster_workspace_bytes(wct_plan* plan, int32_t n_events, int64_t n_rows);
+int wct_plan_tune_raster(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, const char* cache_path,
+                         void* ws, size_t ws_bytes, void* stream);
+
 /* Thread-local text of the last error on this thread ("" if none). */
 const char* wct_last_error(void);
 

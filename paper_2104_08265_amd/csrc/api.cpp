@@ -170,6 +170,8 @@ struct wct_plan {
   int64_t grid_elems = 0, wave_elems = 0, shat_elems = 0, mhat_elems = 0;
   int64_t rows_ev = 0;  // impact rows per event, all planes
   int ntiles_ev = 0;
+  int tile = 0;         // raster tile variant: index among the variants of the plan's dtype
+  int tile_global = 0;  // the same variant's index in the whole list (wct_tile_variant_info)
 
   void* dalloc(size_t bytes, hipError_t* e) {
     void* p = nullptr;
@@ -207,6 +209,31 @@ RasterGeom raster_geom(const wct_plan* P, int n_events, int event_base) {
   g.rows_ev = P->rows_ev;
   for (int p = 0; p < P->n_planes; ++p) g.pl[p] = P->geom[p];
   return g;
+}
+
+// Raster tiles of variant v (index in the whole list): tiles per plane and their offsets.
+int set_tiles(wct_plan* P, int v) {
+  int nvar = 0;
+  const TileVariantDesc* tv = tile_variants(&nvar);
+  if (v < 0 || v >= nvar || tv[v].dbl != (int)(P->dtype == WCT_F64))
+    return fail(WCT_E_INVALID, "tile variant %d does not exist for this plan's dtype", v);
+  int64_t toff = 0;
+  std::vector<PlaneGeom> g = P->geom;
+  for (PlaneGeom& G : g) {
+    G.tile_off = toff;
+    G.ntr = (G.nb + tv[v].th - 1) / tv[v].th;
+    G.ntc = (G.nt + tv[v].tw - 1) / tv[v].tw;
+    toff += (int64_t)G.ntr * G.ntc;
+  }
+  if (toff * (int64_t)P->max_events > 0x3fffffffLL)
+    return fail(WCT_E_UNSUPPORTED, "too many raster tiles (%lld per event)", (long long)toff);
+  P->geom = g;
+  P->ntiles_ev = (int)toff;
+  P->tile_global = v;
+  int local = 0;
+  for (int k = 0; k < v; ++k) local += tv[k].dbl == tv[v].dbl;
+  P->tile = local;
+  return WCT_OK;
 }
 
 // Workspace layouts ---------------------------------------------------------------
@@ -318,8 +345,7 @@ int run_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, T* grid, Carv
   RasterWs ws = carve_raster(P, cv, o->n_events, d->n);
   ws.live = live;
   HIP_TRY(launch_raster<T>(view<T>(d), g, o->nsigma, o->fluctuate, o->seed, grid, ws, P->d_tables, P->d_lfact,
-                           P->n_cu, st,
-                           hook(P)),
+                           P->n_cu, st, hook(P), P->tile),
           "raster launch");
   return WCT_OK;
 }
@@ -717,6 +743,85 @@ size_t tune_ws_bytes(const wct_plan* P, int n_events) {
   return align_up(a.off, 256) + ws_bytes(P, WCT_OP_CONVOLVE, n_events, 0);
 }
 
+// Autotuning of the raster tile ---------------------------------------------------------
+// Cache line per (dtype, plane geometries, mean or fluctuated raster), e.g.
+//   wct-tile f32 3 2400 9600 10 2400 9600 10 3456 9600 10 fluct 1 -> 128 64 4
+std::string tile_key(const wct_plan* P, int fluctuate) {
+  std::string k = std::string("wct-tile ") + (P->dtype == WCT_F32 ? "f32" : "f64") + " " + std::to_string(P->n_planes);
+  for (const PlaneGeom& G : P->geom) k += " " + std::to_string(G.nw) + " " + std::to_string(G.nt) + " " + std::to_string(G.I);
+  return k + " fluct " + std::to_string(fluctuate);
+}
+std::string tile_text(int v) {
+  int n = 0;
+  const TileVariantDesc* tv = tile_variants(&n);
+  return std::to_string(tv[v].th) + " " + std::to_string(tv[v].tw) + " " + std::to_string(tv[v].blocks_per_cu);
+}
+// Workspace of the raster tuner: the grid of n_events events plus the largest raster
+// workspace over the tile variants of the plan's dtype.
+size_t tune_raster_ws_bytes(wct_plan* P, int n_events, int64_t n_rows) {
+  const int keep = P->tile_global;
+  int nvar = 0;
+  const TileVariantDesc* tv = tile_variants(&nvar);
+  size_t most = 0;
+  for (int v = 0; v < nvar; ++v) {
+    if (tv[v].dbl != (int)(P->dtype == WCT_F64) || set_tiles(P, v)) continue;
+    const size_t b = ws_bytes(P, WCT_OP_RASTER, n_events, n_rows);
+    most = b > most ? b : most;
+  }
+  (void)set_tiles(P, keep);
+  return align_up(P->esize * (size_t)n_events * P->grid_elems, 256) + most;
+}
+
+template <typename T>
+int run_tune_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, const char* cache_path, void* ws,
+                    hipStream_t st) {
+  auto cache = read_tune_cache(cache_path);
+  const std::string key = tile_key(P, o->fluctuate);
+  int nvar = 0;
+  const TileVariantDesc* tv = tile_variants(&nvar);
+  std::vector<int> cand;
+  for (int v = 0; v < nvar; ++v)
+    if (tv[v].dbl == (int)(sizeof(T) == 8)) cand.push_back(v);
+  auto it = cache.find(key);
+  if (it != cache.end())
+    for (int v : cand)
+      if (tile_text(v) == it->second) return set_tiles(P, v);
+  T* grid = static_cast<T*>(ws);
+  char* rws = static_cast<char*>(ws) + align_up(P->esize * (size_t)o->n_events * P->grid_elems, 256);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "event create");
+  HIP_TRY(hipEventCreate(&e1), "event create");
+  int best = -1, rc = WCT_OK;
+  float best_ms = 0.f;
+  for (int v : cand) {
+    if ((rc = set_tiles(P, v))) break;
+    float ms = 0.f;
+    for (int rep = 0; rep < 4 && rc == WCT_OK; ++rep) {  // one warm-up, three timed
+      if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) rc = fail(WCT_E_DEVICE, "event record");
+      Carver cv(rws);
+      if (rc == WCT_OK) rc = run_raster<T>(P, d, o, grid, cv, st);
+    }
+    if (rc) break;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = fail(WCT_E_DEVICE, "timing the raster tile variants failed");
+      break;
+    }
+    if (best < 0 || ms < best_ms) best = v, best_ms = ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if ((rc = set_tiles(P, best))) return rc;
+  if (cache_path) {
+    FILE* f = std::fopen(cache_path, "a");
+    if (!f) return fail(WCT_E_INVALID, "cannot append to tune cache %s", cache_path);
+    std::fputs((key + " -> " + tile_text(best) + "\n").c_str(), f);
+    std::fclose(f);
+  }
+  return WCT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -745,9 +850,7 @@ int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
   P->n_planes = desc->n_planes;
   P->max_events = desc->max_events;
   P->esize = desc->dtype == WCT_F32 ? 4 : 8;
-  const int TH = desc->dtype == WCT_F32 ? TileShape<float>::TH : TileShape<double>::TH;
-  const int TW = desc->dtype == WCT_F32 ? TileShape<float>::TW : TileShape<double>::TW;
-  int64_t goff = 0, woff = 0, soff = 0, moff = 0, toff = 0, roff = 0;
+  int64_t goff = 0, woff = 0, soff = 0, moff = 0, roff = 0;
   for (int p = 0; p < P->n_planes; ++p) {
     const wct_plane_desc& pd = desc->planes[p];
     if (pd.n_wires < 1 || pd.n_ticks < 1 || pd.n_impacts < 1 || pd.half_wires < 0 || pd.resp_ticks < 1 ||
@@ -777,15 +880,11 @@ int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
     G.wave_off = woff;
     G.shat_off = soff;
     G.mhat_off = moff;
-    G.tile_off = toff;
     G.row_off = roff;
-    G.ntr = (G.nb + TH - 1) / TH;
-    G.ntc = (G.nt + TW - 1) / TW;
     goff += nbt;
     woff += (int64_t)G.nw * G.nt;
     soff += (int64_t)G.nchunk * kChunk * G.nb;
     moff += (int64_t)G.nw * G.nchunk * kChunk;
-    toff += (int64_t)G.ntr * G.ntc;
     roff += G.nb;
     P->geom.push_back(G);
   }
@@ -795,11 +894,14 @@ int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
   P->wave_elems = woff;
   P->shat_elems = soff;
   P->mhat_elems = moff;
-  if (toff * (int64_t)P->max_events > 0x3fffffffLL) {
+  int tile0 = -1, nvar = 0;  // the first tile variant of the dtype
+  const TileVariantDesc* tv = tile_variants(&nvar);
+  for (int v = 0; v < nvar && tile0 < 0; ++v)
+    if (tv[v].dbl == (int)(P->dtype == WCT_F64)) tile0 = v;
+  if (int rc0 = set_tiles(P, tile0)) {
     delete P;
-    return fail(WCT_E_UNSUPPORTED, "too many raster tiles (%lld per event)", (long long)toff);
+    return rc0;
   }
-  P->ntiles_ev = (int)toff;
 
   DeviceGuard dg(P->device);
   if (!dg.ok) {
@@ -1108,6 +1210,57 @@ int wct_plan_tune(wct_plan* plan, int32_t n_events, const char* cache_path, void
                                         : run_tune<double>(plan, n_events, cache_path, ws, st);
   plan->prof.on = prof;
   return rc;
+}
+
+int wct_tile_variant_count(void) {
+  int n = 0;
+  (void)tile_variants(&n);
+  return n;
+}
+
+int wct_tile_variant_info(int32_t idx, int32_t* out) {
+  int n = 0;
+  const TileVariantDesc* tv = tile_variants(&n);
+  if (idx < 0 || idx >= n || !out) return fail(WCT_E_INVALID, "tile variant %d of %d", idx, n);
+  out[0] = tv[idx].dbl;
+  out[1] = tv[idx].th;
+  out[2] = tv[idx].tw;
+  out[3] = tv[idx].blocks_per_cu;
+  return WCT_OK;
+}
+
+int wct_plan_get_tile(const wct_plan* plan, int32_t* variant) {
+  g_err.clear();
+  if (!plan || !variant) return fail(WCT_E_INVALID, "NULL argument");
+  *variant = plan->tile_global;
+  return WCT_OK;
+}
+
+int wct_plan_set_tile(wct_plan* plan, int32_t variant) {
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  return set_tiles(plan, variant);
+}
+
+size_t wct_tune_raster_workspace_bytes(wct_plan* plan, int32_t n_events, int64_t n_rows) {
+  if (!plan || n_events < 1 || n_events > plan->max_events || n_rows < 0) return 0;
+  return tune_raster_ws_bytes(plan, n_events, n_rows);
+}
+
+int wct_plan_tune_raster(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, const char* cache_path,
+                         void* ws, size_t ws_size, void* stream) {
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  int rc = check_opts(plan, opts, true);
+  if (rc) return rc;
+  if ((rc = check_depos(depos))) return rc;
+  const size_t need = tune_raster_ws_bytes(plan, opts->n_events, depos->n);
+  if (!ws || ws_size < need) return fail(WCT_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_size, need);
+  DeviceGuard dg(plan->device);
+  if (!dg.ok) return fail(WCT_E_DEVICE, "hipSetDevice(%d) failed", plan->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return plan->dtype == WCT_F32 ? run_tune_raster<float>(plan, depos, opts, cache_path, ws, st)
+                                : run_tune_raster<double>(plan, depos, opts, cache_path, ws, st);
 }
 
 int wct_profile_enable(wct_plan* plan, int32_t enable) {

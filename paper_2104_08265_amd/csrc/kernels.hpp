@@ -40,20 +40,34 @@ constexpr int kRowsPerItem = 256;  // rows one tile work item processes at most
 constexpr int kZeroGroup = 16;     // tiles per clearing item of the tile kernel
 constexpr int kScanPerBlock = 4096;
 
-// Raster tile shapes (rows x ticks), 32 KB of LDS each.  Tall tiles: a window of up to
-// 129 impact rows (sigma_p <= 2 pitches at 3 sigma) and 65 ticks spans at most 2 x 2
-// tiles, so typical rows take the tile path.  TW is even so that the tick pairs that
-// share a Philox block never straddle two tiles.
-template <typename T>
-struct TileShape;
-template <>
-struct TileShape<float> {
-  static constexpr int TH = 128, TW = 64;
+// Raster tile variants: X(real type, TH rows, TW ticks, tile-kernel blocks per CU).
+// Tall tiles: a window of up to 129 impact rows (sigma_p <= 2 pitches at 3 sigma) spans
+// at most 2 tile rows, so typical rows take the tile path.  TW is even (the tick pairs that
+// share a Philox block never straddle two tiles) and a multiple of 16 bytes (tiles are
+// cleared with 16-byte stores); TH * TW <= 2^13 (tile offsets beside the packed electron
+// count of the chop-down queue).  Smaller tiles take less LDS, so more blocks share a CU,
+// but more rows straddle tiles.  The first variant of a type is a plan's default; the
+// raster tuner (wct_plan_tune_raster) times them on an event's rows.
+#define WCT_TILE_VARIANTS(X) \
+  X(float, 128, 64, 4)      \
+  X(float, 128, 48, 5)      \
+  X(float, 128, 32, 6)      \
+  X(float, 256, 32, 3)      \
+  X(double, 64, 64, 4)      \
+  X(double, 64, 32, 6)
+
+struct TileVariantDesc {
+  int dbl;  // 0 float, 1 double
+  int th, tw;
+  int blocks_per_cu;
 };
-template <>
-struct TileShape<double> {
-  static constexpr int TH = 64, TW = 64;
-};
+#define WCT_TILE_DESC(TT, TH_, TW_, OCC) TileVariantDesc{sizeof(TT) == 8, TH_, TW_, OCC},
+inline const TileVariantDesc* tile_variants(int* count) {
+  static const TileVariantDesc v[] = {WCT_TILE_VARIANTS(WCT_TILE_DESC)};
+  *count = (int)(sizeof(v) / sizeof(v[0]));
+  return v;
+}
+#undef WCT_TILE_DESC
 
 struct RasterWs {
   int32_t* ctrl;      // kCtrlWords
@@ -94,10 +108,11 @@ struct ProfHook {
 
 // raster.hip
 // lfact: ln(n!) for n < kLfactTable (launch_lfact_table), or NULL (evaluated per cell).
+// tile: index into WCT_TILE_VARIANTS (of type T); the geometry g was built for it.
 template <typename T>
 hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigma, int fluctuate, uint64_t seed,
                          T* grid, const RasterWs& ws, const DetTables* tables, const double* lfact, int n_cu,
-                         hipStream_t st, ProfHook* prof);
+                         hipStream_t st, ProfHook* prof, int tile);
 hipError_t launch_lfact_table(double* out, int n, const DetTables* tables, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 

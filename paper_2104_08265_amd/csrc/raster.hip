@@ -20,6 +20,8 @@
 // Window bounds are formed in FP64 exactly as the oracle forms them, so both sides
 // agree on which cells a row touches; fluctuated counts use the deterministic
 // Philox + binomial chain of fluct.hpp (this file is compiled with contraction off).
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace wct {
@@ -539,8 +541,8 @@ __global__ void k_zero_split(RasterGeom g, const int32_t* __restrict__ counts, i
 // in LDS and written out) and a group of kZeroGroup consecutive tiles, of which those no
 // row touches are cleared.  The clearing stores (HBM-bound) then overlap the arithmetic
 // of the rows instead of costing work items of their own.
-template <typename T, bool FLUCT, int TH, int TW>
-__global__ void __launch_bounds__(256, 4) k_tile(DepoView<T> d, RasterGeom g, double nsigma, uint64_t seed,
+template <typename T, bool FLUCT, int TH, int TW, int OCC>
+__global__ void __launch_bounds__(256, OCC) k_tile(DepoView<T> d, RasterGeom g, double nsigma, uint64_t seed,
                                               T* __restrict__ grid, const int32_t* __restrict__ list,
                                               const int32_t* __restrict__ offs, const int32_t* __restrict__ items,
                                               const int32_t* __restrict__ item_off, const int32_t* __restrict__ counts,
@@ -697,11 +699,10 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
     if (e_ != hipSuccess) return e_;        \
   } while (0)
 
-template <typename T>
-hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigma, int fluctuate, uint64_t seed,
-                         T* grid, const RasterWs& ws, const DetTables* tables, const double* lfact, int n_cu,
-                         hipStream_t st, ProfHook* prof) {
-  constexpr int TH = TileShape<T>::TH, TW = TileShape<T>::TW;
+template <typename T, int TH, int TW, int OCC>
+hipError_t launch_raster_tiles(const DepoView<T>& d, const RasterGeom& g, double nsigma, int fluctuate, uint64_t seed,
+                               T* grid, const RasterWs& ws, const DetTables* tables, const double* lfact, int n_cu,
+                               hipStream_t st, ProfHook* prof) {
   const int64_t nt = ws.ntiles;
   if (nt >= INT32_MAX) return hipErrorInvalidValue;  // tile indices and list offsets are int32
   if (prof) prof->begin("raster_bin", st);
@@ -736,13 +737,13 @@ hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigm
   hipLaunchKernelGGL((k_zero_split<T, TH, TW>), dim3(1024), dim3(256), 0, st, g, ws.counts, nt, grid);
   WCT_CHECK_LAUNCH();
   if (prof) prof->end(st);
-  const unsigned pblocks = (unsigned)(n_cu * 4);  // 4 resident blocks per CU (40 KB of LDS each)
+  const unsigned pblocks = (unsigned)(n_cu * OCC);  // the blocks that fit a CU at once (LDS, registers)
   if (prof) prof->begin(fluctuate ? "raster_tile_fluct" : "raster_tile_mean", st);
   if (fluctuate)
-    hipLaunchKernelGGL((k_tile<T, true, TH, TW>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.list,
-                       ws.offs, ws.items, ws.item_off, ws.counts, nt, ws.ctrl, tables, lfact);
+    hipLaunchKernelGGL((k_tile<T, true, TH, TW, OCC>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid,
+                       ws.list, ws.offs, ws.items, ws.item_off, ws.counts, nt, ws.ctrl, tables, lfact);
   else
-    hipLaunchKernelGGL((k_tile<T, false, TH, TW>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid,
+    hipLaunchKernelGGL((k_tile<T, false, TH, TW, OCC>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid,
                        ws.list, ws.offs, ws.items, ws.item_off, ws.counts, nt, ws.ctrl, tables, lfact);
   WCT_CHECK_LAUNCH();
   if (prof) prof->end(st);
@@ -758,12 +759,29 @@ hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigm
   return hipSuccess;
 }
 
+template <typename T>
+hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigma, int fluctuate, uint64_t seed,
+                         T* grid, const RasterWs& ws, const DetTables* tables, const double* lfact, int n_cu,
+                         hipStream_t st, ProfHook* prof, int tile) {
+  int id = 0;  // index among the variants of type T
+  hipError_t e = hipErrorInvalidValue;
+#define WCT_TILE_CASE(TT, TH_, TW_, OCC)                                                                    \
+  if constexpr (std::is_same<T, TT>::value) {                                                              \
+    if (id++ == tile)                                                                                      \
+      e = launch_raster_tiles<T, TH_, TW_, OCC>(d, g, nsigma, fluctuate, seed, grid, ws, tables, lfact, n_cu, \
+                                                st, prof);                                                  \
+  }
+  WCT_TILE_VARIANTS(WCT_TILE_CASE)
+#undef WCT_TILE_CASE
+  return e;
+}
+
 template hipError_t launch_raster<float>(const DepoView<float>&, const RasterGeom&, double, int, uint64_t, float*,
                                          const RasterWs&, const DetTables*, const double*, int, hipStream_t,
-                                         ProfHook*);
+                                         ProfHook*, int);
 template hipError_t launch_raster<double>(const DepoView<double>&, const RasterGeom&, double, int, uint64_t, double*,
                                           const RasterWs&, const DetTables*, const double*, int, hipStream_t,
-                                          ProfHook*);
+                                          ProfHook*, int);
 
 // ln(n!) table for the chop-down sampler, filled with the sampler's own det_lfact.
 __global__ void k_lfact_table(double* __restrict__ out, int n, const DetTables* __restrict__ tables) {

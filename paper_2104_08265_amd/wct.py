@@ -93,6 +93,13 @@ wct_fft_variant_count = _sig("wct_fft_variant_count", c_int32, [])
 wct_fft_variant_info = _sig("wct_fft_variant_info", c_int32, [c_int32, POINTER(c_int32)])
 wct_plan_get_fft = _sig("wct_plan_get_fft", c_int32, [PlanP, c_int32, c_int32, POINTER(c_int32)])
 wct_plan_set_fft = _sig("wct_plan_set_fft", c_int32, [PlanP, c_int32, c_int32, c_int32])
+wct_tile_variant_count = _sig("wct_tile_variant_count", c_int32, [])
+wct_tile_variant_info = _sig("wct_tile_variant_info", c_int32, [c_int32, POINTER(c_int32)])
+wct_plan_get_tile = _sig("wct_plan_get_tile", c_int32, [PlanP, POINTER(c_int32)])
+wct_plan_set_tile = _sig("wct_plan_set_tile", c_int32, [PlanP, c_int32])
+wct_tune_raster_workspace_bytes = _sig("wct_tune_raster_workspace_bytes", c_size_t, [PlanP, c_int32, c_int64])
+wct_plan_tune_raster = _sig("wct_plan_tune_raster", c_int32, [PlanP, POINTER(wct_depos), POINTER(wct_opts), c_char_p,
+                                                             c_void_p, c_size_t, c_void_p])
 wct_plan_set_noise = _sig("wct_plan_set_noise", c_int32, [PlanP, c_int32, POINTER(c_double), c_int64])
 wct_tune_workspace_bytes = _sig("wct_tune_workspace_bytes", c_size_t, [PlanP, c_int32])
 wct_plan_tune = _sig("wct_plan_tune", c_int32, [PlanP, c_int32, c_char_p, c_void_p, c_size_t, c_void_p])
@@ -110,6 +117,17 @@ def probe_atomic_add(where, blocks=2048, iters=256, buf_elems=None, device=0):
     if code != 0:
         raise WctError(code, f"wct_probe_atomic_add: {wct_probe_last_error().decode()}")
     return rate.value, buf
+
+
+def tile_variants():
+    """Compiled raster tile variants: list of dicts (index, dtype, th, tw, blocks_per_cu)."""
+    out = []
+    buf = (c_int32 * 4)()
+    for k in range(wct_tile_variant_count()):
+        check(wct_tile_variant_info(k, buf), "wct_tile_variant_info")
+        out.append({"index": k, "dtype": "f64" if buf[0] else "f32", "th": buf[1], "tw": buf[2],
+                    "blocks_per_cu": buf[3]})
+    return out
 
 
 def fft_variants():
@@ -308,6 +326,32 @@ class Plan:
 
     def set_fft(self, plane, kind, variant):
         check(wct_plan_set_fft(self.h, plane, kind, variant), "wct_plan_set_fft")
+
+    def tile_candidates(self):
+        """Raster tile variants of this plan's dtype (indices of tile_variants())."""
+        dt = "f64" if self.dtype == WCT_F64 else "f32"
+        return [v["index"] for v in tile_variants() if v["dtype"] == dt]
+
+    def get_tile(self):
+        v = c_int32()
+        check(wct_plan_get_tile(self.h, ctypes.byref(v)), "wct_plan_get_tile")
+        return v.value
+
+    def set_tile(self, variant):
+        check(wct_plan_set_tile(self.h, variant), "wct_plan_set_tile")
+
+    def tune_raster(self, depos: DeviceDepos, o: wct_opts, cache_path=None):
+        """Pick the fastest raster tile variant for these rows (optionally via a cache file)."""
+        torch = _torch()
+        need = int(wct_tune_raster_workspace_bytes(self.h, o.n_events, depos.n))
+        if need == 0:
+            raise WctError(WCT_E_INVALID, "wct_tune_raster_workspace_bytes")
+        ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
+        d = depos.c()
+        path = None if cache_path is None else str(cache_path).encode()
+        check(wct_plan_tune_raster(self.h, ctypes.byref(d), ctypes.byref(o), path, _ptr(ws), need, self._stream()),
+              "wct_plan_tune_raster")
+        return self.get_tile()
 
     def set_noise(self, plane, amp):
         """Noise amplitude spectrum of a plane (host array of F = L_t/2 + 1 values), or None."""
