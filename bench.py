@@ -40,7 +40,13 @@ PROFILE_COMMANDS = {
              "--tune-cache $R/gpurun_out/fft.tune",
     "trace_showers": "rocprofv3 --kernel-trace --stats -f csv -d $R/gpurun_out/prof_cfg3 -o cfg3 -- "
                      "python3 $R/bench.py --showers-only --steps 3",
+    "sq": "rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_LDS_ATOMIC SQ_THREAD_CYCLES_VALU "
+          "SQ_ACTIVE_INST_VALU SQ_WAVES SQ_LDS_BANK_CONFLICT -f csv -d $R/gpurun_out/pmc_sq -o sq -- "
+          "python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --tune-cache $R/gpurun_out/fft.tune",
+    "atomic": "rocprofv3 --pmc TCC_ATOMIC TCP_TOTAL_ATOMIC_WITHOUT_RET -f csv -d $R/gpurun_out/pmc_atomic -o atomic -- "
+              "python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --tune-cache $R/gpurun_out/fft.tune",
 }
+COUNTERS_JSON = os.path.join(PROFILES, "raster_counters.json")
 
 
 def family(kernel_name):
@@ -151,6 +157,74 @@ def summarize(out_dir):
     open(os.path.join(PROFILES, "simulate_3plane_1e5_hbm_traffic.md"), "w").write("\n".join(lines) + "\n")
     json.dump(traffic, open(TRAFFIC_JSON, "w"), indent=1)
     print("\n".join(lines))
+    summarize_counters(out_dir)
+
+
+def summarize_counters(out_dir):
+    """profiles/raster_counters.json and .md: per-launch instruction and atomic counters of
+    each kernel family (the headline step plus the mean raster the bench runs after it)."""
+    import csv
+    import glob
+    import collections
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    n_launch = {}
+    digests = set()
+    for tag in ("sq", "atomic"):
+        paths = glob.glob(os.path.join(out_dir, f"pmc_{tag}", "*counter_collection.csv"))
+        if not paths:
+            return
+        digests.add(log_digest(os.path.join(out_dir, f"pmc_{tag}.log")))
+        last = {}
+        rows = list(csv.DictReader(open(paths[0])))
+        # the bench's own launches are the last ones of each family (the tuners run first)
+        for r in rows:
+            fam = family(r["Kernel_Name"])
+            if fam:
+                last.setdefault(fam, []).append(int(r["Dispatch_Id"]))
+        want = {fam: set(sorted(set(ids))[-3:] if fam in ("rows_r2c", "colpass", "rows_c2r") else sorted(set(ids))[-1:])
+                for fam, ids in last.items()}
+        for r in rows:
+            fam = family(r["Kernel_Name"])
+            if fam and int(r["Dispatch_Id"]) in want[fam]:
+                per[fam][r["Counter_Name"]] += float(r["Counter_Value"])
+        if tag == "sq":
+            n_launch = {fam: len(ids) for fam, ids in want.items()}
+    if len(digests) != 1 or None in digests:
+        raise SystemExit("the counter runs do not name the same library build")
+    out = {"build": digests.pop(), "commands": {k: PROFILE_COMMANDS[k] for k in ("sq", "atomic")}, "kernels": {}}
+    names = ["SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_LDS_ATOMIC", "SQ_THREAD_CYCLES_VALU",
+             "SQ_ACTIVE_INST_VALU", "SQ_WAVES", "SQ_LDS_BANK_CONFLICT", "TCC_ATOMIC", "TCP_TOTAL_ATOMIC_WITHOUT_RET"]
+    lines = ["# Instruction and atomic counters per launch: three-plane track workload", "",
+             "Commands (separate runs, from /tmp, R = repository root):", "",
+             "    " + PROFILE_COMMANDS["sq"], "    " + PROFILE_COMMANDS["atomic"], "",
+             "One headline step (raster_tile_fluct, the three transform passes) and the mean raster of the same "
+             "event that the bench runs after it (raster_tile_mean).  VALU and SALU are wave instructions; "
+             "lane use = SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU).", "",
+             "| family | launches | " + " | ".join(names) + " | lane use |", "|---" * (len(names) + 3) + "|"]
+    for fam in sorted(per):
+        n = max(n_launch.get(fam, 1), 1)
+        vals = {k: per[fam].get(k, 0.0) / n for k in names}
+        use = vals["SQ_THREAD_CYCLES_VALU"] / (64 * vals["SQ_ACTIVE_INST_VALU"]) if vals["SQ_ACTIVE_INST_VALU"] else None
+        vals["lane_use"] = use
+        vals["launches_counted"] = n
+        out["kernels"][fam] = vals
+        use_txt = f"{use:.2f}" if use is not None else "-"
+        lines.append(f"| {fam} | {n} | " + " | ".join(f"{vals[k]:.3e}" for k in names) + f" | {use_txt} |")
+    open(os.path.join(PROFILES, "simulate_3plane_1e5_counters.md"), "w").write("\n".join(lines) + "\n")
+    json.dump(out, open(COUNTERS_JSON, "w"), indent=1)
+    print("\n".join(lines))
+
+
+def measured_counters(kernel):
+    """Per-launch counters of a kernel family from committed profiles, or None when the
+    library changed since."""
+    try:
+        c = json.load(open(COUNTERS_JSON))
+    except (OSError, ValueError):
+        return None
+    if c.get("build") is None or c.get("build") != built_digest():
+        return None
+    return c.get("kernels", {}).get(kernel)
 
 
 def measured_traffic(kernel):
@@ -272,6 +346,102 @@ def cpu_baseline(wl, n_sample_depos=200):
     }
 
 
+def window_cells(wl, nsigma=3.0):
+    """Cells of all rows' truncated windows inside the grid: the mean raster's LDS adds
+    (one per cell; rows wider than four tiles excepted, a small share)."""
+    import numpy as np
+    d = wl.depos
+    total = 0
+    for k, pl in enumerate(wl.planes):
+        m = np.asarray(d.plane) == k
+        u, su = pl.n_impacts * np.asarray(d.p, np.float64)[m], pl.n_impacts * np.asarray(d.sigma_p, np.float64)[m]
+        t, st = np.asarray(d.t, np.float64)[m], np.asarray(d.sigma_t, np.float64)[m]
+        nb = np.minimum(np.ceil(u + nsigma * su), pl.n_impacts * pl.n_wires) - np.maximum(np.floor(u - nsigma * su), 0)
+        nt = np.minimum(np.ceil(t + nsigma * st), pl.n_ticks) - np.maximum(np.floor(t - nsigma * st), 0)
+        total += int(np.sum(np.clip(nb, 0, None) * np.clip(nt, 0, None)))
+    return total
+
+
+def cpu_parallel_baseline(wl, n_sample_rows=30000):
+    """A CPU-parallel leg on this host's cores: the fluctuated raster vectorised in NumPy
+    (window weights by scipy's erf, counts by NumPy's binomial generator, scatter-add by
+    bincount) over thread-pool chunks, and the FFT convolution by scipy.fft with
+    workers = all cores; timed on a sample of rows and one full plane, scaled to the event.
+    Not bit-identical to the draw stream of the GPU and the oracle (its own generator): a
+    throughput baseline only."""
+    import numpy as np
+    import scipy.fft as sfft
+    from concurrent.futures import ThreadPoolExecutor
+    from scipy.special import erf
+    cores = os.cpu_count() or 1
+    d = wl.depos
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(len(d.q), min(n_sample_rows, len(d.q)), replace=False))
+
+    def axis(mu, sig, n, width):
+        lo, hi = mu - 3 * sig, mu + 3 * sig
+        k0 = np.maximum(np.floor(lo), 0)
+        k = k0[:, None] + np.arange(width)[None, :]
+        e0, e1 = np.maximum(k, lo[:, None]), np.minimum(k + 1, hi[:, None])
+        w = 0.5 * (erf((e1 - mu[:, None]) / (sig[:, None] * np.sqrt(2))) - erf((e0 - mu[:, None]) / (sig[:, None] * np.sqrt(2))))
+        ok = (k < np.minimum(np.ceil(hi), n)[:, None]) & (e1 > e0)
+        return k.astype(np.int64), np.where(ok, w, 0.0)
+
+    def chunk(rows, seed):
+        g = np.random.default_rng(seed)
+        out = 0
+        for k, pl in enumerate(wl.planes):
+            r = rows[np.asarray(d.plane)[rows] == k]
+            if r.size == 0:
+                continue
+            u, su = pl.n_impacts * d.p[r].astype(np.float64), pl.n_impacts * d.sigma_p[r].astype(np.float64)
+            t, st = d.t[r].astype(np.float64), d.sigma_t[r].astype(np.float64)
+            bi, a = axis(u, su, pl.n_impacts * pl.n_wires, int(np.ceil(6 * su.max())) + 2)
+            ki, b = axis(t, st, pl.n_ticks, int(np.ceil(6 * st.max())) + 2)
+            p = a[:, :, None] * b[:, None, :]
+            n = g.binomial(np.floor(d.q[r].astype(np.float64) + 0.5).astype(np.int64)[:, None, None], p)
+            cell = bi[:, :, None] * pl.n_ticks + ki[:, None, :]
+            keep = n > 0
+            out += int(np.bincount(cell[keep], weights=n[keep]).size)
+        return out
+
+    parts = np.array_split(idx, cores * 4)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        list(ex.map(chunk, parts, range(len(parts))))
+    t_r = time.perf_counter() - t0
+    # convolution of the first plane: 10 impact phases, rfft2 of each padded phase grid
+    # times the response kernel, summed, inverse (scipy.fft, all cores)
+    pl = wl.planes[0]
+    lw, lt = sfft.next_fast_len(pl.n_wires + pl.half_wires), sfft.next_fast_len(pl.n_ticks + pl.resp_ticks - 1)
+    S = np.zeros((pl.n_impacts, lw, lt), np.float32)
+    S[:, : pl.n_wires, : pl.n_ticks] = 1.0
+    K = np.zeros((pl.n_impacts, lw, lt), np.float32)
+    K[:, : 2 * pl.half_wires + 1, : pl.resp_ticks] = np.transpose(wl.responses[0], (1, 0, 2))
+    t0 = time.perf_counter()
+    acc = np.sum(sfft.rfft2(S, workers=cores) * sfft.rfft2(K, workers=cores), axis=0)
+    sfft.irfft2(acc, s=(lw, lt), workers=cores)
+    t_c = time.perf_counter() - t0
+    cells = sum(p.n_impacts * p.n_wires for p in wl.planes) / pl.n_impacts / pl.n_wires
+    t_event = t_r * len(d.q) / len(idx) + t_c * cells
+    return {"value": wl.n_depos / t_event, "unit": "depos/s", "cores": cores, "kind": "cpu-parallel",
+            "sample": (f"vectorised NumPy fluctuated raster of {len(idx)} of {len(d.q)} depo-plane rows in "
+                       f"{cores} threads ({t_r:.2f} s) + scipy.fft convolution of the {pl.n_wires}-wire plane "
+                       f"with workers={cores} ({t_c:.2f} s), scaled to the full event ({t_event:.2f} s/event); "
+                       f"FP64 raster, FP32 transforms; its own random stream"),
+            "seconds_measured": t_r + t_c}
+
+
+PAPER_CONTEXT = {
+    "note": "the paper's timings of the rasterisation step (2D sampling + fluctuation) on ~100k depositions "
+            "(Sec. 3), other hardware, context only; no FFT convolution timing is published",
+    "ref_cpu_serial_s": {"value": 3.57, "hardware": "AMD Threadripper 3960X, 1 thread", "source": "Table 2"},
+    "ref_cuda_s": {"value": 1.22, "hardware": "NVIDIA V100 + host, one depo per launch", "source": "Table 2"},
+    "kokkos_omp_1thread_s": {"value": 0.29, "hardware": "3960X, pre-computed RNG", "source": "Table 3"},
+    "kokkos_cuda_s": {"value": 2.31, "hardware": "NVIDIA V100", "source": "Table 3"},
+}
+
+
 def fwd_bwd_ratio(wct, synth, steps=10):
     import torch
     wl = synth.config4()
@@ -332,6 +502,9 @@ def batch_bench(wct, synth, sub_batch=16, reps=2):
     we = plan.wave_elems
     wave_b = plan.new_wave(n_ev)
     wave_l = plan.new_wave(n_ev)
+    plan.tune(1)
+    plan.tune_raster(dd, wct.opts(wl.nsigma, True, 4, wl.seed))  # on the rows of the first four events
+    torch.cuda.empty_cache()
     plan.workspace(wct.OP_SIMULATE, sub_batch, dd.n)
     o_all = wct.opts(wl.nsigma, True, n_ev, wl.seed)
     singles = [(dd.slice(int(starts[e]), int(starts[e + 1])), wct.opts(wl.nsigma, True, 1, wl.seed, event_base=e),
@@ -381,6 +554,8 @@ def shower_bench(wct, synth, tune_cache=None, steps=3):
     plan.tune(1, tune_cache)
     dd = wct.DeviceDepos.from_numpy(wl.depos, "cuda:0", torch.float32)
     o = wct.opts(wl.nsigma, True, 1, wl.seed)
+    tile = {v["index"]: v for v in wct.tile_variants()}[plan.tune_raster(dd, o, tune_cache)]
+    alg = algorithmic_bytes(plan)
     wave = plan.new_wave(1)
     plan.workspace(wct.OP_SIMULATE, 1, dd.n)
     plan.simulate(dd, o, wave)
@@ -400,13 +575,88 @@ def shower_bench(wct, synth, tune_cache=None, steps=3):
     kernels = {k: tot / steps for k, (tot, _) in sorted(kt.items(), key=lambda kv: -kv[1][0])}
     t_tile = kernels.get("raster_tile_fluct", 0.0)
     ops = raster_alu_ops(wl)
+    passes = ("rows_r2c", "colpass", "rows_c2r")
+    t_conv = sum(kernels.get(k, 0.0) for k in passes)
+    conv_bytes = sum(alg[k] for k in passes)
+    conv_gbs = conv_bytes / (t_conv * 1e-3) / 1e9
     return {"workload": "2 faces x (800+800+960 wires) x 6000 ticks, 10 impacts/pitch, 1e6 depositions in "
                         "20 seeded showers, binomial fluctuation on, FP32",
             "ms_per_event": ms, "depos_per_s": wl.n_depos / (ms * 1e-3),
             "t_raster_ms": sum(v for k, v in kernels.items() if k.startswith("raster")),
-            "t_conv_ms": sum(v for k, v in kernels.items() if k in ("rows_r2c", "colpass", "rows_c2r")),
+            "t_conv_ms": t_conv,
             "kernels_ms": kernels,
+            "raster_tile": {"rows": tile["th"], "ticks": tile["tw"], "blocks_per_cu": tile["blocks_per_cu"]},
+            "conv_roofline": {"bound": "hbm", "achieved": conv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": conv_gbs / HBM_PEAK_GBS, "alg_bytes": conv_bytes,
+                              "per_pass": {k: {"ms": kernels.get(k), "GBps": alg[k] / (kernels[k] * 1e-3) / 1e9,
+                                               "frac": alg[k] / (kernels[k] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                                           for k in passes if kernels.get(k)},
+                              "note": "algorithmic bytes of the three transform passes (read S, S-hat, M-hat once, "
+                                      "write each once) / their summed time"},
             "tile_raster_alu_frac": ops / (t_tile * 1e-3) / 1e12 / ALU_PEAK_TOPS if t_tile > 0 else None}
+
+
+def raster_atomics(wct, wl, t_mean_ms, t_fluct_ms):
+    """The raster's atomic adds against the chip's peaks (the probes): the mean raster makes
+    one LDS add per window cell (counted on the host); the fluctuated raster's LDS and
+    device-memory atomic instructions come from the committed counters of this build."""
+    lds_peak, _ = wct.probe_atomic_add("lds", blocks=2048, iters=256)
+    glob_peak, _ = wct.probe_atomic_add("global", blocks=2048, iters=32, buf_elems=2048 * 256 * 2)
+    out = {"lds_peak_adds_per_s": lds_peak, "global_peak_adds_per_s": glob_peak,
+           "probe": "wct_probe_atomic_add: 2048 blocks x 256 threads, a wave's 64 lanes on 64 consecutive floats; "
+                    "device-memory adds over a 4 MiB buffer (L2)"}
+    if t_mean_ms:
+        cells = window_cells(wl)
+        rate = cells / (t_mean_ms * 1e-3)
+        out["mean_raster"] = {"lds_adds": cells, "ms": t_mean_ms, "adds_per_s": rate, "frac_of_lds_peak": rate / lds_peak}
+    c = measured_counters("raster_tile_fluct")
+    if c and t_fluct_ms:
+        lds_i = c["SQ_INSTS_LDS_ATOMIC"]
+        out["fluct_raster"] = {"lds_atomic_instructions": lds_i,
+                               "lds_atomic_lane_ops_upper": 64 * lds_i,
+                               "frac_of_lds_peak_upper": 64 * lds_i / (t_fluct_ms * 1e-3) / lds_peak,
+                               "l2_atomics": c["TCC_ATOMIC"],
+                               "note": "counters of the committed profile for this build; lane ops bounded by 64 per "
+                                       "wave instruction"}
+    return out
+
+
+def raster_issue(t_ms, alg_ops):
+    """Issued instructions of the fluctuated tile raster (committed counters of this build)
+    against the cost model's lane operations."""
+    c = measured_counters("raster_tile_fluct")
+    if not c or not t_ms:
+        return None
+    slots = 64 * c["SQ_INSTS_VALU"]
+    return {"valu_instructions": c["SQ_INSTS_VALU"], "salu_instructions": c["SQ_INSTS_SALU"],
+            "lds_instructions": c["SQ_INSTS_LDS"], "lane_use": c.get("lane_use"),
+            "valu_lane_slots_per_alg_op": slots / alg_ops if alg_ops else None,
+            "issued_per_s": (c["SQ_INSTS_VALU"] + c["SQ_INSTS_SALU"]) / (t_ms * 1e-3)}
+
+
+def noise_cost(wct, synth, plan, dd, wl, wave, steps=3):
+    """The headline step with each plane's noise (Eq. 1's N term) added: time per step and
+    the inverse row transform's time with and without it."""
+    import torch
+    for p in range(len(wl.planes)):
+        plan.set_noise(p, synth.noise_amplitude(plan.plane_info(p)["lt"], 300.0))
+    on = wct.opts(wl.nsigma, True, 1, wl.seed, noise=True)
+    plan.simulate(dd, on, wave)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.profile_reset()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.simulate(dd, on, wave)
+    e1.record()
+    torch.cuda.synchronize()
+    k = plan.profile_read()
+    plan.profile(False)
+    for p in range(len(wl.planes)):
+        plan.set_noise(p, None)
+    return {"ms_per_step": e0.elapsed_time(e1) / steps, "rows_c2r_ms": k["rows_c2r"][0] / steps,
+            "spectrum": "synth.noise_amplitude(L_t, rms=300): shaped electronics-like noise, white floor 5%"}
 
 
 def main():
@@ -449,14 +699,16 @@ def main():
 
     wl = synth.config2()
     plan = wct.Plan(wl.planes, synth.round_responses(wl), dtype="f32")
+    dd = wct.DeviceDepos.from_numpy(wl.depos, "cuda:0", torch.float32)
+    o = wct.opts(wl.nsigma, True, 1, wl.seed)
     fft_choice = plan.tune(1, args.tune_cache)  # transform variant per plane and axis, timed on this GPU
+    tile = plan.tune_raster(dd, o, args.tune_cache)  # raster tile shape, timed on this event's rows
+    tiles = {v["index"]: v for v in wct.tile_variants()}
     variants = {v["index"]: v for v in wct.fft_variants()}
     fft_desc = {f"plane{p}_{'ticks' if k == 0 else 'wires'}":
                 ("direct 21-wire sums" if v == wct.WCT_WIRE_DIRECT else "runtime" if v < 0
                  else f"{variants[v]['threads']} threads, radices {variants[v]['radices']}")
                 for (p, k), v in sorted(fft_choice.items())}
-    dd = wct.DeviceDepos.from_numpy(wl.depos, "cuda:0", torch.float32)
-    o = wct.opts(wl.nsigma, True, 1, wl.seed)
     wave = plan.new_wave(1)
     plan.workspace(wct.OP_SIMULATE, 1, dd.n)
     for _ in range(args.warmup):
@@ -474,7 +726,14 @@ def main():
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
     kt = plan.profile_read()
+    # after the timed region: the mean raster of the same event (its LDS adds for the
+    # atomic-throughput evidence), then the same step with noise added
+    plan.profile_reset()
+    plan.raster(dd, wct.opts(wl.nsigma, False, 1, wl.seed))
+    torch.cuda.synchronize()
+    t_mean = plan.profile_read().get("raster_tile_mean", (None, 0))[0]
     plan.profile(False)
+    noise = noise_cost(wct, synth, plan, dd, wl, wave)
 
     n_depos = wl.n_depos
     n_planes = len(wl.planes)
@@ -538,6 +797,13 @@ def main():
         "roofline": roofline,
         "roofline_fft": roofline_fft,
         "fft_plans": fft_desc,
+        "raster_tile": {"rows": tiles[tile]["th"], "ticks": tiles[tile]["tw"],
+                        "blocks_per_cu": tiles[tile]["blocks_per_cu"]},
+        "raster_atomics": raster_atomics(wct, wl, t_mean, kernels.get("raster_tile_fluct", {}).get("ms_per_step")),
+        "raster_issue": raster_issue(kernels.get("raster_tile_fluct", {}).get("ms_per_step"),
+                                     roofline.get("alg_ops_per_launch")),
+        "noise": noise,
+        "paper_context": PAPER_CONTEXT,
         "build": built_digest(),
     }
     plan.close()
@@ -549,6 +815,7 @@ def main():
         cb = cpu_baseline(wl)
         cb["cores_available"] = os.cpu_count()
         out["cpu_baseline"] = cb
+        out["cpu_parallel"] = cpu_parallel_baseline(wl)
     print(json.dumps(out), flush=True)
 
 

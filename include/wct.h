@@ -248,10 +248,10 @@ int wct_plan_get_fft(const wct_plan* plan, int32_t plane, int32_t kind, int32_t*
 int wct_plan_set_fft(wct_plan* plan, int32_t plane, int32_t kind, int32_t variant);
 
 /* Autotuning of the transform variants: for every plane and kind, times the
- * convolution of n_events events of constant charge (HIP events on `stream`, after a
- * warm-up)
- * with each applicable compiled variant and with the runtime plan (wires: and the
- * direct sum), and keeps the fastest.  cache_path (HOST string, NULL = none) names a text file of earlier choices:
+ * convolution of n_events events of constant charge (HIP events on `stream`) with each
+ * applicable compiled variant and with the runtime plan (wires: and the direct sum), and
+ * keeps the fastest.  The candidates take turns: four rounds of three runs each, the
+ * first round a warm-up, a candidate's time its fastest later round.  cache_path (HOST string, NULL = none) names a text file of earlier choices:
  * lines "wct-fft <dtype> <N_w> <N_t> <I> <K> <T_R> kind <k> -> <threads> <radices...>"
  * (or "-> runtime", "-> direct"); choices found there for this library's variants are applied
  * without timing, new ones are appended.  ws: wct_tune_workspace_bytes(plan, n_events)
@@ -274,8 +274,8 @@ int wct_tile_variant_info(int32_t idx, int32_t* out);
 int wct_plan_get_tile(const wct_plan* plan, int32_t* variant);
 int wct_plan_set_tile(wct_plan* plan, int32_t variant);
 
-/* Autotuning of the raster tile: times wct_raster of `depos` with `opts` (one warm-up,
- * three timed runs on `stream`, HIP events) for every tile variant of the plan's dtype and
+/* Autotuning of the raster tile: times wct_raster of `depos` with `opts` (HIP events on
+ * `stream`; turns as in wct_plan_tune) for every tile variant of the plan's dtype and
  * keeps the fastest.  cache_path (HOST, NULL = none): the same text file as
  * wct_plan_tune, lines "wct-tile <dtype> <n_planes> (<N_w> <N_t> <I>)... fluct <0|1> ->
  * <TH> <TW> <blocks>"; a choice found there is applied without timing, a new one is

@@ -623,6 +623,43 @@ int plan_tables(wct_plan* P, const wct_plan_desc* desc) {
   return WCT_OK;
 }
 
+// Position of variant v in a candidate list (v is in it).
+size_t best_at(const std::vector<int>& cand, int v) {
+  size_t i = 0;
+  while (cand[i] != v) ++i;
+  return i;
+}
+
+// Timing of the tuners' candidates: the candidates run in turn for kRounds rounds of kReps
+// back-to-back runs each; the first round only warms up (clocks ramp, caches fill), and a
+// candidate's time is its fastest later round.  Taking turns keeps a slow start of the
+// device, or load from elsewhere, from favouring the candidates timed last.
+template <typename SetF, typename RunF>
+int time_round_robin(const std::vector<int>& cand, SetF set_variant, RunF run_once, hipStream_t st,
+                     std::vector<float>* ms_out) {
+  constexpr int kRounds = 4, kReps = 3;
+  ms_out->assign(cand.size(), 0.f);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  int rc = e == hipSuccess ? WCT_OK : fail(WCT_E_DEVICE, "event create: %s", hipGetErrorString(e));
+  for (int round = 0; round < kRounds && rc == WCT_OK; ++round) {
+    for (size_t c = 0; c < cand.size() && rc == WCT_OK; ++c) {
+      if ((rc = set_variant(cand[c]))) break;
+      if (hipEventRecord(e0, st) != hipSuccess) rc = fail(WCT_E_DEVICE, "event record");
+      for (int rep = 0; rep < kReps && rc == WCT_OK; ++rep) rc = run_once();
+      float ms = 0.f;
+      if (rc == WCT_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(WCT_E_DEVICE, "timing the tuner's candidates failed");
+      if (rc == WCT_OK && round > 0 && (round == 1 || ms < (*ms_out)[c])) (*ms_out)[c] = ms;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return rc;
+}
+
 // Autotuning of the transform variants -------------------------------------------------
 // Cache file: one line per (geometry, dtype, kind) with the chosen variant's threads and
 // radices ("runtime" for the runtime plan), e.g.
@@ -671,20 +708,9 @@ int run_tune(wct_plan* P, int n_events, const char* cache_path, void* ws, hipStr
                           0x3ff00000, st),
           "tune grid fill");
   auto cache = read_tune_cache(cache_path);
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0), "event create");
-  HIP_TRY(hipEventCreate(&e1), "event create");
-  auto time_conv = [&](float* ms) -> int {
-    for (int rep = 0; rep < 4; ++rep) {
-      if (rep == 1) HIP_TRY(hipEventRecord(e0, st), "event record");
-      Carver cc(static_cast<char*>(ws) + conv_off);
-      const int rc = run_convolve<T>(P, grid, n_events, wave, cc, st);
-      if (rc) return rc;
-    }
-    HIP_TRY(hipEventRecord(e1, st), "event record");
-    HIP_TRY(hipEventSynchronize(e1), "event sync");
-    HIP_TRY(hipEventElapsedTime(ms, e0, e1), "event time");
-    return WCT_OK;
+  auto run_once = [&]() -> int {
+    Carver cc(static_cast<char*>(ws) + conv_off);
+    return run_convolve<T>(P, grid, n_events, wave, cc, st);
   };
   int cnt = 0;
   const FftVariantDesc* vd = fft_variants(&cnt);
@@ -706,15 +732,13 @@ int run_tune(wct_plan* P, int n_events, const char* cache_path, void* ws, hipStr
         for (int v : cand)
           if (variant_text(v) == it->second) best = v;
       if (best == kNone) {
-        float best_ms = 0.f, best_fft_ms = 0.f;
-        for (int v : cand) {
-          if ((rc = set_fft<T>(P, p, kind, v))) break;
-          float ms = 0.f;
-          if ((rc = time_conv(&ms))) break;
-          if (best == kNone || ms < best_ms) best = v, best_ms = ms;
-          if (v != WCT_WIRE_DIRECT && (best_fft == kNone || ms < best_fft_ms)) best_fft = v, best_fft_ms = ms;
+        std::vector<float> ms;
+        if ((rc = time_round_robin(cand, [&](int v) { return set_fft<T>(P, p, kind, v); }, run_once, st, &ms))) break;
+        for (size_t c = 0; c < cand.size(); ++c) {
+          if (best == kNone || ms[c] < ms[best_at(cand, best)]) best = cand[c];
+          if (cand[c] != WCT_WIRE_DIRECT && (best_fft == kNone || ms[c] < ms[best_at(cand, best_fft)]))
+            best_fft = cand[c];
         }
-        if (rc) break;
         appended += key + " -> " + variant_text(best) + "\n";
         cache[key] = variant_text(best);  // planes of the same geometry take the same choice
       }
@@ -724,8 +748,6 @@ int run_tune(wct_plan* P, int n_events, const char* cache_path, void* ws, hipStr
       if (rc == WCT_OK) rc = set_fft<T>(P, p, kind, best);
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   if (rc) return rc;
   if (cache_path && !appended.empty()) {
     FILE* f = std::fopen(cache_path, "a");
@@ -788,30 +810,17 @@ int run_tune_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, const ch
       if (tile_text(v) == it->second) return set_tiles(P, v);
   T* grid = static_cast<T*>(ws);
   char* rws = static_cast<char*>(ws) + align_up(P->esize * (size_t)o->n_events * P->grid_elems, 256);
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0), "event create");
-  HIP_TRY(hipEventCreate(&e1), "event create");
-  int best = -1, rc = WCT_OK;
-  float best_ms = 0.f;
-  for (int v : cand) {
-    if ((rc = set_tiles(P, v))) break;
-    float ms = 0.f;
-    for (int rep = 0; rep < 4 && rc == WCT_OK; ++rep) {  // one warm-up, three timed
-      if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) rc = fail(WCT_E_DEVICE, "event record");
-      Carver cv(rws);
-      if (rc == WCT_OK) rc = run_raster<T>(P, d, o, grid, cv, st);
-    }
-    if (rc) break;
-    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-      rc = fail(WCT_E_DEVICE, "timing the raster tile variants failed");
-      break;
-    }
-    if (best < 0 || ms < best_ms) best = v, best_ms = ms;
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  std::vector<float> ms;
+  int rc = time_round_robin(cand, [&](int v) { return set_tiles(P, v); },
+                            [&]() -> int {
+                              Carver cv(rws);
+                              return run_raster<T>(P, d, o, grid, cv, st);
+                            },
+                            st, &ms);
   if (rc) return rc;
+  int best = cand[0];
+  for (size_t c = 1; c < cand.size(); ++c)
+    if (ms[c] < ms[best_at(cand, best)]) best = cand[c];
   if ((rc = set_tiles(P, best))) return rc;
   if (cache_path) {
     FILE* f = std::fopen(cache_path, "a");

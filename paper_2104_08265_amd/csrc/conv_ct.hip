@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_ct(const
 // written together, so each chunk of C frequencies goes out as 2C contiguous values
 // (64 bytes in FP32) instead of two separate C-value pieces.  LDS: the transform buffer
 // plus one staged spectrum.
-template <typename T, int C, typename F, bool FLAGS>
+template <typename T, int C, typename F>
 __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(const T* __restrict__ src,
                                                                   int64_t src_ev_stride, cx<T>* __restrict__ dst,
                                                                   int64_t dst_ev_stride, int nt, int nphase, int nper,
@@ -172,8 +172,9 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
     return X;
   };
   auto post_at = [&](int k) { return k <= M ? post[k] : mk(T(0), T(0)); };
-  // With row flags (FLAGS), a pair whose two rows no window reached is neither loaded nor
-  // transformed: its zero spectrum is written directly.  Each wave reads the flags of its
+  // With row flags (live != NULL), a pair whose two rows no window reached is neither
+  // loaded nor transformed: its zero spectrum is written directly.  Without them every pair
+  // is transformed (one kernel serves both: the test of `live` is uniform).  Each wave reads the flags of its
   // block's next kSpan pairs at once (lane j: the pair j iterations on) and keeps the
   // answers as a ballot mask, so the per-pair test is a bit of a scalar register.  kSpan is
   // the lane count of the block's last wave, which is partial when NT is not a multiple of 64.
@@ -187,7 +188,7 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
   unsigned long long mask = 0;
   int left = 0;  // unused bits of mask
   auto live_at = [&](int Q) -> bool {  // called once per iteration, in order; Q: its pair
-    if constexpr (!FLAGS) {
+    if (!live) {
       return true;
     } else {
       if (left == 0) {
@@ -213,7 +214,7 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
     // chunk q of the pair: [q][i][c .. c + 1][C], 2C contiguous values
     cx<T>* o = dst + ev * dst_ev_stride + ((int64_t)i * nper + c) * C;
     const int64_t cstride = (int64_t)nphase * nper * C;
-    if constexpr (FLAGS) {
+    {
       if (!liveP) {
         if (liveN) load(Pn, 0);
         for (int x = threadIdx.x; x < 2 * fpad; x += NT) {
@@ -510,12 +511,8 @@ hipError_t launch_rows_r2c_ct(const T* src, int64_t src_ev_stride, cx<T>* dst, i
   const hipError_t e = with_variant<T, 0>(plan.variant, [&](auto f) {
     using F = decltype(f);
     const dim3 pgrid(persistent_blocks(n_cu, lds_pair, F::kThreads, total / 2));
-    if (pair && live)
-      hipLaunchKernelGGL((k_rows_r2c_pair_ct<T, kChunk, F, true>), pgrid, dim3(F::kThreads), lds_pair, st, src,
-                         src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, n_events, tw, post, live,
-                         live_ev);
-    else if (pair)
-      hipLaunchKernelGGL((k_rows_r2c_pair_ct<T, kChunk, F, false>), pgrid, dim3(F::kThreads), lds_pair, st, src,
+    if (pair)
+      hipLaunchKernelGGL((k_rows_r2c_pair_ct<T, kChunk, F>), pgrid, dim3(F::kThreads), lds_pair, st, src,
                          src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, n_events, tw, post, live,
                          live_ev);
     else
@@ -582,9 +579,7 @@ static void raise_lds_limits_ct() {
     using F = decltype(f);
     (void)hipFuncSetAttribute((const void*)k_rows_r2c_ct<T, kChunk, F>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               lim);
-    (void)hipFuncSetAttribute((const void*)k_rows_r2c_pair_ct<T, kChunk, F, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)k_rows_r2c_pair_ct<T, kChunk, F, false>,
+    (void)hipFuncSetAttribute((const void*)k_rows_r2c_pair_ct<T, kChunk, F>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)k_rows_c2r_ct<T, kChunk, true, F, false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
