@@ -18,6 +18,9 @@ Acceleration Solutions for LArTPC Simulation Using Wire-Cell Toolkit"):
                  driven by a counter-based Philox4x32-10 stream (the RNG is factored out
                  of the main loop, Sec. 5) and an exact two-regime binomial sampler
                  that uses IEEE +,-,*,/ only.
+* ``normal``   - Sec. 4.3.1 (the Kokkos port's Box-Muller transform): a fluctuation mode
+                 that replaces each cell's binomial count by its normal approximation,
+                 the normals drawn by Box-Muller from the binomial mode's Philox blocks.
 * ``noise``    - Eq. 1's additive noise term N (Sec. 2): stationary noise per wire from
                  an amplitude spectrum and Philox-keyed complex normals, inverse real
                  transform along ticks.
@@ -28,5 +31,6 @@ Acceleration Solutions for LArTPC Simulation Using Wire-Cell Toolkit"):
 Pins (see tests/test_oracle_*.py): closed-form erf sums, charge conservation inside
 the window, brute-force direct convolution, delta / shift responses, linearity,
 padding invariance, adjoint identity, finite differences, the binomial law against
-scipy.stats.binom, and Philox against rocRAND's independent implementation.
+scipy.stats.binom, Philox against rocRAND's independent implementation, the Box-Muller
+normals against libm and the normal law.
 """
