@@ -52,8 +52,9 @@ COUNTERS_JSON = os.path.join(PROFILES, "raster_counters.json")
 def family(kernel_name):
     """Kernel family (the names of the per-kernel table) of a device kernel symbol."""
     n = kernel_name.split("(")[0]
-    if "k_tile<" in n:
-        return "raster_tile_fluct" if ", true," in n else "raster_tile_mean"
+    if "k_tile<" in n:  # k_tile<T, mode, ...>: 0 mean, 1 binomial, 2 normal approximation
+        mode = n.split("k_tile<", 1)[1].split(",")[1].strip()
+        return {"0": "raster_tile_mean", "1": "raster_tile_fluct", "2": "raster_tile_normal"}.get(mode)
     if "k_big<" in n:
         return "raster_wide_rows"
     if "k_rows_r2c" in n:
@@ -727,11 +728,20 @@ def main():
     ms = ev0.elapsed_time(ev1) / args.steps
     kt = plan.profile_read()
     # after the timed region: the mean raster of the same event (its LDS adds for the
-    # atomic-throughput evidence), then the same step with noise added
+    # atomic-throughput evidence), the normal-approximation raster (Box-Muller mode), then
+    # the same step with noise added
     plan.profile_reset()
     plan.raster(dd, wct.opts(wl.nsigma, False, 1, wl.seed))
     torch.cuda.synchronize()
     t_mean = plan.profile_read().get("raster_tile_mean", (None, 0))[0]
+    o_norm = wct.opts(wl.nsigma, wct.FLUCT_NORMAL, 1, wl.seed)
+    plan.raster(dd, o_norm)
+    plan.profile_reset()
+    for _ in range(3):
+        plan.raster(dd, o_norm)
+    torch.cuda.synchronize()
+    t_normal = plan.profile_read().get("raster_tile_normal", (None, 0))[0]
+    t_normal = t_normal / 3 if t_normal is not None else None
     plan.profile(False)
     noise = noise_cost(wct, synth, plan, dd, wl, wave)
 
@@ -803,6 +813,11 @@ def main():
         "raster_issue": raster_issue(kernels.get("raster_tile_fluct", {}).get("ms_per_step"),
                                      roofline.get("alg_ops_per_launch")),
         "noise": noise,
+        "fluct_modes": {"tile_ms": {"mean": t_mean, "binomial": kernels.get("raster_tile_fluct", {}).get("ms_per_step"),
+                                    "normal_box_muller": t_normal},
+                        "note": "k_tile time of the same event per raster mode (tile shape tuned for the "
+                                "binomial mode); the normal mode replaces each binomial count by its normal "
+                                "approximation with Box-Muller normals (Sec. 4.3.1)"},
         "paper_context": PAPER_CONTEXT,
         "build": built_digest(),
     }

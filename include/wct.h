@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define WCT_ABI_VERSION 4
+#define WCT_ABI_VERSION 5
 /* Version of the fluctuation draw stream (counter layout + sampler).  Bumped whenever a
  * change would alter any fluctuated count for the same inputs and seed. */
 #define WCT_FLUCT_SPEC_VERSION 2
@@ -107,7 +107,8 @@ typedef struct {
  * is simulated alone or inside a batch. */
 typedef struct {
   double nsigma;      /* truncation half-width of the Gaussian patch in sigmas, (0, 8] */
-  int32_t fluctuate;  /* 0: mean charge; 1: binomial electron counts (needs nsigma <= 4.2;
+  int32_t fluctuate;  /* 0: mean charge; 1: binomial electron counts; 2: their normal
+                         approximation with Box-Muller normals (1 and 2 need nsigma <= 4.2;
                          electron counts are 32-bit: a charge of 2^31 - 1 or more draws
                          as 2^31 - 1 electrons) */
   int32_t n_events;   /* events in this call: 1..max_events (wct_simulate: any >= 1) */
@@ -149,7 +150,13 @@ size_t wct_workspace_bytes(const wct_plan* plan, int32_t op, int32_t n_events, i
  * `seed`; cells (b, 2m) and (b, 2m+1) share the counter (b*ceil(N_t/2) + m, depo_id,
  * event, plane << 24), the even tick taking words 0-1 and the odd tick words 2-3; the
  * sampler is that of WCT_FLUCT_SPEC_VERSION (bit-reproducible, independent of
- * scheduling and batching; `event` is the row's event id).  Rows with sigma <= 0,
+ * scheduling and batching; `event` is the row's event id).  With fluctuate = 2 (the
+ * Kokkos port's Box-Muller normals, Sec. 4.3.1) a cell with N electrons and probability
+ * p receives min(max(floor(N p + sqrt(N p (1 - p)) z + 1/2), 0), N): the cells (b, 2m),
+ * (b, 2m+1) take z = r cos(2 pi u2) and r sin(2 pi u2) of the same Philox block, with
+ * r = sqrt(-2 ln u1), u1 = 1 - (the even tick's uniform), u2 = the odd tick's uniform;
+ * sqrt, ln, cos and sin are evaluated with IEEE +, -, *, / only, so these counts too are
+ * bit-reproducible.  Rows with sigma <= 0,
  * Q < 0 or non-finite values contribute nothing.  The whole grid of every event of the
  * window is overwritten. */
 int wct_raster(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* grid, void* ws,

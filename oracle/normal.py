@@ -87,11 +87,17 @@ def cell_normal(seed, plane, event, depo_id, b, k, n_ticks):
     c2 = np.asarray(event, np.uint64) + np.zeros_like(c0)
     c3 = (np.asarray(plane, np.uint64) << np.uint64(24)) + np.zeros_like(c0)
     w0, w1, w2, w3 = philox4x32_10(c0, c1, c2, c3, int(seed) & MASK32, (int(seed) >> 32) & MASK32)
+    z_even, z_odd = box_muller_words(w0, w1, w2, w3)
+    return np.where((k & 1) == 1, z_odd, z_even)
+
+
+def box_muller_words(w0, w1, w2, w3):
+    """The Box-Muller pair of one Philox block's words: (r cos theta, r sin theta)."""
     u1 = 1.0 - uniform53(w0, w1)
     u2 = uniform53(w2, w3)
     r = det_sqrt(-2.0 * det_log(u1))
     cos_t, sin_t = det_sincos2pi(u2)
-    return np.where((k & 1) == 1, r * sin_t, r * cos_t)
+    return r * cos_t, r * sin_t
 
 
 def normal_count(N, p, z):

@@ -308,7 +308,7 @@ int check_opts(const wct_plan* P, const wct_opts* o, bool need_nsigma, bool batc
   if (o->noise != 0 && o->noise != 1) return fail(WCT_E_INVALID, "noise must be 0 or 1");
   if (need_nsigma && !(o->nsigma > 0.0 && o->nsigma <= 8.0))
     return fail(WCT_E_INVALID, "nsigma %g outside (0, 8]", o->nsigma);
-  if (o->fluctuate != 0 && o->fluctuate != 1) return fail(WCT_E_INVALID, "fluctuate must be 0 or 1");
+  if (o->fluctuate < kModeMean || o->fluctuate > kModeNormal) return fail(WCT_E_INVALID, "fluctuate must be 0, 1 or 2");
   if (o->fluctuate && o->nsigma > 4.2)
     return fail(WCT_E_INVALID, "fluctuation needs nsigma <= 4.2 (the erf series range), got %g", o->nsigma);
   return WCT_OK;

@@ -315,4 +315,77 @@ WCT_HD int binom_regime_draw(int N, double lfN, double p, double u, const Tab& t
   return flip ? N - k : k;
 }
 
+// Normal-approximation mode (Sec. 4.3.1: the Kokkos port drew normal deviates with the
+// Box-Muller transform).  A cell's count is min(max(floor(N p + sqrt(N p (1 - p)) z + 1/2),
+// 0), N); the cells (b, 2m) and (b, 2m+1) take the two normals of one Box-Muller pair
+// from their shared Philox block: u1 = 1 - uniform53(words 0, 1) in (0, 1], u2 =
+// uniform53(words 2, 3), r = sqrt(-2 ln u1), z = r cos(2 pi u2) (even tick) and
+// r sin(2 pi u2) (odd tick).  sqrt, cos and sin below use +, -, *, / only, like the
+// sampler, so the counts are reproducible bit for bit.
+
+// sqrt(x), x >= 0: x = m 2^e with e even and m in [1/2, 2); seven Newton steps on
+// y = 1/sqrt(m) from y = 3/2 - m/2 (quadratic convergence from a start within 30%), then
+// sqrt(x) = (m y) 2^(e/2); within two units in the last place.
+constexpr int kRsqrtSteps = 7;
+WCT_HD double det_sqrt(double x) {
+  if (!(x > 0.0)) return 0.0;
+  int e;
+  double m = frexp(x, &e);
+  if (e & 1) {
+    m = m * 2.0;
+    e = e - 1;
+  }
+  double y = 1.5 - m * 0.5;
+#pragma unroll
+  for (int i = 0; i < kRsqrtSteps; ++i) y = y * (1.5 - ((m * y) * y) * 0.5);
+  return ldexp(m * y, e / 2);
+}
+
+// cos(2 pi u) and sin(2 pi u) for u in [0, 1): t = 4u (exact), quadrant j = floor(t),
+// f = t - j; g = 1 - f (exact) when f > 1/2, else f; x = g pi/2 in [0, pi/4]; sin x and
+// cos x by their Maclaurin series to x^15 and x^16 (Horner form, 1/j! correctly rounded);
+// the complement swaps the pair and the quadrant rotates it.
+constexpr double kHalfPi = 1.5707963267948966;
+WCT_HD void det_sincos2pi(double u, double* c_out, double* s_out) {
+  const double t = u * 4.0;
+  const double jf = floor(t);
+  const double f = t - jf;
+  const bool swap = f > 0.5;
+  const double g = swap ? 1.0 - f : f;
+  const double x = g * kHalfPi;
+  const double x2 = x * x;
+  double s = kDet.inv_fact[15];
+#pragma unroll
+  for (int n = 13; n >= 1; n -= 2) s = kDet.inv_fact[n] - x2 * s;
+  s = x * s;
+  double c = kDet.inv_fact[16];
+#pragma unroll
+  for (int n = 14; n >= 0; n -= 2) c = kDet.inv_fact[n] - x2 * c;
+  const double sp = swap ? c : s, cp = swap ? s : c;  // sin, cos of (pi/2) f
+  const int j = (int)jf;
+  *c_out = j == 0 ? cp : (j == 1 ? -sp : (j == 2 ? -cp : sp));
+  *s_out = j == 0 ? sp : (j == 1 ? cp : (j == 2 ? -sp : -cp));
+}
+
+// The two normals of a tick pair's Philox block (even tick first).
+WCT_HD void box_muller_pair(const Philox4& ph, double* z_even, double* z_odd) {
+  const double u1 = 1.0 - uniform53(ph.w0, ph.w1);
+  const double u2 = uniform53(ph.w2, ph.w3);
+  const double r = det_sqrt(-2.0 * det_log(u1));
+  double c, s;
+  det_sincos2pi(u2, &c, &s);
+  *z_even = r * c;
+  *z_odd = r * s;
+}
+
+// The normal approximation's count for N >= 0 electrons, probability p in [0, 1], normal z.
+WCT_HD int normal_count(int N, double p, double z) {
+  const double Nf = (double)N;
+  const double mu = Nf * p;
+  const double var = mu * (1.0 - p);
+  const double sd = det_sqrt(var > 0.0 ? var : 0.0);
+  const double x = floor((mu + sd * z) + 0.5);
+  return (int)(x < 0.0 ? 0.0 : (x > Nf ? Nf : x));
+}
+
 }  // namespace wct

@@ -107,10 +107,13 @@ struct ProfHook {
 };
 
 // raster.hip
+// Raster modes (the fluctuate option): the mean charge, binomial electron counts, or the
+// binomial's normal approximation with Box-Muller normals.
+constexpr int kModeMean = 0, kModeBinomial = 1, kModeNormal = 2;
 // lfact: ln(n!) for n < kLfactTable (launch_lfact_table), or NULL (evaluated per cell).
 // tile: index into WCT_TILE_VARIANTS (of type T); the geometry g was built for it.
 template <typename T>
-hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigma, int fluctuate, uint64_t seed,
+hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigma, int mode, uint64_t seed,
                          T* grid, const RasterWs& ws, const DetTables* tables, const double* lfact, int n_cu,
                          hipStream_t st, ProfHook* prof, int tile);
 hipError_t launch_lfact_table(double* out, int n, const DetTables* tables, hipStream_t st);

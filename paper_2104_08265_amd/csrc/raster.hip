@@ -93,7 +93,7 @@ __device__ __forceinline__ int find_plane(const RasterGeom& g, int tin) {
 // Both axes of a patch share one pass over the lanes: the impact edges [b0, b1] first,
 // then the tick edges [k0, k1] (a short tick window would leave most lanes idle in a
 // pass of its own).
-template <bool FLUCT>
+template <int MODE>
 __device__ __forceinline__ void edge_fill2(double* __restrict__ ea, int b0, int b1, double mua, double siga,
                                            double loa, double hia, double* __restrict__ eb, int k0, int k1,
                                            double mub, double sigb, double lob, double hib, int lane) {
@@ -104,7 +104,7 @@ __device__ __forceinline__ void edge_fill2(double* __restrict__ ea, int b0, int 
     const int i = a ? x : x - (na + 1), n = a ? na : nb, c0 = a ? b0 : k0, c1 = a ? b1 : k1;
     const double lo = a ? loa : lob, hi = a ? hia : hib, mu = a ? mua : mub, s2 = a ? s2a : s2b;
     const double edge = i == 0 ? fmax((double)c0, lo) : (i == n ? fmin((double)c1, hi) : (double)(c0 + i));
-    const double v = FLUCT ? det_erf((edge - mu) / s2) : erf((edge - mu) / s2);
+    const double v = MODE != kModeMean ? det_erf((edge - mu) / s2) : erf((edge - mu) / s2);
     (a ? ea : eb)[i] = v;
   }
 }
@@ -234,16 +234,41 @@ __device__ __forceinline__ void cell_route(RegQueue& qi, RegQueue& qc, bool pack
 // b*ceil(N_t/2) + m), words 0-1 for the even tick and 2-3 for the odd one.
 // PACKED: `qc` is the caller's chop-down queue of a whole work item (entries carry their
 // count; the caller empties it at the item's end); otherwise it is emptied here.
-template <typename T, bool FLUCT, bool PACKED, typename Dst, typename Add>
+template <typename T, int MODE, bool PACKED, typename Dst, typename Add>
 __device__ __forceinline__ void patch_cells(const RowWin& w, int b0, int b1, int k0, int k1, int nt, uint32_t did,
                                             uint32_t ev, uint32_t plane, uint32_t key0, uint32_t key1,
                                             double* __restrict__ ea, double* __restrict__ eb,
                                             const DetTablesSmall& tb, const double* __restrict__ lf, int lane, Dst dst,
                                             Add add, RegQueue& qc) {
   const int nbr = b1 - b0, nkr = k1 - k0;
-  edge_fill2<FLUCT>(ea, b0, b1, w.u, w.su, w.ulo, w.uhi, eb, k0, k1, w.t, w.st, w.tlo, w.thi, lane);
+  edge_fill2<MODE>(ea, b0, b1, w.u, w.su, w.ulo, w.uhi, eb, k0, k1, w.t, w.st, w.tlo, w.thi, lane);
   wave_sync();
-  if (!FLUCT) {
+  if (MODE == kModeNormal) {
+    // each cell's count from its own normal: no search, no queue
+    const int N = __builtin_amdgcn_readfirstlane((int)floor(fmin(w.q + 0.5, 2147483647.0)));
+    if (N > 0) {
+      const int j0 = k0 >> 1, np = ((k1 - 1) >> 1) - j0 + 1;
+      const uint32_t half_nt = (uint32_t)((nt + 1) >> 1);
+      const float rd = 1.0f / (float)np;
+      for (int x = lane; x < nbr * np; x += 64) {
+        const int bi = div_small(x, np, rd), pj = x - bi * np;
+        const int b = b0 + bi, m = j0 + pj;
+        const Philox4 ph = philox4x32_10((uint32_t)b * half_nt + (uint32_t)m, did, ev, plane << 24, key0, key1);
+        double ze, zo;
+        box_muller_pair(ph, &ze, &zo);
+        const double a = edge_weight(ea, bi);
+        const int ke = 2 * m, ko = 2 * m + 1;
+        if (ke >= k0) {
+          const int n = normal_count(N, a * edge_weight(eb, ke - k0), ze);
+          if (n > 0) add(dst(b, ke), (T)n);
+        }
+        if (ko < k1) {
+          const int n = normal_count(N, a * edge_weight(eb, ko - k0), zo);
+          if (n > 0) add(dst(b, ko), (T)n);
+        }
+      }
+    }
+  } else if (MODE == kModeMean) {
     const float rd = 1.0f / (float)nkr;
     for (int x = lane; x < nbr * nkr; x += 64) {
       const int bi = div_small(x, nkr, rd), ki = x - bi * nkr;
@@ -541,7 +566,7 @@ __global__ void k_zero_split(RasterGeom g, const int32_t* __restrict__ counts, i
 // in LDS and written out) and a group of kZeroGroup consecutive tiles, of which those no
 // row touches are cleared.  The clearing stores (HBM-bound) then overlap the arithmetic
 // of the rows instead of costing work items of their own.
-template <typename T, bool FLUCT, int TH, int TW, int OCC>
+template <typename T, int MODE, int TH, int TW, int OCC>
 __global__ void __launch_bounds__(256, OCC) k_tile(DepoView<T> d, RasterGeom g, double nsigma, uint64_t seed,
                                               T* __restrict__ grid, const int32_t* __restrict__ list,
                                               const int32_t* __restrict__ offs, const int32_t* __restrict__ items,
@@ -556,7 +581,7 @@ __global__ void __launch_bounds__(256, OCC) k_tile(DepoView<T> d, RasterGeom g, 
   __shared__ DetTablesSmall s_tb;
   __shared__ int s_item, s_zero, s_row;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (FLUCT) {
+  if (MODE == kModeBinomial) {
     for (int x = threadIdx.x; x < 129; x += blockDim.x) s_tb.inv[x] = tables->inv[x];
     for (int x = threadIdx.x; x < 19; x += blockDim.x) s_tb.fact[x] = tables->fact[x];
   }
@@ -621,10 +646,10 @@ __global__ void __launch_bounds__(256, OCC) k_tile(DepoView<T> d, RasterGeom g, 
       const int kk0 = max(w.k0, tk0), kk1 = min(w.k1, tk0 + tw);
       if (!w.ok || bb0 >= bb1 || kk0 >= kk1) continue;
       const uint32_t did = d.depo_id ? (uint32_t)d.depo_id[j] : (uint32_t)j;
-      patch_cells<T, FLUCT, true>(w, bb0, bb1, kk0, kk1, pl.nt, did, (uint32_t)w.key_event, (uint32_t)pi, key0, key1,
+      patch_cells<T, MODE, true>(w, bb0, bb1, kk0, kk1, pl.nt, did, (uint32_t)w.key_event, (uint32_t)pi, key0, key1,
                                   s_ea[wv], s_eb[wv], s_tb, lf, lane, dst, add, qc);
     }
-    if (FLUCT && qc.n > 0) rq_run_chop<T>(qc, qc.n, 0, true, lane, s_tb, lf, add);
+    if (MODE == kModeBinomial && qc.n > 0) rq_run_chop<T>(qc, qc.n, 0, true, lane, s_tb, lf, add);
     __syncthreads();
     T* gp = grid + (int64_t)ev * g.grid_ev_stride + pl.grid_off;
     for (int x = threadIdx.x; x < th * TW; x += blockDim.x) {
@@ -643,7 +668,7 @@ __global__ void __launch_bounds__(256, OCC) k_tile(DepoView<T> d, RasterGeom g, 
 }
 
 // 5. rows wider than 4 tiles: 64 x 64 chunks per wave, straight to global atomics ------
-template <typename T, bool FLUCT>
+template <typename T, int MODE>
 __global__ void __launch_bounds__(256, 3) k_big(DepoView<T> d, RasterGeom g, double nsigma, uint64_t seed,
                                              T* __restrict__ grid, const int32_t* __restrict__ big,
                                              const int32_t* __restrict__ ctrl, const DetTables* __restrict__ tables,
@@ -653,7 +678,7 @@ __global__ void __launch_bounds__(256, 3) k_big(DepoView<T> d, RasterGeom g, dou
   __shared__ double s_eb[NWAVE][CK + 1];
   __shared__ DetTablesSmall s_tb;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (FLUCT) {
+  if (MODE == kModeBinomial) {
     for (int x = threadIdx.x; x < 129; x += blockDim.x) s_tb.inv[x] = tables->inv[x];
     for (int x = threadIdx.x; x < 19; x += blockDim.x) s_tb.fact[x] = tables->fact[x];
     __syncthreads();
@@ -678,7 +703,7 @@ __global__ void __launch_bounds__(256, 3) k_big(DepoView<T> d, RasterGeom g, dou
       const int k0 = max(kstart + ck * CK, w.k0), k1 = min(kstart + (ck + 1) * CK, w.k1);
       RegQueue qc;
       qc.n = 0;
-      patch_cells<T, FLUCT, false>(w, b0, b1, k0, k1, pl.nt, did, (uint32_t)w.key_event, (uint32_t)w.plane, key0, key1,
+      patch_cells<T, MODE, false>(w, b0, b1, k0, k1, pl.nt, did, (uint32_t)w.key_event, (uint32_t)w.plane, key0, key1,
                                    s_ea[wv], s_eb[wv], s_tb, lf, lane, dst, add, qc);
     }
   }
@@ -700,7 +725,7 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
   } while (0)
 
 template <typename T, int TH, int TW, int OCC>
-hipError_t launch_raster_tiles(const DepoView<T>& d, const RasterGeom& g, double nsigma, int fluctuate, uint64_t seed,
+hipError_t launch_raster_tiles(const DepoView<T>& d, const RasterGeom& g, double nsigma, int mode, uint64_t seed,
                                T* grid, const RasterWs& ws, const DetTables* tables, const double* lfact, int n_cu,
                                hipStream_t st, ProfHook* prof) {
   const int64_t nt = ws.ntiles;
@@ -738,37 +763,47 @@ hipError_t launch_raster_tiles(const DepoView<T>& d, const RasterGeom& g, double
   WCT_CHECK_LAUNCH();
   if (prof) prof->end(st);
   const unsigned pblocks = (unsigned)(n_cu * OCC);  // the blocks that fit a CU at once (LDS, registers)
-  if (prof) prof->begin(fluctuate ? "raster_tile_fluct" : "raster_tile_mean", st);
-  if (fluctuate)
-    hipLaunchKernelGGL((k_tile<T, true, TH, TW, OCC>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid,
-                       ws.list, ws.offs, ws.items, ws.item_off, ws.counts, nt, ws.ctrl, tables, lfact);
+  static const char* const kTileName[3] = {"raster_tile_mean", "raster_tile_fluct", "raster_tile_normal"};
+  if (prof) prof->begin(kTileName[mode], st);
+#define WCT_TILE_LAUNCH(M)                                                                                        \
+  hipLaunchKernelGGL((k_tile<T, M, TH, TW, OCC>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.list, \
+                     ws.offs, ws.items, ws.item_off, ws.counts, nt, ws.ctrl, tables, lfact)
+  if (mode == kModeBinomial)
+    WCT_TILE_LAUNCH(kModeBinomial);
+  else if (mode == kModeNormal)
+    WCT_TILE_LAUNCH(kModeNormal);
   else
-    hipLaunchKernelGGL((k_tile<T, false, TH, TW, OCC>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid,
-                       ws.list, ws.offs, ws.items, ws.item_off, ws.counts, nt, ws.ctrl, tables, lfact);
+    WCT_TILE_LAUNCH(kModeMean);
+#undef WCT_TILE_LAUNCH
   WCT_CHECK_LAUNCH();
   if (prof) prof->end(st);
   if (prof) prof->begin("raster_wide_rows", st);
-  if (fluctuate)
-    hipLaunchKernelGGL((k_big<T, true>), dim3(256), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.big, ws.ctrl,
-                       tables, lfact);
+#define WCT_BIG_LAUNCH(M)                                                                                      \
+  hipLaunchKernelGGL((k_big<T, M>), dim3(256), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.big, ws.ctrl, tables, \
+                     lfact)
+  if (mode == kModeBinomial)
+    WCT_BIG_LAUNCH(kModeBinomial);
+  else if (mode == kModeNormal)
+    WCT_BIG_LAUNCH(kModeNormal);
   else
-    hipLaunchKernelGGL((k_big<T, false>), dim3(256), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.big, ws.ctrl,
-                       tables, lfact);
+    WCT_BIG_LAUNCH(kModeMean);
+#undef WCT_BIG_LAUNCH
   WCT_CHECK_LAUNCH();
   if (prof) prof->end(st);
   return hipSuccess;
 }
 
 template <typename T>
-hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigma, int fluctuate, uint64_t seed,
+hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigma, int mode, uint64_t seed,
                          T* grid, const RasterWs& ws, const DetTables* tables, const double* lfact, int n_cu,
                          hipStream_t st, ProfHook* prof, int tile) {
+  if (mode < kModeMean || mode > kModeNormal) return hipErrorInvalidValue;
   int id = 0;  // index among the variants of type T
   hipError_t e = hipErrorInvalidValue;
 #define WCT_TILE_CASE(TT, TH_, TW_, OCC)                                                                    \
   if constexpr (std::is_same<T, TT>::value) {                                                              \
     if (id++ == tile)                                                                                      \
-      e = launch_raster_tiles<T, TH_, TW_, OCC>(d, g, nsigma, fluctuate, seed, grid, ws, tables, lfact, n_cu, \
+      e = launch_raster_tiles<T, TH_, TW_, OCC>(d, g, nsigma, mode, seed, grid, ws, tables, lfact, n_cu,      \
                                                 st, prof);                                                  \
   }
   WCT_TILE_VARIANTS(WCT_TILE_CASE)

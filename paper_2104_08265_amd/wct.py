@@ -209,10 +209,16 @@ class DeviceDepos:
                          _ptr(self.plane), _ptr(self.event), _ptr(self.depo_id))
 
 
+FLUCT_MEAN, FLUCT_BINOMIAL, FLUCT_NORMAL = 0, 1, 2
+
+
 def opts(nsigma=3.0, fluctuate=False, n_events=1, seed=0, event_base=0, noise=False):
-    """Run options; the call simulates events event_base .. event_base + n_events - 1
-    (noise: wct_simulate adds the planes' noise, see Plan.set_noise)."""
-    return wct_opts(float(nsigma), int(bool(fluctuate)), int(n_events), int(seed) & 0xFFFFFFFFFFFFFFFF,
+    """Run options; the call simulates events event_base .. event_base + n_events - 1.
+
+    fluctuate: False / 0 the mean charge, True / 1 binomial counts, 2 (FLUCT_NORMAL) their
+    normal approximation with Box-Muller normals; noise: wct_simulate adds the planes'
+    noise (Plan.set_noise)."""
+    return wct_opts(float(nsigma), int(fluctuate), int(n_events), int(seed) & 0xFFFFFFFFFFFFFFFF,
                     int(event_base), int(bool(noise)))
 
 

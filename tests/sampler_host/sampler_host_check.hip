@@ -9,6 +9,10 @@
 //                                   lane does beside slower lanes of its wave
 //        sampler_host_check philox  stdin lines "c0 c1 c2 c3 k0 k1" (decimal)
 //                                   -> "w0 w1 w2 w3 u_even u_odd" (u as hex floats)
+//        sampler_host_check normal  stdin lines "w0 w1 w2 w3 N p_even p_odd" (words and N
+//                                   decimal, p as hex floats) -> "z_even z_odd n_even
+//                                   n_odd sqrt(x) cos sin" for the normal-approximation
+//                                   mode (x = p_even * 1e6, cos and sin of 2 pi p_odd)
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -25,6 +29,20 @@ int main(int argc, char** argv) {
     while (std::scanf("%u %u %u %u %u %u", &c0, &c1, &c2, &c3, &k0, &k1) == 6) {
       const Philox4 r = philox4x32_10(c0, c1, c2, c3, k0, k1);
       std::printf("%u %u %u %u %a %a\n", r.w0, r.w1, r.w2, r.w3, uniform53(r.w0, r.w1), uniform53(r.w2, r.w3));
+    }
+    return 0;
+  }
+  if (std::strcmp(argv[1], "normal") == 0) {
+    unsigned w0, w1, w2, w3;
+    int N;
+    char be[64], bo[64];
+    while (std::scanf("%u %u %u %u %d %63s %63s", &w0, &w1, &w2, &w3, &N, be, bo) == 7) {
+      const double pe = std::strtod(be, nullptr), po = std::strtod(bo, nullptr);
+      double ze, zo, c, s;
+      box_muller_pair(Philox4{w0, w1, w2, w3}, &ze, &zo);
+      det_sincos2pi(po, &c, &s);
+      std::printf("%a %a %d %d %a %a %a\n", ze, zo, normal_count(N, pe, ze), normal_count(N, po, zo),
+                  det_sqrt(pe * 1e6), c, s);
     }
     return 0;
   }

@@ -6,7 +6,8 @@ combine them; and its Philox4x32-10 with the 53-bit uniforms.  Counts and words 
 equal the oracle's (oracle/fluct.py, Sec. 4.3.1 binomial fluctuation) exactly, over
 seeded triples (N, p, u) that cover both regimes, both sides of p = 1/2, the regime
 switch N p' = 10, the inversion cap (N near 128), the ln(n!) table edge (N near 2^17),
-u at 0 and next to 1, and p near 0 and 1.
+u at 0 and next to 1, and p near 0 and 1.  The normal-approximation mode's Box-Muller
+normals, deterministic sqrt, cos and sin, and counts must equal oracle/normal.py's.
 """
 import os
 import shutil
@@ -16,6 +17,7 @@ import numpy as np
 import pytest
 
 from oracle import fluct as OF
+from oracle import normal as ON
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -124,3 +126,30 @@ def test_counts_unchanged_by_lockstep_passes(checker, seed):
     assert bad.size == 0, [(int(N[i]), float(p[i]), float(u[i]), int(got[i]), int(ref[i])) for i in bad[:5]]
     Ne, pe, ue = edge_triples()
     assert np.array_equal(run_binom(checker, Ne, pe, ue, mode="binom_lockstep"), OF.binomial(Ne, pe, ue))
+
+
+def test_normal_mode_equals_oracle(checker):
+    rng = np.random.default_rng(12)
+    n = 20000
+    w = rng.integers(0, 2**32, (n, 4), dtype=np.uint64)
+    w[:4, :2] = 0                # u1 = 1: r = 0
+    w[4:8, :2] = 2**32 - 1       # u1 = 2^-53: the largest r
+    w[8:12, 2:] = 0              # u2 = 0
+    N = rng.integers(0, 2**31 - 1, n)
+    N[:n // 2] = rng.integers(0, 1000, n // 2)
+    pe = rng.random(n)
+    po = rng.random(n)
+    pe[:50], po[:50] = 0.0, 1.0
+    pe[50:100] = 2.0 ** -rng.integers(10, 60, 50)
+    po[100:200] = np.arange(100) / 100.0  # quadrant edges of the cos/sin argument
+    rows = [f"{a} {b} {c} {d} {m} {x.hex()} {y.hex()}\n" for (a, b, c, d), m, x, y in
+            zip(w.tolist(), N.tolist(), pe.tolist(), po.tolist())]
+    out = subprocess.run([checker, "normal"], input="".join(rows), capture_output=True, text=True, check=True).stdout
+    got = [ln.split() for ln in out.strip().splitlines()]
+    assert len(got) == n
+    ze, zo = ON.box_muller_words(w[:, 0], w[:, 1], w[:, 2], w[:, 3])
+    c, s = ON.det_sincos2pi(po)
+    ref = [ze, zo, ON.normal_count(N, pe, ze), ON.normal_count(N, po, zo), ON.det_sqrt(pe * 1e6), c, s]
+    for col, r in enumerate(ref):
+        g = np.array([float.fromhex(x[col]) if col not in (2, 3) else int(x[col]) for x in got])
+        assert np.array_equal(g, r), (col, int(np.sum(g != r)))
