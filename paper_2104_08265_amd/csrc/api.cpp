@@ -285,7 +285,7 @@ size_t ws_bytes(const wct_plan* P, int op, int n_events, int64_t n_rows) {
     carve_raster(P, r, n_events, n_rows);
     carve_conv(P, c, n_events);
     // the row flags go last, so the grid and the transform buffers keep their places
-    return head + align_up(r.off > c.off ? r.off : c.off, 256) + align_up((size_t)n_events * P->rows_ev, 256);
+    return head + align_up(r.off > c.off ? r.off : c.off, 256) + align_up(sizeof(int2) * n_events * P->rows_ev, 256);
   }
   if (op == WCT_OP_BACKWARD) {
     Carver a(nullptr);
@@ -340,21 +340,22 @@ DepoView<T> view(const wct_depos* d) {
 // Launch sequences -------------------------------------------------------------------
 template <typename T>
 int run_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, T* grid, Carver& cv, hipStream_t st,
-               uint8_t* live = nullptr) {
+               int2* span = nullptr) {
   const RasterGeom g = raster_geom(P, o->n_events, o->event_base);
   RasterWs ws = carve_raster(P, cv, o->n_events, d->n);
-  ws.live = live;
+  ws.span = span;
   HIP_TRY(launch_raster<T>(view<T>(d), g, o->nsigma, o->fluctuate, o->seed, grid, ws, P->d_tables, P->d_lfact,
                            P->n_cu, st, hook(P), P->tile),
           "raster launch");
   return WCT_OK;
 }
 
-// live (optional): the raster's row flags of these events; the row transform then skips
-// the work (not the zero output) of rows, or row pairs, that no window reached.
+// span (optional): the raster's row tick spans of these events; the row transform then
+// skips the work (not the zero output) of rows, or row pairs, that no window reached, and
+// reads the others only inside their spans.
 template <typename T>
 int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, hipStream_t st,
-                 const uint8_t* live = nullptr, const wct_opts* noise = nullptr) {
+                 const int2* span = nullptr, const wct_opts* noise = nullptr) {
   const ConvWs c = carve_conv(P, cv, n_events);
   cx<T>* shat = static_cast<cx<T>*>(c.shat);
   cx<T>* mhat = static_cast<cx<T>*>(c.mhat);
@@ -364,7 +365,7 @@ int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, 
     const cx<T>* post = static_cast<const cx<T>*>(P->post_t[p]);
     const cx<T>* tw_w = static_cast<const cx<T>*>(P->tw_w[p]);
     const cx<T>* tw_wr = static_cast<const cx<T>*>(P->tw_w_rev[p]);
-    const uint8_t* lv = live ? live + G.row_off : nullptr;
+    const int2* lv = span ? span + G.row_off : nullptr;
     PROF_LAUNCH(P, "rows_r2c", st,
                 launch_rows_r2c<T>(grid + G.grid_off, P->grid_elems, shat + G.shat_off, P->shat_elems, G.nt, G.I,
                                    G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, P->n_cu, st, lv, P->rows_ev),
@@ -1104,7 +1105,8 @@ int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, v
   Carver head(ws);
   void* grid = head.take(plan->esize * (size_t)batch * plan->grid_elems);
   const size_t rest = align_up(head.off, 256);
-  uint8_t* live = static_cast<uint8_t*>(ws) + need - align_up((size_t)batch * plan->rows_ev, 256);
+  int2* span = reinterpret_cast<int2*>(static_cast<char*>(ws) + need -
+                                       align_up(sizeof(int2) * (size_t)batch * plan->rows_ev, 256));
   // sub-batches of up to max_events events: raster into the workspace grid, then the
   // transform passes write the sub-batch's slots of `wave`
   for (int e0 = 0; e0 < opts->n_events; e0 += batch) {
@@ -1114,13 +1116,13 @@ int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, v
     Carver cr(static_cast<char*>(ws) + rest), cc(static_cast<char*>(ws) + rest);
     char* w = static_cast<char*>(wave) + plan->esize * (size_t)e0 * plan->wave_elems;
     if (plan->dtype == WCT_F32) {
-      if ((rc = run_raster<float>(plan, depos, &sub, static_cast<float*>(grid), cr, st, live))) return rc;
+      if ((rc = run_raster<float>(plan, depos, &sub, static_cast<float*>(grid), cr, st, span))) return rc;
       rc = run_convolve<float>(plan, static_cast<const float*>(grid), sub.n_events, reinterpret_cast<float*>(w), cc,
-                               st, live, &sub);
+                               st, span, &sub);
     } else {
-      if ((rc = run_raster<double>(plan, depos, &sub, static_cast<double*>(grid), cr, st, live))) return rc;
+      if ((rc = run_raster<double>(plan, depos, &sub, static_cast<double*>(grid), cr, st, span))) return rc;
       rc = run_convolve<double>(plan, static_cast<const double*>(grid), sub.n_events, reinterpret_cast<double*>(w),
-                                cc, st, live, &sub);
+                                cc, st, span, &sub);
     }
     if (rc) return rc;
   }

@@ -25,11 +25,13 @@ namespace wct {
 // ---------------------------------------------------------------------------
 // Pass A: real rows -> half spectra, column-chunk layout.  Persistent: a workgroup
 // walks rows L = first + k * gridDim.x; the next row is loaded into registers while the
-// current one is transformed, so HBM reads overlap the LDS work.  With row flags (FLAGS:
-// the raster's mark per impact row, [event][row], row = wire * nphase + phase), a row no
-// deposition window reached is neither loaded nor transformed: its zero spectrum is
-// written directly.  Each wave reads the flags of its block's next rows at once, one per
-// lane, and keeps them as a ballot mask.
+// current one is transformed, so HBM reads overlap the LDS work.  With row spans (FLAGS:
+// the raster's tick span per impact row, [event][row], row = wire * nphase + phase), a
+// row no deposition window reached is neither loaded nor transformed: its zero spectrum
+// is written directly; the other rows are read only inside their spans (16-byte pieces
+// outside hold zeros: they are taken as zero without a load from HBM).  Each wave reads
+// whether its block's next rows are reached at once, one per lane, and keeps the answers
+// as a ballot mask.
 // ---------------------------------------------------------------------------
 template <typename T, int C, typename F, bool FLAGS>
 __global__ void __launch_bounds__(F::kBound) k_rows_r2c(const T* __restrict__ src, int64_t src_ev_stride,
@@ -37,7 +39,7 @@ __global__ void __launch_bounds__(F::kBound) k_rows_r2c(const T* __restrict__ sr
                                                    int nphase, int nper, int nchunk, int n_events, F f,
                                                    const cx<T>* __restrict__ tw,
                                                    const cx<T>* __restrict__ post,
-                                                   const uint8_t* __restrict__ live, int64_t live_ev) {
+                                                   const int2* __restrict__ span, int64_t span_ev) {
   using V = typename Vec16<T>::type;
   constexpr int VN = Vec16<T>::n;
   constexpr int PF = (2 * F::E + VN - 1) / VN;  // 16-byte loads per thread: a row has <= 2 E reals per thread
@@ -55,7 +57,7 @@ __global__ void __launch_bounds__(F::kBound) k_rows_r2c(const T* __restrict__ sr
   const int ntv = vec ? nt / VN : 0;
   V pre[PF];
   // lanes of the block's last wave (partial when the block is not a multiple of 64)
-  const int span = blockDim.x % 64 == 0 ? 64 : (int)(blockDim.x % 64);
+  const int wspan = blockDim.x % 64 == 0 ? 64 : (int)(blockDim.x % 64);
   unsigned long long mask = 0;
   int left = 0;  // unused bits of mask
   auto live_at = [&](int Q) -> bool {  // called once per iteration, in order; Q: its row
@@ -66,13 +68,13 @@ __global__ void __launch_bounds__(F::kBound) k_rows_r2c(const T* __restrict__ sr
         const int lane = threadIdx.x & 63;
         const int Ql = Q + lane * (int)gridDim.x;
         bool l = false;
-        if (lane < span && Ql < total) {
+        if (lane < wspan && Ql < total) {
           const int ev = Ql / rows, rin = Ql - (Ql / rows) * rows;
           const int i = rin / nper, c = rin - (rin / nper) * nper;
-          l = live[ev * live_ev + (int64_t)c * nphase + i] != 0;
+          l = span[ev * span_ev + (int64_t)c * nphase + i].y != 0;
         }
         mask = __ballot(l);
-        left = span;
+        left = wspan;
       }
       const bool b = mask & 1ull;
       mask >>= 1;
@@ -80,18 +82,26 @@ __global__ void __launch_bounds__(F::kBound) k_rows_r2c(const T* __restrict__ sr
       return b;
     }
   };
-  int L = xcd_remap(blockIdx.x, gridDim.x);
-  bool liveL = L < total && live_at(L);
-  if (vec && liveL) {
-    const int ev = L / rows, rin = L - (L / rows) * rows;
+  // 16-byte pieces u of row Q inside the row and its span; the others are zero (their
+  // loads are clamped to the span's first piece, a cached line, and the value dropped):
+  // unconditional loads keep pre[] in registers
+  auto prefetch = [&](int Q) {
+    const int ev = Q / rows, rin = Q - (Q / rows) * rows;
     const int i = rin / nper, c = rin - (rin / nper) * nper;
+    const int2 sp = row_span(FLAGS ? span : nullptr, ev * span_ev + (int64_t)c * nphase + i, nt);
+    const int u0 = sp.x < sp.y ? sp.x / VN : 0;  // < ntv: a nonempty span lies inside [0, nt)
     const V* s = reinterpret_cast<const V*>(src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt);
 #pragma unroll
-    for (int q = 0; q < PF; ++q) {  // unconditional (clamped) loads keep pre[] in registers
+    for (int q = 0; q < PF; ++q) {
       const int u = threadIdx.x + q * nthr;
-      pre[q] = s[u < ntv ? u : 0];
+      const bool ok = u < ntv && (u + 1) * VN > sp.x && u * VN < sp.y;
+      const V v = s[ok ? u : u0];
+      pre[q] = ok ? v : (V)(T(0));
     }
-  }
+  };
+  int L = xcd_remap(blockIdx.x, gridDim.x);
+  bool liveL = L < total && live_at(L);
+  if (vec && liveL) prefetch(L);
   const int fpad = nchunk * C;
   while (L < total) {
     const int ev = L / rows, rin = L - (L / rows) * rows;
@@ -101,16 +111,7 @@ __global__ void __launch_bounds__(F::kBound) k_rows_r2c(const T* __restrict__ sr
     cx<T>* out = dst + ev * dst_ev_stride;
     if constexpr (FLAGS) {
       if (!liveL) {
-        if (vec && liveN) {
-          const int evn = Ln / rows, rn = Ln - (Ln / rows) * rows;
-          const int in = rn / nper, cn = rn - (rn / nper) * nper;
-          const V* s = reinterpret_cast<const V*>(src + evn * src_ev_stride + ((int64_t)cn * nphase + in) * nt);
-#pragma unroll
-          for (int q = 0; q < PF; ++q) {
-            const int u = threadIdx.x + q * nthr;
-            pre[q] = s[u < ntv ? u : 0];
-          }
-        }
+        if (vec && liveN) prefetch(Ln);
         for (int k = threadIdx.x; k < fpad; k += nthr) {
           const int ch = k / C, cc = k - (k / C) * C;
           out[(((int64_t)ch * nphase + i) * nper + c) * C + cc] = mk(T(0), T(0));
@@ -132,16 +133,7 @@ __global__ void __launch_bounds__(F::kBound) k_rows_r2c(const T* __restrict__ sr
       for (int u = threadIdx.x; u < 2 * M; u += nthr) zr[u] = u < nt ? s[u] : T(0);
     }
     __syncthreads();
-    if (vec && liveN) {  // next row in flight during this row's transform
-      const int evn = Ln / rows, rn = Ln - (Ln / rows) * rows;
-      const int in = rn / nper, cn = rn - (rn / nper) * nper;
-      const V* s = reinterpret_cast<const V*>(src + evn * src_ev_stride + ((int64_t)cn * nphase + in) * nt);
-#pragma unroll
-      for (int q = 0; q < PF; ++q) {
-        const int u = threadIdx.x + q * nthr;
-        pre[q] = s[u < ntv ? u : 0];
-      }
-    }
+    if (vec && liveN) prefetch(Ln);  // next row in flight during this row's transform
     f.template run<false>(z, tw);
     for (int k = threadIdx.x; k < fpad; k += nthr) {
       cx<T> X = mk(T(0), T(0));
@@ -398,21 +390,21 @@ static void for_all_fft(Fn&& fn) {
 template <typename T>
 hipError_t launch_rows_r2c(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt, int nphase,
                            int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
-                           const cx<T>* post, int n_cu, hipStream_t st, const uint8_t* live, int64_t live_ev) {
+                           const cx<T>* post, int n_cu, hipStream_t st, const int2* span, int64_t span_ev) {
   if (plan.variant >= 0)
     return launch_rows_r2c_ct<T>(src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, n_events, plan, tw,
-                                 post, n_cu, st, live, live_ev);
+                                 post, n_cu, st, span, span_ev);
   const size_t lds = sizeof(cx<T>) * plan.n;
   const int total = nphase * nper * n_events;
   const hipError_t e = with_fft<T, 0>(plan, [&](auto f, int thr) {
     using F = decltype(f);
     const dim3 grid(persistent_blocks(n_cu, lds, thr, total));
-    if (live)
+    if (span)
       hipLaunchKernelGGL((k_rows_r2c<T, kChunk, F, true>), grid, dim3(thr), lds, st, src, src_ev_stride, dst,
-                         dst_ev_stride, nt, nphase, nper, nchunk, n_events, f, tw, post, live, live_ev);
+                         dst_ev_stride, nt, nphase, nper, nchunk, n_events, f, tw, post, span, span_ev);
     else
       hipLaunchKernelGGL((k_rows_r2c<T, kChunk, F, false>), grid, dim3(thr), lds, st, src, src_ev_stride, dst,
-                         dst_ev_stride, nt, nphase, nper, nchunk, n_events, f, tw, post, live, live_ev);
+                         dst_ev_stride, nt, nphase, nper, nchunk, n_events, f, tw, post, span, span_ev);
   });
   return e != hipSuccess ? e : hipGetLastError();
 }
@@ -511,7 +503,7 @@ void conv_init_kernels() {
 #define WCT_INST(T)                                                                                            \
   template hipError_t launch_rows_r2c<T>(const T*, int64_t, cx<T>*, int64_t, int, int, int, int, int,          \
                                          const FftPlan&, const cx<T>*, const cx<T>*, int, hipStream_t,        \
-                                         const uint8_t*, int64_t);       \
+                                         const int2*, int64_t);          \
   template hipError_t launch_colpass<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int, int,   \
                                         int, const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);         \
   template hipError_t launch_colpass_adj<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int,    \

@@ -16,22 +16,27 @@
 namespace wct {
 
 // A thread's first-pass inputs of the half-length transform of a row of nt reals:
-// complex sample m is (x[2m], x[2m+1]), zero past the row's end.  The choice between
-// 2-vector and element loads is made once for all of them (it is uniform), so the loads
-// of a thread issue back to back with no branch between them; an index past the end reads
-// element 0 and the zero is selected afterwards.
+// complex sample m is (x[2m], x[2m+1]), zero past the row's end and outside the row's
+// span [sp.x, sp.y) (where the row holds zeros, so those are not read from HBM).  The
+// choice between 2-vector and element loads is made once for all of them (it is uniform),
+// so the loads of a thread issue back to back with no branch between them; an index
+// outside reads the span's first element (a cached line) and the zero is selected
+// afterwards.
 template <typename F, typename T>
-__device__ __forceinline__ void load_row_inputs(const T* __restrict__ s, int nt, bool v2, cx<T>* in) {
+__device__ __forceinline__ void load_row_inputs(const T* __restrict__ s, int nt, bool v2, int2 sp, cx<T>* in) {
   constexpr int R0 = F::R0;
+  const int hi = sp.y < nt ? sp.y : nt;
+  const int lo = sp.x < hi ? sp.x : 0;  // an empty span (a row of a pair no window reached) reads index 0
   if (v2) {  // even row length, 8-byte aligned rows
+    const int m0 = lo >> 1;
 #pragma unroll
     for (int q = 0; q < F::MB0; ++q) {
       if (!F::in_ok(q)) continue;
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
         const int m = F::in_elem(q, r);
-        const bool ok = 2 * m < nt;
-        const cv2<T> p = *reinterpret_cast<const cv2<T>*>(s + (ok ? 2 * m : 0));
+        const bool ok = 2 * m + 2 > lo && 2 * m < hi;
+        const cv2<T> p = *reinterpret_cast<const cv2<T>*>(s + 2 * (ok ? m : m0));
         in[q * R0 + r] = ok ? mk(p.x, p.y) : mk(T(0), T(0));
       }
     }
@@ -42,8 +47,8 @@ __device__ __forceinline__ void load_row_inputs(const T* __restrict__ s, int nt,
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
         const int m = F::in_elem(q, r);
-        const bool ok0 = 2 * m < nt, ok1 = 2 * m + 1 < nt;
-        const T a = s[ok0 ? 2 * m : 0], b = s[ok1 ? 2 * m + 1 : 0];
+        const bool ok0 = 2 * m >= lo && 2 * m < hi, ok1 = 2 * m + 1 >= lo && 2 * m + 1 < hi;
+        const T a = s[ok0 ? 2 * m : lo], b = s[ok1 ? 2 * m + 1 : lo];
         in[q * R0 + r] = mk(ok0 ? a : T(0), ok1 ? b : T(0));
       }
     }
@@ -78,7 +83,7 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_ct(const
   auto load = [&](int L) {
     int ev, i, c;
     row_of(L, ev, i, c);
-    load_row_inputs<F>(src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt, nt, v2, in);
+    load_row_inputs<F>(src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt, nt, v2, make_int2(0, nt), in);
   };
   int L = xcd_remap(blockIdx.x, gridDim.x);
   if (L < total) load(L);
@@ -132,7 +137,7 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
                                                                   int nchunk, int n_events,
                                                                   const cx<T>* __restrict__ tw,
                                                                   const cx<T>* __restrict__ post,
-                                                                  const uint8_t* __restrict__ live, int64_t live_ev) {
+                                                                  const int2* __restrict__ span, int64_t span_ev) {
   constexpr int M = F::N, NT = F::kThreads, R0 = F::R0;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* z = reinterpret_cast<cx<T>*>(smem_raw);
@@ -156,7 +161,8 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
   auto load = [&](int P, int r) {
     int ev, i, c;
     row_of(P, r, ev, i, c);
-    load_row_inputs<F>(src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt, nt, v2, in);
+    const int64_t row = (int64_t)c * nphase + i;
+    load_row_inputs<F>(src + ev * src_ev_stride + row * nt, nt, v2, row_span(span, ev * span_ev + row, nt), in);
   };
   // pw = post[k], loaded by the caller a loop trip ahead (its latency then overlaps a trip)
   auto post_twiddle = [&](int k, cx<T> pw) {
@@ -172,9 +178,9 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
     return X;
   };
   auto post_at = [&](int k) { return k <= M ? post[k] : mk(T(0), T(0)); };
-  // With row flags (live != NULL), a pair whose two rows no window reached is neither
+  // With row spans (span != NULL), a pair whose two rows no window reached is neither
   // loaded nor transformed: its zero spectrum is written directly.  Without them every pair
-  // is transformed (one kernel serves both: the test of `live` is uniform).  Each wave reads the flags of its
+  // is transformed (one kernel serves both: the test of `span` is uniform).  Each wave reads the spans of its
   // block's next kSpan pairs at once (lane j: the pair j iterations on) and keeps the
   // answers as a ballot mask, so the per-pair test is a bit of a scalar register.  kSpan is
   // the lane count of the block's last wave, which is partial when NT is not a multiple of 64.
@@ -182,13 +188,13 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
   auto pair_live = [&](int Q) {
     int ev, i, c;
     row_of(Q, 0, ev, i, c);
-    const uint8_t* f = live + ev * live_ev;
-    return (f[(int64_t)c * nphase + i] | f[(int64_t)(c + 1) * nphase + i]) != 0;
+    const int2* f = span + ev * span_ev;
+    return (f[(int64_t)c * nphase + i].y | f[(int64_t)(c + 1) * nphase + i].y) != 0;
   };
   unsigned long long mask = 0;
   int left = 0;  // unused bits of mask
   auto live_at = [&](int Q) -> bool {  // called once per iteration, in order; Q: its pair
-    if (!live) {
+    if (!span) {
       return true;
     } else {
       if (left == 0) {
@@ -501,7 +507,7 @@ static void for_all_variants(Fn&& fn) {
 template <typename T>
 hipError_t launch_rows_r2c_ct(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt,
                               int nphase, int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
-                              const cx<T>* post, int n_cu, hipStream_t st, const uint8_t* live, int64_t live_ev) {
+                              const cx<T>* post, int n_cu, hipStream_t st, const int2* span, int64_t span_ev) {
   const size_t lds = sizeof(cx<T>) * plan.n;
   const size_t lds_pair = lds + sizeof(cx<T>) * nchunk * kChunk;
   const int total = nphase * nper * n_events;
@@ -513,8 +519,8 @@ hipError_t launch_rows_r2c_ct(const T* src, int64_t src_ev_stride, cx<T>* dst, i
     const dim3 pgrid(persistent_blocks(n_cu, lds_pair, F::kThreads, total / 2));
     if (pair)
       hipLaunchKernelGGL((k_rows_r2c_pair_ct<T, kChunk, F>), pgrid, dim3(F::kThreads), lds_pair, st, src,
-                         src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, n_events, tw, post, live,
-                         live_ev);
+                         src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, n_events, tw, post, span,
+                         span_ev);
     else
       hipLaunchKernelGGL((k_rows_r2c_ct<T, kChunk, F>), dim3(persistent_blocks(n_cu, lds, F::kThreads, total)),
                          dim3(F::kThreads), lds, st, src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk,
@@ -607,7 +613,7 @@ void conv_ct_init_kernels() {
 #define WCT_INST(T)                                                                                              \
   template hipError_t launch_rows_r2c_ct<T>(const T*, int64_t, cx<T>*, int64_t, int, int, int, int, int,         \
                                             const FftPlan&, const cx<T>*, const cx<T>*, int, hipStream_t,       \
-                                            const uint8_t*, int64_t);                                           \
+                                            const int2*, int64_t);                                              \
   template hipError_t launch_colpass_ct<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int, int,  \
                                            int, const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);        \
   template hipError_t launch_colpass_adj_ct<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int,   \

@@ -10,6 +10,14 @@
 
 namespace wct {
 
+// [lo, hi) of a row from its recorded span (kSpanBase - lo, hi); the whole row [0, nt)
+// without spans.  A row no window reached has hi = 0: an empty span.
+__device__ __forceinline__ int2 row_span(const int2* __restrict__ span, int64_t idx, int nt) {
+  if (!span) return make_int2(0, nt);
+  const int2 s = span[idx];
+  return make_int2(kSpanBase - s.x, s.y);
+}
+
 // Blocks are dispatched to the 8 XCDs round-robin; map them so that consecutive
 // logical indices share an XCD (and its L2).
 __device__ __forceinline__ int xcd_remap(int b, int nblk) {
@@ -94,7 +102,7 @@ inline int persistent_blocks(int n_cu, size_t lds, int threads, int work) {
 template <typename T>
 hipError_t launch_rows_r2c_ct(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt,
                               int nphase, int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
-                              const cx<T>* post, int n_cu, hipStream_t st, const uint8_t* live, int64_t live_ev);
+                              const cx<T>* post, int n_cu, hipStream_t st, const int2* span, int64_t span_ev);
 template <typename T>
 hipError_t launch_colpass_ct(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtil, cx<T>* mhat,
                              int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events,

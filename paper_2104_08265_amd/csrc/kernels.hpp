@@ -81,8 +81,14 @@ struct RasterWs {
   int32_t* blocks;    // [2 * nscan_blocks]
   int64_t ntiles;
   int64_t max_items;
-  uint8_t* live = nullptr;  // optional [event][rows_ev]: 1 where some window reaches the row
+  int2* span = nullptr;  // optional [event][rows_ev] tick spans of the rows (row_span)
 };
+
+// Tick span of an impact row as the raster records it: {kSpanBase - lo, hi}, both
+// raised by atomic max from zero, where [lo, hi) is the union hull of the tick windows of
+// the depositions that reach the row; {0, 0} when none does.  The row's samples outside
+// [lo, hi) are zero, so the row transform reads only inside it.
+constexpr int kSpanBase = 1 << 30;
 
 // Noise of Eq. 1's N term, added to the half spectra of the inverse row transform (pass
 // C of the forward): frequency k of wire w in event `event_base + slot` receives
@@ -122,14 +128,15 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 // conv.hip.  A plan with variant >= 0 runs the compiled-plan kernels; the column passes
 // of those take a second twiddle table for the same radices in reverse order (tw_rev).
 // Rows are read with 16-byte loads (and the next row prefetched) when their length and base allow it.
+// span (optional, [event][span_ev] row tick spans of this plane): the runtime kernel
+// and the wire-pair kernel neither load nor transform a row (pair) no window reached and
+// write its zero spectrum directly, and read a row only inside its span; the compiled
+// single-row kernel (odd wire counts) reads and transforms every row whole.
 template <typename T>
-// live (optional, [event][live_ev] row flags of this plane): the wire-pair kernel
-// neither loads nor transforms a pair of rows no window reached and writes its zero
-// spectrum directly; the other kernels transform every row.
 hipError_t launch_rows_r2c(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt, int nphase,
                            int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
-                           const cx<T>* post, int n_cu, hipStream_t st, const uint8_t* live = nullptr,
-                           int64_t live_ev = 0);
+                           const cx<T>* post, int n_cu, hipStream_t st, const int2* span = nullptr,
+                           int64_t span_ev = 0);
 template <typename T>
 hipError_t launch_colpass(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtil, cx<T>* mhat,
                           int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, const FftPlan& plan,

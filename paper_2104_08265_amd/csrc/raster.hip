@@ -340,7 +340,7 @@ template <typename T, int TH, int TW>
 __global__ void __launch_bounds__(kCountBlock) k_count(DepoView<T> d, RasterGeom g, double nsigma,
                                                        int32_t* __restrict__ counts, int32_t* __restrict__ rank,
                                                        int32_t* __restrict__ big, int32_t* __restrict__ ctrl,
-                                                       uint8_t* __restrict__ live) {
+                                                       int2* __restrict__ span) {
   static_assert(kCountSlots > 4 * kCountBlock && (kCountSlots & (kCountSlots - 1)) == 0, "count table size");
   __shared__ int32_t s_key[kCountSlots];  // tile index, -1 = free
   __shared__ int32_t s_cnt[kCountSlots];  // rows of this block in the tile, then their first slot
@@ -356,14 +356,26 @@ __global__ void __launch_bounds__(kCountBlock) k_count(DepoView<T> d, RasterGeom
     const RowWin w = row_window(d, j, g, nsigma);
     if (w.ok) {
       const PlaneGeom& pl = g.pl[w.plane];
-      if (live) {  // the impact rows this window reaches are not empty (most are marked
-                   // already: test first, so neighbouring depositions do not contend)
-        uint8_t* f = live + (int64_t)w.event * g.rows_ev + pl.row_off;
-        for (int b = w.b0; b < w.b1; ++b)
-          if (!f[b]) f[b] = 1;
-      }
       const int tr0 = w.b0 / TH, tr1 = (w.b1 - 1) / TH, tc0 = w.k0 / TW, tc1 = (w.k1 - 1) / TW;
-      if ((tr1 - tr0 + 1) * (tc1 - tc0 + 1) > 4) {
+      const bool wide = (tr1 - tr0 + 1) * (tc1 - tc0 + 1) > 4;
+      if (span) {
+        // The impact rows this window reaches are marked (span hi >= 1).  A row taking
+        // the tile path gets its span from its band's tiles afterwards (k_band_spans); a
+        // wide row, which no tile counts, records its ticks [k0, k1) itself (these rows
+        // are few).  Test first, so that neighbouring depositions do not contend.
+        int2* f = span + (int64_t)w.event * g.rows_ev + pl.row_off;
+        const int a = kSpanBase - w.k0;
+        for (int b = w.b0; b < w.b1; ++b) {
+          const int2 cur = f[b];
+          if (wide) {
+            if (cur.x < a) atomicMax(&f[b].x, a);
+            if (cur.y < w.k1) atomicMax(&f[b].y, w.k1);
+          } else if (cur.y == 0) {
+            atomicMax(&f[b].y, 1);
+          }
+        }
+      }
+      if (wide) {
         big[atomicAdd(&ctrl[kCtrlNBig], 1)] = (int32_t)j;
       } else {
         const int64_t base = (int64_t)w.event * g.ntiles_ev + pl.tile_off;
@@ -391,6 +403,50 @@ __global__ void __launch_bounds__(kCountBlock) k_count(DepoView<T> d, RasterGeom
   for (int n = 0; n < nt; ++n) {
     const int32_t pk = s_pack[4 * threadIdx.x + n];
     rank[4 * j + n] = s_cnt[pk & (kCountSlots - 1)] + (pk >> 11);
+  }
+}
+
+// 1b. row tick spans from the tiles (wct_simulate) -----------------------------
+// One block per band of TH impact rows (one tile row of a plane): the ticks of the band's
+// tiles that some row reaches, [TW * (first such tile), TW * (last + 1)), hold every
+// nonzero cell of the band's tile-path rows, so the band's marked rows take that hull
+// (merged with what wide rows recorded).  Rows no window reached keep {0, 0}.
+template <int TH, int TW>
+__global__ void __launch_bounds__(256) k_band_spans(RasterGeom g, const int32_t* __restrict__ counts,
+                                                     int bands_ev, int2* __restrict__ span) {
+  __shared__ int s_lo[4], s_hi[4];
+  const int ev = blockIdx.x / bands_ev;
+  int bin = blockIdx.x - ev * bands_ev;
+  int p = 0;
+  while (p + 1 < g.n_planes && bin >= g.pl[p].ntr) bin -= g.pl[p++].ntr;
+  const PlaneGeom& pl = g.pl[p];
+  const int tr = bin;
+  const int32_t* cnt = counts + (int64_t)ev * g.ntiles_ev + pl.tile_off + (int64_t)tr * pl.ntc;
+  int lo = INT_MAX, hi = -1;
+  for (int tc = threadIdx.x; tc < pl.ntc; tc += 256)
+    if (cnt[tc] > 0) {
+      lo = min(lo, tc);
+      hi = max(hi, tc);
+    }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = min(lo, __shfl_xor(lo, o, 64));
+    hi = max(hi, __shfl_xor(hi, o, 64));
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_lo[wv] = lo;
+    s_hi[wv] = hi;
+  }
+  __syncthreads();
+  lo = min(min(s_lo[0], s_lo[1]), min(s_lo[2], s_lo[3]));
+  hi = max(max(s_hi[0], s_hi[1]), max(s_hi[2], s_hi[3]));
+  const int klo = hi >= 0 ? lo * TW : kSpanBase, khi = hi >= 0 ? min((hi + 1) * TW, pl.nt) : 0;
+  int2* f = span + (int64_t)ev * g.rows_ev + pl.row_off;
+  const int b1 = min((tr + 1) * TH, pl.nb);
+  for (int b = tr * TH + threadIdx.x; b < b1; b += 256) {
+    const int2 s = f[b];
+    if (s.y != 0) f[b] = make_int2(kSpanBase - min(klo, kSpanBase - s.x), max(khi, s.y));
   }
 }
 
@@ -734,14 +790,21 @@ hipError_t launch_raster_tiles(const DepoView<T>& d, const RasterGeom& g, double
   // control words and counts are contiguous
   hipError_t e = launch_fill_i32(ws.ctrl, kCtrlWords + nt, 0, st);
   if (e != hipSuccess) return e;
-  if (ws.live) {
-    e = launch_fill_i32(reinterpret_cast<int32_t*>(ws.live), (g.n_events * g.rows_ev + 3) / 4, 0, st);
+  if (ws.span) {
+    e = launch_fill_i32(reinterpret_cast<int32_t*>(ws.span), 2 * g.n_events * g.rows_ev, 0, st);
     if (e != hipSuccess) return e;
   }
   const unsigned rblocks = (unsigned)((d.n + 255) / 256);
   if (d.n > 0) {
     hipLaunchKernelGGL((k_count<T, TH, TW>), dim3((unsigned)((d.n + kCountBlock - 1) / kCountBlock)),
-                       dim3(kCountBlock), 0, st, d, g, nsigma, ws.counts, ws.rank, ws.big, ws.ctrl, ws.live);
+                       dim3(kCountBlock), 0, st, d, g, nsigma, ws.counts, ws.rank, ws.big, ws.ctrl, ws.span);
+    WCT_CHECK_LAUNCH();
+  }
+  if (ws.span) {
+    int bands_ev = 0;
+    for (int p = 0; p < g.n_planes; ++p) bands_ev += g.pl[p].ntr;
+    hipLaunchKernelGGL((k_band_spans<TH, TW>), dim3((unsigned)(g.n_events * bands_ev)), dim3(256), 0, st, g,
+                       ws.counts, bands_ev, ws.span);
     WCT_CHECK_LAUNCH();
   }
   const int nsb = (int)((nt + kScanPerBlock - 1) / kScanPerBlock);
