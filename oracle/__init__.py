@@ -24,6 +24,8 @@ Acceleration Solutions for LArTPC Simulation Using Wire-Cell Toolkit"):
 * ``noise``    - Eq. 1's additive noise term N (Sec. 2): stationary noise per wire from
                  an amplitude spectrum and Philox-keyed complex normals, inverse real
                  transform along ticks.
+* ``adc``      - Eq. 1 / Sec. 2: M as an ADC value; a linear converter per plane (gain,
+                 pedestal, largest code), rounding half up, computed in a stated type.
 * ``grad``     - adjoint of the convolution and per-deposition gradients of the
                  raster (differentiable mode; a reading beyond the paper, stated in
                  each function).
