@@ -660,6 +660,28 @@ def noise_cost(wct, synth, plan, dd, wl, wave, steps=3):
             "spectrum": "synth.noise_amplitude(L_t, rms=300): shaped electronics-like noise, white floor 5%"}
 
 
+def adc_cost(plan, wave, reps=5):
+    """ADC digitisation of the step's waveforms (wct_digitize, one 12-bit converter per
+    plane): mean time over `reps` calls from HIP events on the launch stream, and its HBM
+    rate on algorithmic bytes (each sample read once, its 16-bit code written once)."""
+    import torch
+    for p in range(plan.n_planes):
+        plan.set_adc(p, 1.0 / 40.0, 400.0 if p < 2 else 900.0, 4095)
+    adc = plan.digitize(wave, 1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.digitize(wave, 1, adc)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    alg = plan.wave_elems * (wave.element_size() + 2)
+    return {"ms": ms, "alg_bytes": alg, "GBps": alg / (ms * 1e-3) / 1e9,
+            "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "converter": "gain 1/40 count per unit of M, pedestal 400 (induction) / 900 (collection), 12 bits"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -744,6 +766,7 @@ def main():
     t_normal = t_normal / 3 if t_normal is not None else None
     plan.profile(False)
     noise = noise_cost(wct, synth, plan, dd, wl, wave)
+    adc = adc_cost(plan, wave)
 
     n_depos = wl.n_depos
     n_planes = len(wl.planes)
@@ -813,6 +836,7 @@ def main():
         "raster_issue": raster_issue(kernels.get("raster_tile_fluct", {}).get("ms_per_step"),
                                      roofline.get("alg_ops_per_launch")),
         "noise": noise,
+        "adc": adc,
         "fluct_modes": {"tile_ms": {"mean": t_mean, "binomial": kernels.get("raster_tile_fluct", {}).get("ms_per_step"),
                                     "normal_box_muller": t_normal},
                         "note": "k_tile time of the same event per raster mode (tile shape tuned for the "

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define WCT_ABI_VERSION 5
+#define WCT_ABI_VERSION 6
 /* Version of the fluctuation draw stream (counter layout + sampler).  Bumped whenever a
  * change would alter any fluctuated count for the same inputs and seed. */
 #define WCT_FLUCT_SPEC_VERSION 2
@@ -192,6 +192,19 @@ int wct_raster_noalloc(wct_plan* plan, const wct_depos* depos, const wct_opts* o
  * inverse row transform (no extra pass over the waveforms); a batch gives each event the
  * noise it gets alone.  A set-up call: allocates on first use and synchronises. */
 int wct_plan_set_noise(wct_plan* plan, int32_t plane, const double* amp, int64_t n);
+
+/* ADC digitisation (Eq. 1, Sec. 2: M is a measurement such as an ADC value).
+ * wct_plan_set_adc sets plane `plane`'s converter: gain (counts per unit of M), baseline
+ * (the pedestal, counts; both finite) and max_code in [1, 65535] (2^bits - 1); a plan
+ * starts with gain 1, baseline 0, max_code 65535 on every plane.  wct_digitize writes
+ *     adc = min(max(floor(M * gain + baseline + 1/2), 0), max_code)
+ * (0 where M is not a number) for every sample of n_events events of `wave` (DEVICE,
+ * plan dtype, the layout wct_convolve writes) to `adc` (DEVICE, uint16, same layout and
+ * element count).  The arithmetic is in the plan's dtype, gain and baseline rounded to it,
+ * one rounding per operation in the order written.  A run call: enqueued on `stream`, no
+ * workspace, no synchronisation. */
+int wct_plan_set_adc(wct_plan* plan, int32_t plane, double gain, double baseline, int32_t max_code);
+int wct_digitize(const wct_plan* plan, const void* wave, int32_t n_events, uint16_t* adc, void* stream);
 
 /* Convolution by FFT (Eq. 2): wave[event][planes packed][N_w][N_t] = R (*) grid for
  * n_events events.  Row transforms along ticks (real-to-complex, length L_t), column

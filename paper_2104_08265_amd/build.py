@@ -38,6 +38,7 @@ SOURCES = {
     "plan.hip": [],
     "grad.hip": [],
     "probe.cpp": ["-x", "hip"],
+    "adc.hip": [],
 }
 
 

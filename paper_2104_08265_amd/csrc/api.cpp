@@ -166,6 +166,8 @@ struct wct_plan {
   double* d_lfact = nullptr;  // ln(n!), n < kLfactTable, for the chop-down sampler
   void* scratch = nullptr;    // this device's static scratch (wct_raster_noalloc)
   std::vector<void*> noise_amp;  // per plane: amplitude spectrum / L_t, [F] in plan dtype (or null)
+  std::vector<double> adc_gain, adc_base;  // per plane: ADC gain and pedestal (wct_plan_set_adc)
+  std::vector<int> adc_max;                // per plane: largest ADC code
   std::vector<void*> allocs;
   int64_t grid_elems = 0, wave_elems = 0, shat_elems = 0, mhat_elems = 0;
   int64_t rows_ev = 0;  // impact rows per event, all planes
@@ -899,6 +901,9 @@ int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
     P->geom.push_back(G);
   }
   P->noise_amp.assign(P->n_planes, nullptr);
+  P->adc_gain.assign(P->n_planes, 1.0);
+  P->adc_base.assign(P->n_planes, 0.0);
+  P->adc_max.assign(P->n_planes, 65535);
   P->rows_ev = roff;
   P->grid_elems = goff;
   P->wave_elems = woff;
@@ -1067,6 +1072,43 @@ int wct_raster_noalloc(wct_plan* plan, const wct_depos* depos, const wct_opts* o
   hipStream_t st = static_cast<hipStream_t>(stream);
   return plan->dtype == WCT_F32 ? run_raster<float>(plan, depos, opts, static_cast<float*>(grid), cv, st)
                                 : run_raster<double>(plan, depos, opts, static_cast<double*>(grid), cv, st);
+}
+
+int wct_plan_set_adc(wct_plan* plan, int32_t plane, double gain, double baseline, int32_t max_code) {
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  if (plane < 0 || plane >= plan->n_planes) return fail(WCT_E_INVALID, "plane %d of %d", plane, plan->n_planes);
+  if (!std::isfinite(gain) || !std::isfinite(baseline)) return fail(WCT_E_INVALID, "ADC gain and pedestal must be finite");
+  if (max_code < 1 || max_code > 65535) return fail(WCT_E_INVALID, "largest ADC code %d outside [1, 65535]", max_code);
+  plan->adc_gain[plane] = gain;
+  plan->adc_base[plane] = baseline;
+  plan->adc_max[plane] = max_code;
+  return WCT_OK;
+}
+
+int wct_digitize(const wct_plan* plan, const void* wave, int32_t n_events, uint16_t* adc, void* stream) {
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  if (n_events < 1) return fail(WCT_E_INVALID, "n_events %d < 1", n_events);
+  if (!wave || !adc) return fail(WCT_E_INVALID, "wave or adc is NULL");
+  DeviceGuard dg(plan->device);
+  if (!dg.ok) return fail(WCT_E_DEVICE, "hipSetDevice(%d) failed", plan->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int p = 0; p < plan->n_planes; ++p) {
+    const PlaneGeom& G = plan->geom[p];
+    const int64_t n = (int64_t)G.nw * G.nt;
+    hipError_t e;
+    if (plan->dtype == WCT_F32)
+      e = launch_digitize<float>(static_cast<const float*>(wave) + G.wave_off, plan->wave_elems, n, n_events,
+                                 plan->adc_gain[p], plan->adc_base[p], plan->adc_max[p], adc + G.wave_off, plan->n_cu,
+                                 st);
+    else
+      e = launch_digitize<double>(static_cast<const double*>(wave) + G.wave_off, plan->wave_elems, n, n_events,
+                                  plan->adc_gain[p], plan->adc_base[p], plan->adc_max[p], adc + G.wave_off,
+                                  plan->n_cu, st);
+    if (e != hipSuccess) return hip_fail(e, "digitize launch");
+  }
+  return WCT_OK;
 }
 
 int wct_convolve(wct_plan* plan, const void* grid, int32_t n_events, void* wave, void* ws, size_t ws_size,

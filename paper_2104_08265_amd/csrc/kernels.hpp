@@ -123,6 +123,12 @@ hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigm
                          T* grid, const RasterWs& ws, const DetTables* tables, const double* lfact, int n_cu,
                          hipStream_t st, ProfHook* prof, int tile);
 hipError_t launch_lfact_table(double* out, int n, const DetTables* tables, hipStream_t st);
+
+// adc.hip: codes of n samples per event (event stride ev_stride, in samples, for both the
+// waveform and the codes) of one plane.
+template <typename T>
+hipError_t launch_digitize(const T* wave, int64_t ev_stride, int64_t n, int n_events, double gain, double base,
+                           int max_code, uint16_t* out, int n_cu, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 
 // conv.hip.  A plan with variant >= 0 runs the compiled-plan kernels; the column passes

@@ -101,6 +101,8 @@ wct_tune_raster_workspace_bytes = _sig("wct_tune_raster_workspace_bytes", c_size
 wct_plan_tune_raster = _sig("wct_plan_tune_raster", c_int32, [PlanP, POINTER(wct_depos), POINTER(wct_opts), c_char_p,
                                                              c_void_p, c_size_t, c_void_p])
 wct_plan_set_noise = _sig("wct_plan_set_noise", c_int32, [PlanP, c_int32, POINTER(c_double), c_int64])
+wct_plan_set_adc = _sig("wct_plan_set_adc", c_int32, [PlanP, c_int32, c_double, c_double, c_int32])
+wct_digitize = _sig("wct_digitize", c_int32, [PlanP, c_void_p, c_int32, c_void_p, c_void_p])
 wct_tune_workspace_bytes = _sig("wct_tune_workspace_bytes", c_size_t, [PlanP, c_int32])
 wct_plan_tune = _sig("wct_plan_tune", c_int32, [PlanP, c_int32, c_char_p, c_void_p, c_size_t, c_void_p])
 
@@ -366,6 +368,24 @@ class Plan:
             return
         a = np.ascontiguousarray(amp, dtype=np.float64)
         check(wct_plan_set_noise(self.h, plane, a.ctypes.data_as(POINTER(c_double)), a.size), "wct_plan_set_noise")
+
+    def set_adc(self, plane, gain, baseline, max_code):
+        """ADC converter of a plane: code = min(max(floor(M gain + baseline + 1/2), 0), max_code)."""
+        check(wct_plan_set_adc(self.h, plane, float(gain), float(baseline), int(max_code)), "wct_plan_set_adc")
+
+    def digitize(self, wave, n_events=1, adc=None):
+        """ADC codes of n_events events of `wave` (uint16 values, held in an int16 tensor of
+        the waveform's element count; view them as uint16 on the host)."""
+        torch = _torch()
+        n = n_events * self.wave_elems
+        if wave.numel() < n:
+            raise WctError(WCT_E_INVALID, "wave holds fewer than n_events events")
+        if adc is None:
+            adc = torch.empty(n, dtype=torch.int16, device=f"cuda:{self.device}")
+        elif adc.numel() < n or adc.element_size() != 2:
+            raise WctError(WCT_E_INVALID, "adc must hold n_events events of 16-bit codes")
+        check(wct_digitize(self.h, _ptr(wave), n_events, _ptr(adc), self._stream()), "wct_digitize")
+        return adc
 
     def tune(self, n_events=1, cache_path=None):
         """Pick the fastest transform variant per plane and kind (optionally via a cache file)."""
