@@ -24,6 +24,9 @@ Acceleration Solutions for LArTPC Simulation Using Wire-Cell Toolkit"):
 * ``noise``    - Eq. 1's additive noise term N (Sec. 2): stationary noise per wire from
                  an amplitude spectrum and Philox-keyed complex normals, inverse real
                  transform along ticks.
+* ``drift``    - Fig. 2 / Sec. 2.1.1: drift of 3D ionisation clouds to the readout, their
+                 diffusion along and across the drift, attenuation by the electron
+                 lifetime, and projection onto each plane's wire pitch and ticks.
 * ``adc``      - Eq. 1 / Sec. 2: M as an ADC value; a linear converter per plane (gain,
                  pedestal, largest code), rounding half up, computed in a stated type.
 * ``grad``     - adjoint of the convolution and per-deposition gradients of the
