@@ -660,6 +660,29 @@ def noise_cost(wct, synth, plan, dd, wl, wave, steps=3):
             "spectrum": "synth.noise_amplitude(L_t, rms=300): shaped electronics-like noise, white floor 5%"}
 
 
+def drift_cost(wct, synth, plan, reps=5):
+    """wct_drift of the track workload's 1e5 3D depositions onto the three planes (FP32):
+    mean time over `reps` calls from HIP events on the launch stream, and its HBM rate on
+    algorithmic bytes (7 values read per deposition; 5 values and 3 ints written per row)."""
+    import torch
+    pts, det, prm, _ = synth.config2_points()
+    dp = wct.DevicePoints.from_numpy(pts, "cuda:0", torch.float32)
+    params = wct.drift_params(**prm)
+    rows = plan.drift(dp, params)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.drift(dp, params, rows)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    alg = dp.n * 4 * 7 + rows.n * (4 * 5 + 4 * 3)
+    return {"ms": ms, "depositions": dp.n, "rows": rows.n, "alg_bytes": alg, "GBps": alg / (ms * 1e-3) / 1e9,
+            "note": "launch-bound at this size (a few MB); drift speed 0.16 cm/us, D_L 6.2e-6 and D_T 1.32e-5 "
+                    "cm^2/us, lifetime 10 ms"}
+
+
 def adc_cost(plan, wave, reps=5):
     """ADC digitisation of the step's waveforms (wct_digitize, one 12-bit converter per
     plane): mean time over `reps` calls from HIP events on the launch stream, and its HBM
@@ -767,6 +790,7 @@ def main():
     plan.profile(False)
     noise = noise_cost(wct, synth, plan, dd, wl, wave)
     adc = adc_cost(plan, wave)
+    drift = drift_cost(wct, synth, plan)
 
     n_depos = wl.n_depos
     n_planes = len(wl.planes)
@@ -837,6 +861,7 @@ def main():
                                      roofline.get("alg_ops_per_launch")),
         "noise": noise,
         "adc": adc,
+        "drift": drift,
         "fluct_modes": {"tile_ms": {"mean": t_mean, "binomial": kernels.get("raster_tile_fluct", {}).get("ms_per_step"),
                                     "normal_box_muller": t_normal},
                         "note": "k_tile time of the same event per raster mode (tile shape tuned for the "

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define WCT_ABI_VERSION 6
+#define WCT_ABI_VERSION 7
 /* Version of the fluctuation draw stream (counter layout + sampler).  Bumped whenever a
  * change would alter any fluctuated count for the same inputs and seed. */
 #define WCT_FLUCT_SPEC_VERSION 2
@@ -192,6 +192,49 @@ int wct_raster_noalloc(wct_plan* plan, const wct_depos* depos, const wct_opts* o
  * inverse row transform (no extra pass over the waveforms); a batch gives each event the
  * noise it gets alone.  A set-up call: allocates on first use and synchronises. */
 int wct_plan_set_noise(wct_plan* plan, int32_t plane, const double* amp, int64_t n);
+
+/* Drift of 3D depositions to the readout (Fig. 2: ionisation clouds drift to the wire
+ * planes, spreading along and across the drift; Sec. 2.1.1: the raster takes each
+ * cloud's Gaussian at the plane).  Readout planes at x = 0, uniform drift along -x. */
+#define WCT_MAX_PLANES 8
+typedef struct {
+  int64_t n;                /* depositions, >= 0 */
+  const void* x;            /* [n] distance to the readout planes along the drift, cm */
+  const void* y;            /* [n] cm */
+  const void* z;            /* [n] cm */
+  const void* t0;           /* [n] deposition time, us */
+  const void* q;            /* [n] ionisation electrons */
+  const void* sigma_l;      /* [n] initial extent along the drift, cm (>= 0) */
+  const void* sigma_t;      /* [n] initial extent across the drift, cm (>= 0) */
+  const int32_t* event;     /* [n] event id, or NULL (all 0) */
+  const int32_t* depo_id;   /* [n] deposition id, or NULL (the index j) */
+} wct_depos3d;
+typedef struct {
+  double drift_speed;                    /* v, cm/us, > 0 */
+  double diffusion_l, diffusion_t;       /* D_L, D_T, cm^2/us, >= 0 */
+  double lifetime;                       /* electron lifetime tau, us; <= 0: no attenuation */
+  double tick;                           /* T_tick, us per tick, > 0 */
+  double angle[WCT_MAX_PLANES];          /* plane k: angle theta_k (radians) of its wire normal in (y, z) */
+  double pitch[WCT_MAX_PLANES];          /* P_k, cm, > 0 */
+  double wire_offset[WCT_MAX_PLANES];    /* o_k: pitch coordinate of y = z = 0, pitches */
+  double time_offset[WCT_MAX_PLANES];    /* d_k: time added at plane k, us */
+} wct_drift_params;
+typedef struct {
+  void* q; void* t; void* p; void* sigma_t; void* sigma_p; /* [n_planes * n], plan dtype */
+  int32_t* plane; int32_t* event; int32_t* depo_id;         /* [n_planes * n] */
+} wct_depos_out;
+/* wct_drift (DEVICE arrays; inputs in the plan dtype) writes, for deposition j and plane
+ * k, row k n + j of `out`:
+ *   t_d = x / v,  sigma_L^2 = sigma_l^2 + 2 D_L t_d,  sigma_T^2 = sigma_t^2 + 2 D_T t_d,
+ *   q' = q exp(-t_d / tau) (q without a lifetime), 0 unless x >= 0 and all inputs finite,
+ *   t = (t0 + t_d + d_k) / T_tick,  p = (z cos theta_k + y sin theta_k) / P_k + o_k,
+ *   sigma_t = sigma_L / (v T_tick),  sigma_p = sigma_T / P_k,
+ * with plane k, the deposition's event and id: the rows wct_raster / wct_simulate take
+ * (a row of zero width is dropped there).  Evaluated in FP64 and rounded to the plan
+ * dtype.  A run call: enqueued on `stream`, no workspace, no synchronisation.  Invalid
+ * parameters return WCT_E_INVALID before anything is enqueued. */
+int wct_drift(const wct_plan* plan, const wct_depos3d* in, const wct_drift_params* prm, const wct_depos_out* out,
+              void* stream);
 
 /* ADC digitisation (Eq. 1, Sec. 2: M is a measurement such as an ADC value).
  * wct_plan_set_adc sets plane `plane`'s converter: gain (counts per unit of M), baseline

@@ -39,6 +39,7 @@ SOURCES = {
     "grad.hip": [],
     "probe.cpp": ["-x", "hip"],
     "adc.hip": [],
+    "drift.hip": ["-ffp-contract=off"],
 }
 
 

@@ -1074,6 +1074,65 @@ int wct_raster_noalloc(wct_plan* plan, const wct_depos* depos, const wct_opts* o
                                 : run_raster<double>(plan, depos, opts, static_cast<double*>(grid), cv, st);
 }
 
+static_assert(kMaxPlanes == WCT_MAX_PLANES, "plane limit of the kernels and of the ABI");
+
+int wct_drift(const wct_plan* plan, const wct_depos3d* in, const wct_drift_params* prm, const wct_depos_out* out,
+              void* stream) {
+  g_err.clear();
+  if (!plan || !in || !prm || !out) return fail(WCT_E_INVALID, "NULL argument");
+  if (in->n < 0) return fail(WCT_E_INVALID, "n = %lld < 0", (long long)in->n);
+  if (in->n > 0 && (!in->x || !in->y || !in->z || !in->t0 || !in->q || !in->sigma_l || !in->sigma_t))
+    return fail(WCT_E_INVALID, "a deposition array is NULL");
+  if (in->n > 0 && (!out->q || !out->t || !out->p || !out->sigma_t || !out->sigma_p || !out->plane || !out->event ||
+                    !out->depo_id))
+    return fail(WCT_E_INVALID, "a row array is NULL");
+  if (!(prm->drift_speed > 0.0) || !std::isfinite(prm->drift_speed) || !(prm->tick > 0.0) ||
+      !std::isfinite(prm->tick))
+    return fail(WCT_E_INVALID, "drift speed and tick must be positive and finite");
+  if (!(prm->diffusion_l >= 0.0) || !(prm->diffusion_t >= 0.0) || !std::isfinite(prm->diffusion_l) ||
+      !std::isfinite(prm->diffusion_t) || !std::isfinite(prm->lifetime))
+    return fail(WCT_E_INVALID, "diffusion constants must be finite and >= 0, the lifetime finite");
+  DriftArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n_planes = plan->n_planes;
+  a.speed = prm->drift_speed;
+  a.dl = prm->diffusion_l;
+  a.dt = prm->diffusion_t;
+  a.lifetime = prm->lifetime;
+  a.tick = prm->tick;
+  for (int k = 0; k < plan->n_planes; ++k) {
+    if (!std::isfinite(prm->angle[k]) || !(prm->pitch[k] > 0.0) || !std::isfinite(prm->pitch[k]) ||
+        !std::isfinite(prm->wire_offset[k]) || !std::isfinite(prm->time_offset[k]))
+      return fail(WCT_E_INVALID, "plane %d: angle, offsets finite and pitch > 0 required", k);
+    a.cth[k] = std::cos(prm->angle[k]);
+    a.sth[k] = std::sin(prm->angle[k]);
+    a.pitch[k] = prm->pitch[k];
+    a.woff[k] = prm->wire_offset[k];
+    a.toff[k] = prm->time_offset[k];
+  }
+  DeviceGuard dg(plan->device);
+  if (!dg.ok) return fail(WCT_E_DEVICE, "hipSetDevice(%d) failed", plan->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (plan->dtype == WCT_F32) {
+    using T = float;
+    DriftIn<T> di{in->n, (const T*)in->x, (const T*)in->y, (const T*)in->z, (const T*)in->t0, (const T*)in->q,
+                  (const T*)in->sigma_l, (const T*)in->sigma_t, in->event, in->depo_id};
+    DriftOut<T> o{(T*)out->q, (T*)out->t, (T*)out->p, (T*)out->sigma_t, (T*)out->sigma_p, out->plane, out->event,
+                  out->depo_id};
+    e = launch_drift<T>(di, a, o, plan->n_cu, st);
+  } else {
+    using T = double;
+    DriftIn<T> di{in->n, (const T*)in->x, (const T*)in->y, (const T*)in->z, (const T*)in->t0, (const T*)in->q,
+                  (const T*)in->sigma_l, (const T*)in->sigma_t, in->event, in->depo_id};
+    DriftOut<T> o{(T*)out->q, (T*)out->t, (T*)out->p, (T*)out->sigma_t, (T*)out->sigma_p, out->plane, out->event,
+                  out->depo_id};
+    e = launch_drift<T>(di, a, o, plan->n_cu, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "drift launch");
+  return WCT_OK;
+}
+
 int wct_plan_set_adc(wct_plan* plan, int32_t plane, double gain, double baseline, int32_t max_code) {
   g_err.clear();
   if (!plan) return fail(WCT_E_INVALID, "plan is NULL");

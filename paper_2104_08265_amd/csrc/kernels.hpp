@@ -124,6 +124,26 @@ hipError_t launch_raster(const DepoView<T>& d, const RasterGeom& g, double nsigm
                          hipStream_t st, ProfHook* prof, int tile);
 hipError_t launch_lfact_table(double* out, int n, const DetTables* tables, hipStream_t st);
 
+// drift.hip: 3D depositions -> depo-plane rows (plane-major, n_planes * n rows).
+template <typename T>
+struct DriftIn {
+  int64_t n;
+  const T *x, *y, *z, *t0, *q, *sl0, *st0;
+  const int32_t *event, *depo_id;  // may be null (0, and the deposition index)
+};
+struct DriftArgs {
+  int n_planes;
+  double speed, dl, dt, lifetime, tick;
+  double cth[kMaxPlanes], sth[kMaxPlanes], pitch[kMaxPlanes], woff[kMaxPlanes], toff[kMaxPlanes];
+};
+template <typename T>
+struct DriftOut {
+  T *q, *t, *p, *st, *sp;
+  int32_t *plane, *event, *depo_id;
+};
+template <typename T>
+hipError_t launch_drift(const DriftIn<T>& in, const DriftArgs& a, const DriftOut<T>& out, int n_cu, hipStream_t st);
+
 // adc.hip: codes of n samples per event (event stride ev_stride, in samples, for both the
 // waveform and the codes) of one plane.
 template <typename T>

@@ -325,6 +325,56 @@ def config2(n_depos=100_000, n_tracks=50, n_ticks=9600, wires=(2400, 2400, 3456)
     return Workload("config2", det.planes, resp, _finish(d, dtype), dtype=dtype, fluctuate=fluctuate, seed=2)
 
 
+@dataclass
+class Points:
+    """3D depositions before the drift (structure of arrays): position (cm; x is the
+    distance to the readout planes), time (us), electrons, initial extents (cm)."""
+
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    t0: np.ndarray
+    q: np.ndarray
+    sigma_l: np.ndarray
+    sigma_t: np.ndarray
+    event: np.ndarray
+    depo_id: np.ndarray
+
+    def astype(self, dtype) -> "Points":
+        f = lambda a: a.astype(dtype)
+        return Points(f(self.x), f(self.y), f(self.z), f(self.t0), f(self.q), f(self.sigma_l), f(self.sigma_t),
+                      self.event, self.depo_id)
+
+
+def drift_params(det: Detector, tick_us=0.5, diffusion_l=6.2e-6, diffusion_t=13.2e-6, lifetime_us=10000.0):
+    """Drift constants of a detector as plain numbers: liquid-argon-like longitudinal and
+    transverse diffusion (cm^2/us) and electron lifetime, the detector's drift speed
+    (cm_per_tick / tick), and per plane its wire-normal angle (radians), pitch, the pitch
+    coordinate of y = z = 0 (the projection of Detector.project) and a zero time offset."""
+    angles = [math.radians(a) for a in det.angles_deg]
+    offsets = [0.5 * pl.n_wires - (0.5 * det.width * math.cos(a) + 0.5 * det.height * math.sin(a)) / det.pitch_cm
+               for a, pl in zip(angles, det.planes)]
+    return {"drift_speed": det.cm_per_tick / tick_us, "diffusion_l": diffusion_l, "diffusion_t": diffusion_t,
+            "lifetime": lifetime_us, "tick": tick_us, "angles": tuple(angles),
+            "pitches": tuple(det.pitch_cm for _ in angles), "wire_offsets": tuple(offsets),
+            "time_offsets": tuple(0.0 for _ in angles)}
+
+
+def config2_points(n_depos=100_000, n_tracks=50, n_ticks=9600, wires=(2400, 2400, 3456), dtype=F32):
+    """The three-plane track workload before the drift: 1e5 3D depositions on 50 seeded
+    straight tracks in the drift volume, initial extents 0.03-0.06 cm.  Returns (points,
+    detector, drift constants, responses)."""
+    rng = _rng(6)
+    det = detector_uboone_like(n_ticks, wires)
+    resp = [make_response(pl, rng) for pl in det.planes]
+    xyz, t0 = track_points(rng, det, n_tracks, n_depos)
+    q = moyal_charge(rng, n_depos, 6000.0)
+    prm = drift_params(det)
+    pts = Points(xyz[:, 0], xyz[:, 1], xyz[:, 2], t0 * prm["tick"], q, rng.uniform(0.03, 0.06, n_depos),
+                 rng.uniform(0.03, 0.06, n_depos), np.zeros(n_depos, np.int32), np.arange(n_depos, dtype=np.int32))
+    return pts.astype(np.float32 if dtype == F32 else np.float64), det, prm, resp
+
+
 def config3(n_depos=1_000_000, n_showers=20, n_ticks=6000, wires=(800, 800, 960), dtype=F32,
             fluctuate=True) -> Workload:
     """Two faces x (800+800+960 wires) x 6000 ticks, 1e6 depos in 20 showers, FP32, fluctuation on."""

@@ -46,6 +46,26 @@ class wct_depos(ctypes.Structure):
                 ("sigma_p", c_void_p), ("plane", c_void_p), ("event", c_void_p), ("depo_id", c_void_p)]
 
 
+MAX_PLANES = 8
+
+
+class wct_depos3d(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("x", c_void_p), ("y", c_void_p), ("z", c_void_p), ("t0", c_void_p), ("q", c_void_p),
+                ("sigma_l", c_void_p), ("sigma_t", c_void_p), ("event", c_void_p), ("depo_id", c_void_p)]
+
+
+class wct_drift_params(ctypes.Structure):
+    _fields_ = [("drift_speed", c_double), ("diffusion_l", c_double), ("diffusion_t", c_double),
+                ("lifetime", c_double), ("tick", c_double), ("angle", c_double * MAX_PLANES),
+                ("pitch", c_double * MAX_PLANES), ("wire_offset", c_double * MAX_PLANES),
+                ("time_offset", c_double * MAX_PLANES)]
+
+
+class wct_depos_out(ctypes.Structure):
+    _fields_ = [("q", c_void_p), ("t", c_void_p), ("p", c_void_p), ("sigma_t", c_void_p), ("sigma_p", c_void_p),
+                ("plane", c_void_p), ("event", c_void_p), ("depo_id", c_void_p)]
+
+
 class wct_opts(ctypes.Structure):
     _fields_ = [("nsigma", c_double), ("fluctuate", c_int32), ("n_events", c_int32), ("seed", c_uint64),
                 ("event_base", c_int32), ("noise", c_int32)]
@@ -101,6 +121,8 @@ wct_tune_raster_workspace_bytes = _sig("wct_tune_raster_workspace_bytes", c_size
 wct_plan_tune_raster = _sig("wct_plan_tune_raster", c_int32, [PlanP, POINTER(wct_depos), POINTER(wct_opts), c_char_p,
                                                              c_void_p, c_size_t, c_void_p])
 wct_plan_set_noise = _sig("wct_plan_set_noise", c_int32, [PlanP, c_int32, POINTER(c_double), c_int64])
+wct_drift = _sig("wct_drift", c_int32, [PlanP, POINTER(wct_depos3d), POINTER(wct_drift_params),
+                                         POINTER(wct_depos_out), c_void_p])
 wct_plan_set_adc = _sig("wct_plan_set_adc", c_int32, [PlanP, c_int32, c_double, c_double, c_int32])
 wct_digitize = _sig("wct_digitize", c_int32, [PlanP, c_void_p, c_int32, c_void_p, c_void_p])
 wct_tune_workspace_bytes = _sig("wct_tune_workspace_bytes", c_size_t, [PlanP, c_int32])
@@ -209,6 +231,44 @@ class DeviceDepos:
     def c(self):
         return wct_depos(self.n, _ptr(self.q), _ptr(self.t), _ptr(self.p), _ptr(self.sigma_t), _ptr(self.sigma_p),
                          _ptr(self.plane), _ptr(self.event), _ptr(self.depo_id))
+
+
+class DevicePoints:
+    """3D depositions resident on the device (wct_depos3d): x, y, z, t0, q, sigma_l, sigma_t
+    in the plan dtype, event and depo_id int32 (or None)."""
+
+    FIELDS = ("x", "y", "z", "t0", "q", "sigma_l", "sigma_t")
+
+    def __init__(self, **arrays):
+        for f in self.FIELDS + ("event", "depo_id"):
+            setattr(self, f, arrays.get(f))
+        self.n = int(self.x.shape[0])
+        for f in self.FIELDS:
+            a = getattr(self, f)
+            if a.shape[0] != self.n or a.dtype != self.x.dtype or not a.is_contiguous():
+                raise ValueError("point arrays must share length and dtype and be contiguous")
+
+    @staticmethod
+    def from_numpy(pts, device, dtype):
+        torch = _torch()
+        f = lambda a: torch.as_tensor(a).to(device=device, dtype=dtype).contiguous()
+        i = lambda a: None if a is None else torch.as_tensor(a.astype("int32")).to(device=device).contiguous()
+        return DevicePoints(**{k: f(getattr(pts, k)) for k in DevicePoints.FIELDS},
+                            event=i(getattr(pts, "event", None)), depo_id=i(getattr(pts, "depo_id", None)))
+
+    def c(self):
+        return wct_depos3d(self.n, *(_ptr(getattr(self, f)) for f in self.FIELDS), _ptr(self.event),
+                           _ptr(self.depo_id))
+
+
+def drift_params(drift_speed, diffusion_l, diffusion_t, lifetime, tick, angles, pitches, wire_offsets,
+                 time_offsets):
+    """wct_drift_params from plain numbers (per-plane sequences: angle in radians, pitch,
+    wire offset in pitches, time offset)."""
+    prm = wct_drift_params(float(drift_speed), float(diffusion_l), float(diffusion_t), float(lifetime), float(tick))
+    for k, (a, p, o, d) in enumerate(zip(angles, pitches, wire_offsets, time_offsets)):
+        prm.angle[k], prm.pitch[k], prm.wire_offset[k], prm.time_offset[k] = a, p, o, d
+    return prm
 
 
 FLUCT_MEAN, FLUCT_BINOMIAL, FLUCT_NORMAL = 0, 1, 2
@@ -368,6 +428,25 @@ class Plan:
             return
         a = np.ascontiguousarray(amp, dtype=np.float64)
         check(wct_plan_set_noise(self.h, plane, a.ctypes.data_as(POINTER(c_double)), a.size), "wct_plan_set_noise")
+
+    def drift(self, pts: "DevicePoints", prm: "wct_drift_params", out: "DeviceDepos" = None):
+        """Rows of the drifted depositions on every plane (wct_drift), plane-major."""
+        torch = _torch()
+        n = self.n_planes * pts.n
+        if pts.x.dtype != self.torch_dtype:
+            raise WctError(WCT_E_INVALID, "points must be in the plan dtype")
+        if out is None:
+            dev = pts.x.device
+            f = lambda: torch.empty(n, dtype=self.torch_dtype, device=dev)
+            i = lambda: torch.empty(n, dtype=torch.int32, device=dev)
+            out = DeviceDepos(f(), f(), f(), f(), f(), i(), i(), i())
+        elif out.n != n:
+            raise WctError(WCT_E_INVALID, "out must hold n_planes x n rows")
+        o = wct_depos_out(_ptr(out.q), _ptr(out.t), _ptr(out.p), _ptr(out.sigma_t), _ptr(out.sigma_p),
+                          _ptr(out.plane), _ptr(out.event), _ptr(out.depo_id))
+        d = pts.c()
+        check(wct_drift(self.h, ctypes.byref(d), ctypes.byref(prm), ctypes.byref(o), self._stream()), "wct_drift")
+        return out
 
     def set_adc(self, plane, gain, baseline, max_code):
         """ADC converter of a plane: code = min(max(floor(M gain + baseline + 1/2), 0), max_code)."""

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol(wct):
 
 
 def test_versions(wct):
-    assert wct.wct_abi_version() == 6
+    assert wct.wct_abi_version() == 7
     assert wct.wct_fluct_spec_version() == 2
 
 
