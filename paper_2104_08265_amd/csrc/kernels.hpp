@@ -49,8 +49,8 @@ constexpr int kScanPerBlock = 4096;
 // but more rows straddle tiles.  The first variant of a type is a plan's default; the
 // raster tuner (wct_plan_tune_raster) times them on an event's rows.
 #define WCT_TILE_VARIANTS(X) \
-  X(float, 128, 64, 4)      \
   X(float, 128, 48, 5)      \
+  X(float, 128, 64, 4)      \
   X(float, 128, 32, 6)      \
   X(float, 256, 32, 3)      \
   X(double, 64, 64, 4)      \
