@@ -339,7 +339,8 @@ int wct_plan_set_tile(wct_plan* plan, int32_t variant);
 
 /* Autotuning of the raster tile: times wct_raster of `depos` with `opts` (HIP events on
  * `stream`; turns as in wct_plan_tune) for every tile variant of the plan's dtype and
- * keeps the fastest.  cache_path (HOST, NULL = none): the same text file as
+ * keeps the fastest (a variant replaces an earlier one only when more than 1.5% faster,
+ * so the list's first, the plan's default, wins ties within the timing noise).  cache_path (HOST, NULL = none): the same text file as
  * wct_plan_tune, lines "wct-tile <dtype> <n_planes> (<N_w> <N_t> <I>)... fluct <0|1> ->
  * <TH> <TW> <blocks>"; a choice found there is applied without timing, a new one is
  * appended.  ws: wct_tune_raster_workspace_bytes(plan, opts->n_events, depos->n) bytes

@@ -626,6 +626,9 @@ int plan_tables(wct_plan* P, const wct_plan_desc* desc) {
   return WCT_OK;
 }
 
+// Fraction by which a raster tile variant must beat the one kept so far to replace it.
+constexpr float kTileMargin = 0.015f;
+
 // Position of variant v in a candidate list (v is in it).
 size_t best_at(const std::vector<int>& cand, int v) {
   size_t i = 0;
@@ -821,9 +824,11 @@ int run_tune_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, const ch
                             },
                             st, &ms);
   if (rc) return rc;
+  // a later variant replaces the one kept so far only when clearly faster: the first
+  // (the plan's default) wins ties within the timing noise of a few percent
   int best = cand[0];
   for (size_t c = 1; c < cand.size(); ++c)
-    if (ms[c] < ms[best_at(cand, best)]) best = cand[c];
+    if (ms[c] < (1.0f - kTileMargin) * ms[best_at(cand, best)]) best = cand[c];
   if ((rc = set_tiles(P, best))) return rc;
   if (cache_path) {
     FILE* f = std::fopen(cache_path, "a");

@@ -98,13 +98,35 @@ WCT_HD double uniform53(uint32_t w0, uint32_t w1) {
   return ((double)(w0 >> 6) * 134217728.0 + (double)(w1 >> 5)) * 0x1p-53;
 }
 
+// Whether the predicate holds on any active lane of the wave (on the host: for the one
+// caller).
+WCT_HD bool wave_any(bool v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __ballot(v) != 0;
+#else
+  return v;
+#endif
+}
+
+// The series' added terms a_j = x^(2j+1) / (j! (2j+1)) shrink in magnitude from j >= x^2
+// on.  Once one of them is at most 2^-55 |acc| (below a quarter unit in the last place of
+// acc), it and every later one leave acc unchanged under round-to-nearest, so the sum
+// stops there with the bits of the full kErfTerms-term sum.  The test runs at a few
+// checkpoints only, and the lanes of a wave stop together (a lane that could stop keeps
+// adding terms that change nothing).
 WCT_HD double det_erf(double x) {
   const double mx2 = -(x * x);
   double term = x, acc = x;
+  bool more = true;  // this lane's sum may still change
 #pragma unroll
   for (int j = 1; j < kErfTerms; ++j) {
     term = (term * mx2) * kDet.inv[j];
-    acc = acc + term * kDet.inv[2 * j + 1];
+    const double a = term * kDet.inv[2 * j + 1];
+    acc = acc + a;
+    if (j >= 24 && j % 6 == 0) {
+      more = more && !((double)j >= -mx2 && fabs(a) <= fabs(acc) * 0x1p-55);
+      if (!wave_any(more)) break;
+    }
   }
   return kTwoOverSqrtPi * acc;
 }
@@ -191,22 +213,18 @@ WCT_HD Int binom_quick(Int N, double p, double u) {
 inline thread_local int wct_host_extra_passes = 0;
 #endif
 
-// Whether the predicate holds on any active lane of the wave (on the host: for the one
-// caller).  Loops that end on it have uniform control.
+// wave_any for the sampler's loops, which end on it (uniform control); the host check
+// of the lockstep property can make it report more passes.
 WCT_HD bool any_lane(bool v) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  return __ballot(v) != 0;
-#else
-#ifdef WCT_HOST_LOCKSTEP
-  // host check of the lockstep property: the caller sets extra passes that a lane takes
-  // after its own search has ended, as it does beside slower lanes of its wave
+#if !defined(__HIP_DEVICE_COMPILE__) && defined(WCT_HOST_LOCKSTEP)
+  // the caller sets extra passes that a lane takes after its own search has ended, as it
+  // does beside slower lanes of its wave
   if (wct_host_extra_passes > 0) {
     --wct_host_extra_passes;
     return true;
   }
 #endif
-  return v;
-#endif
+  return wave_any(v);
 }
 
 template <typename Tab>
@@ -216,10 +234,16 @@ WCT_HD int binom_inversion_shared(int N, double pp, double q, double u, const Ta
   // the bit tests are scalar)
   double f = q;
   const int top = 31 - __builtin_clz((unsigned)N);
-#pragma unroll 4
   for (int i = top - 1; i >= 0; --i) {
     f = f * f;
-    if ((N >> i) & 1) f = f * q;
+    if ((N >> i) & 1) {  // a uniform branch: the product only where the bit is set
+      f = f * q;
+#if defined(__HIP_DEVICE_COMPILE__)
+      // keeps the compiler from turning the branch into an unconditional product and a
+      // 64-bit select (three vector instructions for every bit instead of one per set bit)
+      __asm__ volatile("" : "+v"(f));
+#endif
+    }
   }
   // F(k) = F(k-1) + f(k), f(k) = f(k-1) * (r (N - k + 1)) / k, while u >= F and k < cap.
   // Every lane takes the shared steps s = 0, 1, ... (the loop ends once no lane has

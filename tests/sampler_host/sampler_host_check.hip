@@ -9,6 +9,7 @@
 //                                   lane does beside slower lanes of its wave
 //        sampler_host_check philox  stdin lines "c0 c1 c2 c3 k0 k1" (decimal)
 //                                   -> "w0 w1 w2 w3 u_even u_odd" (u as hex floats)
+//        sampler_host_check erf     stdin lines "x" (hex float) -> det_erf(x) (hex float)
 //        sampler_host_check normal  stdin lines "w0 w1 w2 w3 N p_even p_odd" (words and N
 //                                   decimal, p as hex floats) -> "z_even z_odd n_even
 //                                   n_odd sqrt(x) cos sin" for the normal-approximation
@@ -30,6 +31,11 @@ int main(int argc, char** argv) {
       const Philox4 r = philox4x32_10(c0, c1, c2, c3, k0, k1);
       std::printf("%u %u %u %u %a %a\n", r.w0, r.w1, r.w2, r.w3, uniform53(r.w0, r.w1), uniform53(r.w2, r.w3));
     }
+    return 0;
+  }
+  if (std::strcmp(argv[1], "erf") == 0) {
+    char bx[64];
+    while (std::scanf("%63s", bx) == 1) std::printf("%a\n", det_erf(std::strtod(bx, nullptr)));
     return 0;
   }
   if (std::strcmp(argv[1], "normal") == 0) {

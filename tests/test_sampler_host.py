@@ -153,3 +153,17 @@ def test_normal_mode_equals_oracle(checker):
     for col, r in enumerate(ref):
         g = np.array([float.fromhex(x[col]) if col not in (2, 3) else int(x[col]) for x in got])
         assert np.array_equal(g, r), (col, int(np.sum(g != r)))
+
+
+def test_erf_equals_oracle(checker):
+    """The device's det_erf stops its series once the remaining terms cannot change the sum;
+    it must still return the oracle's 60-term value bit for bit, over the arguments the
+    raster uses (|x| <= 4.2 / sqrt 2) and beyond the checkpoints' thresholds."""
+    rng = np.random.default_rng(13)
+    x = np.concatenate([rng.uniform(-3.0, 3.0, 200000), rng.uniform(-1e-3, 1e-3, 2000),
+                        np.linspace(-2.97, 2.97, 20001), [0.0, -0.0, 1e-300, -1e-300, 2.97, -2.97, 4.2, 6.0]])
+    out = subprocess.run([checker, "erf"], input="".join(f"{float(v).hex()}\n" for v in x), capture_output=True,
+                         text=True, check=True).stdout.split()
+    got = np.array([float.fromhex(v) for v in out])
+    ref = OF.det_erf(x)
+    assert np.array_equal(got, ref), int(np.sum(got != ref))
