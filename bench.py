@@ -801,6 +801,10 @@ def main():
         if name in alg and tot > 0:
             gbs = alg[name] * args.steps / (tot * 1e-3) / 1e9
             k.update({"alg_bytes_per_step": alg[name], "GBps": gbs, "hbm_frac": gbs / HBM_PEAK_GBS})
+        mt = measured_traffic(name)
+        if mt and tot > 0 and cnt > 0:  # counter bytes (FETCH_SIZE + WRITE_SIZE) per launch of this build
+            cgbs = mt * cnt / (tot * 1e-3) / 1e9
+            k.update({"counter_bytes_per_launch": mt, "counter_GBps": cgbs, "counter_hbm_frac": cgbs / HBM_PEAK_GBS})
         kernels[name] = k
     t_raster = sum(v["ms_per_step"] for k, v in kernels.items() if k.startswith("raster"))
     t_conv = sum(v["ms_per_step"] for k, v in kernels.items() if k in ("rows_r2c", "colpass", "rows_c2r"))

@@ -9,6 +9,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "fftplan.hpp"
 #include "fftvariants.hpp"
 #include "kernels.hpp"
@@ -841,6 +843,15 @@ int run_tune_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, const ch
 
 }  // namespace
 
+// A named range (roctx) around each call that enqueues work, so that a trace with markers
+// (rocprofv3 --marker-trace) groups the kernels under the call that launched them.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+
 extern "C" {
 
 int wct_abi_version(void) { return WCT_ABI_VERSION; }
@@ -848,6 +859,7 @@ int wct_fluct_spec_version(void) { return WCT_FLUCT_SPEC_VERSION; }
 const char* wct_last_error(void) { return g_err.c_str(); }
 
 int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
+  TraceRange trace_range("wct_plan_create");
   g_err.clear();
   if (!out) return fail(WCT_E_INVALID, "out is NULL");
   *out = nullptr;
@@ -1002,6 +1014,7 @@ size_t wct_workspace_bytes(const wct_plan* plan, int32_t op, int32_t n_events, i
 
 int wct_raster(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* grid, void* ws, size_t ws_size,
                void* stream) {
+  TraceRange trace_range("wct_raster");
   g_err.clear();
   if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
   int rc = check_opts(plan, opts, true);
@@ -1083,6 +1096,7 @@ static_assert(kMaxPlanes == WCT_MAX_PLANES, "plane limit of the kernels and of t
 
 int wct_drift(const wct_plan* plan, const wct_depos3d* in, const wct_drift_params* prm, const wct_depos_out* out,
               void* stream) {
+  TraceRange trace_range("wct_drift");
   g_err.clear();
   if (!plan || !in || !prm || !out) return fail(WCT_E_INVALID, "NULL argument");
   if (in->n < 0) return fail(WCT_E_INVALID, "n = %lld < 0", (long long)in->n);
@@ -1151,6 +1165,7 @@ int wct_plan_set_adc(wct_plan* plan, int32_t plane, double gain, double baseline
 }
 
 int wct_digitize(const wct_plan* plan, const void* wave, int32_t n_events, uint16_t* adc, void* stream) {
+  TraceRange trace_range("wct_digitize");
   g_err.clear();
   if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
   if (n_events < 1) return fail(WCT_E_INVALID, "n_events %d < 1", n_events);
@@ -1177,6 +1192,7 @@ int wct_digitize(const wct_plan* plan, const void* wave, int32_t n_events, uint1
 
 int wct_convolve(wct_plan* plan, const void* grid, int32_t n_events, void* wave, void* ws, size_t ws_size,
                  void* stream) {
+  TraceRange trace_range("wct_convolve");
   g_err.clear();
   if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
   if (n_events < 1 || n_events > plan->max_events)
@@ -1196,6 +1212,7 @@ int wct_convolve(wct_plan* plan, const void* grid, int32_t n_events, void* wave,
 
 int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* wave, void* ws, size_t ws_size,
                  void* stream) {
+  TraceRange trace_range("wct_simulate");
   g_err.clear();
   if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
   int rc = check_opts(plan, opts, true, true);
@@ -1238,6 +1255,7 @@ int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, v
 int wct_simulate_backward(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, const void* grad_wave,
                           void* g_q, void* g_t, void* g_p, void* g_sigma_t, void* g_sigma_p, void* ws, size_t ws_size,
                           void* stream) {
+  TraceRange trace_range("wct_simulate_backward");
   g_err.clear();
   if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
   int rc = check_opts(plan, opts, true);
@@ -1312,6 +1330,7 @@ size_t wct_tune_workspace_bytes(const wct_plan* plan, int32_t n_events) {
 }
 
 int wct_plan_tune(wct_plan* plan, int32_t n_events, const char* cache_path, void* ws, size_t ws_size, void* stream) {
+  TraceRange trace_range("wct_plan_tune");
   g_err.clear();
   if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
   if (n_events < 1 || n_events > plan->max_events)
@@ -1366,6 +1385,7 @@ size_t wct_tune_raster_workspace_bytes(wct_plan* plan, int32_t n_events, int64_t
 
 int wct_plan_tune_raster(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, const char* cache_path,
                          void* ws, size_t ws_size, void* stream) {
+  TraceRange trace_range("wct_plan_tune_raster");
   g_err.clear();
   if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
   int rc = check_opts(plan, opts, true);
