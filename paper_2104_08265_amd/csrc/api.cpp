@@ -270,6 +270,24 @@ ConvWs carve_conv(const wct_plan* P, Carver& cv, int n_events) {
   return c;
 }
 
+// Tiles of the direct column pass per event (all planes) and each plane's first tile.
+WireTileGeom wire_tile_geom(const wct_plan* P) {
+  WireTileGeom g;
+  std::memset(&g, 0, sizeof(g));
+  g.n_planes = P->n_planes;
+  g.rows_ev = P->rows_ev;
+  for (int p = 0; p < P->n_planes; ++p) {
+    const PlaneGeom& G = P->geom[p];
+    g.nw[p] = G.nw;
+    g.I[p] = G.I;
+    g.row_off[p] = G.row_off;
+    g.tile_off[p] = g.tiles_ev;
+    g.tiles_ev += (G.nw + kDirectTileWires - 1) / kDirectTileWires;
+  }
+  g.tile_off[P->n_planes] = g.tiles_ev;
+  return g;
+}
+
 size_t ws_bytes(const wct_plan* P, int op, int n_events, int64_t n_rows) {
   if (op == WCT_OP_RASTER) {
     Carver cv(nullptr);
@@ -288,8 +306,10 @@ size_t ws_bytes(const wct_plan* P, int op, int n_events, int64_t n_rows) {
     Carver r(nullptr), c(nullptr);
     carve_raster(P, r, n_events, n_rows);
     carve_conv(P, c, n_events);
-    // the row flags go last, so the grid and the transform buffers keep their places
-    return head + align_up(r.off > c.off ? r.off : c.off, 256) + align_up(sizeof(int2) * n_events * P->rows_ev, 256);
+    // the row spans and the tile flags go last, so the grid and the transform buffers keep
+    // their places
+    return head + align_up(r.off > c.off ? r.off : c.off, 256) + align_up(sizeof(int2) * n_events * P->rows_ev, 256) +
+           align_up((size_t)n_events * wire_tile_geom(P).tiles_ev, 256);
   }
   if (op == WCT_OP_BACKWARD) {
     Carver a(nullptr);
@@ -354,15 +374,22 @@ int run_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, T* grid, Carv
   return WCT_OK;
 }
 
+
 // span (optional): the raster's row tick spans of these events; the row transform then
 // skips the work (not the zero output) of rows, or row pairs, that no window reached, and
-// reads the others only inside their spans.
+// reads the others only inside their spans.  tiles (optional, with span): room for the
+// direct column pass's tile flags of these events; a plane on the direct pass then skips
+// the tiles no row reaches (zero M^ without reading S^), and its row transform does not
+// write the zero spectra that only such tiles would read.
 template <typename T>
 int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, hipStream_t st,
-                 const int2* span = nullptr, const wct_opts* noise = nullptr) {
+                 const int2* span = nullptr, const wct_opts* noise = nullptr, uint8_t* tiles = nullptr) {
   const ConvWs c = carve_conv(P, cv, n_events);
   cx<T>* shat = static_cast<cx<T>*>(c.shat);
   cx<T>* mhat = static_cast<cx<T>*>(c.mhat);
+  const WireTileGeom tg = wire_tile_geom(P);
+  const bool flags = span && tiles;
+  if (flags) HIP_TRY(launch_wire_tiles(tg, n_events, span, tiles, st), "tile flag launch");
   for (int p = 0; p < P->n_planes; ++p) {
     const PlaneGeom& G = P->geom[p];
     const cx<T>* tw_t = static_cast<const cx<T>*>(P->tw_t[p]);
@@ -370,14 +397,20 @@ int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, 
     const cx<T>* tw_w = static_cast<const cx<T>*>(P->tw_w[p]);
     const cx<T>* tw_wr = static_cast<const cx<T>*>(P->tw_w_rev[p]);
     const int2* lv = span ? span + G.row_off : nullptr;
+    WireTiles wt;
+    if (flags && P->wire_direct[p]) {
+      wt.live = tiles + tg.tile_off[p];
+      wt.ev_stride = tg.tiles_ev;
+      wt.ntile = tg.tile_off[p + 1] - tg.tile_off[p];
+    }
     PROF_LAUNCH(P, "rows_r2c", st,
                 launch_rows_r2c<T>(grid + G.grid_off, P->grid_elems, shat + G.shat_off, P->shat_elems, G.nt, G.I,
-                                   G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, P->n_cu, st, lv, P->rows_ev),
+                                   G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, P->n_cu, st, lv, P->rows_ev, wt),
                 "row transform launch");
     if (P->wire_direct[p])
       PROF_LAUNCH(P, "colpass", st,
                   launch_colpass_direct<T>(shat + G.shat_off, P->shat_elems, static_cast<const cx<T>*>(P->rtick[p]),
-                                           mhat + G.mhat_off, P->mhat_elems, G.nw, G.I, G.nchunk, n_events, st),
+                                           mhat + G.mhat_off, P->mhat_elems, G.nw, G.I, G.nchunk, n_events, st, wt),
                   "column pass launch");
     else
       PROF_LAUNCH(P, "colpass", st,
@@ -1228,7 +1261,9 @@ int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, v
   Carver head(ws);
   void* grid = head.take(plan->esize * (size_t)batch * plan->grid_elems);
   const size_t rest = align_up(head.off, 256);
-  int2* span = reinterpret_cast<int2*>(static_cast<char*>(ws) + need -
+  const size_t tile_bytes = align_up((size_t)batch * wire_tile_geom(plan).tiles_ev, 256);
+  uint8_t* tiles = static_cast<uint8_t*>(ws) + need - tile_bytes;
+  int2* span = reinterpret_cast<int2*>(static_cast<char*>(ws) + need - tile_bytes -
                                        align_up(sizeof(int2) * (size_t)batch * plan->rows_ev, 256));
   // sub-batches of up to max_events events: raster into the workspace grid, then the
   // transform passes write the sub-batch's slots of `wave`
@@ -1241,11 +1276,11 @@ int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, v
     if (plan->dtype == WCT_F32) {
       if ((rc = run_raster<float>(plan, depos, &sub, static_cast<float*>(grid), cr, st, span))) return rc;
       rc = run_convolve<float>(plan, static_cast<const float*>(grid), sub.n_events, reinterpret_cast<float*>(w), cc,
-                               st, span, &sub);
+                               st, span, &sub, tiles);
     } else {
       if ((rc = run_raster<double>(plan, depos, &sub, static_cast<double*>(grid), cr, st, span))) return rc;
       rc = run_convolve<double>(plan, static_cast<const double*>(grid), sub.n_events, reinterpret_cast<double*>(w),
-                                cc, st, span, &sub);
+                                cc, st, span, &sub, tiles);
     }
     if (rc) return rc;
   }

@@ -390,10 +390,11 @@ static void for_all_fft(Fn&& fn) {
 template <typename T>
 hipError_t launch_rows_r2c(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt, int nphase,
                            int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
-                           const cx<T>* post, int n_cu, hipStream_t st, const int2* span, int64_t span_ev) {
+                           const cx<T>* post, int n_cu, hipStream_t st, const int2* span, int64_t span_ev,
+                           const WireTiles& wt) {
   if (plan.variant >= 0)
     return launch_rows_r2c_ct<T>(src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, n_events, plan, tw,
-                                 post, n_cu, st, span, span_ev);
+                                 post, n_cu, st, span, span_ev, wt);
   const size_t lds = sizeof(cx<T>) * plan.n;
   const int total = nphase * nper * n_events;
   const hipError_t e = with_fft<T, 0>(plan, [&](auto f, int thr) {
@@ -503,7 +504,7 @@ void conv_init_kernels() {
 #define WCT_INST(T)                                                                                            \
   template hipError_t launch_rows_r2c<T>(const T*, int64_t, cx<T>*, int64_t, int, int, int, int, int,          \
                                          const FftPlan&, const cx<T>*, const cx<T>*, int, hipStream_t,        \
-                                         const int2*, int64_t);          \
+                                         const int2*, int64_t, const WireTiles&); \
   template hipError_t launch_colpass<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int, int,   \
                                         int, const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);         \
   template hipError_t launch_colpass_adj<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int,    \

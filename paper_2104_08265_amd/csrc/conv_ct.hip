@@ -137,7 +137,8 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
                                                                   int nchunk, int n_events,
                                                                   const cx<T>* __restrict__ tw,
                                                                   const cx<T>* __restrict__ post,
-                                                                  const int2* __restrict__ span, int64_t span_ev) {
+                                                                  const int2* __restrict__ span, int64_t span_ev,
+                                                                  WireTiles wt) {
   constexpr int M = F::N, NT = F::kThreads, R0 = F::R0;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* z = reinterpret_cast<cx<T>*>(smem_raw);
@@ -191,6 +192,20 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
     const int2* f = span + ev * span_ev;
     return (f[(int64_t)c * nphase + i].y | f[(int64_t)(c + 1) * nphase + i].y) != 0;
   };
+  // Whether a pair's zero spectrum is read: with tile flags, only a live tile of the direct
+  // column pass reads S^ (wires [t W - K, t W + W + K) of tile t), so a dead pair that no
+  // live tile covers is not written at all.
+  auto pair_read = [&](int Q) -> bool {
+    if (!wt.live) return true;
+    int ev, i, c;
+    row_of(Q, 0, ev, i, c);
+    const uint8_t* tl = wt.live + ev * wt.ev_stride;
+    constexpr int W = kDirectTileWires, K = kDirectHalfWires;
+    const int thi = min(wt.ntile - 1, (c + 1 + K) / W);
+    bool r = false;
+    for (int t = max(0, thi - 2); t <= thi; ++t) r |= (t * W - K <= c + 1) && (c < t * W + W + K) && tl[t] != 0;
+    return r;
+  };
   unsigned long long mask = 0;
   int left = 0;  // unused bits of mask
   auto live_at = [&](int Q) -> bool {  // called once per iteration, in order; Q: its pair
@@ -223,10 +238,11 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
     {
       if (!liveP) {
         if (liveN) load(Pn, 0);
-        for (int x = threadIdx.x; x < 2 * fpad; x += NT) {
-          const int q = x / (2 * C), e = x - q * (2 * C);
-          o[(int64_t)q * cstride + e] = mk(T(0), T(0));
-        }
+        if (pair_read(P))
+          for (int x = threadIdx.x; x < 2 * fpad; x += NT) {
+            const int q = x / (2 * C), e = x - q * (2 * C);
+            o[(int64_t)q * cstride + e] = mk(T(0), T(0));
+          }
         P = Pn;
         liveP = liveN;
         continue;
@@ -507,7 +523,8 @@ static void for_all_variants(Fn&& fn) {
 template <typename T>
 hipError_t launch_rows_r2c_ct(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt,
                               int nphase, int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
-                              const cx<T>* post, int n_cu, hipStream_t st, const int2* span, int64_t span_ev) {
+                              const cx<T>* post, int n_cu, hipStream_t st, const int2* span, int64_t span_ev,
+                              const WireTiles& wt) {
   const size_t lds = sizeof(cx<T>) * plan.n;
   const size_t lds_pair = lds + sizeof(cx<T>) * nchunk * kChunk;
   const int total = nphase * nper * n_events;
@@ -520,7 +537,7 @@ hipError_t launch_rows_r2c_ct(const T* src, int64_t src_ev_stride, cx<T>* dst, i
     if (pair)
       hipLaunchKernelGGL((k_rows_r2c_pair_ct<T, kChunk, F>), pgrid, dim3(F::kThreads), lds_pair, st, src,
                          src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, n_events, tw, post, span,
-                         span_ev);
+                         span_ev, wt);
     else
       hipLaunchKernelGGL((k_rows_r2c_ct<T, kChunk, F>), dim3(persistent_blocks(n_cu, lds, F::kThreads, total)),
                          dim3(F::kThreads), lds, st, src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk,
@@ -613,7 +630,7 @@ void conv_ct_init_kernels() {
 #define WCT_INST(T)                                                                                              \
   template hipError_t launch_rows_r2c_ct<T>(const T*, int64_t, cx<T>*, int64_t, int, int, int, int, int,         \
                                             const FftPlan&, const cx<T>*, const cx<T>*, int, hipStream_t,       \
-                                            const int2*, int64_t);                                              \
+                                            const int2*, int64_t, const WireTiles&);                            \
   template hipError_t launch_colpass_ct<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int, int,  \
                                            int, const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t);        \
   template hipError_t launch_colpass_adj_ct<T>(const cx<T>*, int64_t, const cx<T>*, cx<T>*, int64_t, int, int,   \

@@ -102,7 +102,8 @@ inline int persistent_blocks(int n_cu, size_t lds, int threads, int work) {
 template <typename T>
 hipError_t launch_rows_r2c_ct(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt,
                               int nphase, int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
-                              const cx<T>* post, int n_cu, hipStream_t st, const int2* span, int64_t span_ev);
+                              const cx<T>* post, int n_cu, hipStream_t st, const int2* span, int64_t span_ev,
+                              const WireTiles& wt);
 template <typename T>
 hipError_t launch_colpass_ct(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtil, cx<T>* mhat,
                              int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events,

@@ -154,6 +154,17 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 // conv.hip.  A plan with variant >= 0 runs the compiled-plan kernels; the column passes
 // of those take a second twiddle table for the same radices in reverse order (tw_rev).
 // Rows are read with 16-byte loads (and the next row prefetched) when their length and base allow it.
+// Tiles of the direct column pass (kDirectTileWires output wires each, reading the S^ rows
+// of kDirectHalfWires more wires on either side) that some window's rows reach, as
+// wct_simulate records them: a tile no row reaches writes a zero M^ without reading S^,
+// so a dead row pair that no live tile reads needs no zero spectrum from pass A.
+constexpr int kDirectTileWires = 512, kDirectHalfWires = 10;
+struct WireTiles {
+  const uint8_t* live = nullptr;  // [event][tile] of this plane (ev_stride apart); nullptr: all
+  int64_t ev_stride = 0;
+  int ntile = 0;
+};
+
 // span (optional, [event][span_ev] row tick spans of this plane): the runtime kernel
 // and the wire-pair kernel neither load nor transform a row (pair) no window reached and
 // write its zero spectrum directly, and read a row only inside its span; the compiled
@@ -162,7 +173,7 @@ template <typename T>
 hipError_t launch_rows_r2c(const T* src, int64_t src_ev_stride, cx<T>* dst, int64_t dst_ev_stride, int nt, int nphase,
                            int nper, int nchunk, int n_events, const FftPlan& plan, const cx<T>* tw,
                            const cx<T>* post, int n_cu, hipStream_t st, const int2* span = nullptr,
-                           int64_t span_ev = 0);
+                           int64_t span_ev = 0, const WireTiles& wt = WireTiles());
 template <typename T>
 hipError_t launch_colpass(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtil, cx<T>* mhat,
                           int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, const FftPlan& plan,
@@ -170,9 +181,20 @@ hipError_t launch_colpass(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>
 // wiredirect.hip: pass B as direct sums over the response's 2K+1 wires (K = 10 only)
 bool colpass_direct_fits(int K);
 void wiredirect_init_kernels();
+// wt (optional): the plane's tile flags; a tile no row reaches writes zeros.
 template <typename T>
 hipError_t launch_colpass_direct(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtick, cx<T>* mhat,
-                                 int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, hipStream_t st);
+                                 int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, hipStream_t st,
+                                 const WireTiles& wt = WireTiles());
+// The direct pass's tile flags of every plane and event from the row spans: plane p's
+// tiles start at tile_off[p] of an event's tiles_ev.
+struct WireTileGeom {
+  int n_planes, tiles_ev;
+  int64_t rows_ev;
+  int nw[kMaxPlanes], I[kMaxPlanes], tile_off[kMaxPlanes + 1];
+  int64_t row_off[kMaxPlanes];
+};
+hipError_t launch_wire_tiles(const WireTileGeom& g, int n_events, const int2* span, uint8_t* live, hipStream_t st);
 template <typename T>
 hipError_t launch_colpass_adj_direct(const cx<T>* ghat, int64_t ghat_ev_stride, const cx<T>* rtick, cx<T>* hhat,
                                      int64_t hhat_ev_stride, int nw, int nphase, int nchunk, int n_events,

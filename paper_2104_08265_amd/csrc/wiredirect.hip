@@ -18,9 +18,10 @@ namespace wct {
 
 namespace {
 
-constexpr int kDirectK = 10;                // response half-width the kernel is compiled for
+constexpr int kDirectK = kDirectHalfWires;  // response half-width the kernel is compiled for
 constexpr int kDirectWL = 8;                // output wires per lane
 constexpr int kDirectWT = 64 * kDirectWL;   // output wires per block
+static_assert(kDirectWT == kDirectTileWires, "tile flags and blocks share their wires");
 constexpr int kDirectSpan = kDirectWT + 2 * kDirectK;  // S^ wires staged per phase
 // LDS stride of one frequency's staged wires: one pad element every kDirectWL wires, so
 // that lanes reading wires kDirectWL apart hit distinct banks
@@ -36,7 +37,7 @@ template <typename T>
 __global__ void __launch_bounds__(64 * kChunk) k_colpass_direct(const cx<T>* __restrict__ shat, int64_t shat_ev_stride,
                                                                const cx<T>* __restrict__ rtick, cx<T>* __restrict__ mhat,
                                                                int64_t mhat_ev_stride, int nw, int nphase, int nchunk,
-                                                               int ntile, int n_events) {
+                                                               int ntile, int n_events, WireTiles wt) {
   constexpr int K = kDirectK, NK = 2 * K + 1, WL = kDirectWL, WT = kDirectWT;
   constexpr int SPAN = kDirectSpan, PSTR = kDirectPstr, C = kChunk;
   constexpr int CPV = 16 / (int)sizeof(cx<T>);  // complex values per 16-byte load
@@ -51,6 +52,14 @@ __global__ void __launch_bounds__(64 * kChunk) k_colpass_direct(const cx<T>* __r
   const int w0 = tile * WT;
   const int tid = (int)threadIdx.x, lane = tid & 63;
   const int f = __builtin_amdgcn_readfirstlane(tid >> 6);  // this wave's frequency in the chunk
+  if (wt.live && !wt.live[ev * wt.ev_stride + tile]) {  // no row reaches the tile: M^ = 0
+    cx<T>* dst = mhat + ev * mhat_ev_stride;
+    for (int o = 0; o < WL; ++o) {
+      const int w = w0 + WL * lane + o;
+      if (w < nw) dst[(int64_t)w * (nchunk * C) + ch * C + f] = mk(T(0), T(0));
+    }
+    return;
+  }
   const cx<T>* src = shat + ev * shat_ev_stride + (int64_t)ch * nphase * nw * C;
 
   V stage[NPT];
@@ -203,7 +212,8 @@ void wiredirect_init_kernels() {
 
 template <typename T>
 hipError_t launch_colpass_direct(const cx<T>* shat, int64_t shat_ev_stride, const cx<T>* rtick, cx<T>* mhat,
-                                 int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, hipStream_t st) {
+                                 int64_t mhat_ev_stride, int nw, int nphase, int nchunk, int n_events, hipStream_t st,
+                                 const WireTiles& wt) {
   static_assert(kChunk == 4, "one wave per frequency of a chunk");
   const int ntile = (nw + kDirectWT - 1) / kDirectWT;
   const int64_t nblk = (int64_t)nchunk * n_events * ntile;
@@ -211,7 +221,30 @@ hipError_t launch_colpass_direct(const cx<T>* shat, int64_t shat_ev_stride, cons
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
   const size_t lds = direct_lds<T>();  // FP64: above 64 KB, allowed by wiredirect_init_kernels
   hipLaunchKernelGGL((k_colpass_direct<T>), dim3((unsigned)nblk), dim3(64 * kChunk), lds, st, shat, shat_ev_stride,
-                     rtick, mhat, mhat_ev_stride, nw, nphase, nchunk, ntile, n_events);
+                     rtick, mhat, mhat_ev_stride, nw, nphase, nchunk, ntile, n_events, wt);
+  return hipGetLastError();
+}
+
+// One block per (event, tile): whether any impact row of the tile's wires, halo included,
+// holds a window (span hi != 0).
+__global__ void __launch_bounds__(256) k_wire_tiles(WireTileGeom g, const int2* __restrict__ span,
+                                                     uint8_t* __restrict__ live) {
+  const int ev = blockIdx.x / g.tiles_ev;
+  int t = blockIdx.x - ev * g.tiles_ev;
+  int p = 0;
+  while (p + 1 < g.n_planes && t >= g.tile_off[p + 1]) ++p;
+  t -= g.tile_off[p];
+  const int wlo = max(0, t * kDirectWT - kDirectK), whi = min(g.nw[p], (t + 1) * kDirectWT + kDirectK);
+  const int2* f = span + (int64_t)ev * g.rows_ev + g.row_off[p];
+  int any = 0;
+  for (int r = wlo * g.I[p] + (int)threadIdx.x; r < whi * g.I[p]; r += 256) any |= f[r].y != 0;
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) live[blockIdx.x] = (uint8_t)(any != 0);
+}
+
+hipError_t launch_wire_tiles(const WireTileGeom& g, int n_events, const int2* span, uint8_t* live, hipStream_t st) {
+  if (n_events <= 0 || g.tiles_ev <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_wire_tiles, dim3((unsigned)(n_events * g.tiles_ev)), dim3(256), 0, st, g, span, live);
   return hipGetLastError();
 }
 
@@ -234,8 +267,8 @@ template hipError_t launch_colpass_adj_direct<float>(const cx<float>*, int64_t, 
 template hipError_t launch_colpass_adj_direct<double>(const cx<double>*, int64_t, const cx<double>*, cx<double>*,
                                                       int64_t, int, int, int, int, hipStream_t);
 template hipError_t launch_colpass_direct<float>(const cx<float>*, int64_t, const cx<float>*, cx<float>*, int64_t, int,
-                                                 int, int, int, hipStream_t);
+                                                 int, int, int, hipStream_t, const WireTiles&);
 template hipError_t launch_colpass_direct<double>(const cx<double>*, int64_t, const cx<double>*, cx<double>*, int64_t,
-                                                  int, int, int, int, hipStream_t);
+                                                  int, int, int, int, hipStream_t, const WireTiles&);
 
 }  // namespace wct

@@ -60,3 +60,39 @@ def test_spans_read_only_what_is_there(wct, n_ticks, dtype):
         assert torch.equal(w1, w2), (n_ticks, dtype, v)
         assert rel_l2(to_np(plan.wave_view(w1)[0]), ref) < tol, (n_ticks, dtype, v)
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_direct_pass_tiles_no_row_reaches(wct, dtype):
+    """A sparse plane of three 512-wire tiles of the direct column pass: charge only near
+    the first tile boundary (wires 500-525, whose rows the neighbouring tile reads through
+    its 10-wire halo) and near the last wire.  Tiles no row reaches write zeros without
+    reading S^, and pass A leaves out the zero spectra only such tiles would read; the
+    waveform must still equal wct_raster + wct_convolve bit for bit and the oracle."""
+    pl = synth.Plane(1100, 1024, 10, 10, 200)
+    rows = [(5000.0, 300.0, 500.5, 1.0, 0.3), (4000.0, 400.0, 511.7, 1.5, 0.4), (3000.0, 350.0, 523.9, 1.0, 0.2),
+            (6000.0, 700.0, 1098.2, 2.0, 0.5)]
+    a = np.array(rows)
+    n = len(a)
+    d = synth.Depos(a[:, 0], a[:, 1], a[:, 2], a[:, 3], a[:, 4], np.zeros(n, np.int32), np.zeros(n, np.int32),
+                    np.arange(n, dtype=np.int32))
+    wl = synth.Workload("tiles", [pl], [synth.make_response(pl, np.random.default_rng(6))], synth._finish(d, dtype),
+                        dtype=dtype, seed=23)
+    plan = make_plan(wct, wl)
+    assert plan.get_fft(0, 1) == wct.WCT_WIRE_DIRECT
+    dd = device_depos(wct, wl)
+    o = wct.opts(3.0, False, 1, wl.seed)
+    ref = OC.convolve_fft(OR.raster(wl.depos, wl.planes)[0][0], synth.round_responses(wl)[0].astype(np.float64),
+                          pl.n_impacts)
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    for v in plan.fft_candidates(0, 0):
+        plan.set_fft(0, 0, v)
+        say("direct-pass tiles", dtype, "tick plan", v)
+        # a dense call first: its spectra must not leak into the sparse one
+        plan.simulate(device_depos(wct, wl, synth.uniform_points(np.random.default_rng(7), 0, pl, 400)), o)
+        w1 = plan.simulate(dd, o).clone()
+        w2 = plan.convolve(plan.raster(dd, o), 1)
+        torch.cuda.synchronize()
+        assert torch.equal(w1, w2), (dtype, v)
+        assert rel_l2(to_np(plan.wave_view(w1)[0]), ref) < tol, (dtype, v)
+    plan.close()
