@@ -270,6 +270,13 @@ ConvWs carve_conv(const wct_plan* P, Carver& cv, int n_events) {
   return c;
 }
 
+// Bands of raster tile rows per event, all planes (the current tile variant's TH).
+int64_t bands_ev(const wct_plan* P) {
+  int64_t b = 0;
+  for (const PlaneGeom& G : P->geom) b += G.ntr;
+  return b;
+}
+
 // Tiles of the direct column pass per event (all planes) and each plane's first tile.
 WireTileGeom wire_tile_geom(const wct_plan* P) {
   WireTileGeom g;
@@ -309,6 +316,7 @@ size_t ws_bytes(const wct_plan* P, int op, int n_events, int64_t n_rows) {
     // the row spans and the tile flags go last, so the grid and the transform buffers keep
     // their places
     return head + align_up(r.off > c.off ? r.off : c.off, 256) + align_up(sizeof(int2) * n_events * P->rows_ev, 256) +
+           align_up(sizeof(int2) * n_events * bands_ev(P), 256) +
            align_up((size_t)n_events * wire_tile_geom(P).tiles_ev, 256);
   }
   if (op == WCT_OP_BACKWARD) {
@@ -364,10 +372,11 @@ DepoView<T> view(const wct_depos* d) {
 // Launch sequences -------------------------------------------------------------------
 template <typename T>
 int run_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, T* grid, Carver& cv, hipStream_t st,
-               int2* span = nullptr) {
+               int2* span = nullptr, int2* hull = nullptr) {
   const RasterGeom g = raster_geom(P, o->n_events, o->event_base);
   RasterWs ws = carve_raster(P, cv, o->n_events, d->n);
   ws.span = span;
+  ws.hull = hull;
   HIP_TRY(launch_raster<T>(view<T>(d), g, o->nsigma, o->fluctuate, o->seed, grid, ws, P->d_tables, P->d_lfact,
                            P->n_cu, st, hook(P), P->tile),
           "raster launch");
@@ -1261,9 +1270,12 @@ int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, v
   Carver head(ws);
   void* grid = head.take(plan->esize * (size_t)batch * plan->grid_elems);
   const size_t rest = align_up(head.off, 256);
+  // the tail of the workspace: row spans, band hulls, tile flags
   const size_t tile_bytes = align_up((size_t)batch * wire_tile_geom(plan).tiles_ev, 256);
+  const size_t hull_bytes = align_up(sizeof(int2) * (size_t)batch * bands_ev(plan), 256);
   uint8_t* tiles = static_cast<uint8_t*>(ws) + need - tile_bytes;
-  int2* span = reinterpret_cast<int2*>(static_cast<char*>(ws) + need - tile_bytes -
+  int2* hull = reinterpret_cast<int2*>(static_cast<char*>(ws) + need - tile_bytes - hull_bytes);
+  int2* span = reinterpret_cast<int2*>(static_cast<char*>(ws) + need - tile_bytes - hull_bytes -
                                        align_up(sizeof(int2) * (size_t)batch * plan->rows_ev, 256));
   // sub-batches of up to max_events events: raster into the workspace grid, then the
   // transform passes write the sub-batch's slots of `wave`
@@ -1274,11 +1286,11 @@ int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, v
     Carver cr(static_cast<char*>(ws) + rest), cc(static_cast<char*>(ws) + rest);
     char* w = static_cast<char*>(wave) + plan->esize * (size_t)e0 * plan->wave_elems;
     if (plan->dtype == WCT_F32) {
-      if ((rc = run_raster<float>(plan, depos, &sub, static_cast<float*>(grid), cr, st, span))) return rc;
+      if ((rc = run_raster<float>(plan, depos, &sub, static_cast<float*>(grid), cr, st, span, hull))) return rc;
       rc = run_convolve<float>(plan, static_cast<const float*>(grid), sub.n_events, reinterpret_cast<float*>(w), cc,
                                st, span, &sub, tiles);
     } else {
-      if ((rc = run_raster<double>(plan, depos, &sub, static_cast<double*>(grid), cr, st, span))) return rc;
+      if ((rc = run_raster<double>(plan, depos, &sub, static_cast<double*>(grid), cr, st, span, hull))) return rc;
       rc = run_convolve<double>(plan, static_cast<const double*>(grid), sub.n_events, reinterpret_cast<double*>(w),
                                 cc, st, span, &sub, tiles);
     }

@@ -130,7 +130,8 @@ __global__ void __launch_bounds__(F::kBound) k_rows_r2c(const T* __restrict__ sr
       for (int u = ntv * VN + threadIdx.x; u < 2 * M; u += nthr) zr[u] = T(0);
     } else {
       const T* s = src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt;
-      for (int u = threadIdx.x; u < 2 * M; u += nthr) zr[u] = u < nt ? s[u] : T(0);
+      const int2 sp = row_span(FLAGS ? span : nullptr, ev * span_ev + (int64_t)c * nphase + i, nt);
+      for (int u = threadIdx.x; u < 2 * M; u += nthr) zr[u] = (u < nt && u >= sp.x && u < sp.y) ? s[u] : T(0);
     }
     __syncthreads();
     if (vec && liveN) prefetch(Ln);  // next row in flight during this row's transform

@@ -64,7 +64,8 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_ct(const
                                                              cx<T>* __restrict__ dst, int64_t dst_ev_stride, int nt,
                                                              int nphase, int nper, int nchunk, int n_events,
                                                              const cx<T>* __restrict__ tw,
-                                                             const cx<T>* __restrict__ post) {
+                                                             const cx<T>* __restrict__ post,
+                                                             const int2* __restrict__ span, int64_t span_ev) {
   constexpr int M = F::N, NT = F::kThreads, R0 = F::R0;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* z = reinterpret_cast<cx<T>*>(smem_raw);
@@ -83,7 +84,9 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_ct(const
   auto load = [&](int L) {
     int ev, i, c;
     row_of(L, ev, i, c);
-    load_row_inputs<F>(src + ev * src_ev_stride + ((int64_t)c * nphase + i) * nt, nt, v2, make_int2(0, nt), in);
+    // with row spans a row is read only inside its span (a row no window reached: none of it)
+    const int64_t row = (int64_t)c * nphase + i;
+    load_row_inputs<F>(src + ev * src_ev_stride + row * nt, nt, v2, row_span(span, ev * span_ev + row, nt), in);
   };
   int L = xcd_remap(blockIdx.x, gridDim.x);
   if (L < total) load(L);
@@ -541,7 +544,7 @@ hipError_t launch_rows_r2c_ct(const T* src, int64_t src_ev_stride, cx<T>* dst, i
     else
       hipLaunchKernelGGL((k_rows_r2c_ct<T, kChunk, F>), dim3(persistent_blocks(n_cu, lds, F::kThreads, total)),
                          dim3(F::kThreads), lds, st, src, src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk,
-                         n_events, tw, post);
+                         n_events, tw, post, span, span_ev);
   });
   return e != hipSuccess ? e : hipGetLastError();
 }

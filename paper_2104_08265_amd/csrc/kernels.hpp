@@ -82,7 +82,15 @@ struct RasterWs {
   int64_t ntiles;
   int64_t max_items;
   int2* span = nullptr;  // optional [event][rows_ev] tick spans of the rows (row_span)
+  int2* hull = nullptr;  // with span: [event][bands] tile-column hull of each band of TH rows
 };
+
+// Bands of TH impact rows (tile rows) per event over all planes, and plane p's first band.
+__host__ __device__ inline int bands_before(const RasterGeom& g, int p) {
+  int b = 0;
+  for (int q = 0; q < p; ++q) b += g.pl[q].ntr;
+  return b;
+}
 
 // Tick span of an impact row as the raster records it: {kSpanBase - lo, hi}, both
 // raised by atomic max from zero, where [lo, hi) is the union hull of the tick windows of

@@ -340,7 +340,7 @@ template <typename T, int TH, int TW>
 __global__ void __launch_bounds__(kCountBlock) k_count(DepoView<T> d, RasterGeom g, double nsigma,
                                                        int32_t* __restrict__ counts, int32_t* __restrict__ rank,
                                                        int32_t* __restrict__ big, int32_t* __restrict__ ctrl,
-                                                       int2* __restrict__ span) {
+                                                       int2* __restrict__ span, int2* __restrict__ hull) {
   static_assert(kCountSlots > 4 * kCountBlock && (kCountSlots & (kCountSlots - 1)) == 0, "count table size");
   __shared__ int32_t s_key[kCountSlots];  // tile index, -1 = free
   __shared__ int32_t s_cnt[kCountSlots];  // rows of this block in the tile, then their first slot
@@ -359,19 +359,20 @@ __global__ void __launch_bounds__(kCountBlock) k_count(DepoView<T> d, RasterGeom
       const int tr0 = w.b0 / TH, tr1 = (w.b1 - 1) / TH, tc0 = w.k0 / TW, tc1 = (w.k1 - 1) / TW;
       const bool wide = (tr1 - tr0 + 1) * (tc1 - tc0 + 1) > 4;
       if (span) {
-        // The impact rows this window reaches are marked (span hi >= 1).  A row taking
-        // the tile path gets its span from its band's tiles afterwards (k_band_spans); a
-        // wide row, which no tile counts, records its ticks [k0, k1) itself (these rows
-        // are few).  Test first, so that neighbouring depositions do not contend.
+        // The impact rows this window reaches are marked (span hi >= 1); they get their
+        // band's tile hull afterwards (k_band_spans).  Test first, so that neighbouring
+        // depositions do not contend.  A wide row, which no tile counts, widens the hulls
+        // of its bands itself (these rows are few).
         int2* f = span + (int64_t)w.event * g.rows_ev + pl.row_off;
-        const int a = kSpanBase - w.k0;
-        for (int b = w.b0; b < w.b1; ++b) {
-          const int2 cur = f[b];
-          if (wide) {
-            if (cur.x < a) atomicMax(&f[b].x, a);
-            if (cur.y < w.k1) atomicMax(&f[b].y, w.k1);
-          } else if (cur.y == 0) {
-            atomicMax(&f[b].y, 1);
+        for (int b = w.b0; b < w.b1; ++b)
+          if (f[b].y == 0) atomicMax(&f[b].y, 1);
+        if (wide) {
+          int bands_ev = 0;
+          for (int q = 0; q < g.n_planes; ++q) bands_ev += g.pl[q].ntr;
+          int2* h = hull + (int64_t)w.event * bands_ev + bands_before(g, w.plane);
+          for (int tr = tr0; tr <= tr1; ++tr) {
+            atomicMax(&h[tr].x, kSpanBase - tc0);
+            atomicMax(&h[tr].y, tc1 + 1);
           }
         }
       }
@@ -407,13 +408,15 @@ __global__ void __launch_bounds__(kCountBlock) k_count(DepoView<T> d, RasterGeom
 }
 
 // 1b. row tick spans from the tiles (wct_simulate) -----------------------------
-// One block per band of TH impact rows (one tile row of a plane): the ticks of the band's
-// tiles that some row reaches, [TW * (first such tile), TW * (last + 1)), hold every
-// nonzero cell of the band's tile-path rows, so the band's marked rows take that hull
-// (merged with what wide rows recorded).  Rows no window reached keep {0, 0}.
+// One block per band of TH impact rows (one tile row of a plane): the band's tiles that
+// some row reaches (a tile row's count, or a wide row's window) form the hull of tile
+// columns [lo, hi]; ticks [TW lo, TW (hi + 1)) hold every nonzero cell of the band, so the
+// band's marked rows take that span.  The hull is kept ({2^30 - lo, hi + 1}) for the tile
+// kernel, which clears only the empty tiles inside it: the row transform reads nothing
+// else.  Rows no window reached keep {0, 0}.
 template <int TH, int TW>
 __global__ void __launch_bounds__(256) k_band_spans(RasterGeom g, const int32_t* __restrict__ counts,
-                                                     int bands_ev, int2* __restrict__ span) {
+                                                     int bands_ev, int2* __restrict__ span, int2* __restrict__ hull) {
   __shared__ int s_lo[4], s_hi[4];
   const int ev = blockIdx.x / bands_ev;
   int bin = blockIdx.x - ev * bands_ev;
@@ -441,13 +444,19 @@ __global__ void __launch_bounds__(256) k_band_spans(RasterGeom g, const int32_t*
   __syncthreads();
   lo = min(min(s_lo[0], s_lo[1]), min(s_lo[2], s_lo[3]));
   hi = max(max(s_hi[0], s_hi[1]), max(s_hi[2], s_hi[3]));
-  const int klo = hi >= 0 ? lo * TW : kSpanBase, khi = hi >= 0 ? min((hi + 1) * TW, pl.nt) : 0;
+  int2* hb = hull + blockIdx.x;  // [event][band]: blockIdx.x = ev * bands_ev + band
+  const int2 wide = *hb;         // the wide rows' tile columns, {2^30 - lo, hi + 1} or {0, 0}
+  if (wide.y > 0) {
+    lo = min(lo, kSpanBase - wide.x);
+    hi = max(hi, wide.y - 1);
+  }
+  __syncthreads();  // every thread has read the wide rows' hull
+  if (threadIdx.x == 0) *hb = hi >= 0 ? make_int2(kSpanBase - lo, hi + 1) : make_int2(0, 0);
+  const int klo = hi >= 0 ? lo * TW : 0, khi = hi >= 0 ? min((hi + 1) * TW, pl.nt) : 0;
   int2* f = span + (int64_t)ev * g.rows_ev + pl.row_off;
   const int b1 = min((tr + 1) * TH, pl.nb);
-  for (int b = tr * TH + threadIdx.x; b < b1; b += 256) {
-    const int2 s = f[b];
-    if (s.y != 0) f[b] = make_int2(kSpanBase - min(klo, kSpanBase - s.x), max(khi, s.y));
-  }
+  for (int b = tr * TH + threadIdx.x; b < b1; b += 256)
+    if (f[b].y != 0) f[b] = make_int2(kSpanBase - klo, khi);
 }
 
 // 2. scan of (rows, items) per tile -------------------------------------------
@@ -628,7 +637,8 @@ __global__ void __launch_bounds__(256, OCC) k_tile(DepoView<T> d, RasterGeom g, 
                                               const int32_t* __restrict__ offs, const int32_t* __restrict__ items,
                                               const int32_t* __restrict__ item_off, const int32_t* __restrict__ counts,
                                               int64_t ntiles, int32_t* __restrict__ ctrl,
-                                              const DetTables* __restrict__ tables, const double* __restrict__ lf) {
+                                              const DetTables* __restrict__ tables, const double* __restrict__ lf,
+                                              const int2* __restrict__ hull) {
   constexpr int NWAVE = 4;
   static_assert(TH * TW <= (1 << kDstBits), "tile offsets must fit below the packed electron count");
   __shared__ T tile[TH * TW];
@@ -658,11 +668,41 @@ __global__ void __launch_bounds__(256, OCC) k_tile(DepoView<T> d, RasterGeom g, 
     __syncthreads();  // every thread has read s_item and s_zero
     // the group is cleared after the item, so that its stores drain while the other
     // blocks of the CU compute
+    // With band hulls (wct_simulate), an empty tile outside its band's hull is left as it
+    // is: the row transform reads only inside the hulls.  The group's tiles are walked with
+    // their band and column stepped along (a band's hull is read once).
     auto clear_group = [&]() {
       if (!more_zero) return;
-      const int64_t z1 = min((int64_t)(zg + 1) * kZeroGroup, ntiles);
-      for (int64_t t = (int64_t)zg * kZeroGroup; t < z1; ++t)
-        if (counts[t] == 0) zero_tile<T, TH, TW>(g, t, grid);
+      const int64_t t0 = (int64_t)zg * kZeroGroup, z1 = min(t0 + kZeroGroup, ntiles);
+      if (!hull) {
+        for (int64_t t = t0; t < z1; ++t)
+          if (counts[t] == 0) zero_tile<T, TH, TW>(g, t, grid);
+        return;
+      }
+      int ev = 0, p = 0, tr = 0, tc = 0;
+      int2 h = make_int2(0, 0);
+      auto locate = [&](int64_t t) {  // band, column and hull of tile t
+        ev = (int)(t / g.ntiles_ev);
+        const int tin = (int)(t - (int64_t)ev * g.ntiles_ev);
+        p = find_plane(g, tin);
+        const int tl = tin - (int)g.pl[p].tile_off;
+        tr = tl / g.pl[p].ntc;
+        tc = tl - tr * g.pl[p].ntc;
+        h = hull[(int64_t)ev * bands_before(g, g.n_planes) + bands_before(g, p) + tr];
+      };
+      locate(t0);
+      for (int64_t t = t0; t < z1; ++t) {
+        if (counts[t] == 0 && h.y > 0 && tc >= kSpanBase - h.x && tc < h.y) zero_tile<T, TH, TW>(g, t, grid);
+        if (++tc == g.pl[p].ntc) {  // next band (of this plane, or the next plane or event)
+          if (tr + 1 < g.pl[p].ntr) {
+            tc = 0;
+            ++tr;
+            h = hull[(int64_t)ev * bands_before(g, g.n_planes) + bands_before(g, p) + tr];
+          } else if (t + 1 < z1) {
+            locate(t + 1);
+          }
+        }
+      }
     };
     if (!more_items) {
       clear_group();
@@ -790,21 +830,24 @@ hipError_t launch_raster_tiles(const DepoView<T>& d, const RasterGeom& g, double
   // control words and counts are contiguous
   hipError_t e = launch_fill_i32(ws.ctrl, kCtrlWords + nt, 0, st);
   if (e != hipSuccess) return e;
+  const int bands_ev = bands_before(g, g.n_planes);
+  if (ws.span && !ws.hull) return hipErrorInvalidValue;  // spans come with band hulls
   if (ws.span) {
+    e = launch_fill_i32(reinterpret_cast<int32_t*>(ws.hull), 2 * (int64_t)g.n_events * bands_ev, 0, st);
+    if (e != hipSuccess) return e;
     e = launch_fill_i32(reinterpret_cast<int32_t*>(ws.span), 2 * g.n_events * g.rows_ev, 0, st);
     if (e != hipSuccess) return e;
   }
   const unsigned rblocks = (unsigned)((d.n + 255) / 256);
   if (d.n > 0) {
     hipLaunchKernelGGL((k_count<T, TH, TW>), dim3((unsigned)((d.n + kCountBlock - 1) / kCountBlock)),
-                       dim3(kCountBlock), 0, st, d, g, nsigma, ws.counts, ws.rank, ws.big, ws.ctrl, ws.span);
+                       dim3(kCountBlock), 0, st, d, g, nsigma, ws.counts, ws.rank, ws.big, ws.ctrl, ws.span,
+                       ws.hull);
     WCT_CHECK_LAUNCH();
   }
   if (ws.span) {
-    int bands_ev = 0;
-    for (int p = 0; p < g.n_planes; ++p) bands_ev += g.pl[p].ntr;
     hipLaunchKernelGGL((k_band_spans<TH, TW>), dim3((unsigned)(g.n_events * bands_ev)), dim3(256), 0, st, g,
-                       ws.counts, bands_ev, ws.span);
+                       ws.counts, bands_ev, ws.span, ws.hull);
     WCT_CHECK_LAUNCH();
   }
   const int nsb = (int)((nt + kScanPerBlock - 1) / kScanPerBlock);
@@ -830,7 +873,7 @@ hipError_t launch_raster_tiles(const DepoView<T>& d, const RasterGeom& g, double
   if (prof) prof->begin(kTileName[mode], st);
 #define WCT_TILE_LAUNCH(M)                                                                                        \
   hipLaunchKernelGGL((k_tile<T, M, TH, TW, OCC>), dim3(pblocks), dim3(256), 0, st, d, g, nsigma, seed, grid, ws.list, \
-                     ws.offs, ws.items, ws.item_off, ws.counts, nt, ws.ctrl, tables, lfact)
+                     ws.offs, ws.items, ws.item_off, ws.counts, nt, ws.ctrl, tables, lfact, ws.hull)
   if (mode == kModeBinomial)
     WCT_TILE_LAUNCH(kModeBinomial);
   else if (mode == kModeNormal)
