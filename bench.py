@@ -540,6 +540,12 @@ def batch_bench(wct, synth, sub_batch=16, reps=2):
     torch.cuda.synchronize()
     out["graph_replay_bitwise_equal"] = bool(torch.equal(wave_b, wave_l))
     del gb, gl
+    # the library's own graph of the batched call (wct_simulate_graph: captured on the
+    # first call, launched from the plan's cache after)
+    wave_b.fill_(-1.0)
+    out["batched_abi_graph_ms_per_event"] = timed(lambda: plan.simulate_graph(dd, o_all, wave_b)) / n_ev
+    torch.cuda.synchronize()
+    out["abi_graph_bitwise_equal"] = bool(torch.equal(wave_b, wave_l))
     plan.close()
     return out
 

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define WCT_ABI_VERSION 7
+#define WCT_ABI_VERSION 8
 /* Version of the fluctuation draw stream (counter layout + sampler).  Bumped whenever a
  * change would alter any fluctuated count for the same inputs and seed. */
 #define WCT_FLUCT_SPEC_VERSION 2
@@ -263,6 +263,24 @@ int wct_convolve(wct_plan* plan, const void* grid, int32_t n_events, void* wave,
  * (wct_workspace_bytes(plan, WCT_OP_SIMULATE, n, rows) caps n at max_events). */
 int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* wave, void* ws,
                  size_t ws_bytes, void* stream);
+
+/* wct_simulate replayed from a HIP graph, for callers that repeat the same call and want
+ * one launch instead of one per kernel (the launches of a whole event take a few hundred
+ * microseconds to enqueue one by one).  Same arguments, result and errors as
+ * wct_simulate.  The first call with a given set of arguments (every pointer in depos,
+ * depos->n, every field of opts, wave, ws, the needed workspace size) captures the
+ * launches on a stream the plan owns and keeps the instantiated graph; later calls with
+ * the same arguments launch it on `stream`.  The graph reads the buffers the pointers
+ * name when it runs, so the data behind them may change between calls; new pointers,
+ * sizes or options (a new seed, say) capture a new graph.  The plan keeps at most 32
+ * graphs (the cache is emptied when full) and drops them in every set-up call that
+ * changes what its launches take (wct_plan_set_noise, wct_plan_set_fft, wct_plan_tune,
+ * wct_plan_set_tile, wct_plan_tune_raster) and in wct_plan_destroy; those calls
+ * synchronise the device first.  WCT_E_INVALID while kernel timing is on.  Calls on one
+ * plan are not thread safe; two replays of one graph on different streams race on the
+ * same workspace like two wct_simulate calls would. */
+int wct_simulate_graph(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* wave, void* ws,
+                       size_t ws_bytes, void* stream);
 
 /* Gradients of a scalar loss with respect to each row's (Q, t, p, sigma_t, sigma_p),
  * given grad_wave = dL/dwave (same layout as wave).  Uses the convolution's adjoint

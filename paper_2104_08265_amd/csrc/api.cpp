@@ -177,13 +177,27 @@ struct wct_plan {
   int tile = 0;         // raster tile variant: index among the variants of the plan's dtype
   int tile_global = 0;  // the same variant's index in the whole list (wct_tile_variant_info)
 
+  // wct_simulate_graph: instantiated graphs by call key, and the stream they are captured on
+  std::map<std::string, hipGraphExec_t> graphs;
+  hipStream_t cap_stream = nullptr;
+
   void* dalloc(size_t bytes, hipError_t* e) {
     void* p = nullptr;
     *e = hipMalloc(&p, bytes ? bytes : 1);
     if (*e == hipSuccess) allocs.push_back(p);
     return p;
   }
+  // Graphs hold the plan's choices (transform plans, tile shape, noise spectra) and
+  // buffers as kernel arguments: a set-up call that changes them drops them first.
+  void drop_graphs() {
+    if (graphs.empty()) return;
+    (void)hipDeviceSynchronize();  // a replay may still run
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
   ~wct_plan() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void* p : allocs) (void)hipFree(p);
   }
 };
@@ -1076,6 +1090,7 @@ int wct_raster(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, voi
 int wct_plan_set_noise(wct_plan* plan, int32_t plane, const double* amp, int64_t n) {
   g_err.clear();
   if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  plan->drop_graphs();
   if (plane < 0 || plane >= plan->n_planes) return fail(WCT_E_INVALID, "plane %d of %d", plane, plan->n_planes);
   const PlaneGeom& G = plan->geom[plane];
   if (!amp) {  // no noise on this plane (the buffer stays with the plan)
@@ -1252,21 +1267,14 @@ int wct_convolve(wct_plan* plan, const void* grid, int32_t n_events, void* wave,
                                     st);
 }
 
-int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* wave, void* ws, size_t ws_size,
-                 void* stream) {
-  TraceRange trace_range("wct_simulate");
-  g_err.clear();
-  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
-  int rc = check_opts(plan, opts, true, true);
-  if (rc) return rc;
-  if ((rc = check_depos(depos))) return rc;
-  if (!wave) return fail(WCT_E_INVALID, "wave is NULL");
+// Graphs kept per plan by wct_simulate_graph before the cache is emptied.
+static constexpr size_t kMaxGraphs = 32;
+
+// The launches of wct_simulate on stream st (arguments checked; `need` workspace bytes).
+static int simulate_enqueue(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* wave, void* ws, size_t need,
+                            hipStream_t st) {
+  int rc = WCT_OK;
   const int batch = opts->n_events < plan->max_events ? opts->n_events : plan->max_events;
-  const size_t need = ws_bytes(plan, WCT_OP_SIMULATE, batch, depos->n);
-  if (!ws || ws_size < need) return fail(WCT_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_size, need);
-  DeviceGuard dg(plan->device);
-  if (!dg.ok) return fail(WCT_E_DEVICE, "hipSetDevice(%d) failed", plan->device);
-  hipStream_t st = static_cast<hipStream_t>(stream);
   Carver head(ws);
   void* grid = head.take(plan->esize * (size_t)batch * plan->grid_elems);
   const size_t rest = align_up(head.off, 256);
@@ -1297,6 +1305,70 @@ int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, v
     if (rc) return rc;
   }
   return WCT_OK;
+}
+
+int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* wave, void* ws, size_t ws_size,
+                 void* stream) {
+  TraceRange trace_range("wct_simulate");
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  int rc = check_opts(plan, opts, true, true);
+  if (rc) return rc;
+  if ((rc = check_depos(depos))) return rc;
+  if (!wave) return fail(WCT_E_INVALID, "wave is NULL");
+  const int batch = opts->n_events < plan->max_events ? opts->n_events : plan->max_events;
+  const size_t need = ws_bytes(plan, WCT_OP_SIMULATE, batch, depos->n);
+  if (!ws || ws_size < need) return fail(WCT_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_size, need);
+  DeviceGuard dg(plan->device);
+  if (!dg.ok) return fail(WCT_E_DEVICE, "hipSetDevice(%d) failed", plan->device);
+  return simulate_enqueue(plan, depos, opts, wave, ws, need, static_cast<hipStream_t>(stream));
+}
+
+int wct_simulate_graph(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* wave, void* ws,
+                       size_t ws_size, void* stream) {
+  TraceRange trace_range("wct_simulate_graph");
+  g_err.clear();
+  if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  int rc = check_opts(plan, opts, true, true);
+  if (rc) return rc;
+  if ((rc = check_depos(depos))) return rc;
+  if (!wave) return fail(WCT_E_INVALID, "wave is NULL");
+  if (plan->prof.on) return fail(WCT_E_INVALID, "wct_simulate_graph: kernel timing is on (graphs hold no timing events)");
+  const int batch = opts->n_events < plan->max_events ? opts->n_events : plan->max_events;
+  const size_t need = ws_bytes(plan, WCT_OP_SIMULATE, batch, depos->n);
+  if (!ws || ws_size < need) return fail(WCT_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_size, need);
+  DeviceGuard dg(plan->device);
+  if (!dg.ok) return fail(WCT_E_DEVICE, "hipSetDevice(%d) failed", plan->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // the key: every argument the launches take by value
+  char key[512];
+  std::snprintf(key, sizeof(key), "%p %p %p %p %p %p %p %p %lld|%a %d %d %llu %d %d|%p %p %zu", depos->q, depos->t,
+                depos->p, depos->sigma_t, depos->sigma_p, (const void*)depos->plane, (const void*)depos->event,
+                (const void*)depos->depo_id, (long long)depos->n, opts->nsigma, opts->fluctuate, opts->n_events,
+                (unsigned long long)opts->seed, opts->event_base, opts->noise, wave, ws, need);
+  auto it = plan->graphs.find(key);
+  if (it == plan->graphs.end()) {
+    if (plan->graphs.size() >= kMaxGraphs) plan->drop_graphs();
+    hipError_t e = hipSuccess;
+    if (!plan->cap_stream) e = hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    e = hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "begin capture");
+    rc = simulate_enqueue(plan, depos, opts, wave, ws, need, plan->cap_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(plan->cap_stream, &graph);
+    if (rc == WCT_OK && e != hipSuccess) rc = hip_fail(e, "end capture");
+    hipGraphExec_t exec = nullptr;
+    if (rc == WCT_OK) {
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) rc = hip_fail(e, "graph instantiate");
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc) return rc;
+    it = plan->graphs.emplace(key, exec).first;
+  }
+  const hipError_t e = hipGraphLaunch(it->second, st);
+  return e == hipSuccess ? WCT_OK : hip_fail(e, "graph launch");
 }
 
 int wct_simulate_backward(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, const void* grad_wave,
@@ -1362,6 +1434,7 @@ int wct_plan_get_fft(const wct_plan* plan, int32_t plane, int32_t kind, int32_t*
 int wct_plan_set_fft(wct_plan* plan, int32_t plane, int32_t kind, int32_t variant) {
   g_err.clear();
   if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  plan->drop_graphs();
   if (plane < 0 || plane >= plan->n_planes || (kind != 0 && kind != 1))
     return fail(WCT_E_INVALID, "plane %d / kind %d out of range", plane, kind);
   DeviceGuard dg(plan->device);
@@ -1380,6 +1453,7 @@ int wct_plan_tune(wct_plan* plan, int32_t n_events, const char* cache_path, void
   TraceRange trace_range("wct_plan_tune");
   g_err.clear();
   if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  plan->drop_graphs();
   if (n_events < 1 || n_events > plan->max_events)
     return fail(WCT_E_INVALID, "n_events %d outside [1, %d]", n_events, plan->max_events);
   const size_t need = tune_ws_bytes(plan, n_events);
@@ -1422,6 +1496,7 @@ int wct_plan_get_tile(const wct_plan* plan, int32_t* variant) {
 int wct_plan_set_tile(wct_plan* plan, int32_t variant) {
   g_err.clear();
   if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  plan->drop_graphs();
   return set_tiles(plan, variant);
 }
 
@@ -1435,6 +1510,7 @@ int wct_plan_tune_raster(wct_plan* plan, const wct_depos* depos, const wct_opts*
   TraceRange trace_range("wct_plan_tune_raster");
   g_err.clear();
   if (!plan) return fail(WCT_E_INVALID, "plan is NULL");
+  plan->drop_graphs();
   int rc = check_opts(plan, opts, true);
   if (rc) return rc;
   if ((rc = check_depos(depos))) return rc;

@@ -98,6 +98,8 @@ wct_probe_last_error = _sig("wct_probe_last_error", c_char_p, [])
 wct_convolve = _sig("wct_convolve", c_int32, [PlanP, c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p])
 wct_simulate = _sig("wct_simulate", c_int32, [PlanP, POINTER(wct_depos), POINTER(wct_opts), c_void_p, c_void_p,
                                              c_size_t, c_void_p])
+wct_simulate_graph = _sig("wct_simulate_graph", c_int32, [PlanP, POINTER(wct_depos), POINTER(wct_opts), c_void_p,
+                                                         c_void_p, c_size_t, c_void_p])
 wct_simulate_backward = _sig("wct_simulate_backward", c_int32,
                              [PlanP, POINTER(wct_depos), POINTER(wct_opts), c_void_p, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
@@ -375,6 +377,15 @@ class Plan:
         d = depos.c()
         check(wct_simulate(self.h, ctypes.byref(d), ctypes.byref(o), _ptr(wave), _ptr(ws), nb, self._stream()),
               "wct_simulate")
+        return wave
+
+    def simulate_graph(self, depos: DeviceDepos, o: wct_opts, wave=None):
+        """simulate() replayed from the plan's graph for these arguments (captured on first use)."""
+        wave = self.new_wave(o.n_events) if wave is None else wave
+        ws, nb = self.workspace(OP_SIMULATE, o.n_events, depos.n)
+        d = depos.c()
+        check(wct_simulate_graph(self.h, ctypes.byref(d), ctypes.byref(o), _ptr(wave), _ptr(ws), nb, self._stream()),
+              "wct_simulate_graph")
         return wave
 
     def simulate_backward(self, depos: DeviceDepos, o: wct_opts, grad_wave):

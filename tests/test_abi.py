@@ -21,7 +21,8 @@ def declared_functions():
 
 def test_header_declares_the_calls():
     names = declared_functions()
-    for n in ("wct_raster", "wct_convolve", "wct_simulate", "wct_simulate_backward", "wct_plan_create",
+    for n in ("wct_raster", "wct_convolve", "wct_simulate", "wct_simulate_graph", "wct_simulate_backward",
+              "wct_plan_create",
               "wct_plan_destroy", "wct_workspace_bytes", "wct_last_error"):
         assert n in names
 
@@ -32,7 +33,7 @@ def test_library_exports_every_declared_symbol(wct):
 
 
 def test_versions(wct):
-    assert wct.wct_abi_version() == 7
+    assert wct.wct_abi_version() == 8
     assert wct.wct_fluct_spec_version() == 2
 
 
