@@ -811,6 +811,9 @@ def main():
         if mt and tot > 0 and cnt > 0:  # counter bytes (FETCH_SIZE + WRITE_SIZE) per launch of this build
             cgbs = mt * cnt / (tot * 1e-3) / 1e9
             k.update({"counter_bytes_per_launch": mt, "counter_GBps": cgbs, "counter_hbm_frac": cgbs / HBM_PEAK_GBS})
+        mc = measured_counters(name)
+        if mc and tot > 0 and cnt > 0:  # VALU issue: SQ_INSTS_VALU wave instructions x 64 lanes per launch
+            k["valu_issue_frac"] = mc["SQ_INSTS_VALU"] * 64 / ((tot / cnt) * 1e-3 * ALU_PEAK_TOPS * 1e12)
         kernels[name] = k
     t_raster = sum(v["ms_per_step"] for k, v in kernels.items() if k.startswith("raster"))
     t_conv = sum(v["ms_per_step"] for k, v in kernels.items() if k in ("rows_r2c", "colpass", "rows_c2r"))
@@ -822,7 +825,8 @@ def main():
     roofline_fft = {"kernel": fft_dom, "bound": "hbm", "achieved": kd["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": kd["GBps"] / HBM_PEAK_GBS, "traffic": measured_traffic(fft_dom),
                     "alg_bytes_per_launch": alg[fft_dom] / n_planes,
-                    "avg_launch_ms": kd["ms_per_step"] / kd["launches_per_step"]}
+                    "avg_launch_ms": kd["ms_per_step"] / kd["launches_per_step"],
+                    "valu_issue_frac": kd.get("valu_issue_frac")}
     if dom == "raster_tile_fluct":
         ops = raster_alu_ops(wl)
         t = kernels[dom]["ms_per_step"] * 1e-3
