@@ -177,11 +177,16 @@ def summarize_counters(out_dir):
         digests.add(log_digest(os.path.join(out_dir, f"pmc_{tag}.log")))
         last = {}
         rows = list(csv.DictReader(open(paths[0])))
-        # the bench's own launches are the last ones of each family (the tuners run first)
+        # the headline step's launches: the last of each family before the mean raster that
+        # the bench runs after the step (the tuners run before it; the noise, ADC and drift
+        # figures after it run the transform passes again)
+        ids_mean = [int(r["Dispatch_Id"]) for r in rows if family(r["Kernel_Name"]) == "raster_tile_mean"]
+        cut = min(ids_mean) if ids_mean else None
         for r in rows:
             fam = family(r["Kernel_Name"])
-            if fam:
-                last.setdefault(fam, []).append(int(r["Dispatch_Id"]))
+            did = int(r["Dispatch_Id"])
+            if fam and (cut is None or did < cut or not fam.startswith(("rows_", "colpass", "raster_tile_fluct"))):
+                last.setdefault(fam, []).append(did)
         want = {fam: set(sorted(set(ids))[-3:] if fam in ("rows_r2c", "colpass", "rows_c2r") else sorted(set(ids))[-1:])
                 for fam, ids in last.items()}
         for r in rows:
