@@ -63,7 +63,7 @@ enum wct_status {
   WCT_E_WORKSPACE = -2,   /* workspace smaller than wct_workspace_bytes() asks for     */
   WCT_E_DEVICE = -3,      /* a HIP runtime call failed (text in wct_last_error)        */
   WCT_E_UNSUPPORTED = -4, /* geometry the kernels do not handle (e.g. FFT length)      */
-  WCT_E_NOMEM = -5        /* device allocation at plan creation failed                  */
+  WCT_E_NOMEM = -5        /* device allocation failed, or passed WCT_PLAN_MEM_CAP       */
 };
 
 enum wct_op { WCT_OP_RASTER = 0, WCT_OP_CONVOLVE = 1, WCT_OP_SIMULATE = 2, WCT_OP_BACKWARD = 3 };
@@ -128,7 +128,15 @@ int wct_plane_info(const wct_plan* plan, int32_t plane, int64_t out[10]);
  * device, the response spectrum of every plane (Eq. 2 takes the response in the
  * frequency domain, transformed once ahead of the per-event work).  Allocates device
  * memory and synchronises (as does wct_plan_set_fft; no run call does).  On failure
- * *out is NULL. */
+ * *out is NULL and nothing stays allocated.
+ * Errors: WCT_E_INVALID for a bad description; WCT_E_UNSUPPORTED for a plane grid of
+ * 2^32 cells or more, or when max_events events' buffers (grid, spectra, waveforms,
+ * row records) would exceed 2^60 bytes; WCT_E_DEVICE without a HIP device; WCT_E_NOMEM
+ * when a device allocation fails.  The environment variable WCT_PLAN_MEM_CAP (a
+ * decimal byte count, read by each call) caps the device memory the plan's own tables
+ * may take while it is built: a plan that needs more fails with WCT_E_NOMEM before the
+ * allocation that would pass the cap (a value that is not a byte count: WCT_E_INVALID).
+ * The geometry checks come before any device call, so they answer without a GPU. */
 int wct_plan_create(const wct_plan_desc* desc, wct_plan** out);
 void wct_plan_destroy(wct_plan* plan); /* NULL is a no-op; synchronises the device */
 

@@ -1,6 +1,8 @@
 // C ABI of libwct.so (declared in include/wct.h): plans, workspace carving, argument
 // validation and the launch sequences of the raster, convolution and gradient paths.
+#include <cerrno>
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -33,7 +35,7 @@ int fail(int code, const char* fmt, ...) {
 }
 
 int hip_fail(hipError_t e, const char* what) {
-  return fail(WCT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return fail(e == hipErrorOutOfMemory ? WCT_E_NOMEM : WCT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
 #define HIP_TRY(expr, what)                       \
@@ -181,10 +183,24 @@ struct wct_plan {
   std::map<std::string, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
 
+  // wct_plan_create's device memory cap (WCT_PLAN_MEM_CAP; 0: none), what dalloc has
+  // handed out, and whether the cap refused an allocation
+  size_t mem_cap = 0, mem_used = 0;
+  bool cap_hit = false;
+
   void* dalloc(size_t bytes, hipError_t* e) {
     void* p = nullptr;
-    *e = hipMalloc(&p, bytes ? bytes : 1);
-    if (*e == hipSuccess) allocs.push_back(p);
+    if (bytes == 0) bytes = 1;
+    if (mem_cap && bytes > mem_cap - (mem_used < mem_cap ? mem_used : mem_cap)) {
+      cap_hit = true;
+      *e = hipErrorOutOfMemory;
+      return nullptr;
+    }
+    *e = hipMalloc(&p, bytes);
+    if (*e == hipSuccess) {
+      allocs.push_back(p);
+      mem_used += bytes;
+    }
     return p;
   }
   // Graphs hold the plan's choices (transform plans, tile shape, noise spectra) and
@@ -925,9 +941,15 @@ int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
     return fail(WCT_E_INVALID, "n_planes %d outside [1, %d]", desc->n_planes, kMaxPlanes);
   if (!desc->planes) return fail(WCT_E_INVALID, "planes is NULL");
   if (desc->max_events < 1) return fail(WCT_E_INVALID, "max_events %d < 1", desc->max_events);
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(WCT_E_DEVICE, "no HIP device available");
-  if (desc->device < 0 || desc->device >= ndev) return fail(WCT_E_INVALID, "device %d of %d", desc->device, ndev);
+  size_t mem_cap = 0;
+  if (const char* cs = std::getenv("WCT_PLAN_MEM_CAP")) {
+    char* end = nullptr;
+    errno = 0;
+    const unsigned long long v = std::strtoull(cs, &end, 10);
+    if (end == cs || *end != '\0' || errno != 0 || cs[0] == '-')
+      return fail(WCT_E_INVALID, "WCT_PLAN_MEM_CAP=\"%s\" is not a byte count", cs);
+    mem_cap = (size_t)v;
+  }
 
   wct_plan* P = new wct_plan();
   P->dtype = desc->dtype;
@@ -982,6 +1004,25 @@ int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
   P->wave_elems = woff;
   P->shat_elems = soff;
   P->mhat_elems = moff;
+  {
+    // the per-event buffers of max_events events (grid, both spectra twice over, rows'
+    // records) must stay far from the size_t range of the workspace arithmetic
+    const double per_ev = (double)P->esize * (double)(goff + woff + 4 * soff + 4 * moff) + 64.0 * (double)roff;
+    if ((double)P->max_events * per_ev > 0x1p60) {
+      delete P;
+      return fail(WCT_E_UNSUPPORTED, "max_events %d x %.3g bytes of buffers per event exceeds 2^60 bytes",
+                  desc->max_events, per_ev);
+    }
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    delete P;
+    return fail(WCT_E_DEVICE, "no HIP device available");
+  }
+  if (desc->device < 0 || desc->device >= ndev) {
+    delete P;
+    return fail(WCT_E_INVALID, "device %d of %d", desc->device, ndev);
+  }
   int tile0 = -1, nvar = 0;  // the first tile variant of the dtype
   const TileVariantDesc* tv = tile_variants(&nvar);
   for (int v = 0; v < nvar && tile0 < 0; ++v)
@@ -1005,11 +1046,16 @@ int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
     delete P;
     return rc;
   }
-  rc = P->dtype == WCT_F32 ? plan_tables<float>(P, desc) : plan_tables<double>(P, desc);
-  if (rc) {
+  P->mem_cap = mem_cap;
+  // a refusal by the cap reports as such, whichever allocation it met
+  auto capped = [&](int code) {
+    if (P->cap_hit)
+      code = fail(WCT_E_NOMEM, "the plan's device tables need more than WCT_PLAN_MEM_CAP = %zu bytes", mem_cap);
     delete P;
-    return rc;
-  }
+    return code;
+  };
+  rc = P->dtype == WCT_F32 ? plan_tables<float>(P, desc) : plan_tables<double>(P, desc);
+  if (rc) return capped(rc);
   DetTables tb;
   std::memset(&tb, 0, sizeof(tb));
   for (int j = 1; j < 256; ++j) tb.inv[j] = 1.0 / (double)j;
@@ -1021,10 +1067,7 @@ int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
   }
   hipError_t e;
   P->d_tables = static_cast<DetTables*>(P->dalloc(sizeof(DetTables), &e));
-  if (e != hipSuccess) {
-    delete P;
-    return fail(WCT_E_NOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
-  }
+  if (e != hipSuccess) return capped(fail(WCT_E_NOMEM, "hipMalloc failed: %s", hipGetErrorString(e)));
   e = hipMemcpy(P->d_tables, &tb, sizeof(tb), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     delete P;
@@ -1033,10 +1076,8 @@ int wct_plan_create(const wct_plan_desc* desc, wct_plan** out) {
   P->d_lfact = static_cast<double*>(P->dalloc(sizeof(double) * kLfactTable, &e));
   if (e == hipSuccess) e = launch_lfact_table(P->d_lfact, kLfactTable, P->d_tables, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e != hipSuccess) {
-    delete P;
-    return hip_fail(e, "log-factorial table");
-  }
+  if (e != hipSuccess) return capped(hip_fail(e, "log-factorial table"));
+  P->mem_cap = 0;  // the cap is plan creation's: later set-up calls allocate freely
   *out = P;
   return WCT_OK;
 }

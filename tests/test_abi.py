@@ -67,6 +67,25 @@ def test_null_and_invalid_arguments(wct):
     assert "max_events" in wct.last_error()
 
 
+def test_plan_limits_answer_before_any_device_call(wct, monkeypatch):
+    """Buffers of max_events events past 2^60 bytes, and a WCT_PLAN_MEM_CAP that is not a
+    byte count, are refused from the description alone (no GPU needed)."""
+    import numpy as np
+    from ctypes import byref, c_void_p
+    resp = np.zeros((21, 10, 200), np.float32)
+    planes = (wct.wct_plane_desc * 1)()
+    planes[0] = wct.wct_plane_desc(2400, 9600, 10, 10, 200, resp.ctypes.data_as(c_void_p))
+    h = c_void_p()
+    desc = wct.wct_plan_desc(wct.WCT_F32, 1, planes, 2 ** 31 - 1, 0)
+    assert wct.wct_plan_create(byref(desc), byref(h)) == wct.WCT_E_UNSUPPORTED and not h.value
+    assert "2^60" in wct.last_error()
+    desc = wct.wct_plan_desc(wct.WCT_F32, 1, planes, 1, 0)
+    for bad in ("12kB", "-5", ""):
+        monkeypatch.setenv("WCT_PLAN_MEM_CAP", bad)
+        assert wct.wct_plan_create(byref(desc), byref(h)) == wct.WCT_E_INVALID and not h.value
+        assert "WCT_PLAN_MEM_CAP" in wct.last_error()
+
+
 def test_binding_fails_loudly_without_the_library(tmp_path):
     """The product path has no fallback: importing the binding without libwct.so raises."""
     pkg = tmp_path / "paper_2104_08265_amd"
