@@ -28,7 +28,8 @@ COMMON = [
     "-munsafe-fp-atomics",
 ]
 # Sources and per-file extra flags.  The raster carries the deterministic fluctuation
-# chain, which must not contract a*b+c into fused multiply-adds.
+# chain, the drift its FP64 arithmetic in the order written and the ADC one rounding per
+# operation: none of them may contract a*b+c into fused multiply-adds.
 SOURCES = {
     "api.cpp": ["-x", "hip"],
     "raster.hip": ["-ffp-contract=off"],
@@ -38,7 +39,7 @@ SOURCES = {
     "plan.hip": [],
     "grad.hip": [],
     "probe.cpp": ["-x", "hip"],
-    "adc.hip": [],
+    "adc.hip": ["-ffp-contract=off"],
     "drift.hip": ["-ffp-contract=off"],
 }
 

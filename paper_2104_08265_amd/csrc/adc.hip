@@ -1,7 +1,8 @@
 // ADC digitisation of the waveform (Eq. 1: M is a measurement such as an ADC value,
 // Sec. 2): per plane, code = min(max(floor(M g + b + 1/2), 0), c_max), a non-number
-// giving 0, computed in the plan's type with one rounding per operation (the products
-// and sums below are the round-to-nearest intrinsics, which the compiler may not fuse).
+// giving 0, computed in the plan's type with one rounding per operation: the product and
+// the two sums are rounded one by one (this file is compiled with contraction off; the
+// round-to-nearest intrinsics alone are plain operations that may be fused).
 //
 // HBM-bound: each sample is read once (4 or 8 bytes) and its code written once (2
 // bytes).  A thread handles 4 consecutive samples per step (one 16- or 32-byte load, one

@@ -100,4 +100,5 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
 def test_build_flags_keep_packed_fp32_out_and_contraction_off_for_fluctuation():
     from paper_2104_08265_amd import build as B
     assert "-packed-fp32-ops" in B.COMMON
-    assert "-ffp-contract=off" in B.SOURCES["raster.hip"]
+    for src in ("raster.hip", "drift.hip", "adc.hip"):
+        assert "-ffp-contract=off" in B.SOURCES[src], src

@@ -248,14 +248,18 @@ def test_zero_rows(wct):
     wl = synth.config2(n_depos=10, n_ticks=1024, wires=(240, 240, 346))  # L_t = 1250: compiled tick plans exist
     plan = make_plan(wct, wl)
     assert len(plan.fft_candidates(0, 0)) > 1
-    gen = torch.Generator(device="cuda:0")
-    gen.manual_seed(17)
-    g = torch.rand(plan.grid_elems, device="cuda:0", generator=gen, dtype=plan.torch_dtype)
-    R = [r.astype(np.float64) for r in synth.round_responses(wl)]
-    for k, v in enumerate(plan.grid_view(g)):
+    # a seeded grid written on the host, then uploaded
+    host = np.random.default_rng(17).random(plan.grid_elems).astype(np.float32)
+    views = []
+    for info in plan.info:
+        v = host[info["grid_off"]: info["grid_off"] + info["n_wires"] * info["n_impacts"] * info["n_ticks"]]
+        v = v.reshape(info["n_wires"] * info["n_impacts"], info["n_ticks"])
         v[::2] = 0  # every other impact row empty
         v[7:40] = 0
-    ref = [OC.convolve_fft(to_np(v), R[k], wl.planes[k].n_impacts) for k, v in enumerate(plan.grid_view(g))]
+        views.append(v)
+    g = torch.as_tensor(host).to("cuda:0")
+    R = [r.astype(np.float64) for r in synth.round_responses(wl)]
+    ref = [OC.convolve_fft(v.astype(np.float64), R[k], wl.planes[k].n_impacts) for k, v in enumerate(views)]
     for choice in plan.fft_candidates(0, 0):
         for p in range(plan.n_planes):
             plan.set_fft(p, 0, choice)

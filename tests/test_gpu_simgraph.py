@@ -9,6 +9,7 @@
   graphs, and the next call captures with the new settings.
 * The first graph's waveform equals the oracle's fluctuated raster, FFT convolution and
   noise (FP32, relative L2 1e-5 per plane).
+* No depositions: the noise alone, equal to the eager call.
 * Refused while kernel timing is on.
 """
 import numpy as np
@@ -160,4 +161,20 @@ def test_refused_while_timing(wct):
     w = plan.simulate_graph(dd, wct.opts(3.0, True, 1, 1))
     torch.cuda.synchronize()
     assert torch.equal(w, eager(plan, dd, wct.opts(3.0, True, 1, 1)))
+    plan.close()
+
+
+def test_empty_depositions(wct):
+    """No depositions: the graph holds the transform passes alone (the waveform is the
+    noise), equal to the eager call."""
+    wl, d = five_events()
+    plan = make_plan(wct, wl, max_events=2)
+    noise_on(plan)
+    dd = device_depos(wct, wl, d).slice(0, 0)
+    o = wct.opts(3.0, True, 3, 5, noise=True)
+    ref = eager(plan, dd, o)
+    say("simulate_graph: no depositions, 3 events")
+    w = plan.simulate_graph(dd, o)
+    torch.cuda.synchronize()
+    assert torch.equal(w, ref) and bool(torch.any(ref != 0))
     plan.close()

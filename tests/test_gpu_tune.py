@@ -24,10 +24,10 @@ def test_variants_agree_with_runtime_plan(wct, name):
     import torch
     wl = synth.config2(n_depos=10) if name == "config2" else synth.config3(n_depos=10)
     plan = make_plan(wct, wl)
-    gen = torch.Generator(device="cuda:0")
-    gen.manual_seed(3)
-    g = torch.rand(plan.grid_elems, device="cuda:0", generator=gen, dtype=plan.torch_dtype)
-    g[torch.rand(plan.grid_elems, device="cuda:0", generator=gen) < 0.9] = 0
+    rng = np.random.default_rng(3)  # a seeded sparse grid written on the host
+    host = rng.random(plan.grid_elems)
+    host[rng.random(plan.grid_elems) < 0.9] = 0
+    g = torch.as_tensor(host).to("cuda:0", plan.torch_dtype)
     for p in range(plan.n_planes):
         for k in (0, 1):
             plan.set_fft(p, k, -1)
@@ -59,9 +59,7 @@ def test_tune_and_cache(wct, tmp_path):
     plan2 = make_plan(wct, wl)
     assert plan2.tune(1, cache) == choice
     assert cache.read_text().strip().splitlines() == lines  # nothing appended
-    gen = torch.Generator(device="cuda:0")
-    gen.manual_seed(5)
-    g = torch.rand(plan.grid_elems, device="cuda:0", generator=gen, dtype=plan.torch_dtype)
+    g = torch.as_tensor(np.random.default_rng(5).random(plan.grid_elems)).to("cuda:0", plan.torch_dtype)
     assert rel(plan.convolve(g, 1), plan2.convolve(g, 1)) == 0.0
     plan.close()
     plan2.close()

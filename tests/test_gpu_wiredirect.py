@@ -24,12 +24,12 @@ TOL32 = 1e-5
 
 
 def sparse_grid(plan, seed, density=0.05):
+    """A seeded sparse grid written on the host, then uploaded."""
     import torch
-    gen = torch.Generator(device="cuda:0")
-    gen.manual_seed(seed)
-    g = torch.rand(plan.grid_elems, device="cuda:0", generator=gen, dtype=plan.torch_dtype)
-    g[torch.rand(plan.grid_elems, device="cuda:0", generator=gen) > density] = 0
-    return g
+    rng = np.random.default_rng(seed)
+    g = rng.random(plan.grid_elems)
+    g[rng.random(plan.grid_elems) > density] = 0
+    return torch.as_tensor(g).to("cuda:0", plan.torch_dtype)
 
 
 def test_direct_matches_oracle_fp32(wct):
