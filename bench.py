@@ -608,6 +608,18 @@ def shower_bench(wct, synth, tune_cache=None, steps=3):
             "tile_raster_alu_frac": ops / (t_tile * 1e-3) / 1e12 / ALU_PEAK_TOPS if t_tile > 0 else None}
 
 
+def issue_rates(wct):
+    """The chip's sustained rates for the instruction kinds the kernels issue (the probe):
+    lane operations per second and wave64 instructions per CU per 2.4 GHz cycle."""
+    out = {}
+    for kind in wct.ISSUE_KINDS:
+        r = wct.probe_issue_rate(kind)
+        out[kind] = {"lane_ops_per_s": r, "wave_instr_per_cu_cycle": r / (64 * 256 * 2.4e9)}
+    out["probe"] = ("wct_probe_issue_rate: 16 independent chains per thread, 16 blocks of 256 threads per CU; "
+                    "fma_f32_sgpr takes its multiplier from a scalar register, as the direct wire pass does")
+    return out
+
+
 def raster_atomics(wct, wl, t_mean_ms, t_fluct_ms):
     """The raster's atomic adds against the chip's peaks (the probes): the mean raster makes
     one LDS add per window cell (counted on the host); the fluctuated raster's LDS and
@@ -878,6 +890,7 @@ def main():
         "raster_atomics": raster_atomics(wct, wl, t_mean, kernels.get("raster_tile_fluct", {}).get("ms_per_step")),
         "raster_issue": raster_issue(kernels.get("raster_tile_fluct", {}).get("ms_per_step"),
                                      roofline.get("alg_ops_per_launch")),
+        "issue_rates": issue_rates(wct),
         "noise": noise,
         "adc": adc,
         "drift": drift,

@@ -94,6 +94,8 @@ wct_raster_noalloc = _sig("wct_raster_noalloc", c_int32, [PlanP, POINTER(wct_dep
 NOALLOC_SCRATCH_BYTES = 128 << 20  # WCT_NOALLOC_SCRATCH_BYTES
 wct_probe_atomic_add = _sig("wct_probe_atomic_add", c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int64,
                                                               POINTER(c_double), c_void_p])
+wct_probe_issue_rate = _sig("wct_probe_issue_rate", c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int64,
+                                                              POINTER(c_double), c_void_p])
 wct_probe_last_error = _sig("wct_probe_last_error", c_char_p, [])
 wct_convolve = _sig("wct_convolve", c_int32, [PlanP, c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p])
 wct_simulate = _sig("wct_simulate", c_int32, [PlanP, POINTER(wct_depos), POINTER(wct_opts), c_void_p, c_void_p,
@@ -143,6 +145,26 @@ def probe_atomic_add(where, blocks=2048, iters=256, buf_elems=None, device=0):
     if code != 0:
         raise WctError(code, f"wct_probe_atomic_add: {wct_probe_last_error().decode()}")
     return rate.value, buf
+
+
+ISSUE_KINDS = ("fma_f32_vgpr", "fma_f32_sgpr", "fma_f64", "mad_u64_u32")
+
+
+def probe_issue_rate(kind, blocks=None, iters=2048, device=0):
+    """Lane operations per second of one instruction kind (ISSUE_KINDS, or its index): 16
+    independent chains per thread over 16 blocks of 256 threads per CU.  A measurement
+    call: allocates a buffer and synchronises."""
+    torch = _torch()
+    k = ISSUE_KINDS.index(kind) if isinstance(kind, str) else int(kind)
+    if blocks is None:
+        blocks = 16 * torch.cuda.get_device_properties(device).multi_processor_count
+    buf = torch.empty(blocks * 256, dtype=torch.int64, device=f"cuda:{device}")
+    rate = c_double()
+    code = wct_probe_issue_rate(k, blocks, iters, _ptr(buf), buf.numel() * 8, ctypes.byref(rate),
+                                c_void_p(torch.cuda.current_stream(device).cuda_stream))
+    if code != 0:
+        raise WctError(code, f"wct_probe_issue_rate: {wct_probe_last_error().decode()}")
+    return rate.value
 
 
 def tile_variants():
