@@ -315,13 +315,15 @@ def algorithmic_bytes(plan, esize=4):
     return out
 
 
-def cpu_baseline(wl, n_sample_depos=200):
-    """The FP64 oracle on a bounded sample, scaled to the whole event (depos/s)."""
+def cpu_baseline(wl, n_sample_depos=3000):
+    """The FP64 oracle on a bounded sample (about 10 s of work on one core), scaled to the
+    whole event (depos/s)."""
     import numpy as np
     from oracle import convolve as OC
     from oracle import fluct as OF
     d = wl.depos
-    ids = np.unique(d.depo_id)[:n_sample_depos]
+    # a seeded random sample of the depositions (all their depo-plane rows)
+    ids = np.sort(np.random.default_rng(1).choice(np.unique(d.depo_id), n_sample_depos, replace=False))
     sub = d.select(np.isin(d.depo_id, ids))
     t0 = time.perf_counter()
     OF.raster_fluct(sub, wl.planes, seed=wl.seed)
