@@ -317,11 +317,15 @@ WireTileGeom wire_tile_geom(const wct_plan* P) {
     const PlaneGeom& G = P->geom[p];
     g.nw[p] = G.nw;
     g.I[p] = G.I;
+    g.K[p] = G.K;
     g.row_off[p] = G.row_off;
     g.tile_off[p] = g.tiles_ev;
     g.tiles_ev += (G.nw + kDirectTileWires - 1) / kDirectTileWires;
+    g.wire_off[p] = g.wires_ev;
+    g.wires_ev += G.nw;
   }
   g.tile_off[P->n_planes] = g.tiles_ev;
+  g.wire_off[P->n_planes] = g.wires_ev;
   return g;
 }
 
@@ -343,11 +347,12 @@ size_t ws_bytes(const wct_plan* P, int op, int n_events, int64_t n_rows) {
     Carver r(nullptr), c(nullptr);
     carve_raster(P, r, n_events, n_rows);
     carve_conv(P, c, n_events);
-    // the row spans and the tile flags go last, so the grid and the transform buffers keep
-    // their places
+    // the row spans, band hulls, tile flags and wire flags go last, so the grid and the
+    // transform buffers keep their places
+    const WireTileGeom tg = wire_tile_geom(P);
     return head + align_up(r.off > c.off ? r.off : c.off, 256) + align_up(sizeof(int2) * n_events * P->rows_ev, 256) +
-           align_up(sizeof(int2) * n_events * bands_ev(P), 256) +
-           align_up((size_t)n_events * wire_tile_geom(P).tiles_ev, 256);
+           align_up(sizeof(int2) * n_events * bands_ev(P), 256) + align_up((size_t)n_events * tg.tiles_ev, 256) +
+           align_up((size_t)n_events * tg.wires_ev, 256);
   }
   if (op == WCT_OP_BACKWARD) {
     Carver a(nullptr);
@@ -419,16 +424,21 @@ int run_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, T* grid, Carv
 // reads the others only inside their spans.  tiles (optional, with span): room for the
 // direct column pass's tile flags of these events; a plane on the direct pass then skips
 // the tiles no row reaches (zero M^ without reading S^), and its row transform does not
-// write the zero spectra that only such tiles would read.
+// write the zero spectra that only such tiles would read.  wires (optional, with tiles):
+// room for the per-wire flags; on a plane of the direct column pass without noise, the
+// inverse row transform writes the zero waveform of a wire no window reaches within the
+// response's reach (its M^ is exactly zero there) without transforming it.
 template <typename T>
 int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, hipStream_t st,
-                 const int2* span = nullptr, const wct_opts* noise = nullptr, uint8_t* tiles = nullptr) {
+                 const int2* span = nullptr, const wct_opts* noise = nullptr, uint8_t* tiles = nullptr,
+                 uint8_t* wires = nullptr) {
   const ConvWs c = carve_conv(P, cv, n_events);
   cx<T>* shat = static_cast<cx<T>*>(c.shat);
   cx<T>* mhat = static_cast<cx<T>*>(c.mhat);
   const WireTileGeom tg = wire_tile_geom(P);
   const bool flags = span && tiles;
   if (flags) HIP_TRY(launch_wire_tiles(tg, n_events, span, tiles, st), "tile flag launch");
+  if (flags && wires) HIP_TRY(launch_wire_live(tg, n_events, span, wires, st), "wire flag launch");
   for (int p = 0; p < P->n_planes; ++p) {
     const PlaneGeom& G = P->geom[p];
     const cx<T>* tw_t = static_cast<const cx<T>*>(P->tw_t[p]);
@@ -465,9 +475,14 @@ int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, 
       nz.plane = (uint32_t)p;
       nz.event_base = noise->event_base;
     }
+    WireLive wl;
+    if (flags && wires && P->wire_direct[p] && !nz.amp) {
+      wl.live = wires + tg.wire_off[p];
+      wl.ev_stride = tg.wires_ev;
+    }
     PROF_LAUNCH(P, "rows_c2r", st,
                 launch_rows_c2r<T>(mhat + G.mhat_off, P->mhat_elems, wave + G.wave_off, P->wave_elems, G.nt, false,
-                                   1, G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, st, nz),
+                                   1, G.nw, G.nchunk, n_events, P->fp_t[p], tw_t, post, st, nz, wl),
                 "inverse row transform launch");
   }
   return WCT_OK;
@@ -1319,12 +1334,16 @@ static int simulate_enqueue(wct_plan* plan, const wct_depos* depos, const wct_op
   Carver head(ws);
   void* grid = head.take(plan->esize * (size_t)batch * plan->grid_elems);
   const size_t rest = align_up(head.off, 256);
-  // the tail of the workspace: row spans, band hulls, tile flags
-  const size_t tile_bytes = align_up((size_t)batch * wire_tile_geom(plan).tiles_ev, 256);
+  // the tail of the workspace: row spans, band hulls, tile flags, wire flags
+  const WireTileGeom tg = wire_tile_geom(plan);
+  const size_t wire_bytes = align_up((size_t)batch * tg.wires_ev, 256);
+  const size_t tile_bytes = align_up((size_t)batch * tg.tiles_ev, 256);
   const size_t hull_bytes = align_up(sizeof(int2) * (size_t)batch * bands_ev(plan), 256);
-  uint8_t* tiles = static_cast<uint8_t*>(ws) + need - tile_bytes;
-  int2* hull = reinterpret_cast<int2*>(static_cast<char*>(ws) + need - tile_bytes - hull_bytes);
-  int2* span = reinterpret_cast<int2*>(static_cast<char*>(ws) + need - tile_bytes - hull_bytes -
+  char* tail = static_cast<char*>(ws) + need;
+  uint8_t* wires = reinterpret_cast<uint8_t*>(tail - wire_bytes);
+  uint8_t* tiles = reinterpret_cast<uint8_t*>(tail - wire_bytes - tile_bytes);
+  int2* hull = reinterpret_cast<int2*>(tail - wire_bytes - tile_bytes - hull_bytes);
+  int2* span = reinterpret_cast<int2*>(tail - wire_bytes - tile_bytes - hull_bytes -
                                        align_up(sizeof(int2) * (size_t)batch * plan->rows_ev, 256));
   // sub-batches of up to max_events events: raster into the workspace grid, then the
   // transform passes write the sub-batch's slots of `wave`
@@ -1337,11 +1356,11 @@ static int simulate_enqueue(wct_plan* plan, const wct_depos* depos, const wct_op
     if (plan->dtype == WCT_F32) {
       if ((rc = run_raster<float>(plan, depos, &sub, static_cast<float*>(grid), cr, st, span, hull))) return rc;
       rc = run_convolve<float>(plan, static_cast<const float*>(grid), sub.n_events, reinterpret_cast<float*>(w), cc,
-                               st, span, &sub, tiles);
+                               st, span, &sub, tiles, wires);
     } else {
       if ((rc = run_raster<double>(plan, depos, &sub, static_cast<double*>(grid), cr, st, span, hull))) return rc;
       rc = run_convolve<double>(plan, static_cast<const double*>(grid), sub.n_events, reinterpret_cast<double*>(w),
-                                cc, st, span, &sub, tiles);
+                                cc, st, span, &sub, tiles, wires);
     }
     if (rc) return rc;
   }

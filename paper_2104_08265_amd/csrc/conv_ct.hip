@@ -428,11 +428,18 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_c2r_ct(const
                                                              T* __restrict__ dst, int64_t dst_ev_stride, int nt,
                                                              int nphase, int nper, int nchunk,
                                                              const cx<T>* __restrict__ tw,
-                                                             const cx<T>* __restrict__ post, NoiseArgs<T> nz) {
+                                                             const cx<T>* __restrict__ post, NoiseArgs<T> nz,
+                                                             WireLive wl) {
   constexpr int M = F::N, R0 = F::R0, RL = F::RL;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* z = reinterpret_cast<cx<T>*>(smem_raw);
   const int L = TILED ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  if (!TILED && !NOISE && wl.live && !wl.live[(int64_t)blockIdx.y * wl.ev_stride + L]) {
+    // no window reaches this wire within the response's reach: its waveform is zero
+    T* o = dst + blockIdx.y * dst_ev_stride + (int64_t)L * nt;
+    for (int x = threadIdx.x; x < nt; x += blockDim.x) o[x] = T(0);
+    return;
+  }
   const int i = L / nper, c = L - (L / nper) * nper;
   const int64_t row = TILED ? (int64_t)c * nphase + i : (int64_t)L;
   const cx<T>* inp = src + blockIdx.y * src_ev_stride;
@@ -580,20 +587,21 @@ hipError_t launch_colpass_adj_ct(const cx<T>* ghat, int64_t ghat_ev_stride, cons
 template <typename T>
 hipError_t launch_rows_c2r_ct(const cx<T>* src, int64_t src_ev_stride, T* dst, int64_t dst_ev_stride, int nt,
                               bool tiled, int nphase, int nper, int nchunk, int n_events, const FftPlan& plan,
-                              const cx<T>* tw, const cx<T>* post, hipStream_t st, const NoiseArgs<T>& nz) {
+                              const cx<T>* tw, const cx<T>* post, hipStream_t st, const NoiseArgs<T>& nz,
+                              const WireLive& wl) {
   const size_t lds = sizeof(cx<T>) * plan.n;
   const dim3 grid(nphase * nper, n_events);
   const hipError_t e = with_variant<T, 0>(plan.variant, [&](auto f) {
     using F = decltype(f);
     if (tiled)
       hipLaunchKernelGGL((k_rows_c2r_ct<T, kChunk, true, F, false>), grid, dim3(F::kThreads), lds, st, src,
-                         src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, tw, post, nz);
+                         src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, tw, post, nz, wl);
     else if (nz.amp)
       hipLaunchKernelGGL((k_rows_c2r_ct<T, kChunk, false, F, true>), grid, dim3(F::kThreads), lds, st, src,
-                         src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, tw, post, nz);
+                         src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, tw, post, nz, wl);
     else
       hipLaunchKernelGGL((k_rows_c2r_ct<T, kChunk, false, F, false>), grid, dim3(F::kThreads), lds, st, src,
-                         src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, tw, post, nz);
+                         src_ev_stride, dst, dst_ev_stride, nt, nphase, nper, nchunk, tw, post, nz, wl);
   });
   return e != hipSuccess ? e : hipGetLastError();
 }
@@ -641,7 +649,7 @@ void conv_ct_init_kernels() {
                                                hipStream_t);                                                     \
   template hipError_t launch_rows_c2r_ct<T>(const cx<T>*, int64_t, T*, int64_t, int, bool, int, int, int, int,   \
                                             const FftPlan&, const cx<T>*, const cx<T>*, hipStream_t,            \
-                                            const NoiseArgs<T>&);
+                                            const NoiseArgs<T>&, const WireLive&);
 WCT_INST(float)
 WCT_INST(double)
 #undef WCT_INST

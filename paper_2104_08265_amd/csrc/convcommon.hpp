@@ -115,7 +115,8 @@ hipError_t launch_colpass_adj_ct(const cx<T>* ghat, int64_t ghat_ev_stride, cons
 template <typename T>
 hipError_t launch_rows_c2r_ct(const cx<T>* src, int64_t src_ev_stride, T* dst, int64_t dst_ev_stride, int nt,
                               bool tiled, int nphase, int nper, int nchunk, int n_events, const FftPlan& plan,
-                              const cx<T>* tw, const cx<T>* post, hipStream_t st, const NoiseArgs<T>& nz);
+                              const cx<T>* tw, const cx<T>* post, hipStream_t st, const NoiseArgs<T>& nz,
+                              const WireLive& wl);
 void conv_ct_init_kernels();
 
 }  // namespace wct

@@ -172,6 +172,13 @@ struct WireTiles {
   int64_t ev_stride = 0;
   int ntile = 0;
 };
+// Wires whose output some window reaches (a row of wires w - K .. w + K holds one), as
+// wct_simulate records them: the inverse row transform writes the zero waveform of any
+// other wire without reading or transforming its spectrum (which is exactly zero there).
+struct WireLive {
+  const uint8_t* live = nullptr;  // [event][wire] of this plane (ev_stride apart); nullptr: all
+  int64_t ev_stride = 0;
+};
 
 // span (optional, [event][span_ev] row tick spans of this plane): the runtime kernel
 // and the wire-pair kernel neither load nor transform a row (pair) no window reached and
@@ -197,12 +204,15 @@ hipError_t launch_colpass_direct(const cx<T>* shat, int64_t shat_ev_stride, cons
 // The direct pass's tile flags of every plane and event from the row spans: plane p's
 // tiles start at tile_off[p] of an event's tiles_ev.
 struct WireTileGeom {
-  int n_planes, tiles_ev;
+  int n_planes, tiles_ev, wires_ev;
   int64_t rows_ev;
-  int nw[kMaxPlanes], I[kMaxPlanes], tile_off[kMaxPlanes + 1];
+  int nw[kMaxPlanes], I[kMaxPlanes], K[kMaxPlanes], tile_off[kMaxPlanes + 1], wire_off[kMaxPlanes + 1];
   int64_t row_off[kMaxPlanes];
 };
 hipError_t launch_wire_tiles(const WireTileGeom& g, int n_events, const int2* span, uint8_t* live, hipStream_t st);
+// The per-wire flags of WireLive for every plane and event ([event][wires_ev], plane p's
+// wires from wire_off[p]).
+hipError_t launch_wire_live(const WireTileGeom& g, int n_events, const int2* span, uint8_t* live, hipStream_t st);
 template <typename T>
 hipError_t launch_colpass_adj_direct(const cx<T>* ghat, int64_t ghat_ev_stride, const cx<T>* rtick, cx<T>* hhat,
                                      int64_t hhat_ev_stride, int nw, int nphase, int nchunk, int n_events,
@@ -215,7 +225,7 @@ template <typename T>
 hipError_t launch_rows_c2r(const cx<T>* src, int64_t src_ev_stride, T* dst, int64_t dst_ev_stride, int nt,
                            bool tiled, int nphase, int nper, int nchunk, int n_events, const FftPlan& plan,
                            const cx<T>* tw, const cx<T>* post, hipStream_t st,
-                           const NoiseArgs<T>& noise = NoiseArgs<T>());
+                           const NoiseArgs<T>& noise = NoiseArgs<T>(), const WireLive& wl = WireLive());
 template <typename T>
 bool conv_fits(int elems);  // a transform of `elems` complex values fits one block
 void conv_init_kernels();

@@ -242,6 +242,32 @@ __global__ void __launch_bounds__(256) k_wire_tiles(WireTileGeom g, const int2* 
   if (threadIdx.x == 0) live[blockIdx.x] = (uint8_t)(any != 0);
 }
 
+// One thread per (event, wire): whether any impact row of wires w - K .. w + K (inside
+// the plane) holds a window (span hi != 0).
+__global__ void __launch_bounds__(256) k_wire_live(WireTileGeom g, int64_t n, const int2* __restrict__ span,
+                                                    uint8_t* __restrict__ live) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const int ev = (int)(x / g.wires_ev);
+    int w = (int)(x - (int64_t)ev * g.wires_ev);
+    int p = 0;
+    while (p + 1 < g.n_planes && w >= g.wire_off[p + 1]) ++p;
+    w -= g.wire_off[p];
+    const int wlo = max(0, w - g.K[p]), whi = min(g.nw[p], w + g.K[p] + 1);
+    const int2* f = span + (int64_t)ev * g.rows_ev + g.row_off[p];
+    int any = 0;
+    for (int r = wlo * g.I[p]; r < whi * g.I[p] && !any; ++r) any = f[r].y != 0;
+    live[x] = (uint8_t)any;
+  }
+}
+
+hipError_t launch_wire_live(const WireTileGeom& g, int n_events, const int2* span, uint8_t* live, hipStream_t st) {
+  const int64_t n = (int64_t)n_events * g.wires_ev;
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+  hipLaunchKernelGGL(k_wire_live, dim3((unsigned)blocks), dim3(256), 0, st, g, n, span, live);
+  return hipGetLastError();
+}
+
 hipError_t launch_wire_tiles(const WireTileGeom& g, int n_events, const int2* span, uint8_t* live, hipStream_t st) {
   if (n_events <= 0 || g.tiles_ev <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_wire_tiles, dim3((unsigned)(n_events * g.tiles_ev)), dim3(256), 0, st, g, span, live);

@@ -120,10 +120,12 @@ def test_direct_needs_21_wire_response(wct):
 
 def test_simulate_skips_empty_rows_exactly(wct):
     """wct_simulate passes the raster's row flags to the row transform, which then writes
-    the zero spectrum of a pair of empty rows without loading or transforming it: a sparse
-    event (most impact rows empty) gives the same waveforms, bit for bit, as wct_raster
-    followed by wct_convolve (every row transformed), for every compiled tick transform
-    (block sizes with and without a partial last wave), and the flags of an earlier, denser
+    the zero spectrum of a pair of empty rows without loading or transforming it, and its
+    wire flags to the inverse row transform, which writes the zero waveform of a wire no
+    window reaches within the response's 21 wires: a sparse event (most impact rows and
+    many wires empty) gives the same waveforms as wct_raster followed by wct_convolve
+    (every row and wire transformed), for every tick transform (compiled plans with and
+    without a partial last wave, the runtime plan), and the flags of an earlier, denser
     call leave nothing behind."""
     import torch
     for n_ticks in (1024, 9600):
@@ -144,6 +146,8 @@ def test_simulate_skips_empty_rows_exactly(wct):
             torch.cuda.synchronize()
             assert torch.equal(w1, w2), (n_ticks, v)
             assert not torch.equal(w1, dense)
+            quiet = [int((wv.abs().amax(dim=1) == 0).sum()) for wv in plan.wave_view(w1)]
+            assert all(0 < q < info["n_wires"] for q, info in zip(quiet, plan.info)), quiet
         if n_ticks == 1024:
             ref = OF.raster_fluct(wl.depos, wl.planes, seed=wl.seed)[0]
             R = [r.astype(np.float64) for r in synth.round_responses(wl)]
