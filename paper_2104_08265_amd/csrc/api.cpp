@@ -326,6 +326,11 @@ WireTileGeom wire_tile_geom(const wct_plan* P) {
   }
   g.tile_off[P->n_planes] = g.tiles_ev;
   g.wire_off[P->n_planes] = g.wires_ev;
+  for (int p = 0; p < P->n_planes; ++p) {
+    g.bit_off[p] = g.bits_ev;
+    g.bits_ev += (P->geom[p].nw * P->geom[p].I + 31) / 32;
+  }
+  g.bit_off[P->n_planes] = g.bits_ev;
   return g;
 }
 
@@ -352,7 +357,7 @@ size_t ws_bytes(const wct_plan* P, int op, int n_events, int64_t n_rows) {
     const WireTileGeom tg = wire_tile_geom(P);
     return head + align_up(r.off > c.off ? r.off : c.off, 256) + align_up(sizeof(int2) * n_events * P->rows_ev, 256) +
            align_up(sizeof(int2) * n_events * bands_ev(P), 256) + align_up((size_t)n_events * tg.tiles_ev, 256) +
-           align_up((size_t)n_events * tg.wires_ev, 256);
+           align_up((size_t)n_events * tg.wires_ev, 256) + align_up(sizeof(uint32_t) * n_events * tg.bits_ev, 256);
   }
   if (op == WCT_OP_BACKWARD) {
     Carver a(nullptr);
@@ -431,7 +436,7 @@ int run_raster(wct_plan* P, const wct_depos* d, const wct_opts* o, T* grid, Carv
 template <typename T>
 int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, hipStream_t st,
                  const int2* span = nullptr, const wct_opts* noise = nullptr, uint8_t* tiles = nullptr,
-                 uint8_t* wires = nullptr) {
+                 uint8_t* wires = nullptr, uint32_t* rbits = nullptr) {
   const ConvWs c = carve_conv(P, cv, n_events);
   cx<T>* shat = static_cast<cx<T>*>(c.shat);
   cx<T>* mhat = static_cast<cx<T>*>(c.mhat);
@@ -439,6 +444,7 @@ int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, 
   const bool flags = span && tiles;
   if (flags) HIP_TRY(launch_wire_tiles(tg, n_events, span, tiles, st), "tile flag launch");
   if (flags && wires) HIP_TRY(launch_wire_live(tg, n_events, span, wires, st), "wire flag launch");
+  if (flags && rbits) HIP_TRY(launch_row_bits(tg, n_events, span, rbits, st), "row flag launch");
   for (int p = 0; p < P->n_planes; ++p) {
     const PlaneGeom& G = P->geom[p];
     const cx<T>* tw_t = static_cast<const cx<T>*>(P->tw_t[p]);
@@ -451,6 +457,10 @@ int run_convolve(wct_plan* P, const T* grid, int n_events, T* wave, Carver& cv, 
       wt.live = tiles + tg.tile_off[p];
       wt.ev_stride = tg.tiles_ev;
       wt.ntile = tg.tile_off[p + 1] - tg.tile_off[p];
+      if (rbits && G.I <= 10) {
+        wt.rowbits = rbits + tg.bit_off[p];
+        wt.bits_ev = tg.bits_ev;
+      }
     }
     PROF_LAUNCH(P, "rows_r2c", st,
                 launch_rows_r2c<T>(grid + G.grid_off, P->grid_elems, shat + G.shat_off, P->shat_elems, G.nt, G.I,
@@ -1336,11 +1346,13 @@ static int simulate_enqueue(wct_plan* plan, const wct_depos* depos, const wct_op
   const size_t rest = align_up(head.off, 256);
   // the tail of the workspace: row spans, band hulls, tile flags, wire flags
   const WireTileGeom tg = wire_tile_geom(plan);
-  const size_t wire_bytes = align_up((size_t)batch * tg.wires_ev, 256);
+  const size_t wire_bytes = align_up((size_t)batch * tg.wires_ev, 256) +
+                            align_up(sizeof(uint32_t) * (size_t)batch * tg.bits_ev, 256);
   const size_t tile_bytes = align_up((size_t)batch * tg.tiles_ev, 256);
   const size_t hull_bytes = align_up(sizeof(int2) * (size_t)batch * bands_ev(plan), 256);
   char* tail = static_cast<char*>(ws) + need;
-  uint8_t* wires = reinterpret_cast<uint8_t*>(tail - wire_bytes);
+  uint8_t* wires = reinterpret_cast<uint8_t*>(tail - wire_bytes);  // then the row words
+  uint32_t* rbits = reinterpret_cast<uint32_t*>(tail - wire_bytes + align_up((size_t)batch * tg.wires_ev, 256));
   uint8_t* tiles = reinterpret_cast<uint8_t*>(tail - wire_bytes - tile_bytes);
   int2* hull = reinterpret_cast<int2*>(tail - wire_bytes - tile_bytes - hull_bytes);
   int2* span = reinterpret_cast<int2*>(tail - wire_bytes - tile_bytes - hull_bytes -
@@ -1356,11 +1368,11 @@ static int simulate_enqueue(wct_plan* plan, const wct_depos* depos, const wct_op
     if (plan->dtype == WCT_F32) {
       if ((rc = run_raster<float>(plan, depos, &sub, static_cast<float*>(grid), cr, st, span, hull))) return rc;
       rc = run_convolve<float>(plan, static_cast<const float*>(grid), sub.n_events, reinterpret_cast<float*>(w), cc,
-                               st, span, &sub, tiles, wires);
+                               st, span, &sub, tiles, wires, rbits);
     } else {
       if ((rc = run_raster<double>(plan, depos, &sub, static_cast<double*>(grid), cr, st, span, hull))) return rc;
       rc = run_convolve<double>(plan, static_cast<const double*>(grid), sub.n_events, reinterpret_cast<double*>(w),
-                                cc, st, span, &sub, tiles, wires);
+                                cc, st, span, &sub, tiles, wires, rbits);
     }
     if (rc) return rc;
   }

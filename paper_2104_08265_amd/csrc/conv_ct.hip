@@ -195,10 +195,12 @@ __global__ void __launch_bounds__(F::kThreads, F::kMinWaves) k_rows_r2c_pair_ct(
     const int2* f = span + ev * span_ev;
     return (f[(int64_t)c * nphase + i].y | f[(int64_t)(c + 1) * nphase + i].y) != 0;
   };
-  // Whether a pair's zero spectrum is read: with tile flags, only a live tile of the direct
-  // column pass reads S^ (wires [t W - K, t W + W + K) of tile t), so a dead pair that no
-  // live tile covers is not written at all.
+  // Whether a dead pair's zero spectrum is read: with row flags the direct column pass
+  // takes such rows as zeros, so it is never written; with tile flags alone only a live
+  // tile reads S^ (wires [t W - K, t W + W + K) of tile t), so a dead pair that no live
+  // tile covers is not written.
   auto pair_read = [&](int Q) -> bool {
+    if (wt.rowbits) return false;  // the direct pass reads the rows no window reached as zeros
     if (!wt.live) return true;
     int ev, i, c;
     row_of(Q, 0, ev, i, c);

@@ -163,14 +163,17 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 // of those take a second twiddle table for the same radices in reverse order (tw_rev).
 // Rows are read with 16-byte loads (and the next row prefetched) when their length and base allow it.
 // Tiles of the direct column pass (kDirectTileWires output wires each, reading the S^ rows
-// of kDirectHalfWires more wires on either side) that some window's rows reach, as
-// wct_simulate records them: a tile no row reaches writes a zero M^ without reading S^,
-// so a dead row pair that no live tile reads needs no zero spectrum from pass A.
+// of kDirectHalfWires more wires on either side) that some window's rows reach, and the
+// rows themselves (one bit each), as wct_simulate records them: a tile no row reaches
+// writes a zero M^ without reading S^, a live tile takes the rows no window reached as
+// zeros without reading them, so pass A writes no spectrum for a row pair no window reached.
 constexpr int kDirectTileWires = 512, kDirectHalfWires = 10;
 struct WireTiles {
   const uint8_t* live = nullptr;  // [event][tile] of this plane (ev_stride apart); nullptr: all
   int64_t ev_stride = 0;
   int ntile = 0;
+  const uint32_t* rowbits = nullptr;  // [event][bits_ev words] from this plane's first word:
+  int64_t bits_ev = 0;                // bit r of the plane set when row r holds a window
 };
 // Wires whose output some window reaches (a row of wires w - K .. w + K holds one), as
 // wct_simulate records them: the inverse row transform writes the zero waveform of any
@@ -208,7 +211,9 @@ struct WireTileGeom {
   int64_t rows_ev;
   int nw[kMaxPlanes], I[kMaxPlanes], K[kMaxPlanes], tile_off[kMaxPlanes + 1], wire_off[kMaxPlanes + 1];
   int64_t row_off[kMaxPlanes];
+  int bits_ev, bit_off[kMaxPlanes + 1];  // 32-row words of the row flags per event, per plane
 };
+hipError_t launch_row_bits(const WireTileGeom& g, int n_events, const int2* span, uint32_t* bits, hipStream_t st);
 hipError_t launch_wire_tiles(const WireTileGeom& g, int n_events, const int2* span, uint8_t* live, hipStream_t st);
 // The per-wire flags of WireLive for every plane and event ([event][wires_ev], plane p's
 // wires from wire_off[p]).

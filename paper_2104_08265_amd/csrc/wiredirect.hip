@@ -61,6 +61,21 @@ __global__ void __launch_bounds__(64 * kChunk) k_colpass_direct(const cx<T>* __r
     return;
   }
   const cx<T>* src = shat + ev * shat_ev_stride + (int64_t)ch * nphase * nw * C;
+  // the row flags of the staged wires (rows of wires w0 - K .. w0 + WT + K), one bit each
+  constexpr int kBitWords = (SPAN * 10 + 31) / 32 + 2;  // up to 10 phases
+  __shared__ uint32_t s_bits[kBitWords];
+  const int r_lo = max(0, w0 - K) * nphase, wd0 = r_lo >> 5;
+  const bool bits = wt.rowbits != nullptr && nphase <= 10;
+  if (bits) {
+    const int r_hi = min(nw, w0 + WT + K) * nphase, wd1 = (r_hi + 31) >> 5;
+    for (int x = tid; x < wd1 - wd0; x += 64 * C) s_bits[x] = wt.rowbits[ev * wt.bits_ev + wd0 + x];
+    __syncthreads();
+  }
+  auto row_live = [&](int w, int i) {
+    if (!bits) return true;
+    const int r = w * nphase + i;
+    return ((s_bits[(r >> 5) - wd0] >> (r & 31)) & 1u) != 0;
+  };
 
   V stage[NPT];
   auto load = [&](int i) {
@@ -70,7 +85,7 @@ __global__ void __launch_bounds__(64 * kChunk) k_colpass_direct(const cx<T>* __r
       const int e = tid + u * 64 * C;
       const int w = w0 - K + e / VPW;
       V v = {};
-      if (e < NE && w >= 0 && w < nw) v = *reinterpret_cast<const V*>(s + (int64_t)w * C + (e % VPW) * CPV);
+      if (e < NE && w >= 0 && w < nw && row_live(w, i)) v = *reinterpret_cast<const V*>(s + (int64_t)w * C + (e % VPW) * CPV);
       stage[u] = v;
     }
   };
@@ -201,7 +216,7 @@ bool colpass_direct_fits(int K) { return K == kDirectK; }
 
 // Dynamic LDS above the default 64 KB for the direct kernels (on the current device).
 void wiredirect_init_kernels() {
-  const int lim = 160 * 1024;
+  const int lim = 160 * 1024 - 1024;
   (void)hipFuncSetAttribute((const void*)k_colpass_direct<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   (void)hipFuncSetAttribute((const void*)k_colpass_direct<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   (void)hipFuncSetAttribute((const void*)k_colpass_adj_direct<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -258,6 +273,35 @@ __global__ void __launch_bounds__(256) k_wire_live(WireTileGeom g, int64_t n, co
     for (int r = wlo * g.I[p]; r < whi * g.I[p] && !any; ++r) any = f[r].y != 0;
     live[x] = (uint8_t)any;
   }
+}
+
+// One thread per (event, 32-row word): bit j set when row 32 word + j of the plane holds a
+// window (span hi != 0).
+__global__ void __launch_bounds__(256) k_row_bits(WireTileGeom g, int64_t n, const int2* __restrict__ span,
+                                                   uint32_t* __restrict__ bits) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const int ev = (int)(x / g.bits_ev);
+    int wd = (int)(x - (int64_t)ev * g.bits_ev);
+    int p = 0;
+    while (p + 1 < g.n_planes && wd >= g.bit_off[p + 1]) ++p;
+    wd -= g.bit_off[p];
+    const int nb = g.nw[p] * g.I[p];
+    const int2* f = span + (int64_t)ev * g.rows_ev + g.row_off[p];
+    uint32_t v = 0;
+    for (int j = 0; j < 32; ++j) {
+      const int r = wd * 32 + j;
+      if (r < nb && f[r].y != 0) v |= 1u << j;
+    }
+    bits[x] = v;
+  }
+}
+
+hipError_t launch_row_bits(const WireTileGeom& g, int n_events, const int2* span, uint32_t* bits, hipStream_t st) {
+  const int64_t n = (int64_t)n_events * g.bits_ev;
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+  hipLaunchKernelGGL(k_row_bits, dim3((unsigned)blocks), dim3(256), 0, st, g, n, span, bits);
+  return hipGetLastError();
 }
 
 hipError_t launch_wire_live(const WireTileGeom& g, int n_events, const int2* span, uint8_t* live, hipStream_t st) {

@@ -66,9 +66,11 @@ def test_spans_read_only_what_is_there(wct, n_ticks, dtype):
 def test_direct_pass_tiles_no_row_reaches(wct, dtype):
     """A sparse plane of three 512-wire tiles of the direct column pass: charge only near
     the first tile boundary (wires 500-525, whose rows the neighbouring tile reads through
-    its 10-wire halo) and near the last wire.  Tiles no row reaches write zeros without
-    reading S^, and pass A leaves out the zero spectra only such tiles would read; the
-    waveform must still equal wct_raster + wct_convolve bit for bit and the oracle."""
+    its 10-wire halo) and near the last wire, after a dense call that leaves its spectra
+    behind.  Tiles no row reaches write zeros without reading S^, live tiles take the rows
+    no window reached as zeros without reading them (row flags), and pass A writes no
+    spectrum for a pair no window reached; the waveform must still equal wct_raster +
+    wct_convolve bit for bit and the oracle."""
     pl = synth.Plane(1100, 1024, 10, 10, 200)
     rows = [(5000.0, 300.0, 500.5, 1.0, 0.3), (4000.0, 400.0, 511.7, 1.5, 0.4), (3000.0, 350.0, 523.9, 1.0, 0.2),
             (6000.0, 700.0, 1098.2, 2.0, 0.5)]
