@@ -268,7 +268,12 @@ int wct_convolve(wct_plan* plan, const void* grid, int32_t n_events, void* wave,
  * exceed the plan's max_events: the events are then processed in consecutive
  * sub-batches of max_events (one persistent raster launch and one set of batched
  * transform passes per sub-batch), with the workspace of max_events events
- * (wct_workspace_bytes(plan, WCT_OP_SIMULATE, n, rows) caps n at max_events). */
+ * (wct_workspace_bytes(plan, WCT_OP_SIMULATE, n, rows) caps n at max_events).
+ * The raster also records which impact rows (and the tick span of each), which column
+ * tiles and which wires any window reaches; the transform passes then skip the work on
+ * the rest (rows not transformed, tiles and rows of the direct wire pass taken as zero,
+ * wires without noise written as zero waveforms), which changes no result: the waveform
+ * equals that of wct_raster followed by wct_convolve. */
 int wct_simulate(wct_plan* plan, const wct_depos* depos, const wct_opts* opts, void* wave, void* ws,
                  size_t ws_bytes, void* stream);
 
