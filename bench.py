@@ -31,20 +31,23 @@ TRAFFIC_JSON = os.path.join(PROFILES, "hbm_traffic.json")
 # The commands whose output --summarize reads (run from /tmp on the GPU host, R = repo root).
 PROFILE_COMMANDS = {
     "trace": "rocprofv3 --kernel-trace --stats -f csv -d $R/gpurun_out/prof_cfg2 -o cfg2 -- "
-             "python3 $R/bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-extras --tune-cache $R/gpurun_out/fft.tune",
+             "python3 $R/bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-extras --raster-tile 128x48x5 "
+             "--tune-cache $R/gpurun_out/fft.tune",
     "fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d $R/gpurun_out/pmc_fetch -o fetch -- "
              "python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --copy-calibration-mib 1024 "
-             "--tune-cache $R/gpurun_out/fft.tune",
+             "--raster-tile 128x48x5 --tune-cache $R/gpurun_out/fft.tune",
     "write": "rocprofv3 --pmc WRITE_SIZE -f csv -d $R/gpurun_out/pmc_write -o write -- "
              "python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --copy-calibration-mib 1024 "
-             "--tune-cache $R/gpurun_out/fft.tune",
+             "--raster-tile 128x48x5 --tune-cache $R/gpurun_out/fft.tune",
     "trace_showers": "rocprofv3 --kernel-trace --stats -f csv -d $R/gpurun_out/prof_cfg3 -o cfg3 -- "
                      "python3 $R/bench.py --showers-only --steps 3",
     "sq": "rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_LDS_ATOMIC SQ_THREAD_CYCLES_VALU "
           "SQ_ACTIVE_INST_VALU SQ_WAVES SQ_LDS_BANK_CONFLICT -f csv -d $R/gpurun_out/pmc_sq -o sq -- "
-          "python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --tune-cache $R/gpurun_out/fft.tune",
+          "python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --raster-tile 128x48x5 "
+          "--tune-cache $R/gpurun_out/fft.tune",
     "atomic": "rocprofv3 --pmc TCC_ATOMIC TCP_TOTAL_ATOMIC_WITHOUT_RET -f csv -d $R/gpurun_out/pmc_atomic -o atomic -- "
-              "python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --tune-cache $R/gpurun_out/fft.tune",
+              "python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --raster-tile 128x48x5 "
+          "--tune-cache $R/gpurun_out/fft.tune",
 }
 COUNTERS_JSON = os.path.join(PROFILES, "raster_counters.json")
 
@@ -75,13 +78,19 @@ def built_digest():
         return None
 
 
-def log_digest(path):
-    """The "build" digest printed in a bench JSON line inside a log file."""
+def log_line(path):
+    """The bench JSON line inside a log file (a dict), or None."""
     with open(path) as f:
         for line in f:
             if line.startswith("{") and '"build"' in line:
-                return json.loads(line).get("build")
+                return json.loads(line)
     return None
+
+
+def log_digest(path):
+    """The "build" digest printed in a bench JSON line inside a log file."""
+    line = log_line(path)
+    return line.get("build") if line else None
 
 
 def summarize(out_dir):
@@ -119,6 +128,7 @@ def summarize(out_dir):
         path = glob.glob(os.path.join(out_dir, f"pmc_{tag}", "*counter_collection.csv"))[0]
         acc = collections.defaultdict(lambda: [0.0, 0])
         copies = []
+        seen = []  # (dispatch, family, KiB)
         for r in csv.DictReader(open(path)):
             if r["Counter_Name"] != counter:
                 continue
@@ -127,6 +137,19 @@ def summarize(out_dir):
                 copies.append(kib)
             fam = family(r["Kernel_Name"])
             if fam:
+                seen.append((int(r["Dispatch_Id"]), fam, kib))
+        # the headline step's launches of its own kernels: the last of each family before
+        # the mean raster the bench runs after the step (the tuners' launches come before
+        # it, the noise, ADC and drift figures after it); the other families whole
+        means = [d for d, fam, _ in seen if fam == "raster_tile_mean"]
+        cut = min(means) if means else None
+        step_fams = {"rows_r2c": 3, "colpass": 3, "rows_c2r": 3, "raster_tile_fluct": 1}
+        keep = set()
+        for fam, n in step_fams.items():
+            ids = sorted({d for d, f, _ in seen if f == fam and (cut is None or d < cut)})
+            keep.update((fam, d) for d in ids[-n:])
+        for d, fam, kib in seen:
+            if fam not in step_fams or (fam, d) in keep:
                 acc[fam][0] += kib
                 acc[fam][1] += 1
         # three 1 GiB device copies: the counter's reading for a known 1 GiB (= 1048576 KiB)
@@ -139,7 +162,10 @@ def summarize(out_dir):
     digest = log_digest(os.path.join(out_dir, "pmc_fetch.log"))
     if digest is None or digest != log_digest(os.path.join(out_dir, "pmc_write.log")):
         raise SystemExit("the two counter runs do not name the same library build")
-    traffic = {"build": digest, "fetch_scale": fs, "write_scale": ws, "kernels": {},
+    # the raster's traffic depends on the tile shape the tuner chose in those runs
+    tiles = [(log_line(os.path.join(out_dir, f"pmc_{t}.log")) or {}).get("raster_tile") for t in ("fetch", "write")]
+    tile = tiles[0] if tiles[0] is not None and tiles[0] == tiles[1] else None
+    traffic = {"build": digest, "fetch_scale": fs, "write_scale": ws, "kernels": {}, "raster_tile": tile,
                "commands": {k: PROFILE_COMMANDS[k] for k in ("fetch", "write")}}
     lines = ["# HBM traffic per kernel family: three-plane track workload, one step", "",
              "Commands (separate runs, from /tmp, R = repository root):", "",
@@ -147,6 +173,10 @@ def summarize(out_dir):
              f"Calibration: three plain 1 GiB device copies read {1048576 / fs:.0f} KiB (FETCH_SIZE) and wrote "
              f"{1048576 / ws:.0f} KiB (WRITE_SIZE) per copy, so the counters are scaled by {fs:.4f} (fetch) "
              f"and {ws:.4f} (write).", "",
+             (f"Raster tile shape of both runs (the tuner's choice): {tile['rows']} x {tile['ticks']}, "
+              f"{tile['blocks_per_cu']} blocks per CU; the bench reports the raster's traffic only when it runs "
+              f"the same shape." if tile else "The two runs chose different raster tile shapes: the raster's "
+              "traffic is not reported."), "",
              "| family | launches | fetch GB | write GB | total GB per launch |", "|---|---|---|---|---|"]
     for fam in sorted(set(fetch) | set(write)):
         f_b = fetch[fam][0] * 1024 * fs
@@ -197,7 +227,9 @@ def summarize_counters(out_dir):
             n_launch = {fam: len(ids) for fam, ids in want.items()}
     if len(digests) != 1 or None in digests:
         raise SystemExit("the counter runs do not name the same library build")
-    out = {"build": digests.pop(), "commands": {k: PROFILE_COMMANDS[k] for k in ("sq", "atomic")}, "kernels": {}}
+    tiles = [(log_line(os.path.join(out_dir, f"pmc_{t}.log")) or {}).get("raster_tile") for t in ("sq", "atomic")]
+    out = {"build": digests.pop(), "commands": {k: PROFILE_COMMANDS[k] for k in ("sq", "atomic")}, "kernels": {},
+           "raster_tile": tiles[0] if tiles[0] is not None and tiles[0] == tiles[1] else None}
     names = ["SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_LDS_ATOMIC", "SQ_THREAD_CYCLES_VALU",
              "SQ_ACTIVE_INST_VALU", "SQ_WAVES", "SQ_LDS_BANK_CONFLICT", "TCC_ATOMIC", "TCP_TOTAL_ATOMIC_WITHOUT_RET"]
     lines = ["# Instruction and atomic counters per launch: three-plane track workload", "",
@@ -221,25 +253,31 @@ def summarize_counters(out_dir):
     print("\n".join(lines))
 
 
-def measured_counters(kernel):
+def measured_counters(kernel, tile=None):
     """Per-launch counters of a kernel family from committed profiles, or None when the
-    library changed since."""
+    library changed since (or, for the raster tiles, when `tile` is not the tile shape the
+    counter runs used)."""
     try:
         c = json.load(open(COUNTERS_JSON))
     except (OSError, ValueError):
         return None
     if c.get("build") is None or c.get("build") != built_digest():
         return None
+    if kernel.startswith("raster_tile") and (tile is None or c.get("raster_tile") != tile):
+        return None
     return c.get("kernels", {}).get(kernel)
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch from committed counters, or None when the kernels changed since."""
+def measured_traffic(kernel, tile=None):
+    """HBM bytes per launch from committed counters, or None when the kernels changed since
+    (or, for the raster tiles, when `tile` is not the tile shape the counter runs used)."""
     try:
         t = json.load(open(TRAFFIC_JSON))
     except (OSError, ValueError):
         return None
     if t.get("build") is None or t.get("build") != built_digest() or kernel not in t.get("kernels", {}):
+        return None
+    if kernel.startswith("raster_tile") and (tile is None or t.get("raster_tile") != tile):
         return None
     return t["kernels"][kernel]["bytes_per_launch"]
 
@@ -622,7 +660,7 @@ def issue_rates(wct):
     return out
 
 
-def raster_atomics(wct, wl, t_mean_ms, t_fluct_ms):
+def raster_atomics(wct, wl, t_mean_ms, t_fluct_ms, tile=None):
     """The raster's atomic adds against the chip's peaks (the probes): the mean raster makes
     one LDS add per window cell (counted on the host); the fluctuated raster's LDS and
     device-memory atomic instructions come from the committed counters of this build."""
@@ -635,7 +673,7 @@ def raster_atomics(wct, wl, t_mean_ms, t_fluct_ms):
         cells = window_cells(wl)
         rate = cells / (t_mean_ms * 1e-3)
         out["mean_raster"] = {"lds_adds": cells, "ms": t_mean_ms, "adds_per_s": rate, "frac_of_lds_peak": rate / lds_peak}
-    c = measured_counters("raster_tile_fluct")
+    c = measured_counters("raster_tile_fluct", tile)
     if c and t_fluct_ms:
         lds_i = c["SQ_INSTS_LDS_ATOMIC"]
         out["fluct_raster"] = {"lds_atomic_instructions": lds_i,
@@ -647,10 +685,10 @@ def raster_atomics(wct, wl, t_mean_ms, t_fluct_ms):
     return out
 
 
-def raster_issue(t_ms, alg_ops):
+def raster_issue(t_ms, alg_ops, tile=None):
     """Issued instructions of the fluctuated tile raster (committed counters of this build)
     against the cost model's lane operations."""
-    c = measured_counters("raster_tile_fluct")
+    c = measured_counters("raster_tile_fluct", tile)
     if not c or not t_ms:
         return None
     slots = 64 * c["SQ_INSTS_VALU"]
@@ -741,6 +779,9 @@ def main():
                     help="time only the shower workload (two faces, 1e6 depositions) and print its JSON")
     ap.add_argument("--summarize", metavar="DIR", help="write profiles/ summaries from rocprofv3 output in DIR")
     ap.add_argument("--tune-cache", metavar="FILE", help="transform-variant choices: read from / appended to FILE")
+    ap.add_argument("--raster-tile", metavar="RxTxB",
+                    help="use this raster tile shape (rows x ticks x blocks per CU) instead of the tuner's choice "
+                         "(the counter runs fix the shape their per-launch figures hold for)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run 3 plain device copies of this many MiB (a known-size reference for "
                          "hardware byte counters)")
@@ -773,8 +814,14 @@ def main():
     dd = wct.DeviceDepos.from_numpy(wl.depos, "cuda:0", torch.float32)
     o = wct.opts(wl.nsigma, True, 1, wl.seed)
     fft_choice = plan.tune(1, args.tune_cache)  # transform variant per plane and axis, timed on this GPU
-    tile = plan.tune_raster(dd, o, args.tune_cache)  # raster tile shape, timed on this event's rows
     tiles = {v["index"]: v for v in wct.tile_variants()}
+    if args.raster_tile:
+        want = tuple(int(x) for x in args.raster_tile.split("x"))
+        tile = next(i for i, v in tiles.items() if v["dtype"] == "f32" and (v["th"], v["tw"], v["blocks_per_cu"]) == want)
+        plan.set_tile(tile)
+    else:
+        tile = plan.tune_raster(dd, o, args.tune_cache)  # raster tile shape, timed on this event's rows
+    tile_shape = {"rows": tiles[tile]["th"], "ticks": tiles[tile]["tw"], "blocks_per_cu": tiles[tile]["blocks_per_cu"]}
     variants = {v["index"]: v for v in wct.fft_variants()}
     fft_desc = {f"plane{p}_{'ticks' if k == 0 else 'wires'}":
                 ("direct 21-wire sums" if v == wct.WCT_WIRE_DIRECT else "runtime" if v < 0
@@ -826,11 +873,11 @@ def main():
         if name in alg and tot > 0:
             gbs = alg[name] * args.steps / (tot * 1e-3) / 1e9
             k.update({"alg_bytes_per_step": alg[name], "GBps": gbs, "hbm_frac": gbs / HBM_PEAK_GBS})
-        mt = measured_traffic(name)
+        mt = measured_traffic(name, tile_shape)
         if mt and tot > 0 and cnt > 0:  # counter bytes (FETCH_SIZE + WRITE_SIZE) per launch of this build
             cgbs = mt * cnt / (tot * 1e-3) / 1e9
             k.update({"counter_bytes_per_launch": mt, "counter_GBps": cgbs, "counter_hbm_frac": cgbs / HBM_PEAK_GBS})
-        mc = measured_counters(name)
+        mc = measured_counters(name, tile_shape)
         if mc and tot > 0 and cnt > 0:  # VALU issue: SQ_INSTS_VALU wave instructions x 64 lanes per launch
             k["valu_issue_frac"] = mc["SQ_INSTS_VALU"] * 64 / ((tot / cnt) * 1e-3 * ALU_PEAK_TOPS * 1e12)
         kernels[name] = k
@@ -850,7 +897,7 @@ def main():
         ops = raster_alu_ops(wl)
         t = kernels[dom]["ms_per_step"] * 1e-3
         roofline = {"kernel": dom, "bound": "alu", "achieved": ops / t / 1e12, "peak": ALU_PEAK_TOPS,
-                    "unit": "Tops/s", "frac": ops / t / 1e12 / ALU_PEAK_TOPS, "traffic": measured_traffic(dom),
+                    "unit": "Tops/s", "frac": ops / t / 1e12 / ALU_PEAK_TOPS, "traffic": measured_traffic(dom, tile_shape),
                     "alg_ops_per_launch": ops, "avg_launch_ms": kernels[dom]["ms_per_step"],
                     "note": "algorithmic lane operations (bench.raster_alu_ops cost model) / mean launch time "
                             "from HIP events on the launch stream; peak = 256 CUs x 64 lanes x 2.4 GHz"}
@@ -887,11 +934,11 @@ def main():
         "roofline": roofline,
         "roofline_fft": roofline_fft,
         "fft_plans": fft_desc,
-        "raster_tile": {"rows": tiles[tile]["th"], "ticks": tiles[tile]["tw"],
-                        "blocks_per_cu": tiles[tile]["blocks_per_cu"]},
-        "raster_atomics": raster_atomics(wct, wl, t_mean, kernels.get("raster_tile_fluct", {}).get("ms_per_step")),
+        "raster_tile": tile_shape,
+        "raster_atomics": raster_atomics(wct, wl, t_mean, kernels.get("raster_tile_fluct", {}).get("ms_per_step"),
+                                         tile_shape),
         "raster_issue": raster_issue(kernels.get("raster_tile_fluct", {}).get("ms_per_step"),
-                                     roofline.get("alg_ops_per_launch")),
+                                     roofline.get("alg_ops_per_launch"), tile_shape),
         "issue_rates": issue_rates(wct),
         "noise": noise,
         "adc": adc,
