@@ -173,7 +173,7 @@ def summarize(out_dir):
              f"Calibration: three plain 1 GiB device copies read {1048576 / fs:.0f} KiB (FETCH_SIZE) and wrote "
              f"{1048576 / ws:.0f} KiB (WRITE_SIZE) per copy, so the counters are scaled by {fs:.4f} (fetch) "
              f"and {ws:.4f} (write).", "",
-             (f"Raster tile shape of both runs (the tuner's choice): {tile['rows']} x {tile['ticks']}, "
+             (f"Raster tile shape of both runs (set with --raster-tile): {tile['rows']} x {tile['ticks']}, "
               f"{tile['blocks_per_cu']} blocks per CU; the bench reports the raster's traffic only when it runs "
               f"the same shape." if tile else "The two runs chose different raster tile shapes: the raster's "
               "traffic is not reported."), "",
